@@ -1,0 +1,65 @@
+"""Plausible mistakes planted in a copy of the oracle source must fail a pin.
+
+Each mutant is a textual edit of ``oracle/epi_oracle.c`` compiled into a
+temporary library and checked in a child process (a broken oracle may crash
+or loop).  The real oracle source is never modified.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "epi_oracle.c")
+
+MUTANTS = {
+    # cell index built with the operands of the mixed radix transposed
+    "cell_index_transposed": ("x = x * 3 + g;", "x = g * 3 + x;"),
+    # joint entropy accumulated with the wrong sign
+    "hxy_sign": ("h_xy -= p * log(p);", "h_xy += p * log(p);"),
+    # H(Y) dropped from Equation 1
+    "drop_hy": ("return h_x + h_y - h_xy;", "return h_x - h_xy;"),
+    # wrong denominator for p(x)
+    "px_denominator": ("double p = n_x / m;", "double p = n_x / (m + 1.0);"),
+    # cases and controls swapped in the table
+    "class_swap": ("int cls = y[s] ? 0 : 1;", "int cls = y[s] ? 1 : 0;"),
+    # enumeration stops one value early
+    "enum_off_by_one": ("c[t] == M - k + t)", "c[t] == M - k + t - 1)"),
+    # ties broken towards the larger combination
+    "tie_break_reversed": ("return a[t] < b[t];", "return a[t] > b[t];"),
+    # unranking off by one (splits of the rank space overlap)
+    "unrank_off_by_one": ("if (rank < block)", "if (rank <= block)"),
+    # top-K keeps the worse entry
+    "topk_compare": ("return a->mi > b->mi;", "return a->mi < b->mi;"),
+}
+
+CHILD = r"""
+import sys
+sys.path.insert(0, {root!r}); sys.path.insert(0, {tests!r})
+import oracle, oracle_pins
+o = oracle.Oracle(oracle.load({lib!r}))
+print(",".join(oracle_pins.run_battery(o)))
+"""
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, name):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not unique"
+    mut = tmp_path / "mutant.c"
+    mut.write_text(src.replace(old, new))
+    sys.path.insert(0, ROOT)
+    import oracle
+
+    lib = oracle.build(str(mut), str(tmp_path / "libmutant.so"))
+    code = CHILD.format(root=ROOT, tests=os.path.join(ROOT, "tests"), lib=lib)
+    try:
+        proc = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    except subprocess.TimeoutExpired:
+        return  # a mutant that never finishes is caught too
+    if proc.returncode != 0:
+        return  # crashed: caught
+    failed = [f for f in proc.stdout.strip().splitlines()[-1].split(",") if f] if proc.stdout.strip() else []
+    assert failed, f"mutant {name} passed every pin"
