@@ -1,0 +1,244 @@
+/*
+ * epi.h -- C ABI of the MI355X (gfx950) exhaustive k-order epistasis scanner.
+ *
+ * The library enumerates every combination of `order` SNPs out of M, builds
+ * each combination's contingency table (3^order genotype cells x {cases,
+ * controls}) from bit-packed per-genotype, per-class individual masks with
+ * bitwise AND and population count, scores every table by mutual information
+ * and keeps the best `top_k` combinations.
+ *
+ * Paper (Ponte-Fernandez, Gonzalez-Dominguez, Martin, "A SIMD algorithm for
+ * the detection of epistatic interactions of any order"):
+ *   - genotype tables: Section 2.1 (one bit per individual, one row per
+ *     genotype, cases and controls in separate subtables);
+ *   - contingency tables: Section 2.2 (popcount of the AND of rows; the last
+ *     level is fused with the popcount and never stored);
+ *   - score: Section 2.3, Equations 1-3 (MI = H(X) + H(Y) - H(X,Y), natural
+ *     logarithm, probabilities over all individuals, empty cells skipped);
+ *   - exploration: Section 2.4, Algorithm 1 (every combination of the order
+ *     exactly once; only the highest-MI combinations are kept).
+ *
+ * Conventions shared by every call:
+ *   - Every function returns EPI_OK (0) or a negative EPI_E* status; no C++
+ *     exception, abort or exit crosses this boundary.  epi_last_error()
+ *     returns a message for the calling thread's most recent failure.
+ *   - Genotypes are uint8 in {0,1,2}: homozygous dominant, heterozygous,
+ *     homozygous recessive (the three genotype-table rows of Section 2.1).
+ *     Phenotypes are uint8: 1 = case, 0 = control.
+ *   - Host pointers are borrowed only for the duration of the call.  Device
+ *     pointers (the *_device variants) must be readable by the context's
+ *     device and stay valid until the call returns.
+ *   - `stream` arguments are hipStream_t values passed as void*; NULL selects
+ *     the context's own stream.  Work is ordered after prior work on that
+ *     stream.
+ *   - Results are ordered best first: larger MI, then the lexicographically
+ *     smaller combination (ascending SNP indices).
+ *   - A contingency table is returned as 2 x 3^order uint32 counts: cases
+ *     first, then controls; cell index x = sum_t g_t * 3^(order-1-t), first
+ *     SNP most significant (the row index i*3+j used when a SNP is added to a
+ *     genotype table, Section 2.1).
+ *   - Scores are float32 values of MI in nats.
+ */
+#ifndef EPI_H
+#define EPI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define EPI_OK 0
+#define EPI_EINVAL (-1)       /* invalid argument or input value            */
+#define EPI_ENOMEM (-2)       /* device memory budget or allocation failed  */
+#define EPI_EDEVICE (-3)      /* HIP runtime error                          */
+#define EPI_EUNSUPPORTED (-4) /* valid request outside the built limits     */
+#define EPI_ENOTREADY (-5)    /* result not available yet                   */
+#define EPI_ENOTFOUND (-6)    /* unknown dataset / scan / batch / request   */
+
+/* ---- limits -------------------------------------------------------------- */
+#define EPI_MIN_ORDER 2
+#define EPI_MAX_ORDER 5
+#define EPI_MAX_TOP_K 256
+/* A combination is keyed by its indices packed big-endian into 64 bits with
+ * floor(64/order) bits each, so M may not exceed 2^floor(64/order)
+ * (order 5: M <= 4096). */
+
+typedef struct epi_ctx epi_ctx;
+
+/* Message of the calling thread's last failed call ("" if none).  The pointer
+ * stays valid until the thread's next call into the library. */
+const char *epi_last_error(void);
+
+/* Library version string. */
+const char *epi_version(void);
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`.  `hbm_budget_bytes` caps the
+ * device memory the context may hold at once (datasets + scan buffers);
+ * 0 = 90% of the device's free memory at creation.  *out receives the
+ * handle.  Errors: EINVAL (bad device / null out), EDEVICE. */
+int epi_create(int32_t device, uint64_t hbm_budget_bytes, epi_ctx **out);
+
+/* Wait for all work of the context, then free every dataset, scan, batch and
+ * server it owns.  NULL is accepted. */
+int epi_destroy(epi_ctx *ctx);
+
+/* Device memory currently held by the context and its budget, in bytes. */
+int epi_memory(epi_ctx *ctx, uint64_t *used_bytes, uint64_t *budget_bytes);
+
+/* ---- datasets (Section 2.1: genotype tables) ---------------------------- */
+
+/* Pack a dataset into device-resident genotype masks.
+ * geno: host, M rows of N genotypes, row stride `ld` bytes (ld >= N).
+ * pheno: host, N phenotypes.  Individuals keep their input order within each
+ * class.  The packed masks stay on the device until epi_unload/epi_destroy.
+ * Errors: EINVAL (M < 1, N < 2, ld < N, a genotype not in {0,1,2}, a
+ * phenotype not in {0,1}, no case or no control), ENOMEM, EDEVICE.
+ * *dataset_id receives the handle. */
+int epi_load_genotypes(epi_ctx *ctx, const uint8_t *geno, int64_t ld, const uint8_t *pheno, int32_t M,
+                       int32_t N, int32_t *dataset_id);
+
+/* Same as epi_load_genotypes with geno/pheno in device memory (e.g. torch
+ * tensors).  Synchronises `stream` once to validate the input. */
+int epi_load_genotypes_device(epi_ctx *ctx, const uint8_t *d_geno, int64_t ld, const uint8_t *d_pheno,
+                              int32_t M, int32_t N, void *stream, int32_t *dataset_id);
+
+/* Repack new genotypes and phenotypes of the same shape and class sizes into
+ * an existing dataset, from device memory, asynchronously on `stream`
+ * (no allocation, no synchronisation).  Values are not validated: they must
+ * already be known to lie in {0,1,2} and {0,1} with the dataset's class
+ * sizes.  Errors: ENOTFOUND, EINVAL (shape or class sizes differ). */
+int epi_repack_device(epi_ctx *ctx, int32_t dataset_id, const uint8_t *d_geno, int64_t ld,
+                      const uint8_t *d_pheno, void *stream);
+
+/* Free a dataset (waits for scans that still read it). */
+int epi_unload(epi_ctx *ctx, int32_t dataset_id);
+
+/* Shape of a dataset and the device bytes it holds. */
+int epi_dataset_info(epi_ctx *ctx, int32_t dataset_id, int32_t *M, int32_t *N, int32_t *n_cases,
+                     uint64_t *device_bytes);
+
+/* ---- scans (Algorithm 1 + Sections 2.2-2.3) ----------------------------- */
+
+typedef struct {
+    int32_t dataset_id;
+    int32_t order; /* EPI_MIN_ORDER..EPI_MAX_ORDER */
+    int32_t top_k; /* 1..EPI_MAX_TOP_K */
+    int32_t reserved; /* must be 0 */
+} epi_scan_desc;
+
+/* Start one exhaustive scan of `order` over a dataset, keeping the best
+ * `top_k` combinations (plain launch).  Asynchronous on `stream`; poll with
+ * epi_query or block with epi_wait.  *scan_id receives the handle.
+ * Errors: ENOTFOUND (dataset), EINVAL (order < 2 or > M, top_k < 1),
+ * EUNSUPPORTED (order > EPI_MAX_ORDER, top_k > EPI_MAX_TOP_K, M too large
+ * for the order's key width), ENOMEM, EDEVICE. */
+int epi_scan(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t top_k, void *stream,
+             int32_t *scan_id);
+
+/* Start n scans as ONE persistent launch fed by a device-side work queue,
+ * captured once into a HIP graph.  scan_ids[i] receives the handle of
+ * descs[i]; each behaves like a scan from epi_scan.  Same errors as
+ * epi_scan, checked for every descriptor before anything is launched. */
+int epi_scan_batch(epi_ctx *ctx, const epi_scan_desc *descs, int32_t n, void *stream, int32_t *scan_ids);
+
+/* *done = 1 when the scan's results are ready, else 0. */
+int epi_query(epi_ctx *ctx, int32_t scan_id, int32_t *done);
+
+/* Block until the scan's results are ready. */
+int epi_wait(epi_ctx *ctx, int32_t scan_id);
+
+/* Copy a finished scan's results into caller buffers.
+ * combos: capacity * order int32 (ascending SNP indices per row);
+ * scores: capacity float (MI, nats); tables: nullable, capacity * 2 *
+ * 3^order uint32.  *n_written = min(capacity, top_k, C(M, order)).
+ * Errors: ENOTFOUND, ENOTREADY (not finished; call epi_wait), EINVAL. */
+int epi_results(epi_ctx *ctx, int32_t scan_id, int32_t capacity, int32_t *combos, float *scores,
+                uint32_t *tables, int32_t *n_written);
+
+/* Device timings of a finished scan in milliseconds (HIP events on the
+ * scan's stream): ms[0] whole scan, ms[1] sub-table pass, ms[2] main
+ * counting/scoring kernel, ms[3] top-K merge + result tables.  Entries that
+ * do not apply (or scans run inside a batch graph) are -1. */
+int epi_scan_timing(epi_ctx *ctx, int32_t scan_id, float ms[4]);
+
+/* Number of combinations C(M, order) of a scan and the kernel variant it ran
+ * (0 = per-combination generic kernel, 1 = order-2 reduced-cell kernel,
+ * 2 = order-3 reduced-cell kernel) and its prefix block. */
+int epi_scan_info(epi_ctx *ctx, int32_t scan_id, uint64_t *n_combinations, int32_t *variant,
+                  int32_t *prefix_block);
+
+/* Free a scan's buffers (waits for it first). */
+int epi_release(epi_ctx *ctx, int32_t scan_id);
+
+/* ---- re-runnable batches ------------------------------------------------- */
+
+/* Build a batch of n scans once: work queue, per-scan buffers and (if
+ * use_graph) a captured HIP graph of the whole launch sequence.  Run it with
+ * epi_batch_run any number of times; each run overwrites the results.
+ * persistent = 1: all scans in one persistent launch (what epi_scan_batch
+ * does); 0: back-to-back plain launches, one per scan. */
+int epi_batch_create(epi_ctx *ctx, const epi_scan_desc *descs, int32_t n, int32_t persistent,
+                     int32_t use_graph, int32_t *batch_id);
+int epi_batch_run(epi_ctx *ctx, int32_t batch_id, void *stream);
+int epi_batch_wait(epi_ctx *ctx, int32_t batch_id);
+/* Results of scan `index` of the batch; same layout as epi_results. */
+int epi_batch_results(epi_ctx *ctx, int32_t batch_id, int32_t index, int32_t capacity, int32_t *combos,
+                      float *scores, uint32_t *tables, int32_t *n_written);
+/* Device milliseconds of the batch's last run (events around the run). */
+int epi_batch_timing(epi_ctx *ctx, int32_t batch_id, float *ms);
+int epi_batch_destroy(epi_ctx *ctx, int32_t batch_id);
+
+/* ---- autotuner ----------------------------------------------------------- */
+
+/* Time the kernel variants (prefix block, word unroll) for `order` on a
+ * bounded slice of the dataset's combination space and remember the fastest
+ * for datasets of the same words-per-individual bucket.  The choice is also
+ * written to the cache file named by EPI_TUNE_CACHE (if set).  Scans use
+ * tuned choices automatically; untuned shapes use built-in defaults.
+ * *choice receives the chosen prefix block. */
+int epi_autotune(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t *choice);
+
+/* ---- serving: continuous batching -------------------------------------- */
+
+typedef struct {
+    int32_t max_active;        /* requests resident on the device at once (>= 1) */
+    int32_t round_items;       /* work items per launch round (0 = auto) */
+    uint64_t request_budget;   /* device bytes for request buffers (0 = ctx budget) */
+} epi_server_config;
+
+/* Start a server thread that admits requests by device-memory footprint and
+ * runs every admitted request's work as slices of shared persistent launches
+ * (continuous batching: requests join and leave between launch rounds). */
+int epi_server_start(epi_ctx *ctx, const epi_server_config *cfg, int32_t *server_id);
+
+/* Enqueue a scan request on a resident dataset; thread-safe, non-blocking.
+ * Same argument checks as epi_scan. */
+int epi_server_submit(epi_ctx *ctx, int32_t server_id, int32_t dataset_id, int32_t order, int32_t top_k,
+                      int32_t *request_id);
+
+/* *state: 0 queued, 1 admitted (on the device), 2 done. */
+int epi_server_poll(epi_ctx *ctx, int32_t server_id, int32_t request_id, int32_t *state);
+
+/* Results of a finished request (layout as epi_results) and its latency in
+ * milliseconds from submission to results ready (nullable).  The request is
+ * freed after this call.  Errors: ENOTREADY, ENOTFOUND. */
+int epi_server_results(epi_ctx *ctx, int32_t server_id, int32_t request_id, int32_t capacity,
+                       int32_t *combos, float *scores, uint32_t *tables, int32_t *n_written,
+                       double *latency_ms);
+
+/* Counters: [0] requests done, [1] launch rounds, [2] combos*individuals done,
+ * [3] peak request bytes, [4] peak concurrently admitted requests. */
+int epi_server_stats(epi_ctx *ctx, int32_t server_id, uint64_t out[5]);
+
+/* Finish all submitted requests, then stop the server thread. */
+int epi_server_stop(epi_ctx *ctx, int32_t server_id);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EPI_H */

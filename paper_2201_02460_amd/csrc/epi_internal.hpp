@@ -1,0 +1,96 @@
+// Internal layout shared by the host runtime and the gfx950 kernels.
+//
+// Device layout of a packed dataset (the genotype tables of Section 2.1 of the
+// paper, stored per class and per genotype as bitsets of individuals):
+//
+//   masks   : v4u [(W4[0] + W4[1]) * 2][Mp]
+//             element ((wbase[c] + w4) * 2 + g) * Mp + s holds bits
+//             128*w4 .. 128*w4+127 of class c's row for genotype g of SNP s
+//             (4 x 32-bit words, bit b of word q = individual 32*(4*w4+q)+b
+//             of that class, in input order).  Only genotypes 0 and 1 are
+//             stored; genotype 2 is valid & ~(row0 | row1).  Bits past the
+//             class size and SNPs s >= M are zero.  Class 0 = cases.
+//   single  : u32 [Mp][2 classes][2 genotypes] per-SNP class counts of
+//             genotypes 0 and 1.
+//   tlog    : i64 [N + 1], tlog[n] = round(n * ln(n) * 2^shift).
+//
+// Lanes of a wave read 16 consecutive bytes each of 64 consecutive SNPs, so a
+// wave-wide load of one mask row group is one contiguous 1 KiB segment.
+#pragma once
+
+#include <stdint.h>
+
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
+namespace epi {
+
+constexpr int kMaxTopK = 256;
+constexpr int kWave = 64;
+constexpr int kMergeSlots = 4096;      // LDS entries of the top-K merge
+constexpr int kMaxBinomOrder = 8;
+
+enum Variant : int32_t {
+    kGeneric = 0,  // one combination per lane, all 3^k cells counted
+    kF2 = 1,       // order 2, reduced cells, prefix block of i's
+    kF3 = 2,       // order 3, reduced cells, prefix block of i's sharing j
+    kF2Emit = 3,   // order-2 reduced cells written to the pair sub-table
+};
+
+struct DsView {
+    const v4u *masks;
+    const uint32_t *single;
+    const long long *tlog;
+    int32_t M, Mp, N, shift;
+    int32_t ncls[2];
+    int32_t w4[2];
+    int32_t wbase[2];
+};
+
+// One top-K candidate: larger num is better; on equal num the smaller key
+// (the combination's indices packed big-endian) is better.
+struct Cand {
+    long long num;
+    unsigned long long key;
+};
+
+struct Task {
+    DsView ds;
+    uint32_t *pairs;                  // lex-ordered pair sub-table, 8 u32 per pair
+    const unsigned long long *item_off;  // per-prefix item offsets (kF2/kF2Emit: per i-block, kF3: per j)
+    unsigned long long n_items;
+    unsigned long long item_base;     // first global item of this task in its launch
+    unsigned long long n_combos;
+    long long score_const;            // tlog[N] - tlog[n_case] - tlog[n_ctrl]
+    Cand *cand;                       // candidate sink
+    unsigned int *cand_count;
+    unsigned long long *thr;          // running lower bound of the K-th best num (sign-flipped int64)
+    unsigned int cand_cap;
+    int32_t variant, order, top_k;
+    int32_t np;                       // prefix block (kF2/kF3) or ranks per lane (kGeneric)
+    int32_t n_blocks;                 // number of prefix blocks (kF2: i-blocks, kF3: j values + 1)
+    int32_t key_bits;                 // bits per index in the packed key
+    int32_t pad;
+};
+
+// Per-task result block written by the finalize kernel:
+//   int32 n_valid, int32 pad[3],
+//   int32 combos[top_k][order], float scores[top_k],
+//   uint32 tables[top_k][2][3^order]
+struct ResultLayout {
+    long long offset;  // byte offset of the block in the plan's result buffer
+    int32_t top_k, order;
+};
+
+inline int pow3i(int k) {
+    int p = 1;
+    for (int t = 0; t < k; ++t) p *= 3;
+    return p;
+}
+
+inline long long result_block_bytes(int top_k, int order) {
+    long long b = 16 + (long long)top_k * order * 4 + (long long)top_k * 4 +
+                  (long long)top_k * 2 * pow3i(order) * 4;
+    return (b + 255) & ~255LL;
+}
+
+}  // namespace epi

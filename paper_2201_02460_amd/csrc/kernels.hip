@@ -1,0 +1,950 @@
+// gfx950 kernels of the exhaustive k-order epistasis scan.
+//
+// Paper mapping:
+//   pack_kernel / singles_kernel  genotype tables of single SNPs (Section 2.1)
+//   scan_persistent               enumeration (Algorithm 1), contingency
+//                                 tables (Section 2.2), mutual information
+//                                 (Section 2.3, Equations 1-3), best-K
+//                                 retention (Section 2.4)
+//   merge_kernel                  final best-K selection
+//   finalize_kernel               combinations, scores and full 2 x 3^k
+//                                 tables of the retained combinations
+//
+// Counting.  The paper intersects genotype rows with AND and counts bits.  A
+// cell of a combination's table is popcount(AND of one row per SNP).  Here a
+// lane counts the cells of one combination; the rows of SNPs shared by every
+// lane of the wave (the prefix of Algorithm 1) are read with scalar loads, so
+// each cell of each 32-individual word costs one v_bitop3_b32 (three-input
+// AND) and one v_bcnt_u32_b32 (popcount + accumulate).
+//
+// Reduced cells (kF2, kF3).  Only cells whose genotypes are all 0 or 1 are
+// counted.  Every other cell follows exactly by inclusion-exclusion from
+// counts of sub-combinations: the indicator of genotype 2 is 1 minus the
+// indicators of genotypes 0 and 1, so a cell with genotype 2 at SNP t equals
+// the table of the combination without SNP t minus the two cells with
+// genotype 0 and 1 at t.  Order 2 needs the single-SNP counts, order 3 the
+// pair sub-table (written by the kF2Emit variant) as well.  The integers are
+// those of counting all 3^k cells.
+//
+// Score.  N * MI = sum_xy n_xy ln n_xy - sum_x n_x ln n_x - sum_y n_y ln n_y
+// + N ln N (Equation 1 with p = n / N).  Each n ln n is read from a table of
+// round(n ln n * 2^shift) and summed in int64, so the score of a combination
+// is the same integer whatever kernel, tile or batch computes it.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "epi_internal.hpp"
+
+namespace epi {
+
+typedef __attribute__((address_space(4))) const v4u cv4u;  // wave-uniform rows: scalar loads
+typedef __attribute__((address_space(1))) const v4u gv4u;  // per-lane rows: vector loads
+
+#define EPI_DEV __device__ __forceinline__
+
+// popcount(x) + acc as one v_bcnt_u32_b32 (the compiler would otherwise
+// reassociate chains of popcounts into extra v_add3 instructions).
+EPI_DEV unsigned bcnt_acc(unsigned x, unsigned acc) {
+    unsigned r;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+    return r;
+}
+
+EPI_DEV unsigned long long rfl64(unsigned long long v) {
+    unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+EPI_DEV unsigned long long readlane64(unsigned long long v, int lane) {
+    unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, lane);
+    unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), lane);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+EPI_DEV unsigned lane_prefix(unsigned long long mask) {
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+// Pin a wave-uniform value to a scalar register (values decoded with VALU
+// arithmetic, such as integer division, would otherwise stay in VGPRs and
+// turn the uniform mask-row loads into vector loads).
+EPI_DEV int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+EPI_DEV unsigned long long bias(long long v) { return (unsigned long long)v ^ 0x8000000000000000ull; }
+EPI_DEV long long unbias(unsigned long long v) { return (long long)(v ^ 0x8000000000000000ull); }
+
+EPI_DEV long long load_thr(unsigned long long *p) {
+    return unbias(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+EPI_DEV bool better(long long an, unsigned long long ak, long long bn, unsigned long long bk) {
+    return an > bn || (an == bn && ak < bk);
+}
+
+// Rank of pair (x, y), x < y, in the lexicographic order of the pairs of M.
+EPI_DEV unsigned long long lexpair(long long x, long long y, long long M) {
+    return (unsigned long long)(x * (2 * M - x - 1) / 2 + (y - x - 1));
+}
+
+// Valid-individual bits of words 4*w4 .. 4*w4+3 of a class of n individuals.
+EPI_DEV v4u valid_mask(int n, int w4) {
+    v4u v;
+    #pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int left = n - 32 * (4 * w4 + q);
+        v[q] = left >= 32 ? 0xffffffffu : (left <= 0 ? 0u : ((1u << left) - 1u));
+    }
+    return v;
+}
+
+// In-place inclusion-exclusion over a 3^2 / 3^3 table whose index 2 along an
+// axis holds the marginal over that SNP on input and genotype 2 on output.
+EPI_DEV void mobius2(int (&R)[9]) {
+    #pragma unroll
+    for (int e = 0; e < 3; ++e) R[6 + e] -= R[e] + R[3 + e];
+    #pragma unroll
+    for (int a = 0; a < 3; ++a) R[3 * a + 2] -= R[3 * a] + R[3 * a + 1];
+}
+
+EPI_DEV void mobius3(int (&R)[27]) {
+    #pragma unroll
+    for (int r = 0; r < 9; ++r) R[18 + r] -= R[r] + R[9 + r];
+    #pragma unroll
+    for (int a = 0; a < 3; ++a)
+        #pragma unroll
+        for (int e = 0; e < 3; ++e) R[9 * a + 6 + e] -= R[9 * a + e] + R[9 * a + 3 + e];
+    #pragma unroll
+    for (int ab = 0; ab < 9; ++ab) R[3 * ab + 2] -= R[3 * ab] + R[3 * ab + 1];
+}
+
+// ---------------------------------------------------------------------------
+// Per-wave best-K list in LDS (unsorted) with its current worst entry.
+// ---------------------------------------------------------------------------
+struct TopK {
+    int n, K, wi;
+    long long wn;
+    unsigned long long wk;
+};
+
+EPI_DEV void tk_recompute(TopK &t, const Cand *list) {
+    const int lane = threadIdx.x;
+    long long bn = 0;
+    unsigned long long bk = 0;
+    int bi = -1;
+    for (int i = lane; i < t.n; i += kWave) {
+        Cand c = list[i];
+        if (bi < 0 || better(bn, bk, c.num, c.key)) {
+            bn = c.num;
+            bk = c.key;
+            bi = i;
+        }
+    }
+    #pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        long long on = __shfl_xor(bn, off);
+        unsigned long long ok = __shfl_xor(bk, off);
+        int oi = __shfl_xor(bi, off);
+        if (oi >= 0 && (bi < 0 || better(bn, bk, on, ok))) {
+            bn = on;
+            bk = ok;
+            bi = oi;
+        }
+    }
+    t.wn = (long long)rfl64((unsigned long long)bn);
+    t.wk = rfl64(bk);
+    t.wi = __builtin_amdgcn_readfirstlane(bi);
+}
+
+EPI_DEV void tk_offer(TopK &t, Cand *list, bool valid, long long num, unsigned long long key, long long gthr) {
+    bool want = valid && num >= gthr && (t.n < t.K || better(num, key, t.wn, t.wk));
+    unsigned long long mask = __ballot(want);
+    while (mask) {
+        const int src = __builtin_ctzll(mask);
+        const long long cn = (long long)readlane64((unsigned long long)num, src);
+        const unsigned long long ck = readlane64(key, src);
+        if (t.n < t.K) {
+            if (threadIdx.x == 0) list[t.n] = Cand{cn, ck};
+            t.n++;
+            if (t.n == t.K) {
+                __syncthreads();
+                tk_recompute(t, list);
+            }
+        } else if (better(cn, ck, t.wn, t.wk)) {
+            if (threadIdx.x == 0) list[t.wi] = Cand{cn, ck};
+            __syncthreads();
+            tk_recompute(t, list);
+        }
+        mask &= mask - 1;
+        if (t.n == t.K) mask &= __ballot(want && better(num, key, t.wn, t.wk));
+    }
+}
+
+// Append the list's entries that can still be in the final best K to the
+// task's candidate buffer, then empty the list.
+EPI_DEV void tk_flush(TopK &t, const Cand *list, const Task &task) {
+    __syncthreads();
+    const long long g = load_thr(task.thr);
+    for (int base = 0; base < t.n; base += kWave) {
+        const int i = base + (int)threadIdx.x;
+        Cand c{0, 0};
+        bool keep = false;
+        if (i < t.n) {
+            c = list[i];
+            keep = c.num >= g;
+        }
+        unsigned long long m = __ballot(keep);
+        unsigned cnt = (unsigned)__popcll(m);
+        unsigned off = 0;
+        if (threadIdx.x == 0 && cnt) off = atomicAdd(task.cand_count, cnt);
+        off = __builtin_amdgcn_readfirstlane(off);
+        unsigned pos = off + lane_prefix(m);
+        if (keep && pos < task.cand_cap) task.cand[pos] = c;
+    }
+    __syncthreads();
+    t.n = 0;
+}
+
+// One cell's contribution T(n0) + T(n1) - T(n0 + n1).  Counts are clamped to
+// [0, N] so that no value can index past the table.
+EPI_DEV long long cell_term(const long long *T, int n0, int n1, unsigned N) {
+    const unsigned a = min((unsigned)n0, N);
+    const unsigned b = min((unsigned)n1, N);
+    const unsigned ab = min(a + b, N);
+    return T[a] + T[b] - T[ab];
+}
+
+// ---------------------------------------------------------------------------
+// kF2 / kF2Emit: order 2.  A work item is (block of NP SNPs i, block of 64
+// SNPs m > i); lane = m.  Reduced cells (a, d) in {0,1}^2 per class.
+// ---------------------------------------------------------------------------
+template <int NP, bool EMIT>
+EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr) {
+    const DsView d = t.ds;
+    int lo = 0, hi = t.n_blocks - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (t.item_off[mid] <= local) lo = mid; else hi = mid - 1;
+    }
+    const int ib = uni(lo);
+    const int mb = uni((int)(local - t.item_off[ib]));
+    const int i0 = ib * NP;
+    const int lane = threadIdx.x;
+    const int m = i0 + 1 + mb * kWave + lane;
+    const bool mv = m < d.M;
+    const int m_ld = mv ? m : d.Mp - 1;
+    int ip[NP];
+    #pragma unroll
+    for (int p = 0; p < NP; ++p) ip[p] = uni(min(i0 + p, d.M - 1));
+
+    cv4u *cm = (cv4u *)d.masks;
+    gv4u *gm = (gv4u *)d.masks;
+    unsigned acc[NP][2][4];
+    #pragma unroll
+    for (int p = 0; p < NP; ++p)
+        #pragma unroll
+        for (int c = 0; c < 2; ++c)
+            #pragma unroll
+            for (int e = 0; e < 4; ++e) acc[p][c][e] = 0;
+
+    const long long Mp = d.Mp;
+    #pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int W = d.w4[c];
+        long long off = (long long)d.wbase[c] * 2 * Mp;
+        for (int w = 0; w < W; ++w, off += 2 * Mp) {
+            const v4u m0 = gm[off + m_ld];
+            const v4u m1 = gm[off + Mp + m_ld];
+            #pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const v4u a0 = cm[off + ip[p]];
+                const v4u a1 = cm[off + Mp + ip[p]];
+                #pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    acc[p][c][0] = bcnt_acc(a0[q] & m0[q], acc[p][c][0]);
+                    acc[p][c][1] = bcnt_acc(a0[q] & m1[q], acc[p][c][1]);
+                    acc[p][c][2] = bcnt_acc(a1[q] & m0[q], acc[p][c][2]);
+                    acc[p][c][3] = bcnt_acc(a1[q] & m1[q], acc[p][c][3]);
+                }
+            }
+        }
+    }
+
+    const v4u *single4 = (const v4u *)d.single;
+    const v4u sm = single4[m_ld];
+    #pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int i = i0 + p;
+        const bool valid = mv && i < m && i <= d.M - 2;
+        if (EMIT) {
+            if (valid) {
+                v4u *pv = (v4u *)t.pairs;
+                const unsigned long long r = lexpair(i, m, d.M);
+                pv[2 * r + 0] = v4u{acc[p][0][0], acc[p][0][1], acc[p][0][2], acc[p][0][3]};
+                pv[2 * r + 1] = v4u{acc[p][1][0], acc[p][1][1], acc[p][1][2], acc[p][1][3]};
+            }
+        } else {
+            const v4u si = single4[ip[p]];
+            int F[2][9];
+            #pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                F[c][0] = acc[p][c][0];
+                F[c][1] = acc[p][c][1];
+                F[c][3] = acc[p][c][2];
+                F[c][4] = acc[p][c][3];
+                F[c][2] = si[2 * c + 0];
+                F[c][5] = si[2 * c + 1];
+                F[c][6] = sm[2 * c + 0];
+                F[c][7] = sm[2 * c + 1];
+                F[c][8] = d.ncls[c];
+                mobius2(F[c]);
+                #pragma unroll
+                for (int x = 0; x < 9; ++x) F[c][x] = valid ? F[c][x] : 0;
+            }
+            long long num = t.score_const;
+            #pragma unroll
+            for (int x = 0; x < 9; ++x) num += cell_term(d.tlog, F[0][x], F[1][x], (unsigned)d.N);
+            const unsigned long long key = ((unsigned long long)i << 32) | (unsigned long long)m;
+            tk_offer(tk, list, valid, num, key, gthr);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// kF3: order 3.  A work item is (j, block of NP SNPs i < j, block of 64 SNPs
+// m > j); lane = m.  Reduced cells (a, b, d) in {0,1}^3 per class; every
+// other cell comes from the pair sub-table and the single-SNP counts.
+// ---------------------------------------------------------------------------
+template <int NP>
+EPI_DEV void item_f3(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr) {
+    const DsView d = t.ds;
+    int lo = 1, hi = t.n_blocks - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (t.item_off[mid] <= local) lo = mid; else hi = mid - 1;
+    }
+    const int j = uni(lo);
+    const int nmb = uni((d.M - 1 - j + kWave - 1) / kWave);
+    const unsigned r = (unsigned)(local - t.item_off[j]);
+    const int ib = uni((int)(r / (unsigned)nmb));
+    const int mb = uni((int)(r - (unsigned)ib * (unsigned)nmb));
+    const int i0 = ib * NP;
+    const int lane = threadIdx.x;
+    const int m = j + 1 + mb * kWave + lane;
+    const bool mv = m < d.M;
+    const int m_ld = mv ? m : d.Mp - 1;
+    int ip[NP];
+    #pragma unroll
+    for (int p = 0; p < NP; ++p) ip[p] = uni(min(i0 + p, j - 1));
+
+    cv4u *cm = (cv4u *)d.masks;
+    gv4u *gm = (gv4u *)d.masks;
+    unsigned acc[NP][2][8];
+    #pragma unroll
+    for (int p = 0; p < NP; ++p)
+        #pragma unroll
+        for (int c = 0; c < 2; ++c)
+            #pragma unroll
+            for (int e = 0; e < 8; ++e) acc[p][c][e] = 0;
+
+    const long long Mp = d.Mp;
+    #pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int W = d.w4[c];
+        long long off = (long long)d.wbase[c] * 2 * Mp;
+        for (int w = 0; w < W; ++w, off += 2 * Mp) {
+            const v4u m0 = gm[off + m_ld];
+            const v4u m1 = gm[off + Mp + m_ld];
+            const v4u b0 = cm[off + j];
+            const v4u b1 = cm[off + Mp + j];
+            #pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const v4u a0 = cm[off + ip[p]];
+                const v4u a1 = cm[off + Mp + ip[p]];
+                #pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    acc[p][c][0] = bcnt_acc(a0[q] & b0[q] & m0[q], acc[p][c][0]);
+                    acc[p][c][1] = bcnt_acc(a0[q] & b0[q] & m1[q], acc[p][c][1]);
+                    acc[p][c][2] = bcnt_acc(a0[q] & b1[q] & m0[q], acc[p][c][2]);
+                    acc[p][c][3] = bcnt_acc(a0[q] & b1[q] & m1[q], acc[p][c][3]);
+                    acc[p][c][4] = bcnt_acc(a1[q] & b0[q] & m0[q], acc[p][c][4]);
+                    acc[p][c][5] = bcnt_acc(a1[q] & b0[q] & m1[q], acc[p][c][5]);
+                    acc[p][c][6] = bcnt_acc(a1[q] & b1[q] & m0[q], acc[p][c][6]);
+                    acc[p][c][7] = bcnt_acc(a1[q] & b1[q] & m1[q], acc[p][c][7]);
+                }
+            }
+        }
+    }
+
+    const v4u *single4 = (const v4u *)d.single;
+    const v4u *pair4 = (const v4u *)t.pairs;
+    const v4u sm = single4[m_ld];
+    const v4u sj = single4[j];
+    const unsigned long long rjm = mv ? lexpair(j, m, d.M) : 0ull;
+    const v4u pjm[2] = {pair4[2 * rjm], pair4[2 * rjm + 1]};
+    #pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int i = i0 + p;
+        const bool valid = mv && i < j;
+        const v4u si = single4[ip[p]];
+        const unsigned long long rij = lexpair(ip[p], j, d.M);
+        const unsigned long long rim = valid ? lexpair(i, m, d.M) : 0ull;
+        int F[2][27];
+        #pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const v4u pij = pair4[2 * rij + c];
+            const v4u pim = pair4[2 * rim + c];
+            // F[a*9 + b*3 + e]; index 2 on an axis = marginal over that SNP
+            #pragma unroll
+            for (int a = 0; a < 2; ++a)
+                #pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    #pragma unroll
+                    for (int e = 0; e < 2; ++e) F[c][9 * a + 3 * b + e] = acc[p][c][4 * a + 2 * b + e];
+            #pragma unroll
+            for (int a = 0; a < 2; ++a)
+                #pragma unroll
+                for (int b = 0; b < 2; ++b) F[c][9 * a + 3 * b + 2] = pij[2 * a + b];
+            #pragma unroll
+            for (int a = 0; a < 2; ++a)
+                #pragma unroll
+                for (int e = 0; e < 2; ++e) F[c][9 * a + 6 + e] = pim[2 * a + e];
+            #pragma unroll
+            for (int b = 0; b < 2; ++b)
+                #pragma unroll
+                for (int e = 0; e < 2; ++e) F[c][18 + 3 * b + e] = pjm[c][2 * b + e];
+            F[c][9 * 0 + 8] = si[2 * c + 0];
+            F[c][9 * 1 + 8] = si[2 * c + 1];
+            F[c][18 + 2] = sj[2 * c + 0];
+            F[c][18 + 5] = sj[2 * c + 1];
+            F[c][24] = sm[2 * c + 0];
+            F[c][25] = sm[2 * c + 1];
+            F[c][26] = d.ncls[c];
+            mobius3(F[c]);
+            #pragma unroll
+            for (int x = 0; x < 27; ++x) F[c][x] = valid ? F[c][x] : 0;
+        }
+        long long num = t.score_const;
+        #pragma unroll
+        for (int x = 0; x < 27; ++x) num += cell_term(d.tlog, F[0][x], F[1][x], (unsigned)d.N);
+        const unsigned long long key =
+            ((unsigned long long)i << 42) | ((unsigned long long)j << 21) | (unsigned long long)m;
+        tk_offer(tk, list, valid, num, key, gthr);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// kGeneric: any order K.  A work item is 64 * kGenRanks consecutive colex
+// ranks; lane l takes ranks l, l + 64, ...  Each lane counts all 3^K cells of
+// its own combination, 27 cells (the last three SNPs) at a time for each
+// genotype choice of the first K - 3 SNPs.
+// ---------------------------------------------------------------------------
+constexpr int kGenRanks = 4;
+
+constexpr int pow3c(int k) { return k <= 0 ? 1 : 3 * pow3c(k - 1); }
+
+template <int K>
+EPI_DEV void colex_unrank(unsigned long long rank, int M, const unsigned long long *binom, int bstride, int (&c)[K]) {
+    #pragma unroll
+    for (int t = K; t >= 1; --t) {
+        const unsigned long long *row = binom + (long long)t * bstride;
+        int lo = t - 1, hi = M - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (row[mid] <= rank) lo = mid; else hi = mid - 1;
+        }
+        c[t - 1] = lo;
+        rank -= row[lo];
+    }
+}
+
+template <int K>
+EPI_DEV long long generic_num(const DsView &d, const int (&c)[K], long long score_const) {
+    constexpr int NPRE = K > 3 ? K - 3 : 0;
+    constexpr int NCH = pow3c(NPRE);
+    constexpr int L = K >= 3 ? 3 : 2;
+    constexpr int CELLS = L == 3 ? 27 : 9;
+    gv4u *gm = (gv4u *)d.masks;
+    const long long Mp = d.Mp;
+    long long num = score_const;
+    for (int ch = 0; ch < NCH; ++ch) {
+        int dig[NPRE > 0 ? NPRE : 1];
+        {
+            int x = ch;
+            #pragma unroll
+            for (int t = NPRE - 1; t >= 0; --t) {
+                dig[t] = x % 3;
+                x /= 3;
+            }
+        }
+        unsigned acc[2][CELLS];
+        #pragma unroll
+        for (int cl = 0; cl < 2; ++cl) {
+            #pragma unroll
+            for (int x = 0; x < CELLS; ++x) acc[cl][x] = 0;
+            const int W = d.w4[cl];
+            long long off = (long long)d.wbase[cl] * 2 * Mp;
+            for (int w = 0; w < W; ++w, off += 2 * Mp) {
+                const v4u vm = valid_mask(d.ncls[cl], w);
+                v4u X = vm;
+                #pragma unroll
+                for (int t = 0; t < NPRE; ++t) {
+                    const v4u r0 = gm[off + c[t]];
+                    const v4u r1 = gm[off + Mp + c[t]];
+                    const v4u r2 = vm & ~(r0 | r1);
+                    X &= dig[t] == 0 ? r0 : (dig[t] == 1 ? r1 : r2);
+                }
+                v4u rows[L][3];
+                #pragma unroll
+                for (int u = 0; u < L; ++u) {
+                    const int s = c[K - L + u];
+                    rows[u][0] = gm[off + s];
+                    rows[u][1] = gm[off + Mp + s];
+                    rows[u][2] = vm & ~(rows[u][0] | rows[u][1]);
+                }
+                #pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if constexpr (L == 3) {
+                        #pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            const unsigned xa = X[q] & rows[0][a][q];
+                            #pragma unroll
+                            for (int b = 0; b < 3; ++b)
+                                #pragma unroll
+                                for (int e = 0; e < 3; ++e)
+                                    acc[cl][9 * a + 3 * b + e] =
+                                        bcnt_acc(xa & rows[1][b][q] & rows[2][e][q], acc[cl][9 * a + 3 * b + e]);
+                        }
+                    } else {
+                        #pragma unroll
+                        for (int a = 0; a < 3; ++a)
+                            #pragma unroll
+                            for (int b = 0; b < 3; ++b)
+                                acc[cl][3 * a + b] = bcnt_acc(rows[0][a][q] & rows[1][b][q], acc[cl][3 * a + b]);
+                    }
+                }
+            }
+        }
+        #pragma unroll
+        for (int x = 0; x < CELLS; ++x) num += cell_term(d.tlog, (int)acc[0][x], (int)acc[1][x], (unsigned)d.N);
+    }
+    return num;
+}
+
+template <int K>
+EPI_DEV void item_generic(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr,
+                          const unsigned long long *binom, int bstride) {
+    const DsView d = t.ds;
+    const int bits = t.key_bits;
+    for (int rr = 0; rr < kGenRanks; ++rr) {
+        unsigned long long rank = (local * kGenRanks + rr) * kWave + threadIdx.x;
+        const bool valid = rank < t.n_combos;
+        rank = valid ? rank : 0ull;
+        int c[K];
+        colex_unrank<K>(rank, d.M, binom, bstride, c);
+        const long long num = generic_num<K>(d, c, t.score_const);
+        unsigned long long key = 0;
+        #pragma unroll
+        for (int u = 0; u < K; ++u) key = (key << bits) | (unsigned long long)c[u];
+        tk_offer(tk, list, valid, num, key, gthr);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent scan kernel: one wave per workgroup; waves pop work items from a
+// device queue (one atomic per item) that runs over the concatenated item
+// spaces of all tasks of the launch, in task order.
+// ---------------------------------------------------------------------------
+template <int NP2, int NP3, int GK>
+__global__ void __launch_bounds__(64) scan_persistent(const Task *__restrict__ tasks, int n_tasks,
+                                                      unsigned long long total_items,
+                                                      unsigned long long *__restrict__ queue,
+                                                      const unsigned long long *__restrict__ binom, int bstride) {
+    __shared__ Cand s_list[kMaxTopK];
+    TopK tk;
+    tk.n = 0;
+    tk.K = 1;
+    tk.wi = 0;
+    tk.wn = 0;
+    tk.wk = 0;
+    int cur = -1;
+    long long gthr = (long long)0x8000000000000000ull;
+    for (;;) {
+        unsigned long long item = 0;
+        if (threadIdx.x == 0) item = atomicAdd(queue, 1ull);
+        item = rfl64(item);
+        if (item >= total_items) break;
+        int lo = 0, hi = n_tasks - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (tasks[mid].item_base <= item) lo = mid; else hi = mid - 1;
+        }
+        if (lo != cur) {
+            if (cur >= 0 && tasks[cur].variant != kF2Emit) tk_flush(tk, s_list, tasks[cur]);
+            cur = lo;
+            tk.n = 0;
+            tk.K = tasks[cur].top_k;
+            gthr = (long long)0x8000000000000000ull;
+        }
+        const Task &T = tasks[cur];
+        const unsigned long long local = item - T.item_base;
+        if (T.variant != kF2Emit) {
+            long long g = 0;
+            if (threadIdx.x == 0) g = load_thr(T.thr);
+            g = (long long)rfl64((unsigned long long)g);
+            gthr = g > gthr ? g : gthr;
+        }
+        switch (T.variant) {
+        case kF2:
+            if constexpr (NP2 > 0) item_f2<NP2, false>(T, local, tk, s_list, gthr);
+            break;
+        case kF2Emit:
+            if constexpr (NP2 > 0) item_f2<NP2, true>(T, local, tk, s_list, gthr);
+            break;
+        case kF3:
+            if constexpr (NP3 > 0) item_f3<NP3>(T, local, tk, s_list, gthr);
+            break;
+        default:
+            if constexpr (GK > 0) item_generic<GK>(T, local, tk, s_list, gthr, binom, bstride);
+            break;
+        }
+        if (T.variant != kF2Emit && tk.n == tk.K && tk.wn > gthr) {
+            if (threadIdx.x == 0) atomicMax(T.thr, bias(tk.wn));
+            gthr = tk.wn;
+        }
+    }
+    if (cur >= 0 && tasks[cur].variant != kF2Emit) tk_flush(tk, s_list, tasks[cur]);
+}
+
+// ---------------------------------------------------------------------------
+// Best-K selection over a task's candidate buffer: one 1024-thread workgroup
+// per task; candidates below the task's final threshold are dropped, the rest
+// are bitonic-sorted in LDS (best first) chunk by chunk.
+// ---------------------------------------------------------------------------
+EPI_DEV void bitonic_sort_best_first(Cand *buf, int P) {
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int i = threadIdx.x; i < P; i += blockDim.x) {
+                const int ixj = i ^ jj;
+                if (ixj > i) {
+                    const Cand a = buf[i], b = buf[ixj];
+                    const bool up = (i & k) == 0;
+                    const bool sw = up ? better(b.num, b.key, a.num, a.key) : better(a.num, a.key, b.num, b.key);
+                    if (sw) {
+                        buf[i] = b;
+                        buf[ixj] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__global__ void __launch_bounds__(1024) merge_kernel(const Task *__restrict__ tasks, Cand *__restrict__ results) {
+    __shared__ Cand buf[kMergeSlots];
+    __shared__ int s_ctr;
+    const Task &t = tasks[blockIdx.x];
+    const Cand sentinel{(long long)0x8000000000000000ull, ~0ull};
+    const int K = t.top_k;
+    const unsigned cap = t.cand_cap;
+    unsigned count = *t.cand_count;
+    count = count < cap ? count : cap;
+    const long long g = load_thr(t.thr);
+    for (int i = threadIdx.x; i < kMergeSlots; i += blockDim.x) buf[i] = sentinel;
+    __syncthreads();
+    int fill = K;
+    for (unsigned base = 0; base < count; base += blockDim.x) {
+        const unsigned i = base + threadIdx.x;
+        Cand c = sentinel;
+        bool keep = false;
+        if (i < count) {
+            c = t.cand[i];
+            keep = c.num >= g;
+        }
+        const int n = __syncthreads_count(keep);
+        if (fill + n > kMergeSlots) {
+            int P = 64;
+            while (P < fill) P <<= 1;
+            bitonic_sort_best_first(buf, P);
+            for (int x = K + threadIdx.x; x < kMergeSlots; x += blockDim.x) buf[x] = sentinel;
+            fill = K;
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) s_ctr = fill;
+        __syncthreads();
+        if (keep) buf[atomicAdd(&s_ctr, 1)] = c;
+        __syncthreads();
+        fill += n;
+    }
+    int P = 64;
+    while (P < fill) P <<= 1;
+    bitonic_sort_best_first(buf, P);
+    for (int r = threadIdx.x; r < K; r += blockDim.x) results[(long long)blockIdx.x * kMaxTopK + r] = buf[r];
+}
+
+// ---------------------------------------------------------------------------
+// Result tables: one wave per (task, result).  Decodes the combination,
+// converts the score, and counts the full 2 x 3^k table straight from the
+// masks (genotype-2 rows = valid & ~(row0 | row1)).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) finalize_kernel(const Task *__restrict__ tasks, const Cand *__restrict__ results,
+                                                      const ResultLayout *__restrict__ layout, char *__restrict__ out) {
+    const int ti = blockIdx.y;
+    const int r = blockIdx.x;
+    const Task &t = tasks[ti];
+    const int K = t.top_k;
+    if (r >= K) return;
+    const int k = t.order;
+    const DsView d = t.ds;
+    char *blk = out + layout[ti].offset;
+    int32_t *hdr = (int32_t *)blk;
+    int32_t *combos = (int32_t *)(blk + 16);
+    float *scores = (float *)(blk + 16 + (long long)K * k * 4);
+    uint32_t *tables = (uint32_t *)(blk + 16 + (long long)K * k * 4 + (long long)K * 4);
+    const Cand *res = results + (long long)ti * kMaxTopK;
+    const unsigned long long sentinel_key = ~0ull;
+    if (r == 0) {
+        int nv = 0;
+        for (int x = threadIdx.x; x < K; x += kWave) nv += res[x].key != sentinel_key ? 1 : 0;
+        #pragma unroll
+        for (int off = 32; off > 0; off >>= 1) nv += __shfl_xor(nv, off);
+        if (threadIdx.x == 0) hdr[0] = nv;
+    }
+    const Cand e = res[r];
+    if (e.key == sentinel_key) return;
+    const int bits = t.key_bits;
+    const unsigned long long kmask = (1ull << bits) - 1ull;
+    int c[kMaxBinomOrder];
+    for (int u = 0; u < k; ++u) c[u] = min((int)((e.key >> (bits * (k - 1 - u))) & kmask), d.Mp - 1);
+    if (threadIdx.x < k) combos[r * k + threadIdx.x] = c[threadIdx.x];
+    if (threadIdx.x == 0) scores[r] = (float)(ldexp((double)e.num, -d.shift) / (double)d.N);
+    int cells = 1;
+    for (int u = 0; u < k; ++u) cells *= 3;
+    gv4u *gm = (gv4u *)d.masks;
+    const long long Mp = d.Mp;
+    for (int x = threadIdx.x; x < cells; x += kWave) {
+        int g[kMaxBinomOrder];
+        int y = x;
+        for (int u = k - 1; u >= 0; --u) {
+            g[u] = y % 3;
+            y /= 3;
+        }
+        for (int cl = 0; cl < 2; ++cl) {
+            unsigned cnt = 0;
+            long long off = (long long)d.wbase[cl] * 2 * Mp;
+            for (int w = 0; w < d.w4[cl]; ++w, off += 2 * Mp) {
+                const v4u vm = valid_mask(d.ncls[cl], w);
+                v4u X = vm;
+                for (int u = 0; u < k; ++u) {
+                    const v4u r0 = gm[off + c[u]];
+                    const v4u r1 = gm[off + Mp + c[u]];
+                    X &= g[u] == 0 ? r0 : (g[u] == 1 ? r1 : (vm & ~(r0 | r1)));
+                }
+                cnt += __builtin_popcount(X[0]) + __builtin_popcount(X[1]) + __builtin_popcount(X[2]) +
+                       __builtin_popcount(X[3]);
+            }
+            tables[((long long)r * 2 + cl) * cells + x] = cnt;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Packing (Section 2.1): one thread per (SNP, 128-individual group of a
+// class).  idx lists the input position of each class's individuals (cases
+// first).  Genotypes outside {0,1,2} raise *err.
+// ---------------------------------------------------------------------------
+__global__ void pack_kernel(const uint8_t *__restrict__ geno, long long ld, const int32_t *__restrict__ idx, DsView d,
+                            v4u *__restrict__ masks, int *__restrict__ err) {
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int G4 = d.w4[0] + d.w4[1];
+    if (tid >= (long long)G4 * d.Mp) return;
+    const int s = (int)(tid % d.Mp);
+    const int g4 = (int)(tid / d.Mp);
+    const int cl = g4 < d.w4[0] ? 0 : 1;
+    const int w4 = g4 - d.wbase[cl];
+    const int32_t *cidx = idx + (cl == 0 ? 0 : d.ncls[0]);
+    v4u r0 = {0u, 0u, 0u, 0u}, r1 = {0u, 0u, 0u, 0u};
+    int bad = 0;
+    if (s < d.M) {
+        const uint8_t *row = geno + (long long)s * ld;
+        #pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            unsigned b0 = 0, b1 = 0;
+            for (int b = 0; b < 32; ++b) {
+                const int pos = 32 * (4 * w4 + q) + b;
+                if (pos < d.ncls[cl]) {
+                    const unsigned si = (unsigned)cidx[pos];
+                    if (si >= (unsigned)d.N) {
+                        bad |= 8;
+                        continue;
+                    }
+                    const unsigned g = row[si];
+                    b0 |= (g == 0u ? 1u : 0u) << b;
+                    b1 |= (g == 1u ? 1u : 0u) << b;
+                    bad |= g > 2u ? 1 : 0;
+                }
+            }
+            r0[q] = b0;
+            r1[q] = b1;
+        }
+    }
+    masks[((long long)g4 * 2 + 0) * d.Mp + s] = r0;
+    masks[((long long)g4 * 2 + 1) * d.Mp + s] = r1;
+    if (bad) atomicOr(err, bad);
+}
+
+__global__ void singles_kernel(DsView d, uint32_t *__restrict__ single) {
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= d.Mp * 2) return;
+    const int s = tid >> 1, cl = tid & 1;
+    gv4u *gm = (gv4u *)d.masks;
+    unsigned n0 = 0, n1 = 0;
+    long long off = (long long)d.wbase[cl] * 2 * d.Mp;
+    for (int w = 0; w < d.w4[cl]; ++w, off += 2 * d.Mp) {
+        const v4u r0 = gm[off + s], r1 = gm[off + d.Mp + s];
+        #pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            n0 += __builtin_popcount(r0[q]);
+            n1 += __builtin_popcount(r1[q]);
+        }
+    }
+    single[(s * 2 + cl) * 2 + 0] = n0;
+    single[(s * 2 + cl) * 2 + 1] = n1;
+}
+
+// Class index map: idx[0 .. n_case) = input positions of the cases in input
+// order, idx[n_case .. N) = those of the controls.  One 1024-thread
+// workgroup; a phenotype outside {0,1} raises *err.
+__global__ void __launch_bounds__(1024) classidx_kernel(const uint8_t *__restrict__ pheno, int N, int n_case,
+                                                        int32_t *__restrict__ idx, int *__restrict__ err) {
+    __shared__ int s_scan[1024];
+    __shared__ int s_cases;
+    const int tid = threadIdx.x;
+    if (tid == 0) s_cases = 0;
+    __syncthreads();
+    for (int base = 0; base < N; base += 1024) {
+        const int s = base + tid;
+        int f = 0;
+        if (s < N) {
+            const unsigned v = pheno[s];
+            f = v == 1u ? 1 : 0;
+            if (v > 1u) atomicOr(err, 2);
+        }
+        s_scan[tid] = f;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const int v = tid >= off ? s_scan[tid - off] : 0;
+            __syncthreads();
+            s_scan[tid] += v;
+            __syncthreads();
+        }
+        const int before = s_scan[tid] - f;  // cases before s within this chunk
+        const int bc = s_cases;
+        if (s < N) {
+            if (f) {
+                if (bc + before < n_case) idx[bc + before] = s;
+                else atomicOr(err, 4);
+            } else {
+                const int pos = n_case + (base - bc) + (tid - before);
+                if (pos < N) idx[pos] = s;
+                else atomicOr(err, 4);
+            }
+        }
+        __syncthreads();
+        if (tid == 1023) s_cases = bc + s_scan[1023];
+        __syncthreads();
+    }
+}
+
+// Counters of a launch sequence: queues, candidate counts, thresholds.
+__global__ void init_counters_kernel(unsigned long long *queues, int nq, unsigned *cand_counts,
+                                     unsigned long long *thrs, int n_tasks) {
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid < nq) queues[tid] = 0;
+    if (tid < n_tasks) {
+        cand_counts[tid] = 0;
+        thrs[tid] = 0;  // bias(INT64_MIN)
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (called by the runtime).
+// ---------------------------------------------------------------------------
+typedef void (*ScanKernelFn)(const Task *, int, unsigned long long, unsigned long long *, const unsigned long long *,
+                             int);
+
+struct ScanKernelEntry {
+    int np2, np3, gk;
+    ScanKernelFn fn;
+};
+
+#define EPI_K(a, b, c) {a, b, c, scan_persistent<a, b, c>}
+static const ScanKernelEntry kScanKernels[] = {
+    EPI_K(2, 0, 0), EPI_K(4, 0, 0), EPI_K(8, 0, 0),                   // order 2 / pair sub-table
+    EPI_K(0, 1, 0), EPI_K(0, 2, 0), EPI_K(0, 4, 0), EPI_K(0, 8, 0),   // order 3
+    EPI_K(0, 0, 2), EPI_K(0, 0, 3), EPI_K(0, 0, 4), EPI_K(0, 0, 5),   // per-combination kernel
+    EPI_K(4, 2, 0), EPI_K(4, 4, 0),                                   // persistent orders 2-3
+    EPI_K(4, 2, 4), EPI_K(4, 4, 4),                                   // persistent orders 2-4
+};
+#undef EPI_K
+
+ScanKernelFn find_scan_kernel(int np2, int np3, int gk) {
+    for (const auto &e : kScanKernels)
+        if (e.np2 == np2 && e.np3 == np3 && e.gk == gk) return e.fn;
+    return nullptr;
+}
+
+hipError_t launch_scan(int np2, int np3, int gk, int grid, hipStream_t st, const Task *tasks, int n_tasks,
+                       unsigned long long total_items, unsigned long long *queue, const unsigned long long *binom,
+                       int bstride) {
+    ScanKernelFn fn = find_scan_kernel(np2, np3, gk);
+    if (!fn) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(kWave), 0, st, tasks, n_tasks, total_items, queue, binom, bstride);
+    return hipGetLastError();
+}
+
+hipError_t scan_occupancy(int np2, int np3, int gk, int *blocks_per_cu) {
+    ScanKernelFn fn = find_scan_kernel(np2, np3, gk);
+    if (!fn) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kWave, 0);
+}
+
+hipError_t launch_merge(int n_tasks, hipStream_t st, const Task *tasks, Cand *results) {
+    hipLaunchKernelGGL(merge_kernel, dim3(n_tasks), dim3(1024), 0, st, tasks, results);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(int n_tasks, int max_k, hipStream_t st, const Task *tasks, const Cand *results,
+                           const ResultLayout *layout, char *out) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(max_k, n_tasks), dim3(kWave), 0, st, tasks, results, layout, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_counters(hipStream_t st, unsigned long long *queues, int nq, unsigned *cand_counts,
+                                unsigned long long *thrs, int n_tasks) {
+    int n = nq > n_tasks ? nq : n_tasks;
+    hipLaunchKernelGGL(init_counters_kernel, dim3((n + 255) / 256), dim3(256), 0, st, queues, nq, cand_counts, thrs,
+                       n_tasks);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(hipStream_t st, const uint8_t *geno, long long ld, const int32_t *idx, const DsView &d,
+                       v4u *masks, int *err) {
+    const long long n = (long long)(d.w4[0] + d.w4[1]) * d.Mp;
+    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, geno, ld, idx, d, masks, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_classidx(hipStream_t st, const uint8_t *pheno, int N, int n_case, int32_t *idx, int *err) {
+    hipLaunchKernelGGL(classidx_kernel, dim3(1), dim3(1024), 0, st, pheno, N, n_case, idx, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_singles(hipStream_t st, const DsView &d, uint32_t *single) {
+    const int n = d.Mp * 2;
+    hipLaunchKernelGGL(singles_kernel, dim3((n + 255) / 256), dim3(256), 0, st, d, single);
+    return hipGetLastError();
+}
+
+}  // namespace epi

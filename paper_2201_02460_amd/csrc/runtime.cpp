@@ -1,0 +1,1202 @@
+// Host runtime of the epistasis scanner: contexts, a caching device
+// allocator with a byte budget, resident datasets, scan plans (plain,
+// back-to-back and persistent/graph-captured), the autotuner and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/epi.h"
+#include "epi_internal.hpp"
+#include "runtime_internal.hpp"
+
+namespace epi {
+
+hipError_t launch_scan(int np2, int np3, int gk, int grid, hipStream_t st, const Task *tasks, int n_tasks,
+                       unsigned long long total_items, unsigned long long *queue, const unsigned long long *binom,
+                       int bstride);
+hipError_t scan_occupancy(int np2, int np3, int gk, int *blocks_per_cu);
+hipError_t launch_merge(int n_tasks, hipStream_t st, const Task *tasks, Cand *results);
+hipError_t launch_finalize(int n_tasks, int max_k, hipStream_t st, const Task *tasks, const Cand *results,
+                           const ResultLayout *layout, char *out);
+hipError_t launch_init_counters(hipStream_t st, unsigned long long *queues, int nq, unsigned *cand_counts,
+                                unsigned long long *thrs, int n_tasks);
+hipError_t launch_pack(hipStream_t st, const uint8_t *geno, long long ld, const int32_t *idx, const DsView &d,
+                       v4u *masks, int *err);
+hipError_t launch_classidx(hipStream_t st, const uint8_t *pheno, int N, int n_case, int32_t *idx, int *err);
+hipError_t launch_singles(hipStream_t st, const DsView &d, uint32_t *single);
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string t_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    return code;
+}
+
+void clear_error() { t_err.clear(); }
+const char *last_error() { return t_err.c_str(); }
+
+#define HIPCHK(x)                                                                        \
+    do {                                                                                 \
+        hipError_t e_ = (x);                                                             \
+        if (e_ != hipSuccess) return fail(EPI_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// caching device allocator with a byte budget
+// ---------------------------------------------------------------------------
+static size_t round_size(size_t b) {
+    if (b == 0) b = 1;
+    if (b >= (1u << 20)) return (b + (1u << 20) - 1) & ~(size_t)((1u << 20) - 1);
+    size_t p = 256;
+    while (p < b) p <<= 1;
+    return p;
+}
+
+int DevAlloc::alloc(size_t bytes, void **out) {
+    std::lock_guard<std::mutex> g(mu);
+    const size_t sz = round_size(bytes);
+    if (used + sz > budget) return fail(EPI_ENOMEM, "device budget exceeded: %zu used + %zu requested > %zu", used, sz, budget);
+    auto it = free_.find(sz);
+    void *p = nullptr;
+    if (it != free_.end()) {
+        p = it->second;
+        free_.erase(it);
+        cached -= sz;
+    } else {
+        hipError_t e = hipMalloc(&p, sz);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            trim_locked();
+            e = hipMalloc(&p, sz);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(EPI_ENOMEM, "hipMalloc(%zu) failed: %s", sz, hipGetErrorString(e));
+            }
+        }
+    }
+    live[p] = sz;
+    used += sz;
+    peak = std::max(peak, used);
+    *out = p;
+    return EPI_OK;
+}
+
+void DevAlloc::release(void *p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = live.find(p);
+    if (it == live.end()) return;
+    used -= it->second;
+    cached += it->second;
+    free_.emplace(it->second, p);
+    live.erase(it);
+}
+
+void DevAlloc::trim_locked() {
+    for (auto &kv : free_) (void)hipFree(kv.second);
+    free_.clear();
+    cached = 0;
+}
+
+void DevAlloc::trim() {
+    std::lock_guard<std::mutex> g(mu);
+    trim_locked();
+}
+
+void DevAlloc::destroy() {
+    std::lock_guard<std::mutex> g(mu);
+    trim_locked();
+    for (auto &kv : live) (void)hipFree(kv.first);
+    live.clear();
+    used = 0;
+}
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+static uint64_t binom_u64(int64_t n, int64_t k) {
+    if (k < 0 || n < 0 || k > n) return 0;
+    if (k > n - k) k = n - k;
+    unsigned __int128 r = 1;
+    for (int64_t i = 0; i < k; ++i) {
+        r = r * (unsigned __int128)(n - i) / (unsigned __int128)(i + 1);
+        if (r > (unsigned __int128)UINT64_MAX) return UINT64_MAX;
+    }
+    return (uint64_t)r;
+}
+
+int key_bits_for(int order) { return 64 / order; }
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+Ctx *as_ctx(epi_ctx *c) { return reinterpret_cast<Ctx *>(c); }
+
+int ctx_init(Ctx *c, int device, uint64_t budget) {
+    int n = 0;
+    HIPCHK(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(EPI_EINVAL, "device %d not in [0, %d)", device, n);
+    c->device = device;
+    HIPCHK(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, device));
+    c->n_cu = prop.multiProcessorCount;
+    c->arch = prop.gcnArchName;
+    size_t fr = 0, tot = 0;
+    HIPCHK(hipMemGetInfo(&fr, &tot));
+    c->alloc.budget = budget ? budget : (uint64_t)(0.9 * (double)fr);
+    HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    // binomial table for colex unranking: rows t = 0..kMaxBinomOrder, n = 0..kBinomN-1
+    c->bstride = kBinomN;
+    std::vector<unsigned long long> h((size_t)(kMaxBinomOrder + 1) * kBinomN);
+    for (int t = 0; t <= kMaxBinomOrder; ++t)
+        for (int n2 = 0; n2 < kBinomN; ++n2) h[(size_t)t * kBinomN + n2] = binom_u64(n2, t);
+    int rc = c->alloc.alloc(h.size() * 8, (void **)&c->d_binom);
+    if (rc) return rc;
+    HIPCHK(hipMemcpy(c->d_binom, h.data(), h.size() * 8, hipMemcpyHostToDevice));
+    const char *tc = getenv("EPI_TUNE_CACHE");
+    if (tc) {
+        c->tune_path = tc;
+        load_tune_cache(c);
+    }
+    return EPI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// datasets
+// ---------------------------------------------------------------------------
+static int choose_shift(int N) {
+    const double maxv = (double)N * std::log((double)std::max(N, 2)) + 1.0;
+    int s = (int)std::floor(61.0 - std::log2(maxv));
+    return std::min(40, std::max(8, s));
+}
+
+static void build_tlog(int N, int shift, std::vector<long long> &out) {
+    out.assign((size_t)N + 1, 0);
+    const long double sc = std::ldexp((long double)1.0, shift);
+    for (int n = 2; n <= N; ++n) out[n] = llroundl((long double)n * logl((long double)n) * sc);
+}
+
+static void ds_free(Ctx *c, Dataset *d) {
+    c->alloc.release(d->masks);
+    c->alloc.release(d->single);
+    c->alloc.release(d->tlog);
+    c->alloc.release(d->idx);
+    c->alloc.release(d->err);
+    d->masks = d->single = d->tlog = d->idx = d->err = nullptr;
+}
+
+static int ds_layout(Dataset *d, int M, int N, int n_case) {
+    d->M = M;
+    d->N = N;
+    d->n_case = n_case;
+    d->n_ctrl = N - n_case;
+    d->Mp = (M + 63) / 64 * 64;
+    d->w4[0] = (d->n_case + 127) / 128;
+    d->w4[1] = (d->n_ctrl + 127) / 128;
+    d->shift = choose_shift(N);
+    return EPI_OK;
+}
+
+static void ds_view(Dataset *d) {
+    DsView &v = d->view;
+    v.masks = (const v4u *)d->masks;
+    v.single = (const uint32_t *)d->single;
+    v.tlog = (const long long *)d->tlog;
+    v.M = d->M;
+    v.Mp = d->Mp;
+    v.N = d->N;
+    v.shift = d->shift;
+    v.ncls[0] = d->n_case;
+    v.ncls[1] = d->n_ctrl;
+    v.w4[0] = d->w4[0];
+    v.w4[1] = d->w4[1];
+    v.wbase[0] = 0;
+    v.wbase[1] = d->w4[0];
+}
+
+static int ds_alloc(Ctx *c, Dataset *d) {
+    const size_t mask_bytes = (size_t)(d->w4[0] + d->w4[1]) * 2 * d->Mp * 16;
+    int rc;
+    if ((rc = c->alloc.alloc(std::max<size_t>(mask_bytes, 16), &d->masks))) return rc;
+    if ((rc = c->alloc.alloc((size_t)d->Mp * 16, &d->single))) return rc;
+    if ((rc = c->alloc.alloc(((size_t)d->N + 1) * 8, &d->tlog))) return rc;
+    if ((rc = c->alloc.alloc((size_t)d->N * 4, &d->idx))) return rc;
+    if ((rc = c->alloc.alloc(256, &d->err))) return rc;
+    d->bytes = mask_bytes + (size_t)d->Mp * 16 + ((size_t)d->N + 1) * 8 + (size_t)d->N * 4;
+    ds_view(d);
+    std::vector<long long> tl;
+    build_tlog(d->N, d->shift, tl);
+    HIPCHK(hipMemcpy(d->tlog, tl.data(), tl.size() * 8, hipMemcpyHostToDevice));
+    d->score_const = tl[d->N] - tl[d->n_case] - tl[d->n_ctrl];
+    return EPI_OK;
+}
+
+// classidx + pack + singles, asynchronous on st
+static int ds_pack(Dataset *d, const uint8_t *d_geno, int64_t ld, const uint8_t *d_pheno, hipStream_t st) {
+    HIPCHK(launch_classidx(st, d_pheno, d->N, d->n_case, (int32_t *)d->idx, (int *)d->err));
+    HIPCHK(launch_pack(st, d_geno, ld, (const int32_t *)d->idx, d->view, (v4u *)d->masks, (int *)d->err));
+    HIPCHK(launch_singles(st, d->view, (uint32_t *)d->single));
+    return EPI_OK;
+}
+
+static int load_common(Ctx *c, const uint8_t *d_geno, int64_t ld, const uint8_t *d_pheno,
+                       const std::vector<uint8_t> &h_pheno, int32_t M, int32_t N, hipStream_t st,
+                       int32_t *dataset_id) {
+    int n_case = 0;
+    for (int s = 0; s < N; ++s) {
+        if (h_pheno[s] > 1) return fail(EPI_EINVAL, "phenotype of individual %d is %d (must be 0 or 1)", s, h_pheno[s]);
+        n_case += h_pheno[s];
+    }
+    if (n_case == 0 || n_case == N) return fail(EPI_EINVAL, "need at least one case and one control (cases = %d of %d)", n_case, N);
+    auto d = std::make_unique<Dataset>();
+    ds_layout(d.get(), M, N, n_case);
+    int rc = ds_alloc(c, d.get());
+    if (rc) {
+        ds_free(c, d.get());
+        return rc;
+    }
+    HIPCHK(hipMemsetAsync(d->err, 0, 4, st));
+    rc = ds_pack(d.get(), d_geno, ld, d_pheno, st);
+    int herr = 0;
+    if (!rc) {
+        hipError_t e = hipMemcpyAsync(&herr, d->err, 4, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = fail(EPI_EDEVICE, "dataset pack: %s", hipGetErrorString(e));
+    }
+    if (!rc && (herr & 1)) rc = fail(EPI_EINVAL, "a genotype is outside {0,1,2}");
+    if (!rc && herr) rc = fail(EPI_EINVAL, "phenotype check failed on the device (code %d)", herr);
+    if (rc) {
+        ds_free(c, d.get());
+        return rc;
+    }
+    std::lock_guard<std::mutex> g(c->mu);
+    d->id = c->next_id++;
+    *dataset_id = d->id;
+    c->datasets[d->id] = std::move(d);
+    return EPI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// plans
+// ---------------------------------------------------------------------------
+static int tuned_np(Ctx *c, int order, const Dataset *d) {
+    const int words = (d->w4[0] + d->w4[1]) * 4;
+    int bucket = 0;
+    while ((1 << bucket) < words) ++bucket;
+    std::lock_guard<std::mutex> g(c->tune_mu);
+    auto it = c->tuned.find(TuneKey{order, bucket});
+    if (it != c->tuned.end()) return it->second;
+    return order == 2 ? 4 : (order == 3 ? 4 : kGenRanksHost);
+}
+
+static unsigned long long build_f2_offsets(int M, int np, std::vector<unsigned long long> &off) {
+    const int nib = std::max(1, (M - 1 + np - 1) / np);
+    off.assign((size_t)nib + 1, 0);
+    for (int ib = 0; ib < nib; ++ib) {
+        const int i0 = ib * np;
+        const long long nm = std::max(0, M - 1 - i0);
+        off[ib + 1] = off[ib] + (unsigned long long)((nm + 63) / 64);
+    }
+    return off[nib];
+}
+
+static unsigned long long build_f3_offsets(int M, int np, std::vector<unsigned long long> &off) {
+    // off[j] = items of all j' < j; j runs over 1 .. M-2
+    off.assign((size_t)M + 1, 0);
+    for (int j = 0; j < M; ++j) {
+        unsigned long long cnt = 0;
+        if (j >= 1 && j <= M - 2) {
+            const unsigned long long ni = (unsigned long long)((j + np - 1) / np);
+            const unsigned long long nm = (unsigned long long)((M - 1 - j + 63) / 64);
+            cnt = ni * nm;
+        }
+        off[j + 1] = off[j] + cnt;
+    }
+    return off[M];
+}
+
+void plan_free(Ctx *c, Plan *p) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+    for (auto &s : p->scans) {
+        c->alloc.release(s.item_off);
+        c->alloc.release(s.emit_off);
+        c->alloc.release(s.pairs);
+        c->alloc.release(s.cand);
+    }
+    c->alloc.release(p->d_tasks);
+    c->alloc.release(p->d_counters);
+    c->alloc.release(p->d_results);
+    c->alloc.release(p->d_layout);
+    c->alloc.release(p->d_out);
+    if (p->h_out) (void)hipHostFree(p->h_out);
+    p->h_out = nullptr;
+    for (auto &e : p->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto &e : p->ev) e = nullptr;
+}
+
+static int check_desc(Ctx *c, const epi_scan_desc &d, Dataset **out) {
+    auto it = c->datasets.find(d.dataset_id);
+    if (it == c->datasets.end()) return fail(EPI_ENOTFOUND, "unknown dataset %d", d.dataset_id);
+    Dataset *ds = it->second.get();
+    if (d.reserved != 0) return fail(EPI_EINVAL, "reserved field must be 0");
+    if (d.order < EPI_MIN_ORDER) return fail(EPI_EINVAL, "order %d < %d", d.order, EPI_MIN_ORDER);
+    if (d.order > ds->M) return fail(EPI_EINVAL, "order %d > M = %d", d.order, ds->M);
+    if (d.order > EPI_MAX_ORDER) return fail(EPI_EUNSUPPORTED, "order %d > %d", d.order, EPI_MAX_ORDER);
+    if (d.top_k < 1) return fail(EPI_EINVAL, "top_k %d < 1", d.top_k);
+    if (d.top_k > EPI_MAX_TOP_K) return fail(EPI_EUNSUPPORTED, "top_k %d > %d", d.top_k, EPI_MAX_TOP_K);
+    const int bits = key_bits_for(d.order);
+    if (bits < 32 && ds->M > (1 << bits))
+        return fail(EPI_EUNSUPPORTED, "M = %d exceeds 2^%d for order %d", ds->M, bits, d.order);
+    if ((long long)ds->M >= kBinomN && d.order >= 4)
+        return fail(EPI_EUNSUPPORTED, "M = %d too large for the order-%d kernel", ds->M, d.order);
+    *out = ds;
+    return EPI_OK;
+}
+
+// Kernel instantiation for a group of tasks in one persistent launch.
+static void pick_group_kernel(const std::vector<int> &orders, int np3_hint, int *np2, int *np3, int *gk) {
+    bool has2 = false, has3 = false;
+    int gen = 0;
+    for (int o : orders) {
+        if (o == 2) has2 = true;
+        else if (o == 3) has3 = true;
+        else gen = o;
+    }
+    if (gen == 5) {
+        *np2 = 0;
+        *np3 = 0;
+        *gk = 5;
+        return;
+    }
+    if (!has3 && gen == 0) {
+        *np2 = 4;
+        *np3 = 0;
+        *gk = 0;
+        return;
+    }
+    if (!has2 && !has3) {
+        *np2 = 0;
+        *np3 = 0;
+        *gk = gen;
+        return;
+    }
+    *np2 = 4;
+    *np3 = np3_hint <= 2 ? 2 : 4;
+    *gk = gen == 4 ? 4 : 0;
+}
+
+static int grid_for(Ctx *c, int np2, int np3, int gk, unsigned long long items) {
+    int per_cu = 0;
+    if (scan_occupancy(np2, np3, gk, &per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
+    long long g = (long long)per_cu * c->n_cu;
+    if ((unsigned long long)g > items) g = (long long)std::max<unsigned long long>(items, 1);
+    return (int)g;
+}
+
+int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool graph, Plan **out,
+               int force_np) {
+    if (n < 1) return fail(EPI_EINVAL, "empty scan list");
+    std::vector<Dataset *> dss(n);
+    for (int i = 0; i < n; ++i) {
+        int rc = check_desc(c, descs[i], &dss[i]);
+        if (rc) return rc;
+    }
+    auto p = std::make_unique<Plan>();
+    p->persistent = persistent;
+    p->use_graph = graph;
+    p->scans.resize(n);
+    int rc = EPI_OK;
+    auto cleanup = [&](int code) {
+        plan_free(c, p.get());
+        return code;
+    };
+    // per-scan variant, items and offsets
+    for (int i = 0; i < n; ++i) {
+        PlanScan &s = p->scans[i];
+        s.desc = descs[i];
+        s.ds = dss[i];
+        s.n_combos = binom_u64(s.ds->M, s.desc.order);
+        const int o = s.desc.order;
+        std::vector<unsigned long long> off;
+        if (o == 2) {
+            s.variant = kF2;
+            s.np = persistent ? 4 : (force_np > 0 ? force_np : tuned_np(c, 2, s.ds));
+            s.n_items = build_f2_offsets(s.ds->M, s.np, off);
+            s.n_blocks = (int)off.size() - 1;
+        } else if (o == 3) {
+            s.variant = kF3;
+            int np = force_np > 0 ? force_np : tuned_np(c, 3, s.ds);
+            if (persistent) np = np <= 2 ? 2 : 4;
+            s.np = np;
+            s.n_items = build_f3_offsets(s.ds->M, s.np, off);
+            s.n_blocks = s.ds->M;  // binary search over j in [1, M-1]
+        } else {
+            s.variant = kGeneric;
+            s.np = kGenRanksHost;
+            s.n_items = (s.n_combos + 64ull * kGenRanksHost - 1) / (64ull * kGenRanksHost);
+        }
+        if (!off.empty()) {
+            if ((rc = c->alloc.alloc(off.size() * 8, &s.item_off))) return cleanup(rc);
+            HIPCHK(hipMemcpy(s.item_off, off.data(), off.size() * 8, hipMemcpyHostToDevice));
+        }
+        if (o == 3) {
+            // pair sub-table pass (order-2 reduced cells of every pair)
+            std::vector<unsigned long long> eoff;
+            s.emit_np = 4;
+            s.emit_items = build_f2_offsets(s.ds->M, s.emit_np, eoff);
+            s.emit_blocks = (int)eoff.size() - 1;
+            if ((rc = c->alloc.alloc(eoff.size() * 8, &s.emit_off))) return cleanup(rc);
+            HIPCHK(hipMemcpy(s.emit_off, eoff.data(), eoff.size() * 8, hipMemcpyHostToDevice));
+            const size_t pb = (size_t)binom_u64(s.ds->M, 2) * 32;
+            if ((rc = c->alloc.alloc(std::max<size_t>(pb, 32), &s.pairs))) return cleanup(rc);
+        }
+    }
+    // launch groups
+    if (persistent) {
+        // emit group: all order-3 pair passes; main groups by kernel instantiation
+        std::vector<int> orders_a, orders_b;
+        int np3_hint = 4;
+        for (auto &s : p->scans) {
+            if (s.desc.order == 5) orders_b.push_back(5);
+            else orders_a.push_back(s.desc.order);
+            if (s.desc.order == 3) np3_hint = s.np;
+        }
+        if (!orders_a.empty()) {
+            LaunchGroup g;
+            pick_group_kernel(orders_a, np3_hint, &g.np2, &g.np3, &g.gk);
+            for (int i = 0; i < n; ++i)
+                if (p->scans[i].desc.order != 5) g.scans.push_back(i);
+            p->groups.push_back(g);
+        }
+        if (!orders_b.empty()) {
+            LaunchGroup g;
+            g.np2 = 0;
+            g.np3 = 0;
+            g.gk = 5;
+            for (int i = 0; i < n; ++i)
+                if (p->scans[i].desc.order == 5) g.scans.push_back(i);
+            p->groups.push_back(g);
+        }
+        for (auto &g : p->groups)
+            for (int i : g.scans)
+                if (p->scans[i].desc.order == 3) {
+                    p->scans[i].np = g.np3;
+                }
+        // rebuild order-3 offsets for the group's prefix block
+        for (auto &s : p->scans) {
+            if (s.desc.order != 3) continue;
+            std::vector<unsigned long long> off;
+            s.n_items = build_f3_offsets(s.ds->M, s.np, off);
+            HIPCHK(hipMemcpy(s.item_off, off.data(), off.size() * 8, hipMemcpyHostToDevice));
+        }
+    } else {
+        for (int i = 0; i < n; ++i) {
+            LaunchGroup g;
+            const PlanScan &s = p->scans[i];
+            if (s.desc.order == 2) {
+                g.np2 = s.np;
+                g.np3 = 0;
+                g.gk = 0;
+            } else if (s.desc.order == 3) {
+                g.np2 = 0;
+                g.np3 = s.np;
+                g.gk = 0;
+            } else {
+                g.np2 = 0;
+                g.np3 = 0;
+                g.gk = s.desc.order;
+            }
+            g.scans.push_back(i);
+            p->groups.push_back(g);
+        }
+    }
+    // tasks: [main tasks in scan order][emit tasks]
+    const int nt = n;
+    int n_emit = 0;
+    for (auto &s : p->scans) n_emit += s.desc.order == 3 ? 1 : 0;
+    p->n_emit = n_emit;
+    for (auto &g : p->groups) {
+        unsigned long long tot = 0;
+        for (int i : g.scans) tot += p->scans[i].n_items;
+        g.total_items = tot;
+        g.grid = grid_for(c, g.np2, g.np3, g.gk, tot);
+    }
+    // emit launch shape (kernel <4,0,0>)
+    unsigned long long emit_total = 0;
+    for (auto &s : p->scans) emit_total += s.desc.order == 3 ? s.emit_items : 0;
+    p->emit_grid = grid_for(c, 4, 0, 0, std::max<unsigned long long>(emit_total, 1));
+    // candidate buffers and result layout
+    long long out_bytes = 0;
+    for (int i = 0; i < n; ++i) {
+        PlanScan &s = p->scans[i];
+        int grid = 0;
+        for (auto &g : p->groups)
+            for (int j : g.scans)
+                if (j == i) grid = g.grid;
+        s.cand_cap = (unsigned)std::min<unsigned long long>((unsigned long long)grid * s.desc.top_k + 64, 0xffffffffull);
+        if ((rc = c->alloc.alloc((size_t)s.cand_cap * sizeof(Cand), &s.cand))) return cleanup(rc);
+        s.lay.offset = out_bytes;
+        s.lay.top_k = s.desc.top_k;
+        s.lay.order = s.desc.order;
+        out_bytes += result_block_bytes(s.desc.top_k, s.desc.order);
+    }
+    p->out_bytes = out_bytes;
+    const int nq = (int)p->groups.size() + 1;
+    p->n_queues = nq;
+    const size_t cnt_bytes = (size_t)nq * 8 + (size_t)nt * 8 + (size_t)nt * 4;
+    if ((rc = c->alloc.alloc(cnt_bytes, &p->d_counters))) return cleanup(rc);
+    p->d_queues = (unsigned long long *)p->d_counters;
+    p->d_thr = p->d_queues + nq;
+    p->d_cand_count = (unsigned *)(p->d_thr + nt);
+    if ((rc = c->alloc.alloc((size_t)nt * kMaxTopK * sizeof(Cand), &p->d_results))) return cleanup(rc);
+    if ((rc = c->alloc.alloc((size_t)nt * sizeof(ResultLayout), &p->d_layout))) return cleanup(rc);
+    if ((rc = c->alloc.alloc((size_t)std::max<long long>(out_bytes, 256), &p->d_out))) return cleanup(rc);
+    HIPCHK(hipHostMalloc(&p->h_out, (size_t)std::max<long long>(out_bytes, 256), hipHostMallocDefault));
+    std::vector<ResultLayout> lay(nt);
+    for (int i = 0; i < nt; ++i) lay[i] = p->scans[i].lay;
+    HIPCHK(hipMemcpy(p->d_layout, lay.data(), nt * sizeof(ResultLayout), hipMemcpyHostToDevice));
+    // task array: [main tasks in scan order][emit tasks][per-group launch copies (persistent)]
+    std::vector<Task> tasks(nt + n_emit);
+    for (int i = 0; i < nt; ++i) {
+        PlanScan &s = p->scans[i];
+        Task &t = tasks[i];
+        memset(&t, 0, sizeof t);
+        t.ds = s.ds->view;
+        t.pairs = (uint32_t *)s.pairs;
+        t.item_off = (const unsigned long long *)s.item_off;
+        t.n_items = s.n_items;
+        t.item_base = 0;
+        t.n_combos = s.n_combos;
+        t.score_const = s.ds->score_const;
+        t.cand = (Cand *)s.cand;
+        t.cand_count = p->d_cand_count + i;
+        t.thr = p->d_thr + i;
+        t.cand_cap = s.cand_cap;
+        t.variant = s.variant;
+        t.order = s.desc.order;
+        t.top_k = s.desc.top_k;
+        t.np = s.np;
+        t.n_blocks = s.variant == kF3 ? s.ds->M : s.n_blocks;
+        t.key_bits = key_bits_for(s.desc.order);
+    }
+    {
+        int e = nt;
+        unsigned long long base = 0;
+        for (int i = 0; i < nt; ++i) {
+            PlanScan &s = p->scans[i];
+            if (s.desc.order != 3) continue;
+            s.emit_task = e;
+            Task &t = tasks[e++];
+            t = tasks[i];
+            t.variant = kF2Emit;
+            t.item_off = (const unsigned long long *)s.emit_off;
+            t.n_items = s.emit_items;
+            t.item_base = persistent ? base : 0;
+            base += s.emit_items;
+            t.np = s.emit_np;
+            t.n_blocks = s.emit_blocks;
+            t.order = 2;
+        }
+    }
+    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+        LaunchGroup &g = p->groups[gi];
+        if (!persistent) {
+            g.task_off = g.scans.front();
+            continue;
+        }
+        g.task_off = (int)tasks.size();
+        unsigned long long base = 0;
+        for (int i : g.scans) {
+            Task t = tasks[i];
+            t.item_base = base;
+            base += t.n_items;
+            tasks.push_back(t);
+        }
+    }
+    if ((rc = c->alloc.alloc(tasks.size() * sizeof(Task), &p->d_tasks))) return cleanup(rc);
+    HIPCHK(hipMemcpy(p->d_tasks, tasks.data(), tasks.size() * sizeof(Task), hipMemcpyHostToDevice));
+    p->emit_total = emit_total;
+    for (auto &ev : p->ev) HIPCHK(hipEventCreate(&ev));
+    *out = p.release();
+    return EPI_OK;
+}
+
+// Enqueue the whole launch sequence of a plan on st.  With timing, events
+// bracket the sub-table pass, the main kernel and the merge/finalize of a
+// single-scan plan.
+static int plan_enqueue(Ctx *c, Plan *p, hipStream_t st, bool timing, unsigned long long item_cap) {
+    const Task *tasks = (const Task *)p->d_tasks;
+    const int nt = (int)p->scans.size();
+    HIPCHK(launch_init_counters(st, p->d_queues, p->n_queues, p->d_cand_count, p->d_thr, nt));
+    int q = 0;
+    const bool single = nt == 1 && !p->persistent;
+    if (timing && single) HIPCHK(hipEventRecord(p->ev[1], st));
+    if (p->persistent) {
+        if (p->n_emit > 0) {
+            HIPCHK(launch_scan(4, 0, 0, p->emit_grid, st, tasks + nt, p->n_emit, p->emit_total, p->d_queues + q,
+                               c->d_binom, c->bstride));
+        }
+        ++q;
+        if (timing && single) HIPCHK(hipEventRecord(p->ev[2], st));
+        for (auto &g : p->groups) {
+            HIPCHK(launch_scan(g.np2, g.np3, g.gk, g.grid, st, tasks + g.task_off, (int)g.scans.size(),
+                               std::min(g.total_items, item_cap), p->d_queues + q, c->d_binom, c->bstride));
+            ++q;
+        }
+        if (timing && single) HIPCHK(hipEventRecord(p->ev[3], st));
+        HIPCHK(launch_merge(nt, st, tasks, (Cand *)p->d_results));
+        int maxk = 1;
+        for (auto &s : p->scans) maxk = std::max(maxk, s.desc.top_k);
+        HIPCHK(launch_finalize(nt, maxk, st, tasks, (const Cand *)p->d_results, (const ResultLayout *)p->d_layout,
+                               (char *)p->d_out));
+    } else {
+        // back-to-back: per scan, [pair pass] main merge finalize
+        for (int i = 0; i < nt; ++i) {
+            PlanScan &s = p->scans[i];
+            LaunchGroup &g = p->groups[i];
+            if (s.desc.order == 3) {
+                const int eg = grid_for(c, 4, 0, 0, s.emit_items);
+                HIPCHK(launch_scan(4, 0, 0, eg, st, tasks + s.emit_task, 1, s.emit_items, p->d_queues + 0,
+                                   c->d_binom, c->bstride));
+                HIPCHK(launch_init_counters(st, p->d_queues, 1, nullptr, nullptr, 0));
+            }
+            if (timing && single) HIPCHK(hipEventRecord(p->ev[2], st));
+            HIPCHK(launch_scan(g.np2, g.np3, g.gk, g.grid, st, tasks + i, 1, std::min(s.n_items, item_cap),
+                               p->d_queues + 1, c->d_binom, c->bstride));
+            HIPCHK(launch_init_counters(st, p->d_queues + 1, 1, nullptr, nullptr, 0));
+            if (timing && single) HIPCHK(hipEventRecord(p->ev[3], st));
+            HIPCHK(launch_merge(1, st, tasks + i, (Cand *)p->d_results + (size_t)i * kMaxTopK));
+            HIPCHK(launch_finalize(1, s.desc.top_k, st, tasks + i, (const Cand *)p->d_results + (size_t)i * kMaxTopK,
+                                   (const ResultLayout *)p->d_layout + i, (char *)p->d_out));
+        }
+    }
+    HIPCHK(hipMemcpyAsync(p->h_out, p->d_out, (size_t)std::max<long long>(p->out_bytes, 256), hipMemcpyDeviceToHost, st));
+    return EPI_OK;
+}
+
+int plan_run(Ctx *c, Plan *p, hipStream_t st, unsigned long long item_cap) {
+    if (!st) st = c->stream;
+    p->stream = st;
+    p->timed = false;
+    if (p->use_graph) {
+        if (!p->exec) {
+            hipStream_t cap;
+            HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+            int rc = plan_enqueue(c, p, cap, false, item_cap);
+            hipGraph_t gr = nullptr;
+            hipError_t e = hipStreamEndCapture(cap, &gr);
+            (void)hipStreamDestroy(cap);
+            if (rc) return rc;
+            if (e != hipSuccess) return fail(EPI_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+            p->graph = gr;
+            HIPCHK(hipGraphInstantiate(&p->exec, gr, nullptr, nullptr, 0));
+        }
+        HIPCHK(hipEventRecord(p->ev[0], st));
+        HIPCHK(hipGraphLaunch(p->exec, st));
+        HIPCHK(hipEventRecord(p->ev[4], st));
+    } else {
+        HIPCHK(hipEventRecord(p->ev[0], st));
+        int rc = plan_enqueue(c, p, st, true, item_cap);
+        if (rc) return rc;
+        HIPCHK(hipEventRecord(p->ev[4], st));
+        p->timed = p->scans.size() == 1;
+    }
+    p->ran = true;
+    return EPI_OK;
+}
+
+int plan_wait(Plan *p) {
+    if (!p->ran) return fail(EPI_ENOTREADY, "plan has not run");
+    HIPCHK(hipEventSynchronize(p->ev[4]));
+    return EPI_OK;
+}
+
+int plan_results(Plan *p, int index, int capacity, int32_t *combos, float *scores, uint32_t *tables,
+                 int32_t *n_written) {
+    if (index < 0 || index >= (int)p->scans.size()) return fail(EPI_EINVAL, "scan index %d out of range", index);
+    if (!p->ran) return fail(EPI_ENOTREADY, "scan has not run");
+    hipError_t q = hipEventQuery(p->ev[4]);
+    if (q == hipErrorNotReady) return fail(EPI_ENOTREADY, "scan not finished");
+    if (q != hipSuccess) return fail(EPI_EDEVICE, "scan failed: %s", hipGetErrorString(q));
+    if (capacity < 0 || !n_written) return fail(EPI_EINVAL, "bad capacity / n_written");
+    const PlanScan &s = p->scans[index];
+    const int K = s.desc.top_k, k = s.desc.order, cells = pow3i(k);
+    const char *blk = (const char *)p->h_out + s.lay.offset;
+    const int32_t nv = *(const int32_t *)blk;
+    const int32_t *hc = (const int32_t *)(blk + 16);
+    const float *hs = (const float *)(blk + 16 + (size_t)K * k * 4);
+    const uint32_t *ht = (const uint32_t *)(blk + 16 + (size_t)K * k * 4 + (size_t)K * 4);
+    const int n = std::min(capacity, nv);
+    if (n > 0 && (!combos || !scores)) return fail(EPI_EINVAL, "null combos/scores buffer");
+    for (int r = 0; r < n; ++r) {
+        memcpy(combos + (size_t)r * k, hc + (size_t)r * k, (size_t)k * 4);
+        scores[r] = hs[r];
+        if (tables) memcpy(tables + (size_t)r * 2 * cells, ht + (size_t)r * 2 * cells, (size_t)2 * cells * 4);
+    }
+    *n_written = n;
+    return EPI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+void load_tune_cache(Ctx *c) {
+    std::ifstream f(c->tune_path);
+    std::string arch;
+    int order, bucket, np;
+    while (f >> arch >> order >> bucket >> np)
+        if (arch == c->arch) c->tuned[TuneKey{order, bucket}] = np;
+}
+
+static void save_tune_cache(Ctx *c) {
+    if (c->tune_path.empty()) return;
+    std::ofstream f(c->tune_path, std::ios::trunc);
+    for (auto &kv : c->tuned) f << c->arch << " " << kv.first.order << " " << kv.first.bucket << " " << kv.second << "\n";
+}
+
+int autotune(Ctx *c, int ds_id, int order, int *choice) {
+    Dataset *ds;
+    epi_scan_desc d{ds_id, order, 16, 0};
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        int rc = check_desc(c, d, &ds);
+        if (rc) return rc;
+    }
+    std::vector<int> cands;
+    if (order == 2) cands = {2, 4, 8};
+    else if (order == 3) cands = {1, 2, 4, 8};
+    else {
+        *choice = kGenRanksHost;
+        return EPI_OK;
+    }
+    double best_t = 1e30;
+    int best = cands[0];
+    for (int np : cands) {
+        Plan *p = nullptr;
+        int rc = plan_build(c, &d, 1, false, false, &p, np);
+        if (rc) return rc;
+        // a bounded slice: about 32 items per wave slot
+        const unsigned long long cap = std::min<unsigned long long>(p->scans[0].n_items, (unsigned long long)p->groups[0].grid * 32);
+        double t = 1e30;
+        for (int rep = 0; rep < 4 && !rc; ++rep) {
+            rc = plan_run(c, p, c->stream, cap);
+            if (!rc) rc = plan_wait(p);
+            float ms = 0;
+            if (!rc && rep > 0 && hipEventElapsedTime(&ms, p->ev[2], p->ev[3]) == hipSuccess) {
+                // per combination: items cover np*64 combinations each (order 3) or 64*np (order 2)
+                const double per = ms / (double)cap / (double)np;
+                t = std::min(t, per);
+            }
+        }
+        plan_free(c, p);
+        delete p;
+        if (rc) return rc;
+        if (t < best_t) {
+            best_t = t;
+            best = np;
+        }
+    }
+    const int words = (ds->w4[0] + ds->w4[1]) * 4;
+    int bucket = 0;
+    while ((1 << bucket) < words) ++bucket;
+    {
+        std::lock_guard<std::mutex> g(c->tune_mu);
+        c->tuned[TuneKey{order, bucket}] = best;
+        save_tune_cache(c);
+    }
+    *choice = best;
+    return EPI_OK;
+}
+
+}  // namespace epi
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+using namespace epi;
+
+#define CTX_OR_FAIL(ctx)                                                  \
+    if (!(ctx)) return fail(EPI_EINVAL, "null context");                  \
+    Ctx *C = as_ctx(ctx);                                                 \
+    if (hipSetDevice(C->device) != hipSuccess) return fail(EPI_EDEVICE, "hipSetDevice failed");
+
+extern "C" {
+
+const char *epi_last_error(void) { return last_error(); }
+
+const char *epi_version(void) { return "epi-mi355x 0.1 (gfx950)"; }
+
+int epi_create(int32_t device, uint64_t hbm_budget_bytes, epi_ctx **out) {
+    clear_error();
+    if (!out) return fail(EPI_EINVAL, "null out");
+    auto c = std::make_unique<Ctx>();
+    int rc = ctx_init(c.get(), device, hbm_budget_bytes);
+    if (rc) {
+        c->alloc.destroy();
+        return rc;
+    }
+    *out = reinterpret_cast<epi_ctx *>(c.release());
+    return EPI_OK;
+}
+
+int epi_destroy(epi_ctx *ctx) {
+    clear_error();
+    if (!ctx) return EPI_OK;
+    Ctx *C = as_ctx(ctx);
+    (void)hipSetDevice(C->device);
+    server_shutdown_all(C);
+    (void)hipDeviceSynchronize();
+    for (auto &kv : C->plans) plan_free(C, kv.second.get());
+    C->plans.clear();
+    for (auto &kv : C->datasets) ds_free(C, kv.second.get());
+    C->datasets.clear();
+    C->alloc.destroy();
+    if (C->stream) (void)hipStreamDestroy(C->stream);
+    delete C;
+    return EPI_OK;
+}
+
+int epi_memory(epi_ctx *ctx, uint64_t *used_bytes, uint64_t *budget_bytes) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    if (used_bytes) *used_bytes = C->alloc.used;
+    if (budget_bytes) *budget_bytes = C->alloc.budget;
+    return EPI_OK;
+}
+
+int epi_load_genotypes(epi_ctx *ctx, const uint8_t *geno, int64_t ld, const uint8_t *pheno, int32_t M, int32_t N,
+                       int32_t *dataset_id) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    if (!geno || !pheno || !dataset_id) return fail(EPI_EINVAL, "null argument");
+    if (M < 1 || N < 2 || ld < N) return fail(EPI_EINVAL, "bad shape M=%d N=%d ld=%lld", M, N, (long long)ld);
+    // genotype check on the host (the device kernel checks too)
+    for (int32_t s = 0; s < M; ++s) {
+        const uint8_t *row = geno + (size_t)s * ld;
+        for (int32_t i = 0; i < N; ++i)
+            if (row[i] > 2) return fail(EPI_EINVAL, "genotype of SNP %d individual %d is %d", s, i, row[i]);
+    }
+    std::vector<uint8_t> hp(pheno, pheno + N);
+    void *dg = nullptr, *dp = nullptr;
+    int rc = C->alloc.alloc((size_t)M * N, &dg);
+    if (!rc) rc = C->alloc.alloc((size_t)N, &dp);
+    if (!rc) {
+        hipError_t e = hipMemcpy2DAsync(dg, N, geno, ld, N, M, hipMemcpyHostToDevice, C->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(dp, pheno, N, hipMemcpyHostToDevice, C->stream);
+        if (e != hipSuccess) rc = fail(EPI_EDEVICE, "upload: %s", hipGetErrorString(e));
+    }
+    if (!rc) rc = load_common(C, (const uint8_t *)dg, N, (const uint8_t *)dp, hp, M, N, C->stream, dataset_id);
+    (void)hipStreamSynchronize(C->stream);
+    C->alloc.release(dg);
+    C->alloc.release(dp);
+    return rc;
+}
+
+int epi_load_genotypes_device(epi_ctx *ctx, const uint8_t *d_geno, int64_t ld, const uint8_t *d_pheno, int32_t M,
+                              int32_t N, void *stream, int32_t *dataset_id) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    if (!d_geno || !d_pheno || !dataset_id) return fail(EPI_EINVAL, "null argument");
+    if (M < 1 || N < 2 || ld < N) return fail(EPI_EINVAL, "bad shape M=%d N=%d ld=%lld", M, N, (long long)ld);
+    hipStream_t st = stream ? (hipStream_t)stream : C->stream;
+    std::vector<uint8_t> hp(N);
+    HIPCHK(hipMemcpyAsync(hp.data(), d_pheno, N, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return load_common(C, d_geno, ld, d_pheno, hp, M, N, st, dataset_id);
+}
+
+int epi_repack_device(epi_ctx *ctx, int32_t dataset_id, const uint8_t *d_geno, int64_t ld, const uint8_t *d_pheno,
+                      void *stream) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    auto it = C->datasets.find(dataset_id);
+    if (it == C->datasets.end()) return fail(EPI_ENOTFOUND, "unknown dataset %d", dataset_id);
+    Dataset *d = it->second.get();
+    if (!d_geno || !d_pheno || ld < d->N) return fail(EPI_EINVAL, "bad repack arguments");
+    hipStream_t st = stream ? (hipStream_t)stream : C->stream;
+    return ds_pack(d, d_geno, ld, d_pheno, st);
+}
+
+int epi_unload(epi_ctx *ctx, int32_t dataset_id) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    std::unique_ptr<Dataset> d;
+    {
+        std::lock_guard<std::mutex> g(C->mu);
+        auto it = C->datasets.find(dataset_id);
+        if (it == C->datasets.end()) return fail(EPI_ENOTFOUND, "unknown dataset %d", dataset_id);
+        d = std::move(it->second);
+        C->datasets.erase(it);
+    }
+    (void)hipDeviceSynchronize();
+    ds_free(C, d.get());
+    return EPI_OK;
+}
+
+int epi_dataset_info(epi_ctx *ctx, int32_t dataset_id, int32_t *M, int32_t *N, int32_t *n_cases,
+                     uint64_t *device_bytes) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    auto it = C->datasets.find(dataset_id);
+    if (it == C->datasets.end()) return fail(EPI_ENOTFOUND, "unknown dataset %d", dataset_id);
+    const Dataset *d = it->second.get();
+    if (M) *M = d->M;
+    if (N) *N = d->N;
+    if (n_cases) *n_cases = d->n_case;
+    if (device_bytes) *device_bytes = d->bytes;
+    return EPI_OK;
+}
+
+static int register_plan(Ctx *C, Plan *p, int32_t *scan_ids) {
+    std::lock_guard<std::mutex> g(C->mu);
+    p->id = C->next_id++;
+    for (size_t i = 0; i < p->scans.size(); ++i) {
+        const int sid = C->next_id++;
+        C->scan_index[sid] = ScanRef{p->id, (int)i};
+        p->scans[i].scan_id = sid;
+        if (scan_ids) scan_ids[i] = sid;
+        p->live_scans++;
+    }
+    C->plans[p->id] = std::unique_ptr<Plan>(p);
+    return p->id;
+}
+
+static Plan *plan_of_scan(Ctx *C, int32_t scan_id, int *index) {
+    auto it = C->scan_index.find(scan_id);
+    if (it == C->scan_index.end()) return nullptr;
+    auto pit = C->plans.find(it->second.plan);
+    if (pit == C->plans.end()) return nullptr;
+    *index = it->second.index;
+    return pit->second.get();
+}
+
+int epi_scan(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t top_k, void *stream, int32_t *scan_id) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    if (!scan_id) return fail(EPI_EINVAL, "null scan_id");
+    epi_scan_desc d{dataset_id, order, top_k, 0};
+    Plan *p = nullptr;
+    int rc = plan_build(C, &d, 1, false, false, &p, 0);
+    if (rc) return rc;
+    register_plan(C, p, scan_id);
+    p->transient = true;
+    return plan_run(C, p, (hipStream_t)stream, ~0ull);
+}
+
+int epi_scan_batch(epi_ctx *ctx, const epi_scan_desc *descs, int32_t n, void *stream, int32_t *scan_ids) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    if (!descs || !scan_ids || n < 1) return fail(EPI_EINVAL, "bad batch arguments");
+    Plan *p = nullptr;
+    int rc = plan_build(C, descs, n, true, true, &p, 0);
+    if (rc) return rc;
+    register_plan(C, p, scan_ids);
+    p->transient = true;
+    return plan_run(C, p, (hipStream_t)stream, ~0ull);
+}
+
+int epi_query(epi_ctx *ctx, int32_t scan_id, int32_t *done) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    int idx;
+    Plan *p = plan_of_scan(C, scan_id, &idx);
+    if (!p) return fail(EPI_ENOTFOUND, "unknown scan %d", scan_id);
+    if (!done) return fail(EPI_EINVAL, "null done");
+    if (!p->ran) {
+        *done = 0;
+        return EPI_OK;
+    }
+    hipError_t q = hipEventQuery(p->ev[4]);
+    if (q != hipSuccess && q != hipErrorNotReady) return fail(EPI_EDEVICE, "%s", hipGetErrorString(q));
+    *done = q == hipSuccess ? 1 : 0;
+    return EPI_OK;
+}
+
+int epi_wait(epi_ctx *ctx, int32_t scan_id) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    int idx;
+    Plan *p = plan_of_scan(C, scan_id, &idx);
+    if (!p) return fail(EPI_ENOTFOUND, "unknown scan %d", scan_id);
+    return plan_wait(p);
+}
+
+int epi_results(epi_ctx *ctx, int32_t scan_id, int32_t capacity, int32_t *combos, float *scores, uint32_t *tables,
+                int32_t *n_written) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    int idx;
+    Plan *p = plan_of_scan(C, scan_id, &idx);
+    if (!p) return fail(EPI_ENOTFOUND, "unknown scan %d", scan_id);
+    return plan_results(p, idx, capacity, combos, scores, tables, n_written);
+}
+
+int epi_scan_timing(epi_ctx *ctx, int32_t scan_id, float ms[4]) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    int idx;
+    Plan *p = plan_of_scan(C, scan_id, &idx);
+    if (!p) return fail(EPI_ENOTFOUND, "unknown scan %d", scan_id);
+    if (!ms) return fail(EPI_EINVAL, "null ms");
+    int rc = plan_wait(p);
+    if (rc) return rc;
+    for (int i = 0; i < 4; ++i) ms[i] = -1.0f;
+    HIPCHK(hipEventElapsedTime(&ms[0], p->ev[0], p->ev[4]));
+    if (p->timed) {
+        if (p->scans[0].desc.order == 3) HIPCHK(hipEventElapsedTime(&ms[1], p->ev[1], p->ev[2]));
+        HIPCHK(hipEventElapsedTime(&ms[2], p->ev[2], p->ev[3]));
+        HIPCHK(hipEventElapsedTime(&ms[3], p->ev[3], p->ev[4]));
+    }
+    return EPI_OK;
+}
+
+int epi_scan_info(epi_ctx *ctx, int32_t scan_id, uint64_t *n_combinations, int32_t *variant, int32_t *prefix_block) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    int idx;
+    Plan *p = plan_of_scan(C, scan_id, &idx);
+    if (!p) return fail(EPI_ENOTFOUND, "unknown scan %d", scan_id);
+    const PlanScan &s = p->scans[idx];
+    if (n_combinations) *n_combinations = s.n_combos;
+    if (variant) *variant = s.variant;
+    if (prefix_block) *prefix_block = s.np;
+    return EPI_OK;
+}
+
+int epi_release(epi_ctx *ctx, int32_t scan_id) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    std::unique_ptr<Plan> dead;
+    {
+        std::lock_guard<std::mutex> g(C->mu);
+        auto it = C->scan_index.find(scan_id);
+        if (it == C->scan_index.end()) return fail(EPI_ENOTFOUND, "unknown scan %d", scan_id);
+        auto pit = C->plans.find(it->second.plan);
+        C->scan_index.erase(it);
+        if (pit == C->plans.end()) return EPI_OK;
+        Plan *p = pit->second.get();
+        if (--p->live_scans <= 0 && p->transient) {
+            dead = std::move(pit->second);
+            C->plans.erase(pit);
+        }
+    }
+    if (dead) {
+        if (dead->ran) (void)hipEventSynchronize(dead->ev[4]);
+        plan_free(C, dead.get());
+    }
+    return EPI_OK;
+}
+
+int epi_batch_create(epi_ctx *ctx, const epi_scan_desc *descs, int32_t n, int32_t persistent, int32_t use_graph,
+                     int32_t *batch_id) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    if (!descs || !batch_id || n < 1) return fail(EPI_EINVAL, "bad batch arguments");
+    Plan *p = nullptr;
+    int rc = plan_build(C, descs, n, persistent != 0, use_graph != 0, &p, 0);
+    if (rc) return rc;
+    *batch_id = register_plan(C, p, nullptr);
+    p->transient = false;
+    return EPI_OK;
+}
+
+static Plan *batch_of(Ctx *C, int32_t id) {
+    auto it = C->plans.find(id);
+    if (it == C->plans.end() || it->second->transient) return nullptr;
+    return it->second.get();
+}
+
+int epi_batch_run(epi_ctx *ctx, int32_t batch_id, void *stream) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    Plan *p = batch_of(C, batch_id);
+    if (!p) return fail(EPI_ENOTFOUND, "unknown batch %d", batch_id);
+    for (auto &s : p->scans)
+        if (!C->datasets.count(s.desc.dataset_id)) return fail(EPI_ENOTFOUND, "dataset %d was unloaded", s.desc.dataset_id);
+    return plan_run(C, p, (hipStream_t)stream, ~0ull);
+}
+
+int epi_batch_wait(epi_ctx *ctx, int32_t batch_id) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    Plan *p = batch_of(C, batch_id);
+    if (!p) return fail(EPI_ENOTFOUND, "unknown batch %d", batch_id);
+    return plan_wait(p);
+}
+
+int epi_batch_results(epi_ctx *ctx, int32_t batch_id, int32_t index, int32_t capacity, int32_t *combos, float *scores,
+                      uint32_t *tables, int32_t *n_written) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    Plan *p = batch_of(C, batch_id);
+    if (!p) return fail(EPI_ENOTFOUND, "unknown batch %d", batch_id);
+    return plan_results(p, index, capacity, combos, scores, tables, n_written);
+}
+
+int epi_batch_timing(epi_ctx *ctx, int32_t batch_id, float *ms) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    Plan *p = batch_of(C, batch_id);
+    if (!p) return fail(EPI_ENOTFOUND, "unknown batch %d", batch_id);
+    if (!ms) return fail(EPI_EINVAL, "null ms");
+    int rc = plan_wait(p);
+    if (rc) return rc;
+    HIPCHK(hipEventElapsedTime(ms, p->ev[0], p->ev[4]));
+    return EPI_OK;
+}
+
+int epi_batch_destroy(epi_ctx *ctx, int32_t batch_id) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    std::unique_ptr<Plan> dead;
+    {
+        std::lock_guard<std::mutex> g(C->mu);
+        auto it = C->plans.find(batch_id);
+        if (it == C->plans.end() || it->second->transient) return fail(EPI_ENOTFOUND, "unknown batch %d", batch_id);
+        dead = std::move(it->second);
+        C->plans.erase(it);
+    }
+    if (dead->ran) (void)hipEventSynchronize(dead->ev[4]);
+    plan_free(C, dead.get());
+    return EPI_OK;
+}
+
+int epi_autotune(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t *choice) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    if (!choice) return fail(EPI_EINVAL, "null choice");
+    return autotune(C, dataset_id, order, choice);
+}
+
+}  // extern "C"

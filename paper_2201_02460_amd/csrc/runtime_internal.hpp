@@ -1,0 +1,133 @@
+// Host-side state of the runtime (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/epi.h"
+#include "epi_internal.hpp"
+
+namespace epi {
+
+constexpr int kBinomN = 65537;     // binomial table columns (n = 0 .. 65536)
+constexpr int kGenRanksHost = 4;   // ranks per lane of the per-combination kernel
+
+int fail(int code, const char *fmt, ...);
+void clear_error();
+const char *last_error();
+
+// Caching device allocator: freed blocks are kept per rounded size and
+// reused; `used` (live bytes) may not exceed `budget`.
+struct DevAlloc {
+    std::mutex mu;
+    std::multimap<size_t, void *> free_;
+    std::map<void *, size_t> live;
+    uint64_t used = 0, cached = 0, peak = 0, budget = 0;
+    int alloc(size_t bytes, void **out);
+    void release(void *p);
+    void trim();
+    void trim_locked();
+    void destroy();
+};
+
+struct Dataset {
+    int id = 0;
+    int M = 0, N = 0, n_case = 0, n_ctrl = 0, Mp = 0, shift = 0;
+    int w4[2] = {0, 0};
+    void *masks = nullptr, *single = nullptr, *tlog = nullptr, *idx = nullptr, *err = nullptr;
+    long long score_const = 0;
+    uint64_t bytes = 0;
+    DsView view{};
+};
+
+struct PlanScan {
+    epi_scan_desc desc{};
+    Dataset *ds = nullptr;
+    int variant = 0, np = 0, n_blocks = 0;
+    unsigned long long n_combos = 0, n_items = 0;
+    void *item_off = nullptr;
+    // order 3: pair sub-table pass
+    int emit_np = 0, emit_blocks = 0, emit_task = -1;
+    unsigned long long emit_items = 0;
+    void *emit_off = nullptr, *pairs = nullptr;
+    void *cand = nullptr;
+    unsigned cand_cap = 0;
+    ResultLayout lay{};
+    int scan_id = -1;
+};
+
+struct LaunchGroup {
+    int np2 = 0, np3 = 0, gk = 0, grid = 1;
+    int task_off = 0;  // first task of the group in the plan's task array
+    std::vector<int> scans;
+    unsigned long long total_items = 0;
+};
+
+struct Plan {
+    int id = 0;
+    bool persistent = false, use_graph = false, transient = false, ran = false, timed = false;
+    int live_scans = 0;
+    std::vector<PlanScan> scans;
+    std::vector<LaunchGroup> groups;
+    int n_emit = 0, emit_grid = 1, n_queues = 0;
+    unsigned long long emit_total = 0;
+    void *d_tasks = nullptr, *d_counters = nullptr, *d_results = nullptr, *d_layout = nullptr, *d_out = nullptr;
+    void *h_out = nullptr;
+    unsigned long long *d_queues = nullptr, *d_thr = nullptr;
+    unsigned *d_cand_count = nullptr;
+    long long out_bytes = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipStream_t stream = nullptr;
+};
+
+struct ScanRef {
+    int plan = 0, index = 0;
+};
+
+struct TuneKey {
+    int order, bucket;
+    bool operator<(const TuneKey &o) const { return order != o.order ? order < o.order : bucket < o.bucket; }
+};
+
+struct Server;
+
+struct Ctx {
+    int device = 0, n_cu = 1, bstride = 0;
+    std::string arch;
+    hipStream_t stream = nullptr;
+    DevAlloc alloc;
+    unsigned long long *d_binom = nullptr;
+    std::mutex mu;
+    int next_id = 1;
+    std::map<int, std::unique_ptr<Dataset>> datasets;
+    std::map<int, std::unique_ptr<Plan>> plans;
+    std::map<int, ScanRef> scan_index;
+    std::mutex tune_mu;
+    std::map<TuneKey, int> tuned;
+    std::string tune_path;
+    std::map<int, std::shared_ptr<Server>> servers;
+};
+
+Ctx *as_ctx(epi_ctx *c);
+int key_bits_for(int order);
+void load_tune_cache(Ctx *c);
+int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool graph, Plan **out, int force_np);
+int plan_run(Ctx *c, Plan *p, hipStream_t st, unsigned long long item_cap);
+int plan_wait(Plan *p);
+int plan_results(Plan *p, int index, int capacity, int32_t *combos, float *scores, uint32_t *tables,
+                 int32_t *n_written);
+void plan_free(Ctx *c, Plan *p);
+void server_shutdown_all(Ctx *c);
+
+}  // namespace epi

@@ -1,0 +1,227 @@
+"""GPU scan vs CPU oracle, through the C ABI (needs an MI355X)."""
+from __future__ import annotations
+
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from parity import check_scores_tables, check_topk
+from synth import WORKLOADS, make_case_control, make_workload, random_genotypes
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def cx():
+    from paper_2201_02460_amd import epi
+
+    with epi.Context(0) as c:
+        yield c
+
+
+def run_scan(cx, G, y, order, K):
+    from paper_2201_02460_amd import epi
+
+    ds = cx.load(G, y)
+    try:
+        return cx.scan(ds, order, K)
+    finally:
+        epi.epi_unload(cx.ctx, ds)
+
+
+# Several 64-SNP blocks and 128-individual groups with ragged tails, every
+# order, unbalanced and balanced classes.
+CASES = [
+    # order, M, N, n_cases, K
+    (2, 3, 2, 1, 5),
+    (2, 130, 257, 128, 20),
+    (2, 200, 1000, 500, 10),
+    (2, 65, 129, 1, 7),
+    (3, 3, 5, 2, 2),
+    (3, 70, 300, 100, 25),
+    (3, 131, 385, 257, 40),
+    (3, 66, 640, 511, 9),
+    (4, 4, 40, 19, 3),
+    (4, 30, 260, 90, 30),
+    (4, 41, 129, 64, 17),
+    (5, 5, 33, 16, 1),
+    (5, 22, 200, 60, 50),
+    (5, 26, 130, 65, 8),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "k%d_M%d_N%d_c%d_K%d" % c)
+def test_small_random_vs_oracle(cx, orc, case):
+    order, M, N, n_cases, K = case
+    say("case", case)
+    G, y = random_genotypes(M, N, seed=M * 31 + N + order, case_fraction=n_cases / N)
+    res = run_scan(cx, G, y, order, K)
+    check_topk(orc, G, y, order, K, res["combos"], res["scores"], res["tables"])
+
+
+@pytest.mark.parametrize("order", [2, 3, 4, 5])
+def test_planted_vs_oracle(cx, orc, order):
+    M = {2: 150, 3: 90, 4: 34, 5: 20}[order]
+    planted = tuple(range(3, 3 + 7 * order, 7))
+    G, y, info = make_case_control(M, 600, 240, planted, seed=40 + order)
+    say("planted", order, planted, info["h2"])
+    res = run_scan(cx, G, y, order, 15)
+    check_topk(orc, G, y, order, 15, res["combos"], res["scores"], res["tables"])
+
+
+def test_deterministic_planted_ranks_first(cx):
+    rng = np.random.default_rng(5)
+    for order, planted in ((2, (10, 77)), (3, (4, 30, 61)), (4, (2, 9, 17, 25))):
+        M = {2: 100, 3: 70, 4: 30}[order]
+        G = rng.choice(3, size=(M, 700), p=[0.25, 0.5, 0.25]).astype(np.uint8)
+        y = (sum((G[p] == 1).astype(int) for p in planted) % 2).astype(np.uint8)
+        res = run_scan(cx, G, y, order, 3)
+        assert tuple(res["combos"][0]) == planted
+
+
+def test_more_results_than_combinations(cx, orc):
+    G, y = random_genotypes(6, 90, seed=3)
+    for order in (2, 3, 4, 5):
+        n = math.comb(6, order)
+        res = run_scan(cx, G, y, order, n + 7)
+        assert len(res["combos"]) == n
+        check_topk(orc, G, y, order, n + 7, res["combos"], res["scores"], res["tables"])
+
+
+def test_exact_ties_are_lexicographic(cx):
+    G0, y = random_genotypes(1, 77, seed=9)
+    G = np.repeat(G0, 9, axis=0)
+    for order in (2, 3, 4):
+        n = math.comb(9, order)
+        res = run_scan(cx, G, y, order, n)
+        assert [tuple(c) for c in res["combos"]] == list(itertools.combinations(range(9), order))
+        assert len(set(res["scores"].tolist())) == 1
+
+
+def test_invalid_inputs_are_rejected(cx):
+    from paper_2201_02460_amd import epi
+
+    G, y = random_genotypes(5, 40, seed=1)
+    bad = G.copy()
+    bad[2, 7] = 3
+    with pytest.raises(epi.EpiError) as e:
+        cx.load(bad, y)
+    assert e.value.code == epi.EPI_EINVAL
+    yb = y.copy()
+    yb[0] = 2
+    with pytest.raises(epi.EpiError):
+        cx.load(G, yb)
+    with pytest.raises(epi.EpiError):
+        cx.load(G, np.ones_like(y))
+    ds = cx.load(G, y)
+    for order, K, code in ((1, 5, epi.EPI_EINVAL), (6, 5, epi.EPI_EINVAL), (3, 0, epi.EPI_EINVAL),
+                           (3, 257, epi.EPI_EUNSUPPORTED)):
+        with pytest.raises(epi.EpiError) as e:
+            epi.epi_scan(cx.ctx, ds, order, K)
+        assert e.value.code == code
+    with pytest.raises(epi.EpiError) as e:
+        epi.epi_scan(cx.ctx, ds + 999, 2, 5)
+    assert e.value.code == epi.EPI_ENOTFOUND
+    epi.epi_unload(cx.ctx, ds)
+
+
+def test_device_load_and_repack(cx, orc):
+    import torch
+
+    from paper_2201_02460_amd import epi
+
+    G, y = random_genotypes(80, 333, seed=12, case_fraction=0.4)
+    dG = torch.from_numpy(G).cuda()
+    dy = torch.from_numpy(y).cuda()
+    ds = epi.epi_load_genotypes_device(cx.ctx, dG, dy)
+    res = cx.scan(ds, 3, 10)
+    check_topk(orc, G, y, 3, 10, res["combos"], res["scores"], res["tables"])
+    # new genotypes with the same class sizes, repacked asynchronously
+    G2, _ = random_genotypes(80, 333, seed=13)
+    y2 = np.random.default_rng(2).permutation(y)
+    epi.epi_repack_device(cx.ctx, ds, torch.from_numpy(G2).cuda(), torch.from_numpy(y2).cuda())
+    res2 = cx.scan(ds, 3, 10)
+    check_topk(orc, G2, y2, 3, 10, res2["combos"], res2["scores"], res2["tables"])
+    epi.epi_unload(cx.ctx, ds)
+
+
+def _golden_names():
+    return [n for n in WORKLOADS if os.path.exists(os.path.join(GOLDEN, n + ".json"))]
+
+
+@pytest.mark.parametrize("name", _golden_names())
+def test_full_size_workload_vs_stored_oracle(cx, orc, name):
+    """The named workloads at full size, in the plain launch the benchmark
+    times, against the oracle's full scan stored in tests/golden."""
+    with open(os.path.join(GOLDEN, name + ".json")) as f:
+        gold = json.load(f)
+    G, y, spec, info = make_workload(name)
+    say("workload", name, spec)
+    res = run_scan(cx, G, y, spec["order"], spec["top_k"])
+    ref = {"combos": np.asarray(gold["combos"], np.int32), "scores": np.asarray(gold["scores"])}
+    check_topk(orc, G, y, spec["order"], spec["top_k"], res["combos"], res["scores"], res["tables"], ref=ref)
+    gold_tab = {tuple(c): np.asarray(t, np.int64) for c, t in zip(gold["combos"], gold["tables"])}
+    for c, t in zip(res["combos"], res["tables"]):
+        if tuple(c) in gold_tab:
+            assert np.array_equal(t.astype(np.int64), gold_tab[tuple(c)])
+    say("top-1", tuple(res["combos"][0]), float(res["scores"][0]), "planted", spec["planted"], "ms", res["ms"])
+
+
+def test_batch_matches_single_scans(cx, orc):
+    from paper_2201_02460_amd import epi
+
+    specs = [(2, 140, 700, 300), (3, 75, 410, 150), (4, 28, 300, 100), (3, 120, 260, 60), (2, 33, 97, 40)]
+    data, dss = [], []
+    for i, (order, M, N, nc) in enumerate(specs):
+        G, y = random_genotypes(M, N, seed=100 + i, case_fraction=nc / N)
+        data.append((G, y))
+        dss.append(cx.load(G, y))
+    K = 12
+    descs = [(dss[i], specs[i][0], K) for i in range(len(specs))]
+    singles = [cx.scan(dss[i], specs[i][0], K) for i in range(len(specs))]
+    bid = epi.epi_batch_create(cx.ctx, descs, persistent=True, use_graph=True)
+    for rep in range(3):
+        say("batch replay", rep)
+        epi.epi_batch_run(cx.ctx, bid)
+        epi.epi_batch_wait(cx.ctx, bid)
+        for i, (order, M, N, nc) in enumerate(specs):
+            c, s, t = epi.epi_batch_results(cx.ctx, bid, i, K, order)
+            assert np.array_equal(c, singles[i]["combos"])
+            assert np.array_equal(s, singles[i]["scores"])
+            assert np.array_equal(t, singles[i]["tables"])
+            if rep == 0:
+                G, y = data[i]
+                check_topk(orc, G, y, order, K, c, s, t)
+    epi.epi_batch_destroy(cx.ctx, bid)
+    # one-shot persistent batch through epi_scan_batch
+    ids = epi.epi_scan_batch(cx.ctx, descs)
+    for i, sid in enumerate(ids):
+        epi.epi_wait(cx.ctx, sid)
+        c, s, t = epi.epi_results(cx.ctx, sid, K, specs[i][0])
+        assert np.array_equal(c, singles[i]["combos"]) and np.array_equal(s, singles[i]["scores"])
+        epi.epi_release(cx.ctx, sid)
+    for d in dss:
+        epi.epi_unload(cx.ctx, d)
+
+
+def test_autotune_keeps_results(cx, orc):
+    from paper_2201_02460_amd import epi
+
+    G, y = random_genotypes(160, 700, seed=21, case_fraction=0.3)
+    ds = cx.load(G, y)
+    before = cx.scan(ds, 3, 20)
+    choice = epi.epi_autotune(cx.ctx, ds, 3)
+    assert choice in (1, 2, 4, 8)
+    after = cx.scan(ds, 3, 20)
+    assert np.array_equal(before["combos"], after["combos"]) and np.array_equal(before["scores"], after["scores"])
+    check_topk(orc, G, y, 3, 20, after["combos"], after["scores"], after["tables"])
+    epi.epi_unload(cx.ctx, ds)
