@@ -18,8 +18,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 SOURCES = ["kernels.hip", "runtime.cpp", "server.cpp"]
 # Packed FP32 VALU instructions are disabled for all device code.
-FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
-         "-packed-fp32-ops", "-Wno-unused-command-line-argument", f"-I{INCLUDE}", "-Wall"]
+FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-mcode-object-version=5", "-Xclang",
+         "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument", f"-I{INCLUDE}", "-Wall"]
 
 
 def _compile(src):

@@ -27,6 +27,7 @@ namespace epi {
 constexpr int kMaxTopK = 256;
 constexpr int kWave = 64;
 constexpr int kMergeSlots = 4096;      // LDS entries of the top-K merge
+constexpr int kMergeParts = 32;        // first-stage merge workgroups per task
 constexpr int kMaxBinomOrder = 8;
 
 enum Variant : int32_t {
@@ -56,7 +57,7 @@ struct Cand {
 struct Task {
     DsView ds;
     uint32_t *pairs;                  // lex-ordered pair sub-table, 8 u32 per pair
-    const unsigned long long *item_off;  // per-prefix item offsets (kF2/kF2Emit: per i-block, kF3: per j)
+    const unsigned long long *items;  // per-item descriptors: kF3 j<<40 | ib<<20 | mb, kF2 ib<<20 | mb
     unsigned long long n_items;
     unsigned long long item_base;     // first global item of this task in its launch
     unsigned long long n_combos;

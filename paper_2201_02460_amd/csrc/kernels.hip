@@ -6,7 +6,7 @@
 //                                 tables (Section 2.2), mutual information
 //                                 (Section 2.3, Equations 1-3), best-K
 //                                 retention (Section 2.4)
-//   merge_kernel                  final best-K selection
+//   merge_part/final_kernel       final best-K selection (two stages)
 //   finalize_kernel               combinations, scores and full 2 x 3^k
 //                                 tables of the retained combinations
 //
@@ -205,13 +205,22 @@ EPI_DEV void tk_flush(TopK &t, const Cand *list, const Task &task) {
     t.n = 0;
 }
 
-// One cell's contribution T(n0) + T(n1) - T(n0 + n1).  Counts are clamped to
-// [0, N] so that no value can index past the table.
+typedef __attribute__((address_space(1))) const long long glong;
+
+// One cell's contribution T(n0) + T(n1) - T(n0 + n1) for counts derived by
+// inclusion-exclusion.  The table holds 2N + 1 entries and each class count
+// is clamped to N, so no value can index past it.
 EPI_DEV long long cell_term(const long long *T, int n0, int n1, unsigned N) {
     const unsigned a = min((unsigned)n0, N);
     const unsigned b = min((unsigned)n1, N);
-    const unsigned ab = min(a + b, N);
-    return T[a] + T[b] - T[ab];
+    glong *g = (glong *)T;
+    return g[a] + g[b] - g[a + b];
+}
+
+// Same for counts that are popcounts of one class each (n0 + n1 <= N).
+EPI_DEV long long cell_term_counted(const long long *T, unsigned n0, unsigned n1) {
+    glong *g = (glong *)T;
+    return g[n0] + g[n1] - g[n0 + n1];
 }
 
 // ---------------------------------------------------------------------------
@@ -221,13 +230,9 @@ EPI_DEV long long cell_term(const long long *T, int n0, int n1, unsigned N) {
 template <int NP, bool EMIT>
 EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr) {
     const DsView d = t.ds;
-    int lo = 0, hi = t.n_blocks - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (t.item_off[mid] <= local) lo = mid; else hi = mid - 1;
-    }
-    const int ib = uni(lo);
-    const int mb = uni((int)(local - t.item_off[ib]));
+    const unsigned long long dsc = t.items[local];
+    const int ib = uni((int)((dsc >> 20) & 0xfffffu));
+    const int mb = uni((int)(dsc & 0xfffffu));
     const int i0 = ib * NP;
     const int lane = threadIdx.x;
     const int m = i0 + 1 + mb * kWave + lane;
@@ -252,9 +257,15 @@ EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *li
     for (int c = 0; c < 2; ++c) {
         const int W = d.w4[c];
         long long off = (long long)d.wbase[c] * 2 * Mp;
+        v4u m0n = gm[off + m_ld];
+        v4u m1n = gm[off + Mp + m_ld];
         for (int w = 0; w < W; ++w, off += 2 * Mp) {
-            const v4u m0 = gm[off + m_ld];
-            const v4u m1 = gm[off + Mp + m_ld];
+            const v4u m0 = m0n;
+            const v4u m1 = m1n;
+            // next iteration's lane rows (the last iteration re-reads its own)
+            const long long offn = w + 1 < W ? off + 2 * Mp : off;
+            m0n = gm[offn + m_ld];
+            m1n = gm[offn + Mp + m_ld];
             #pragma unroll
             for (int p = 0; p < NP; ++p) {
                 const v4u a0 = cm[off + ip[p]];
@@ -298,8 +309,6 @@ EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *li
                 F[c][7] = sm[2 * c + 1];
                 F[c][8] = d.ncls[c];
                 mobius2(F[c]);
-                #pragma unroll
-                for (int x = 0; x < 9; ++x) F[c][x] = valid ? F[c][x] : 0;
             }
             long long num = t.score_const;
             #pragma unroll
@@ -318,16 +327,10 @@ EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *li
 template <int NP>
 EPI_DEV void item_f3(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr) {
     const DsView d = t.ds;
-    int lo = 1, hi = t.n_blocks - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (t.item_off[mid] <= local) lo = mid; else hi = mid - 1;
-    }
-    const int j = uni(lo);
-    const int nmb = uni((d.M - 1 - j + kWave - 1) / kWave);
-    const unsigned r = (unsigned)(local - t.item_off[j]);
-    const int ib = uni((int)(r / (unsigned)nmb));
-    const int mb = uni((int)(r - (unsigned)ib * (unsigned)nmb));
+    const unsigned long long dsc = t.items[local];
+    const int j = uni((int)((dsc >> 40) & 0xfffffu));
+    const int ib = uni((int)((dsc >> 20) & 0xfffffu));
+    const int mb = uni((int)(dsc & 0xfffffu));
     const int i0 = ib * NP;
     const int lane = threadIdx.x;
     const int m = j + 1 + mb * kWave + lane;
@@ -352,9 +355,15 @@ EPI_DEV void item_f3(const Task &t, unsigned long long local, TopK &tk, Cand *li
     for (int c = 0; c < 2; ++c) {
         const int W = d.w4[c];
         long long off = (long long)d.wbase[c] * 2 * Mp;
+        v4u m0n = gm[off + m_ld];
+        v4u m1n = gm[off + Mp + m_ld];
         for (int w = 0; w < W; ++w, off += 2 * Mp) {
-            const v4u m0 = gm[off + m_ld];
-            const v4u m1 = gm[off + Mp + m_ld];
+            const v4u m0 = m0n;
+            const v4u m1 = m1n;
+            // next iteration's lane rows (the last iteration re-reads its own)
+            const long long offn = w + 1 < W ? off + 2 * Mp : off;
+            m0n = gm[offn + m_ld];
+            m1n = gm[offn + Mp + m_ld];
             const v4u b0 = cm[off + j];
             const v4u b1 = cm[off + Mp + j];
             #pragma unroll
@@ -421,8 +430,6 @@ EPI_DEV void item_f3(const Task &t, unsigned long long local, TopK &tk, Cand *li
             F[c][25] = sm[2 * c + 1];
             F[c][26] = d.ncls[c];
             mobius3(F[c]);
-            #pragma unroll
-            for (int x = 0; x < 27; ++x) F[c][x] = valid ? F[c][x] : 0;
         }
         long long num = t.score_const;
         #pragma unroll
@@ -526,7 +533,7 @@ EPI_DEV long long generic_num(const DsView &d, const int (&c)[K], long long scor
             }
         }
         #pragma unroll
-        for (int x = 0; x < CELLS; ++x) num += cell_term(d.tlog, (int)acc[0][x], (int)acc[1][x], (unsigned)d.N);
+        for (int x = 0; x < CELLS; ++x) num += cell_term_counted(d.tlog, acc[0][x], acc[1][x]);
     }
     return num;
 }
@@ -555,8 +562,17 @@ EPI_DEV void item_generic(const Task &t, unsigned long long local, TopK &tk, Can
 // device queue (one atomic per item) that runs over the concatenated item
 // spaces of all tasks of the launch, in task order.
 // ---------------------------------------------------------------------------
+// Register budget per instantiation: enough waves per SIMD to hide load
+// latency; the accumulators (16 per prefix for order 3, 8 for order 2) set the
+// floor.
 template <int NP2, int NP3, int GK>
-__global__ void __launch_bounds__(64) scan_persistent(const Task *__restrict__ tasks, int n_tasks,
+constexpr int scan_waves_per_eu() {
+    return GK >= 4 ? 2 : (GK == 3 ? 3 : (NP3 >= 4 ? 2 : (NP3 >= 2 ? 4 : (NP2 >= 8 ? 3 : 4))));
+}
+
+template <int NP2, int NP3, int GK>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<NP2, NP3, GK>())))
+scan_persistent(const Task *__restrict__ tasks, int n_tasks,
                                                       unsigned long long total_items,
                                                       unsigned long long *__restrict__ queue,
                                                       const unsigned long long *__restrict__ binom, int bstride) {
@@ -641,25 +657,19 @@ EPI_DEV void bitonic_sort_best_first(Cand *buf, int P) {
     }
 }
 
-__global__ void __launch_bounds__(1024) merge_kernel(const Task *__restrict__ tasks, Cand *__restrict__ results) {
-    __shared__ Cand buf[kMergeSlots];
-    __shared__ int s_ctr;
-    const Task &t = tasks[blockIdx.x];
+// Best K of src[lo, hi) (entries below g dropped) into out[0, K), best first.
+EPI_DEV void merge_range(const Cand *src, unsigned lo, unsigned hi, long long g, int K, Cand *buf, int *s_ctr,
+                         Cand *out) {
     const Cand sentinel{(long long)0x8000000000000000ull, ~0ull};
-    const int K = t.top_k;
-    const unsigned cap = t.cand_cap;
-    unsigned count = *t.cand_count;
-    count = count < cap ? count : cap;
-    const long long g = load_thr(t.thr);
     for (int i = threadIdx.x; i < kMergeSlots; i += blockDim.x) buf[i] = sentinel;
     __syncthreads();
     int fill = K;
-    for (unsigned base = 0; base < count; base += blockDim.x) {
+    for (unsigned base = lo; base < hi; base += blockDim.x) {
         const unsigned i = base + threadIdx.x;
         Cand c = sentinel;
         bool keep = false;
-        if (i < count) {
-            c = t.cand[i];
+        if (i < hi) {
+            c = src[i];
             keep = c.num >= g;
         }
         const int n = __syncthreads_count(keep);
@@ -671,12 +681,63 @@ __global__ void __launch_bounds__(1024) merge_kernel(const Task *__restrict__ ta
             fill = K;
             __syncthreads();
         }
-        if (threadIdx.x == 0) s_ctr = fill;
+        if (threadIdx.x == 0) *s_ctr = fill;
         __syncthreads();
-        if (keep) buf[atomicAdd(&s_ctr, 1)] = c;
+        if (keep) buf[atomicAdd(s_ctr, 1)] = c;
         __syncthreads();
         fill += n;
     }
+    int P = 64;
+    while (P < fill) P <<= 1;
+    bitonic_sort_best_first(buf, P);
+    for (int r = threadIdx.x; r < K; r += blockDim.x) out[r] = buf[r];
+}
+
+// Stage 1: workgroup (part, task) reduces its slice of the task's candidate
+// buffer to the best K.
+__global__ void __launch_bounds__(1024) merge_part_kernel(const Task *__restrict__ tasks, Cand *__restrict__ parts) {
+    __shared__ Cand buf[kMergeSlots];
+    __shared__ int s_ctr;
+    const Task &t = tasks[blockIdx.y];
+    unsigned count = *t.cand_count;
+    count = count < t.cand_cap ? count : t.cand_cap;
+    const unsigned lo = (unsigned)((unsigned long long)count * blockIdx.x / gridDim.x);
+    const unsigned hi = (unsigned)((unsigned long long)count * (blockIdx.x + 1) / gridDim.x);
+    merge_range(t.cand, lo, hi, load_thr(t.thr), t.top_k, buf, &s_ctr,
+                parts + ((long long)blockIdx.y * gridDim.x + blockIdx.x) * kMaxTopK);
+}
+
+// Stage 2: one workgroup per task merges the stage-1 lists.
+__global__ void __launch_bounds__(1024) merge_final_kernel(const Task *__restrict__ tasks, const Cand *__restrict__ parts,
+                                                           int n_parts, Cand *__restrict__ results) {
+    __shared__ Cand buf[kMergeSlots];
+    __shared__ int s_ctr;
+    const Task &t = tasks[blockIdx.x];
+    const int K = t.top_k;
+    const Cand *src = parts + (long long)blockIdx.x * n_parts * kMaxTopK;
+    // gather the n_parts lists (K entries each, stride kMaxTopK) behind the best K
+    const Cand sentinel{(long long)0x8000000000000000ull, ~0ull};
+    for (int i = threadIdx.x; i < kMergeSlots; i += blockDim.x) buf[i] = sentinel;
+    __syncthreads();
+    const long long g = load_thr(t.thr);
+    int fill = K;
+    for (int p = 0; p < n_parts; ++p) {
+        if (fill + K > kMergeSlots) {
+            int P = 64;
+            while (P < fill) P <<= 1;
+            bitonic_sort_best_first(buf, P);
+            for (int x = K + threadIdx.x; x < kMergeSlots; x += blockDim.x) buf[x] = sentinel;
+            fill = K;
+            __syncthreads();
+        }
+        for (int r = threadIdx.x; r < K; r += blockDim.x) {
+            const Cand c = src[(long long)p * kMaxTopK + r];
+            buf[fill + r] = c.num >= g ? c : sentinel;
+        }
+        __syncthreads();
+        fill += K;
+    }
+    (void)s_ctr;
     int P = 64;
     while (P < fill) P <<= 1;
     bitonic_sort_best_first(buf, P);
@@ -910,9 +971,24 @@ hipError_t scan_occupancy(int np2, int np3, int gk, int *blocks_per_cu) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kWave, 0);
 }
 
-hipError_t launch_merge(int n_tasks, hipStream_t st, const Task *tasks, Cand *results) {
-    hipLaunchKernelGGL(merge_kernel, dim3(n_tasks), dim3(1024), 0, st, tasks, results);
+hipError_t launch_merge(int n_tasks, hipStream_t st, const Task *tasks, Cand *parts, Cand *results) {
+    hipLaunchKernelGGL(merge_part_kernel, dim3(kMergeParts, n_tasks), dim3(1024), 0, st, tasks, parts);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(merge_final_kernel, dim3(n_tasks), dim3(1024), 0, st, tasks, (const Cand *)parts, kMergeParts,
+                       results);
     return hipGetLastError();
+}
+
+hipError_t scan_attributes(int np2, int np3, int gk, int *vgprs, int *lds_bytes) {
+    ScanKernelFn fn = find_scan_kernel(np2, np3, gk);
+    if (!fn) return hipErrorInvalidValue;
+    hipFuncAttributes a;
+    hipError_t e = hipFuncGetAttributes(&a, (const void *)fn);
+    if (e != hipSuccess) return e;
+    *vgprs = a.numRegs;
+    *lds_bytes = (int)a.sharedSizeBytes;
+    return hipSuccess;
 }
 
 hipError_t launch_finalize(int n_tasks, int max_k, hipStream_t st, const Task *tasks, const Cand *results,

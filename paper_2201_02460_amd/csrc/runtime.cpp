@@ -32,7 +32,8 @@ hipError_t launch_scan(int np2, int np3, int gk, int grid, hipStream_t st, const
                        unsigned long long total_items, unsigned long long *queue, const unsigned long long *binom,
                        int bstride);
 hipError_t scan_occupancy(int np2, int np3, int gk, int *blocks_per_cu);
-hipError_t launch_merge(int n_tasks, hipStream_t st, const Task *tasks, Cand *results);
+hipError_t launch_merge(int n_tasks, hipStream_t st, const Task *tasks, Cand *parts, Cand *results);
+hipError_t scan_attributes(int np2, int np3, int gk, int *vgprs, int *lds_bytes);
 hipError_t launch_finalize(int n_tasks, int max_k, hipStream_t st, const Task *tasks, const Cand *results,
                            const ResultLayout *layout, char *out);
 hipError_t launch_init_counters(hipStream_t st, unsigned long long *queues, int nq, unsigned *cand_counts,
@@ -191,15 +192,17 @@ int ctx_init(Ctx *c, int device, uint64_t budget) {
 // datasets
 // ---------------------------------------------------------------------------
 static int choose_shift(int N) {
-    const double maxv = (double)N * std::log((double)std::max(N, 2)) + 1.0;
+    const double maxv = 2.0 * N * std::log(2.0 * std::max(N, 2)) + 1.0;
     int s = (int)std::floor(61.0 - std::log2(maxv));
     return std::min(40, std::max(8, s));
 }
 
+// round(n ln n * 2^shift) for n = 0 .. 2N (entries past N keep clamped
+// lookups in bounds; valid tables never reach them).
 static void build_tlog(int N, int shift, std::vector<long long> &out) {
-    out.assign((size_t)N + 1, 0);
+    out.assign((size_t)2 * N + 1, 0);
     const long double sc = std::ldexp((long double)1.0, shift);
-    for (int n = 2; n <= N; ++n) out[n] = llroundl((long double)n * logl((long double)n) * sc);
+    for (int n = 2; n <= 2 * N; ++n) out[n] = llroundl((long double)n * logl((long double)n) * sc);
 }
 
 static void ds_free(Ctx *c, Dataset *d) {
@@ -245,10 +248,10 @@ static int ds_alloc(Ctx *c, Dataset *d) {
     int rc;
     if ((rc = c->alloc.alloc(std::max<size_t>(mask_bytes, 16), &d->masks))) return rc;
     if ((rc = c->alloc.alloc((size_t)d->Mp * 16, &d->single))) return rc;
-    if ((rc = c->alloc.alloc(((size_t)d->N + 1) * 8, &d->tlog))) return rc;
+    if ((rc = c->alloc.alloc(((size_t)2 * d->N + 1) * 8, &d->tlog))) return rc;
     if ((rc = c->alloc.alloc((size_t)d->N * 4, &d->idx))) return rc;
     if ((rc = c->alloc.alloc(256, &d->err))) return rc;
-    d->bytes = mask_bytes + (size_t)d->Mp * 16 + ((size_t)d->N + 1) * 8 + (size_t)d->N * 4;
+    d->bytes = mask_bytes + (size_t)d->Mp * 16 + ((size_t)2 * d->N + 1) * 8 + (size_t)d->N * 4;
     ds_view(d);
     std::vector<long long> tl;
     build_tlog(d->N, d->shift, tl);
@@ -315,30 +318,49 @@ static int tuned_np(Ctx *c, int order, const Dataset *d) {
     return order == 2 ? 4 : (order == 3 ? 4 : kGenRanksHost);
 }
 
-static unsigned long long build_f2_offsets(int M, int np, std::vector<unsigned long long> &off) {
-    const int nib = std::max(1, (M - 1 + np - 1) / np);
-    off.assign((size_t)nib + 1, 0);
+// Work items of the order-2 kernels: (i-block ib of np SNPs, block mb of 64
+// SNPs m > i0), descriptor ib << 20 | mb.
+static void build_f2_items(int M, int np, std::vector<unsigned long long> &out) {
+    out.clear();
+    const int nib = std::max(0, (M - 1 + np - 1) / np);
     for (int ib = 0; ib < nib; ++ib) {
-        const int i0 = ib * np;
-        const long long nm = std::max(0, M - 1 - i0);
-        off[ib + 1] = off[ib] + (unsigned long long)((nm + 63) / 64);
+        const int nm = std::max(0, M - 1 - ib * np);
+        for (int mb = 0; mb < (nm + 63) / 64; ++mb) out.push_back(((unsigned long long)ib << 20) | (unsigned)mb);
     }
-    return off[nib];
 }
 
-static unsigned long long build_f3_offsets(int M, int np, std::vector<unsigned long long> &off) {
-    // off[j] = items of all j' < j; j runs over 1 .. M-2
-    off.assign((size_t)M + 1, 0);
-    for (int j = 0; j < M; ++j) {
-        unsigned long long cnt = 0;
-        if (j >= 1 && j <= M - 2) {
-            const unsigned long long ni = (unsigned long long)((j + np - 1) / np);
-            const unsigned long long nm = (unsigned long long)((M - 1 - j + 63) / 64);
-            cnt = ni * nm;
-        }
-        off[j + 1] = off[j] + cnt;
+// Work items of the order-3 kernel: (j, block ib of np SNPs i < j, block mb
+// of 64 SNPs m > j), descriptor j << 40 | ib << 20 | mb.
+static void build_f3_items(int M, int np, std::vector<unsigned long long> &out) {
+    out.clear();
+    for (int j = 1; j <= M - 2; ++j) {
+        const int ni = (j + np - 1) / np;
+        const int nm = (M - 1 - j + 63) / 64;
+        for (int ib = 0; ib < ni; ++ib)
+            for (int mb = 0; mb < nm; ++mb)
+                out.push_back(((unsigned long long)j << 40) | ((unsigned long long)ib << 20) | (unsigned)mb);
     }
-    return off[M];
+}
+
+// Descriptor table of a shape, built once per context and cached.
+static int get_items(Ctx *c, int variant, int M, int np, const void **d, unsigned long long *n) {
+    std::lock_guard<std::mutex> g(c->items_mu);
+    const auto key = std::make_tuple(variant, M, np);
+    auto it = c->item_tables.find(key);
+    if (it == c->item_tables.end()) {
+        std::vector<unsigned long long> h;
+        if (variant == kF3) build_f3_items(M, np, h);
+        else build_f2_items(M, np, h);
+        ItemTable t;
+        t.n = h.size();
+        int rc = c->alloc.alloc(std::max<size_t>(h.size(), 1) * 8, &t.d);
+        if (rc) return rc;
+        if (!h.empty()) HIPCHK(hipMemcpy(t.d, h.data(), h.size() * 8, hipMemcpyHostToDevice));
+        it = c->item_tables.emplace(key, t).first;
+    }
+    *d = it->second.d;
+    *n = it->second.n;
+    return EPI_OK;
 }
 
 void plan_free(Ctx *c, Plan *p) {
@@ -347,11 +369,10 @@ void plan_free(Ctx *c, Plan *p) {
     p->exec = nullptr;
     p->graph = nullptr;
     for (auto &s : p->scans) {
-        c->alloc.release(s.item_off);
-        c->alloc.release(s.emit_off);
         c->alloc.release(s.pairs);
         c->alloc.release(s.cand);
     }
+    c->alloc.release(p->d_parts);
     c->alloc.release(p->d_tasks);
     c->alloc.release(p->d_counters);
     c->alloc.release(p->d_results);
@@ -415,10 +436,23 @@ static void pick_group_kernel(const std::vector<int> &orders, int np3_hint, int 
     *gk = gen == 4 ? 4 : 0;
 }
 
+// Persistent grid: as many one-wave workgroups as fit on the device, from
+// the kernel's VGPR count (512 registers per SIMD lane, at most 8 waves per
+// SIMD) and LDS use (160 KiB per CU).  EPI_WAVES_PER_SIMD overrides the wave
+// count.  Extra workgroups only queue: the work queue drains either way.
 static int grid_for(Ctx *c, int np2, int np3, int gk, unsigned long long items) {
-    int per_cu = 0;
-    if (scan_occupancy(np2, np3, gk, &per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
-    long long g = (long long)per_cu * c->n_cu;
+    int vgprs = 128, lds = 4096;
+    if (scan_attributes(np2, np3, gk, &vgprs, &lds) != hipSuccess) {
+        (void)hipGetLastError();
+        vgprs = 128;
+        lds = 4096;
+    }
+    const int alloc = std::max(8, (vgprs + 7) / 8 * 8);
+    int waves = std::min(8, 512 / alloc);
+    if (lds > 0) waves = std::min(waves, (160 * 1024 / lds) / 4);
+    if (const char *e = getenv("EPI_WAVES_PER_SIMD")) waves = std::max(1, std::min(16, atoi(e)));
+    waves = std::max(1, waves);
+    long long g = (long long)waves * 4 * c->n_cu;
     if ((unsigned long long)g > items) g = (long long)std::max<unsigned long long>(items, 1);
     return (int)g;
 }
@@ -440,50 +474,28 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         plan_free(c, p.get());
         return code;
     };
-    // per-scan variant, items and offsets
+    // per-scan variant and prefix block
     for (int i = 0; i < n; ++i) {
         PlanScan &s = p->scans[i];
         s.desc = descs[i];
         s.ds = dss[i];
         s.n_combos = binom_u64(s.ds->M, s.desc.order);
         const int o = s.desc.order;
-        std::vector<unsigned long long> off;
         if (o == 2) {
             s.variant = kF2;
             s.np = persistent ? 4 : (force_np > 0 ? force_np : tuned_np(c, 2, s.ds));
-            s.n_items = build_f2_offsets(s.ds->M, s.np, off);
-            s.n_blocks = (int)off.size() - 1;
         } else if (o == 3) {
             s.variant = kF3;
-            int np = force_np > 0 ? force_np : tuned_np(c, 3, s.ds);
-            if (persistent) np = np <= 2 ? 2 : 4;
-            s.np = np;
-            s.n_items = build_f3_offsets(s.ds->M, s.np, off);
-            s.n_blocks = s.ds->M;  // binary search over j in [1, M-1]
+            s.np = force_np > 0 ? force_np : tuned_np(c, 3, s.ds);
         } else {
             s.variant = kGeneric;
             s.np = kGenRanksHost;
             s.n_items = (s.n_combos + 64ull * kGenRanksHost - 1) / (64ull * kGenRanksHost);
         }
-        if (!off.empty()) {
-            if ((rc = c->alloc.alloc(off.size() * 8, &s.item_off))) return cleanup(rc);
-            HIPCHK(hipMemcpy(s.item_off, off.data(), off.size() * 8, hipMemcpyHostToDevice));
-        }
-        if (o == 3) {
-            // pair sub-table pass (order-2 reduced cells of every pair)
-            std::vector<unsigned long long> eoff;
-            s.emit_np = 4;
-            s.emit_items = build_f2_offsets(s.ds->M, s.emit_np, eoff);
-            s.emit_blocks = (int)eoff.size() - 1;
-            if ((rc = c->alloc.alloc(eoff.size() * 8, &s.emit_off))) return cleanup(rc);
-            HIPCHK(hipMemcpy(s.emit_off, eoff.data(), eoff.size() * 8, hipMemcpyHostToDevice));
-            const size_t pb = (size_t)binom_u64(s.ds->M, 2) * 32;
-            if ((rc = c->alloc.alloc(std::max<size_t>(pb, 32), &s.pairs))) return cleanup(rc);
-        }
     }
     // launch groups
     if (persistent) {
-        // emit group: all order-3 pair passes; main groups by kernel instantiation
+        // main groups by kernel instantiation (order 5 runs in a group of its own)
         std::vector<int> orders_a, orders_b;
         int np3_hint = 4;
         for (auto &s : p->scans) {
@@ -509,16 +521,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         }
         for (auto &g : p->groups)
             for (int i : g.scans)
-                if (p->scans[i].desc.order == 3) {
-                    p->scans[i].np = g.np3;
-                }
-        // rebuild order-3 offsets for the group's prefix block
-        for (auto &s : p->scans) {
-            if (s.desc.order != 3) continue;
-            std::vector<unsigned long long> off;
-            s.n_items = build_f3_offsets(s.ds->M, s.np, off);
-            HIPCHK(hipMemcpy(s.item_off, off.data(), off.size() * 8, hipMemcpyHostToDevice));
-        }
+                if (p->scans[i].desc.order == 3) p->scans[i].np = g.np3;
     } else {
         for (int i = 0; i < n; ++i) {
             LaunchGroup g;
@@ -538,6 +541,18 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
             }
             g.scans.push_back(i);
             p->groups.push_back(g);
+        }
+    }
+    // work-item descriptor tables and order-3 sub-table buffers
+    for (auto &s : p->scans) {
+        if (s.variant == kF2 || s.variant == kF3) {
+            if ((rc = get_items(c, s.variant, s.ds->M, s.np, &s.items, &s.n_items))) return cleanup(rc);
+        }
+        if (s.desc.order == 3) {
+            s.emit_np = 4;
+            if ((rc = get_items(c, kF2, s.ds->M, s.emit_np, &s.emit_items_d, &s.emit_items))) return cleanup(rc);
+            const size_t pb = (size_t)binom_u64(s.ds->M, 2) * 32;
+            if ((rc = c->alloc.alloc(std::max<size_t>(pb, 32), &s.pairs))) return cleanup(rc);
         }
     }
     // tasks: [main tasks in scan order][emit tasks]
@@ -579,6 +594,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
     p->d_thr = p->d_queues + nq;
     p->d_cand_count = (unsigned *)(p->d_thr + nt);
     if ((rc = c->alloc.alloc((size_t)nt * kMaxTopK * sizeof(Cand), &p->d_results))) return cleanup(rc);
+    if ((rc = c->alloc.alloc((size_t)nt * kMergeParts * kMaxTopK * sizeof(Cand), &p->d_parts))) return cleanup(rc);
     if ((rc = c->alloc.alloc((size_t)nt * sizeof(ResultLayout), &p->d_layout))) return cleanup(rc);
     if ((rc = c->alloc.alloc((size_t)std::max<long long>(out_bytes, 256), &p->d_out))) return cleanup(rc);
     HIPCHK(hipHostMalloc(&p->h_out, (size_t)std::max<long long>(out_bytes, 256), hipHostMallocDefault));
@@ -593,7 +609,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         memset(&t, 0, sizeof t);
         t.ds = s.ds->view;
         t.pairs = (uint32_t *)s.pairs;
-        t.item_off = (const unsigned long long *)s.item_off;
+        t.items = (const unsigned long long *)s.items;
         t.n_items = s.n_items;
         t.item_base = 0;
         t.n_combos = s.n_combos;
@@ -606,7 +622,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         t.order = s.desc.order;
         t.top_k = s.desc.top_k;
         t.np = s.np;
-        t.n_blocks = s.variant == kF3 ? s.ds->M : s.n_blocks;
+        t.n_blocks = 0;
         t.key_bits = key_bits_for(s.desc.order);
     }
     {
@@ -619,12 +635,12 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
             Task &t = tasks[e++];
             t = tasks[i];
             t.variant = kF2Emit;
-            t.item_off = (const unsigned long long *)s.emit_off;
+            t.items = (const unsigned long long *)s.emit_items_d;
             t.n_items = s.emit_items;
             t.item_base = persistent ? base : 0;
             base += s.emit_items;
             t.np = s.emit_np;
-            t.n_blocks = s.emit_blocks;
+            t.n_blocks = 0;
             t.order = 2;
         }
     }
@@ -674,7 +690,7 @@ static int plan_enqueue(Ctx *c, Plan *p, hipStream_t st, bool timing, unsigned l
             ++q;
         }
         if (timing && single) HIPCHK(hipEventRecord(p->ev[3], st));
-        HIPCHK(launch_merge(nt, st, tasks, (Cand *)p->d_results));
+        HIPCHK(launch_merge(nt, st, tasks, (Cand *)p->d_parts, (Cand *)p->d_results));
         int maxk = 1;
         for (auto &s : p->scans) maxk = std::max(maxk, s.desc.top_k);
         HIPCHK(launch_finalize(nt, maxk, st, tasks, (const Cand *)p->d_results, (const ResultLayout *)p->d_layout,
@@ -695,7 +711,8 @@ static int plan_enqueue(Ctx *c, Plan *p, hipStream_t st, bool timing, unsigned l
                                p->d_queues + 1, c->d_binom, c->bstride));
             HIPCHK(launch_init_counters(st, p->d_queues + 1, 1, nullptr, nullptr, 0));
             if (timing && single) HIPCHK(hipEventRecord(p->ev[3], st));
-            HIPCHK(launch_merge(1, st, tasks + i, (Cand *)p->d_results + (size_t)i * kMaxTopK));
+            HIPCHK(launch_merge(1, st, tasks + i, (Cand *)p->d_parts + (size_t)i * kMergeParts * kMaxTopK,
+                                (Cand *)p->d_results + (size_t)i * kMaxTopK));
             HIPCHK(launch_finalize(1, s.desc.top_k, st, tasks + i, (const Cand *)p->d_results + (size_t)i * kMaxTopK,
                                    (const ResultLayout *)p->d_layout + i, (char *)p->d_out));
         }
@@ -879,6 +896,7 @@ int epi_destroy(epi_ctx *ctx) {
     (void)hipDeviceSynchronize();
     for (auto &kv : C->plans) plan_free(C, kv.second.get());
     C->plans.clear();
+    C->item_tables.clear();
     for (auto &kv : C->datasets) ds_free(C, kv.second.get());
     C->datasets.clear();
     C->alloc.destroy();

@@ -11,6 +11,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "../../include/epi.h"
@@ -52,13 +53,14 @@ struct Dataset {
 struct PlanScan {
     epi_scan_desc desc{};
     Dataset *ds = nullptr;
-    int variant = 0, np = 0, n_blocks = 0;
+    int variant = 0, np = 0;
     unsigned long long n_combos = 0, n_items = 0;
-    void *item_off = nullptr;
+    const void *items = nullptr;  // cached per-item descriptors (owned by the context)
     // order 3: pair sub-table pass
-    int emit_np = 0, emit_blocks = 0, emit_task = -1;
+    int emit_np = 0, emit_task = -1;
     unsigned long long emit_items = 0;
-    void *emit_off = nullptr, *pairs = nullptr;
+    const void *emit_items_d = nullptr;
+    void *pairs = nullptr;
     void *cand = nullptr;
     unsigned cand_cap = 0;
     ResultLayout lay{};
@@ -81,6 +83,7 @@ struct Plan {
     int n_emit = 0, emit_grid = 1, n_queues = 0;
     unsigned long long emit_total = 0;
     void *d_tasks = nullptr, *d_counters = nullptr, *d_results = nullptr, *d_layout = nullptr, *d_out = nullptr;
+    void *d_parts = nullptr;
     void *h_out = nullptr;
     unsigned long long *d_queues = nullptr, *d_thr = nullptr;
     unsigned *d_cand_count = nullptr;
@@ -102,6 +105,12 @@ struct TuneKey {
 
 struct Server;
 
+// Work-item descriptor table of one (variant, M, prefix block) shape.
+struct ItemTable {
+    void *d = nullptr;
+    unsigned long long n = 0;
+};
+
 struct Ctx {
     int device = 0, n_cu = 1, bstride = 0;
     std::string arch;
@@ -117,6 +126,8 @@ struct Ctx {
     std::map<TuneKey, int> tuned;
     std::string tune_path;
     std::map<int, std::shared_ptr<Server>> servers;
+    std::mutex items_mu;
+    std::map<std::tuple<int, int, int>, ItemTable> item_tables;
 };
 
 Ctx *as_ctx(epi_ctx *c);

@@ -89,6 +89,13 @@ def lib():
     """The loaded library (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # torch bundles its own HIP runtime (same SONAME as the system one);
+        # loading it first makes this library bind to that single runtime so
+        # torch tensors, streams and this library share one device context.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2201_02460_amd.build`")
         L = ctypes.CDLL(LIB_PATH)

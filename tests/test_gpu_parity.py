@@ -70,7 +70,7 @@ def test_small_random_vs_oracle(cx, orc, case):
 
 @pytest.mark.parametrize("order", [2, 3, 4, 5])
 def test_planted_vs_oracle(cx, orc, order):
-    M = {2: 150, 3: 90, 4: 34, 5: 20}[order]
+    M = {2: 150, 3: 90, 4: 34, 5: 40}[order]
     planted = tuple(range(3, 3 + 7 * order, 7))
     G, y, info = make_case_control(M, 600, 240, planted, seed=40 + order)
     say("planted", order, planted, info["h2"])
