@@ -41,6 +41,8 @@ struct DsView {
     const v4u *masks;
     const uint32_t *single;
     const long long *tlog;
+    const float *ftab;     // float(n ln n), n = 0 .. N (screening table)
+    float ferr;            // bound on the float screening sum error
     int32_t M, Mp, N, shift;
     int32_t ncls[2];
     int32_t w4[2];

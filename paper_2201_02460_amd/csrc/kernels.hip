@@ -13,9 +13,10 @@
 // Counting.  The paper intersects genotype rows with AND and counts bits.  A
 // cell of a combination's table is popcount(AND of one row per SNP).  Here a
 // lane counts the cells of one combination; the rows of SNPs shared by every
-// lane of the wave (the prefix of Algorithm 1) are read with scalar loads, so
-// each cell of each 32-individual word costs one v_bitop3_b32 (three-input
-// AND) and one v_bcnt_u32_b32 (popcount + accumulate).
+// lane of the wave (the prefix of Algorithm 1) are staged once per work item
+// in the wave's LDS slot and read back with broadcast loads, so each cell of
+// each 32-individual word costs one v_bitop3_b32 (three-input AND) and one
+// v_bcnt_u32_b32 (popcount + accumulate).
 //
 // Reduced cells (kF2, kF3).  Only cells whose genotypes are all 0 or 1 are
 // counted.  Every other cell follows exactly by inclusion-exclusion from
@@ -60,6 +61,16 @@ EPI_DEV unsigned long long readlane64(unsigned long long v, int lane) {
     unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, lane);
     unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), lane);
     return ((unsigned long long)hi << 32) | lo;
+}
+
+EPI_DEV int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
+// Orders this wave's LDS accesses (lane-0 writes before all-lane reads) without
+// a workgroup barrier: the waves of a workgroup run independently.
+EPI_DEV void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 EPI_DEV unsigned lane_prefix(unsigned long long mask) {
@@ -128,7 +139,7 @@ struct TopK {
 };
 
 EPI_DEV void tk_recompute(TopK &t, const Cand *list) {
-    const int lane = threadIdx.x;
+    const int lane = lane_id();
     long long bn = 0;
     unsigned long long bk = 0;
     int bi = -1;
@@ -164,15 +175,15 @@ EPI_DEV void tk_offer(TopK &t, Cand *list, bool valid, long long num, unsigned l
         const long long cn = (long long)readlane64((unsigned long long)num, src);
         const unsigned long long ck = readlane64(key, src);
         if (t.n < t.K) {
-            if (threadIdx.x == 0) list[t.n] = Cand{cn, ck};
+            if (lane_id() == 0) list[t.n] = Cand{cn, ck};
             t.n++;
             if (t.n == t.K) {
-                __syncthreads();
+                wave_sync();
                 tk_recompute(t, list);
             }
         } else if (better(cn, ck, t.wn, t.wk)) {
-            if (threadIdx.x == 0) list[t.wi] = Cand{cn, ck};
-            __syncthreads();
+            if (lane_id() == 0) list[t.wi] = Cand{cn, ck};
+            wave_sync();
             tk_recompute(t, list);
         }
         mask &= mask - 1;
@@ -183,10 +194,10 @@ EPI_DEV void tk_offer(TopK &t, Cand *list, bool valid, long long num, unsigned l
 // Append the list's entries that can still be in the final best K to the
 // task's candidate buffer, then empty the list.
 EPI_DEV void tk_flush(TopK &t, const Cand *list, const Task &task) {
-    __syncthreads();
+    wave_sync();
     const long long g = load_thr(task.thr);
     for (int base = 0; base < t.n; base += kWave) {
-        const int i = base + (int)threadIdx.x;
+        const int i = base + lane_id();
         Cand c{0, 0};
         bool keep = false;
         if (i < t.n) {
@@ -196,12 +207,12 @@ EPI_DEV void tk_flush(TopK &t, const Cand *list, const Task &task) {
         unsigned long long m = __ballot(keep);
         unsigned cnt = (unsigned)__popcll(m);
         unsigned off = 0;
-        if (threadIdx.x == 0 && cnt) off = atomicAdd(task.cand_count, cnt);
+        if (lane_id() == 0 && cnt) off = atomicAdd(task.cand_count, cnt);
         off = __builtin_amdgcn_readfirstlane(off);
         unsigned pos = off + lane_prefix(m);
         if (keep && pos < task.cand_cap) task.cand[pos] = c;
     }
-    __syncthreads();
+    wave_sync();
     t.n = 0;
 }
 
@@ -224,17 +235,70 @@ EPI_DEV long long cell_term_counted(const long long *T, unsigned n0, unsigned n1
 }
 
 // ---------------------------------------------------------------------------
+// Score screening.  A combination can only enter a wave's best-K list if its
+// score reaches te (the task's global bound, or the list's current worst once
+// the list is full).  A float sum of the same cell terms from the float table
+// (the workgroup's LDS copy, reloaded when a chunk of work starts a dataset
+// whose table fits) differs from the exact score by at most ds.ferr,
+// so combinations whose float sum is below the bound minus that margin skip
+// the exact int64 sum; the exact path is unchanged.  Datasets whose table is
+// not in LDS take the exact path for every combination.
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) const float lfloat;
+typedef __attribute__((address_space(3))) v4u lv4u;
+
+// Stage the genotype-0/1 rows of `nsnp` wave-uniform SNPs (snp_of(r) for row
+// pair r) over words [w0, w0 + wn) of class c into the wave's LDS slot:
+// slot[(2 * r + g) * cw + w].  One coalesced pass by all lanes; the counting
+// loop then reads them with broadcast LDS loads instead of scalar loads.
+template <class SnpOf>
+EPI_DEV void stage_rows(lv4u *slot, gv4u *gm, long long Mp, int wbase, int w0, int wn, int cw, int nsnp,
+                        SnpOf snp_of) {
+    wave_sync();
+    const int n = 2 * nsnp * wn;
+    for (int e = lane_id(); e < n; e += kWave) {
+        const int r2 = e / wn;
+        const int w = e - r2 * wn;
+        const int r = r2 >> 1, g = r2 & 1;
+        slot[r2 * cw + w] = gm[((long long)(wbase + w0 + w) * 2 + g) * Mp + snp_of(r)];
+    }
+    wave_sync();
+}
+
+template <int CELLS>
+EPI_DEV float screen_sum(const float *tab, const int (&F0)[CELLS], const int (&F1)[CELLS]) {
+    // LDS reads cannot fault; the counts of valid lanes are always in range
+    lfloat *l = (lfloat *)tab;
+    float s = 0.f;
+    #pragma unroll
+    for (int x = 0; x < CELLS; ++x) s += (l[F0[x]] + l[F1[x]]) - l[F0[x] + F1[x]];
+    return s;
+}
+
+// Float bound below which a combination cannot reach `te` (num units).
+EPI_DEV float screen_bound(long long te, long long score_const, int shift, float ferr) {
+    if (te == (long long)0x8000000000000000ull) return -__builtin_inff();
+    const double v = ldexp((double)(te - score_const), -shift);
+    return (float)v - 2.0f * ferr - 1e-3f;
+}
+
+EPI_DEV long long entry_bound(const TopK &tk, long long gthr) {
+    return tk.n < tk.K ? gthr : (tk.wn > gthr ? tk.wn : gthr);
+}
+
+// ---------------------------------------------------------------------------
 // kF2 / kF2Emit: order 2.  A work item is (block of NP SNPs i, block of 64
 // SNPs m > i); lane = m.  Reduced cells (a, d) in {0,1}^2 per class.
 // ---------------------------------------------------------------------------
-template <int NP, bool EMIT>
-EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr) {
+template <int NP, bool EMIT, bool LDS>
+EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr,
+                     const float *tab, v4u *stage, int stage_cap) {
     const DsView d = t.ds;
     const unsigned long long dsc = t.items[local];
     const int ib = uni((int)((dsc >> 20) & 0xfffffu));
     const int mb = uni((int)(dsc & 0xfffffu));
     const int i0 = ib * NP;
-    const int lane = threadIdx.x;
+    const int lane = lane_id();
     const int m = i0 + 1 + mb * kWave + lane;
     const bool mv = m < d.M;
     const int m_ld = mv ? m : d.Mp - 1;
@@ -242,7 +306,6 @@ EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *li
     #pragma unroll
     for (int p = 0; p < NP; ++p) ip[p] = uni(min(i0 + p, d.M - 1));
 
-    cv4u *cm = (cv4u *)d.masks;
     gv4u *gm = (gv4u *)d.masks;
     unsigned acc[NP][2][4];
     #pragma unroll
@@ -253,23 +316,28 @@ EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *li
             for (int e = 0; e < 4; ++e) acc[p][c][e] = 0;
 
     const long long Mp = d.Mp;
+    lv4u *slot = (lv4u *)stage;
+    const int cw = stage_cap / (2 * NP);  // words (x4) per staged chunk
     #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const int W = d.w4[c];
         long long off = (long long)d.wbase[c] * 2 * Mp;
         v4u m0n = gm[off + m_ld];
         v4u m1n = gm[off + Mp + m_ld];
-        for (int w = 0; w < W; ++w, off += 2 * Mp) {
+        for (int w0 = 0; w0 < W; w0 += cw) {
+            const int wn = min(cw, W - w0);
+            stage_rows(slot, gm, Mp, d.wbase[c], w0, wn, cw, NP, [&](int r) { return min(i0 + r, d.M - 1); });
+        for (int w = 0; w < wn; ++w, off += 2 * Mp) {
             const v4u m0 = m0n;
             const v4u m1 = m1n;
             // next iteration's lane rows (the last iteration re-reads its own)
-            const long long offn = w + 1 < W ? off + 2 * Mp : off;
+            const long long offn = w0 + w + 1 < W ? off + 2 * Mp : off;
             m0n = gm[offn + m_ld];
             m1n = gm[offn + Mp + m_ld];
             #pragma unroll
             for (int p = 0; p < NP; ++p) {
-                const v4u a0 = cm[off + ip[p]];
-                const v4u a1 = cm[off + Mp + ip[p]];
+                const v4u a0 = slot[(2 * p + 0) * cw + w];
+                const v4u a1 = slot[(2 * p + 1) * cw + w];
                 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     acc[p][c][0] = bcnt_acc(a0[q] & m0[q], acc[p][c][0]);
@@ -279,6 +347,7 @@ EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *li
                 }
             }
         }
+        }
     }
 
     const v4u *single4 = (const v4u *)d.single;
@@ -287,7 +356,7 @@ EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *li
     for (int p = 0; p < NP; ++p) {
         const int i = i0 + p;
         const bool valid = mv && i < m && i <= d.M - 2;
-        if (EMIT) {
+        if constexpr (EMIT) {
             if (valid) {
                 v4u *pv = (v4u *)t.pairs;
                 const unsigned long long r = lexpair(i, m, d.M);
@@ -310,11 +379,18 @@ EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *li
                 F[c][8] = d.ncls[c];
                 mobius2(F[c]);
             }
-            long long num = t.score_const;
-            #pragma unroll
-            for (int x = 0; x < 9; ++x) num += cell_term(d.tlog, F[0][x], F[1][x], (unsigned)d.N);
-            const unsigned long long key = ((unsigned long long)i << 32) | (unsigned long long)m;
-            tk_offer(tk, list, valid, num, key, gthr);
+            bool pass = valid;
+            if constexpr (LDS) {
+                const float sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.ferr);
+                pass = pass && screen_sum<9>(tab, F[0], F[1]) >= sb;
+            }
+            if (__ballot(pass)) {
+                long long num = t.score_const;
+                #pragma unroll
+                for (int x = 0; x < 9; ++x) num += cell_term(d.tlog, F[0][x], F[1][x], (unsigned)d.N);
+                const unsigned long long key = ((unsigned long long)i << 32) | (unsigned long long)m;
+                tk_offer(tk, list, pass, num, key, gthr);
+            }
         }
     }
 }
@@ -324,15 +400,16 @@ EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *li
 // m > j); lane = m.  Reduced cells (a, b, d) in {0,1}^3 per class; every
 // other cell comes from the pair sub-table and the single-SNP counts.
 // ---------------------------------------------------------------------------
-template <int NP>
-EPI_DEV void item_f3(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr) {
+template <int NP, bool LDS>
+EPI_DEV void item_f3(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr,
+                     const float *tab, v4u *stage, int stage_cap) {
     const DsView d = t.ds;
     const unsigned long long dsc = t.items[local];
     const int j = uni((int)((dsc >> 40) & 0xfffffu));
     const int ib = uni((int)((dsc >> 20) & 0xfffffu));
     const int mb = uni((int)(dsc & 0xfffffu));
     const int i0 = ib * NP;
-    const int lane = threadIdx.x;
+    const int lane = lane_id();
     const int m = j + 1 + mb * kWave + lane;
     const bool mv = m < d.M;
     const int m_ld = mv ? m : d.Mp - 1;
@@ -340,7 +417,15 @@ EPI_DEV void item_f3(const Task &t, unsigned long long local, TopK &tk, Cand *li
     #pragma unroll
     for (int p = 0; p < NP; ++p) ip[p] = uni(min(i0 + p, j - 1));
 
-    cv4u *cm = (cv4u *)d.masks;
+    // sub-table rows the epilogue needs, issued before the counting loop
+    const v4u *single4 = (const v4u *)d.single;
+    const v4u *pair4 = (const v4u *)t.pairs;
+    const v4u sm = single4[m_ld];
+    const unsigned long long rjm = mv ? lexpair(j, m, d.M) : 0ull;
+    const v4u pjm0 = pair4[2 * rjm], pjm1 = pair4[2 * rjm + 1];
+    unsigned long long rim = (mv && i0 < j) ? lexpair(i0, m, d.M) : 0ull;
+    v4u pim_n0 = pair4[2 * rim], pim_n1 = pair4[2 * rim + 1];
+
     gv4u *gm = (gv4u *)d.masks;
     unsigned acc[NP][2][8];
     #pragma unroll
@@ -351,25 +436,32 @@ EPI_DEV void item_f3(const Task &t, unsigned long long local, TopK &tk, Cand *li
             for (int e = 0; e < 8; ++e) acc[p][c][e] = 0;
 
     const long long Mp = d.Mp;
+    lv4u *slot = (lv4u *)stage;
+    const int cw = stage_cap / (2 * (NP + 1));  // words (x4) per staged chunk
     #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const int W = d.w4[c];
         long long off = (long long)d.wbase[c] * 2 * Mp;
         v4u m0n = gm[off + m_ld];
         v4u m1n = gm[off + Mp + m_ld];
-        for (int w = 0; w < W; ++w, off += 2 * Mp) {
+        for (int w0 = 0; w0 < W; w0 += cw) {
+            const int wn = min(cw, W - w0);
+            // row pair 0 = j, row pair 1 + p = i0 + p
+            stage_rows(slot, gm, Mp, d.wbase[c], w0, wn, cw, NP + 1,
+                       [&](int r) { return r == 0 ? j : min(i0 + r - 1, j - 1); });
+        for (int w = 0; w < wn; ++w, off += 2 * Mp) {
             const v4u m0 = m0n;
             const v4u m1 = m1n;
             // next iteration's lane rows (the last iteration re-reads its own)
-            const long long offn = w + 1 < W ? off + 2 * Mp : off;
+            const long long offn = w0 + w + 1 < W ? off + 2 * Mp : off;
             m0n = gm[offn + m_ld];
             m1n = gm[offn + Mp + m_ld];
-            const v4u b0 = cm[off + j];
-            const v4u b1 = cm[off + Mp + j];
+            const v4u b0 = slot[0 * cw + w];
+            const v4u b1 = slot[1 * cw + w];
             #pragma unroll
             for (int p = 0; p < NP; ++p) {
-                const v4u a0 = cm[off + ip[p]];
-                const v4u a1 = cm[off + Mp + ip[p]];
+                const v4u a0 = slot[(2 * p + 2) * cw + w];
+                const v4u a1 = slot[(2 * p + 3) * cw + w];
                 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     acc[p][c][0] = bcnt_acc(a0[q] & b0[q] & m0[q], acc[p][c][0]);
@@ -383,26 +475,29 @@ EPI_DEV void item_f3(const Task &t, unsigned long long local, TopK &tk, Cand *li
                 }
             }
         }
+        }
     }
 
-    const v4u *single4 = (const v4u *)d.single;
-    const v4u *pair4 = (const v4u *)t.pairs;
-    const v4u sm = single4[m_ld];
     const v4u sj = single4[j];
-    const unsigned long long rjm = mv ? lexpair(j, m, d.M) : 0ull;
-    const v4u pjm[2] = {pair4[2 * rjm], pair4[2 * rjm + 1]};
     #pragma unroll
     for (int p = 0; p < NP; ++p) {
         const int i = i0 + p;
         const bool valid = mv && i < j;
+        const v4u pim0 = pim_n0, pim1 = pim_n1;
+        if (p + 1 < NP) {
+            // next prefix's pair row, in flight while this one is scored
+            rim = (mv && i + 1 < j) ? lexpair(i + 1, m, d.M) : 0ull;
+            pim_n0 = pair4[2 * rim];
+            pim_n1 = pair4[2 * rim + 1];
+        }
         const v4u si = single4[ip[p]];
         const unsigned long long rij = lexpair(ip[p], j, d.M);
-        const unsigned long long rim = valid ? lexpair(i, m, d.M) : 0ull;
         int F[2][27];
         #pragma unroll
         for (int c = 0; c < 2; ++c) {
             const v4u pij = pair4[2 * rij + c];
-            const v4u pim = pair4[2 * rim + c];
+            const v4u pim = c == 0 ? pim0 : pim1;
+            const v4u pjm = c == 0 ? pjm0 : pjm1;
             // F[a*9 + b*3 + e]; index 2 on an axis = marginal over that SNP
             #pragma unroll
             for (int a = 0; a < 2; ++a)
@@ -421,7 +516,7 @@ EPI_DEV void item_f3(const Task &t, unsigned long long local, TopK &tk, Cand *li
             #pragma unroll
             for (int b = 0; b < 2; ++b)
                 #pragma unroll
-                for (int e = 0; e < 2; ++e) F[c][18 + 3 * b + e] = pjm[c][2 * b + e];
+                for (int e = 0; e < 2; ++e) F[c][18 + 3 * b + e] = pjm[2 * b + e];
             F[c][9 * 0 + 8] = si[2 * c + 0];
             F[c][9 * 1 + 8] = si[2 * c + 1];
             F[c][18 + 2] = sj[2 * c + 0];
@@ -431,12 +526,19 @@ EPI_DEV void item_f3(const Task &t, unsigned long long local, TopK &tk, Cand *li
             F[c][26] = d.ncls[c];
             mobius3(F[c]);
         }
-        long long num = t.score_const;
-        #pragma unroll
-        for (int x = 0; x < 27; ++x) num += cell_term(d.tlog, F[0][x], F[1][x], (unsigned)d.N);
-        const unsigned long long key =
-            ((unsigned long long)i << 42) | ((unsigned long long)j << 21) | (unsigned long long)m;
-        tk_offer(tk, list, valid, num, key, gthr);
+        bool pass = valid;
+        if constexpr (LDS) {
+            const float sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.ferr);
+            pass = pass && screen_sum<27>(tab, F[0], F[1]) >= sb;
+        }
+        if (__ballot(pass)) {
+            long long num = t.score_const;
+            #pragma unroll
+            for (int x = 0; x < 27; ++x) num += cell_term(d.tlog, F[0][x], F[1][x], (unsigned)d.N);
+            const unsigned long long key =
+                ((unsigned long long)i << 42) | ((unsigned long long)j << 21) | (unsigned long long)m;
+            tk_offer(tk, list, pass, num, key, gthr);
+        }
     }
 }
 
@@ -544,7 +646,7 @@ EPI_DEV void item_generic(const Task &t, unsigned long long local, TopK &tk, Can
     const DsView d = t.ds;
     const int bits = t.key_bits;
     for (int rr = 0; rr < kGenRanks; ++rr) {
-        unsigned long long rank = (local * kGenRanks + rr) * kWave + threadIdx.x;
+        unsigned long long rank = (local * kGenRanks + rr) * kWave + lane_id();
         const bool valid = rank < t.n_combos;
         rank = valid ? rank : 0ull;
         int c[K];
@@ -567,16 +669,23 @@ EPI_DEV void item_generic(const Task &t, unsigned long long local, TopK &tk, Can
 // floor.
 template <int NP2, int NP3, int GK>
 constexpr int scan_waves_per_eu() {
-    return GK >= 4 ? 2 : (GK == 3 ? 3 : (NP3 >= 4 ? 2 : (NP3 >= 2 ? 4 : (NP2 >= 8 ? 3 : 4))));
+    return GK >= 4 ? 2 : (GK == 3 ? 3 : (NP3 >= 8 ? 2 : (NP3 >= 4 ? 3 : (NP3 >= 2 ? 4 : (NP2 >= 8 ? 3 : 4)))));
 }
 
 template <int NP2, int NP3, int GK>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<NP2, NP3, GK>())))
-scan_persistent(const Task *__restrict__ tasks, int n_tasks,
-                                                      unsigned long long total_items,
-                                                      unsigned long long *__restrict__ queue,
-                                                      const unsigned long long *__restrict__ binom, int bstride) {
-    __shared__ Cand s_list[kMaxTopK];
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<NP2, NP3, GK>())))
+scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long total_items,
+                unsigned long long *__restrict__ queue, const unsigned long long *__restrict__ binom, int bstride,
+                int tab_cap, int kmax, int stage_cap) {
+    // dynamic LDS: [tab_cap floats: screening table of the current dataset]
+    //              [4 x kmax best-K lists][4 x stage_cap uint4: staged prefix rows]
+    extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
+    __shared__ unsigned long long s_chunk[2];
+    float *s_tab = (float *)s_dyn;
+    const int wave = uni((int)(threadIdx.x >> 6));  // wave index in the workgroup (uniform per wave)
+    Cand *s_list = (Cand *)(s_dyn + (((long long)tab_cap * 4 + 15) & ~15LL)) + wave * kmax;
+    v4u *s_stage = (v4u *)(s_dyn + (((long long)tab_cap * 4 + 15) & ~15LL) + (long long)4 * kmax * sizeof(Cand)) +
+                   wave * stage_cap;
     TopK tk;
     tk.n = 0;
     tk.K = 1;
@@ -585,47 +694,96 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks,
     tk.wk = 0;
     int cur = -1;
     long long gthr = (long long)0x8000000000000000ull;
+    const float *loaded = nullptr;  // dataset whose screening table is in s_tab
+    // Guided self-scheduling, one queue atomic per chunk of 4 x `per` items for
+    // the whole workgroup; the chunk shrinks with the remaining work (estimated
+    // from the last chunk).  Wave w takes items first + w, first + w + 4, ...
+    const unsigned long long n_waves = (unsigned long long)gridDim.x * 4;
+    unsigned long long est = 0;
+    #pragma unroll 1
     for (;;) {
-        unsigned long long item = 0;
-        if (threadIdx.x == 0) item = atomicAdd(queue, 1ull);
-        item = rfl64(item);
-        if (item >= total_items) break;
-        int lo = 0, hi = n_tasks - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (tasks[mid].item_base <= item) lo = mid; else hi = mid - 1;
+        if (threadIdx.x == 0) {
+            unsigned long long per = (total_items - min(est, total_items)) / (2 * n_waves);
+            per = per < 1 ? 1 : (per > 32 ? 32 : per);
+            s_chunk[0] = atomicAdd(queue, 4 * per);
+            s_chunk[1] = per;
         }
-        if (lo != cur) {
-            if (cur >= 0 && tasks[cur].variant != kF2Emit) tk_flush(tk, s_list, tasks[cur]);
-            cur = lo;
-            tk.n = 0;
-            tk.K = tasks[cur].top_k;
-            gthr = (long long)0x8000000000000000ull;
+        __syncthreads();
+        // values read back from LDS are wave-uniform: keep them in SGPRs
+        const unsigned long long first = rfl64(s_chunk[0]), per = rfl64(s_chunk[1]);
+        __syncthreads();
+        if (first >= total_items) break;
+        const unsigned long long end = min(first + 4 * per, total_items);
+        est = end;
+        // the chunk's dataset takes the LDS screening table if it fits
+        {
+            int lo = 0, hi = n_tasks - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (tasks[mid].item_base <= first) lo = mid; else hi = mid - 1;
+            }
+            const Task &T0 = tasks[lo];
+            const bool want = (T0.variant == kF2 || T0.variant == kF3) && T0.ds.N + 1 <= tab_cap;
+            if (want && loaded != T0.ds.ftab) {
+                #pragma unroll 1
+                for (int x = threadIdx.x; x <= T0.ds.N; x += blockDim.x) s_tab[x] = T0.ds.ftab[x];
+                __syncthreads();
+                loaded = T0.ds.ftab;
+            }
         }
-        const Task &T = tasks[cur];
-        const unsigned long long local = item - T.item_base;
-        if (T.variant != kF2Emit) {
-            long long g = 0;
-            if (threadIdx.x == 0) g = load_thr(T.thr);
-            g = (long long)rfl64((unsigned long long)g);
-            gthr = g > gthr ? g : gthr;
+        bool fresh = true;
+        #pragma unroll 1
+        for (unsigned long long item = first + wave; item < end; item += 4) {
+            int lo = 0, hi = n_tasks - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (tasks[mid].item_base <= item) lo = mid; else hi = mid - 1;
+            }
+            if (lo != cur) {
+                if (cur >= 0 && tasks[cur].variant != kF2Emit) {
+                    if (tk.n == tk.K && tk.wn > gthr && lane_id() == 0) atomicMax(tasks[cur].thr, bias(tk.wn));
+                    tk_flush(tk, s_list, tasks[cur]);
+                }
+                cur = lo;
+                tk.n = 0;
+                tk.K = tasks[cur].top_k;
+                gthr = (long long)0x8000000000000000ull;
+                fresh = true;
+            }
+            const Task &T = tasks[cur];
+            if (fresh && T.variant != kF2Emit) {
+                long long g = 0;
+                if (lane_id() == 0) g = load_thr(T.thr);
+                g = (long long)rfl64((unsigned long long)g);
+                gthr = g > gthr ? g : gthr;
+                fresh = false;
+            }
+            const unsigned long long local = item - T.item_base;
+            const bool lds = loaded != nullptr && T.ds.ftab == loaded;
+            switch (T.variant) {
+            case kF2:
+                if constexpr (NP2 > 0) {
+                    if (lds) item_f2<NP2, false, true>(T, local, tk, s_list, gthr, s_tab, s_stage, stage_cap);
+                    else item_f2<NP2, false, false>(T, local, tk, s_list, gthr, T.ds.ftab, s_stage, stage_cap);
+                }
+                break;
+            case kF2Emit:
+                if constexpr (NP2 > 0)
+                    item_f2<NP2, true, false>(T, local, tk, s_list, gthr, T.ds.ftab, s_stage, stage_cap);
+                break;
+            case kF3:
+                if constexpr (NP3 > 0) {
+                    if (lds) item_f3<NP3, true>(T, local, tk, s_list, gthr, s_tab, s_stage, stage_cap);
+                    else item_f3<NP3, false>(T, local, tk, s_list, gthr, T.ds.ftab, s_stage, stage_cap);
+                }
+                break;
+            default:
+                if constexpr (GK > 0) item_generic<GK>(T, local, tk, s_list, gthr, binom, bstride);
+                break;
+            }
         }
-        switch (T.variant) {
-        case kF2:
-            if constexpr (NP2 > 0) item_f2<NP2, false>(T, local, tk, s_list, gthr);
-            break;
-        case kF2Emit:
-            if constexpr (NP2 > 0) item_f2<NP2, true>(T, local, tk, s_list, gthr);
-            break;
-        case kF3:
-            if constexpr (NP3 > 0) item_f3<NP3>(T, local, tk, s_list, gthr);
-            break;
-        default:
-            if constexpr (GK > 0) item_generic<GK>(T, local, tk, s_list, gthr, binom, bstride);
-            break;
-        }
-        if (T.variant != kF2Emit && tk.n == tk.K && tk.wn > gthr) {
-            if (threadIdx.x == 0) atomicMax(T.thr, bias(tk.wn));
+        if (cur >= 0 && tasks[cur].variant != kF2Emit && tk.n == tk.K && tk.wn > gthr) {
+            if (lane_id() == 0) atomicMax(tasks[cur].thr, bias(tk.wn));
             gthr = tk.wn;
         }
     }
@@ -933,7 +1091,7 @@ __global__ void init_counters_kernel(unsigned long long *queues, int nq, unsigne
 // Host-side launchers (called by the runtime).
 // ---------------------------------------------------------------------------
 typedef void (*ScanKernelFn)(const Task *, int, unsigned long long, unsigned long long *, const unsigned long long *,
-                             int);
+                             int, int, int, int);
 
 struct ScanKernelEntry {
     int np2, np3, gk;
@@ -950,25 +1108,27 @@ static const ScanKernelEntry kScanKernels[] = {
 };
 #undef EPI_K
 
+size_t scan_lds_bytes(int tab_cap, int kmax, int stage_cap) {
+    return (((size_t)tab_cap * 4 + 15) & ~(size_t)15) + (size_t)4 * kmax * sizeof(Cand) +
+           (size_t)4 * stage_cap * sizeof(v4u);
+}
+
 ScanKernelFn find_scan_kernel(int np2, int np3, int gk) {
     for (const auto &e : kScanKernels)
         if (e.np2 == np2 && e.np3 == np3 && e.gk == gk) return e.fn;
     return nullptr;
 }
 
+// grid = number of 4-wave workgroups
 hipError_t launch_scan(int np2, int np3, int gk, int grid, hipStream_t st, const Task *tasks, int n_tasks,
                        unsigned long long total_items, unsigned long long *queue, const unsigned long long *binom,
-                       int bstride) {
+                       int bstride, int tab_cap, int kmax, int stage_cap) {
     ScanKernelFn fn = find_scan_kernel(np2, np3, gk);
     if (!fn) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(kWave), 0, st, tasks, n_tasks, total_items, queue, binom, bstride);
+    const size_t lds = scan_lds_bytes(tab_cap, kmax, stage_cap);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(4 * kWave), lds, st, tasks, n_tasks, total_items, queue, binom, bstride,
+                       tab_cap, kmax, stage_cap);
     return hipGetLastError();
-}
-
-hipError_t scan_occupancy(int np2, int np3, int gk, int *blocks_per_cu) {
-    ScanKernelFn fn = find_scan_kernel(np2, np3, gk);
-    if (!fn) return hipErrorInvalidValue;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kWave, 0);
 }
 
 hipError_t launch_merge(int n_tasks, hipStream_t st, const Task *tasks, Cand *parts, Cand *results) {

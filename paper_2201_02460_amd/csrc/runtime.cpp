@@ -30,8 +30,8 @@ namespace epi {
 
 hipError_t launch_scan(int np2, int np3, int gk, int grid, hipStream_t st, const Task *tasks, int n_tasks,
                        unsigned long long total_items, unsigned long long *queue, const unsigned long long *binom,
-                       int bstride);
-hipError_t scan_occupancy(int np2, int np3, int gk, int *blocks_per_cu);
+                       int bstride, int tab_cap, int kmax, int stage_cap);
+size_t scan_lds_bytes(int tab_n, int kmax, int stage_cap);
 hipError_t launch_merge(int n_tasks, hipStream_t st, const Task *tasks, Cand *parts, Cand *results);
 hipError_t scan_attributes(int np2, int np3, int gk, int *vgprs, int *lds_bytes);
 hipError_t launch_finalize(int n_tasks, int max_k, hipStream_t st, const Task *tasks, const Cand *results,
@@ -168,6 +168,7 @@ int ctx_init(Ctx *c, int device, uint64_t budget) {
     HIPCHK(hipGetDeviceProperties(&prop, device));
     c->n_cu = prop.multiProcessorCount;
     c->arch = prop.gcnArchName;
+    c->arch = c->arch.substr(0, c->arch.find(':'));  // "gfx950:sramecc+:xnack-" -> "gfx950"
     size_t fr = 0, tot = 0;
     HIPCHK(hipMemGetInfo(&fr, &tot));
     c->alloc.budget = budget ? budget : (uint64_t)(0.9 * (double)fr);
@@ -209,9 +210,10 @@ static void ds_free(Ctx *c, Dataset *d) {
     c->alloc.release(d->masks);
     c->alloc.release(d->single);
     c->alloc.release(d->tlog);
+    c->alloc.release(d->ftab);
     c->alloc.release(d->idx);
     c->alloc.release(d->err);
-    d->masks = d->single = d->tlog = d->idx = d->err = nullptr;
+    d->masks = d->single = d->tlog = d->ftab = d->idx = d->err = nullptr;
 }
 
 static int ds_layout(Dataset *d, int M, int N, int n_case) {
@@ -231,6 +233,8 @@ static void ds_view(Dataset *d) {
     v.masks = (const v4u *)d->masks;
     v.single = (const uint32_t *)d->single;
     v.tlog = (const long long *)d->tlog;
+    v.ftab = (const float *)d->ftab;
+    v.ferr = d->ferr;
     v.M = d->M;
     v.Mp = d->Mp;
     v.N = d->N;
@@ -250,12 +254,21 @@ static int ds_alloc(Ctx *c, Dataset *d) {
     if ((rc = c->alloc.alloc((size_t)d->Mp * 16, &d->single))) return rc;
     if ((rc = c->alloc.alloc(((size_t)2 * d->N + 1) * 8, &d->tlog))) return rc;
     if ((rc = c->alloc.alloc((size_t)d->N * 4, &d->idx))) return rc;
+    if ((rc = c->alloc.alloc(((size_t)d->N + 1) * 4, &d->ftab))) return rc;
     if ((rc = c->alloc.alloc(256, &d->err))) return rc;
     d->bytes = mask_bytes + (size_t)d->Mp * 16 + ((size_t)2 * d->N + 1) * 8 + (size_t)d->N * 4;
     ds_view(d);
     std::vector<long long> tl;
     build_tlog(d->N, d->shift, tl);
     HIPCHK(hipMemcpy(d->tlog, tl.data(), tl.size() * 8, hipMemcpyHostToDevice));
+    // float screening table and a bound on its 27-cell sum error: each cell
+    // term costs 3 rounded table values and 2 roundings of magnitude <= N ln N,
+    // the cell sum 26 more (215 roundings in all); 256 of 2^-24 covers it.
+    std::vector<float> ft((size_t)d->N + 1, 0.f);
+    for (int n = 2; n <= d->N; ++n) ft[n] = (float)((long double)n * logl((long double)n));
+    HIPCHK(hipMemcpy(d->ftab, ft.data(), ft.size() * 4, hipMemcpyHostToDevice));
+    d->ferr = (float)(256.0 * std::ldexp(1.0, -24) * (double)d->N * std::log((double)std::max(d->N, 2)));
+    d->view.ferr = d->ferr;
     d->score_const = tl[d->N] - tl[d->n_case] - tl[d->n_ctrl];
     return EPI_OK;
 }
@@ -436,25 +449,54 @@ static void pick_group_kernel(const std::vector<int> &orders, int np3_hint, int 
     *gk = gen == 4 ? 4 : 0;
 }
 
-// Persistent grid: as many one-wave workgroups as fit on the device, from
-// the kernel's VGPR count (512 registers per SIMD lane, at most 8 waves per
-// SIMD) and LDS use (160 KiB per CU).  EPI_WAVES_PER_SIMD overrides the wave
-// count.  Extra workgroups only queue: the work queue drains either way.
-static int grid_for(Ctx *c, int np2, int np3, int gk, unsigned long long items) {
-    int vgprs = 128, lds = 4096;
-    if (scan_attributes(np2, np3, gk, &vgprs, &lds) != hipSuccess) {
+// Persistent grid, in 4-wave workgroups (one wave per SIMD each): as many as
+// fit on the device by the kernel's VGPR count (512 registers per SIMD lane,
+// at most 8 waves per SIMD) and LDS use (160 KiB per CU).
+// EPI_WAVES_PER_SIMD overrides the register-based count.  Extra workgroups
+// only queue: the work queue drains either way.
+static int grid_for(Ctx *c, int np2, int np3, int gk, unsigned long long items, int tab_cap, int kmax, int stage_cap) {
+    int vgprs = 128, lds_static = 0;
+    if (scan_attributes(np2, np3, gk, &vgprs, &lds_static) != hipSuccess) {
         (void)hipGetLastError();
         vgprs = 128;
-        lds = 4096;
+        lds_static = 0;
     }
     const int alloc = std::max(8, (vgprs + 7) / 8 * 8);
     int waves = std::min(8, 512 / alloc);
-    if (lds > 0) waves = std::min(waves, (160 * 1024 / lds) / 4);
     if (const char *e = getenv("EPI_WAVES_PER_SIMD")) waves = std::max(1, std::min(16, atoi(e)));
-    waves = std::max(1, waves);
-    long long g = (long long)waves * 4 * c->n_cu;
-    if ((unsigned long long)g > items) g = (long long)std::max<unsigned long long>(items, 1);
+    const size_t lds = scan_lds_bytes(tab_cap, kmax, stage_cap) + (size_t)lds_static;
+    const int by_lds = (int)std::max<size_t>(1, (160 * 1024) / std::max<size_t>(lds, 1));
+    const int wgs_per_cu = std::max(1, std::min(waves, by_lds));
+    long long g = (long long)wgs_per_cu * c->n_cu;
+    const long long need = (long long)((items + 3) / 4);
+    if (g > need) g = std::max(1LL, need);
     return (int)g;
+}
+
+// Per-wave LDS slot (uint4 entries) for the staged prefix rows: 2 rows per
+// prefix SNP (order 2: NP SNPs, order 3: NP + 1) times the words of one chunk
+// (at most 32 groups of 4 words).
+static int stage_cap_for(int np2, int np3, int w4_max) {
+    const int rows = std::max(np2 > 0 ? 2 * np2 : 0, np3 > 0 ? 2 * (np3 + 1) : 0);
+    if (rows == 0) return 0;
+    return rows * std::max(1, std::min(w4_max, 32));
+}
+
+// LDS capacity of a group's float screening table: the largest table among
+// its order-2/3 datasets that fits (kTabMax entries); a workgroup reloads the
+// table when a chunk of work starts another dataset.  Larger datasets take
+// the exact score path for every combination.
+static void pick_tab_cap(const Plan *p, LaunchGroup &g) {
+    g.tab_cap = 0;
+    g.kmax = 1;
+    g.stage_cap = stage_cap_for(g.np2, g.np3, 0);
+    for (int i : g.scans) {
+        const PlanScan &s = p->scans[i];
+        g.kmax = std::max(g.kmax, s.desc.top_k);
+        g.stage_cap = std::max(g.stage_cap, stage_cap_for(g.np2, g.np3, std::max(s.ds->w4[0], s.ds->w4[1])));
+        if ((s.variant == kF2 || s.variant == kF3) && s.ds->N + 1 <= Plan::kTabMax)
+            g.tab_cap = std::max(g.tab_cap, s.ds->N + 1);
+    }
 }
 
 int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool graph, Plan **out,
@@ -564,12 +606,17 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         unsigned long long tot = 0;
         for (int i : g.scans) tot += p->scans[i].n_items;
         g.total_items = tot;
-        g.grid = grid_for(c, g.np2, g.np3, g.gk, tot);
+        pick_tab_cap(p.get(), g);
+        g.grid = grid_for(c, g.np2, g.np3, g.gk, tot, g.tab_cap, g.kmax, g.stage_cap);
     }
     // emit launch shape (kernel <4,0,0>)
     unsigned long long emit_total = 0;
     for (auto &s : p->scans) emit_total += s.desc.order == 3 ? s.emit_items : 0;
-    p->emit_grid = grid_for(c, 4, 0, 0, std::max<unsigned long long>(emit_total, 1));
+    int emit_w4 = 1;
+    for (auto &s : p->scans)
+        if (s.desc.order == 3) emit_w4 = std::max(emit_w4, std::max(s.ds->w4[0], s.ds->w4[1]));
+    p->emit_stage = stage_cap_for(4, 0, emit_w4);
+    p->emit_grid = grid_for(c, 4, 0, 0, std::max<unsigned long long>(emit_total, 1), 0, 1, p->emit_stage);
     // candidate buffers and result layout
     long long out_bytes = 0;
     for (int i = 0; i < n; ++i) {
@@ -578,7 +625,9 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         for (auto &g : p->groups)
             for (int j : g.scans)
                 if (j == i) grid = g.grid;
-        s.cand_cap = (unsigned)std::min<unsigned long long>((unsigned long long)grid * s.desc.top_k + 64, 0xffffffffull);
+        // each wave of the launch flushes at most top_k entries per task
+        s.cand_cap = (unsigned)std::min<unsigned long long>((unsigned long long)grid * 4 * s.desc.top_k + 64,
+                                                            0xffffffffull);
         if ((rc = c->alloc.alloc((size_t)s.cand_cap * sizeof(Cand), &s.cand))) return cleanup(rc);
         s.lay.offset = out_bytes;
         s.lay.top_k = s.desc.top_k;
@@ -680,13 +729,14 @@ static int plan_enqueue(Ctx *c, Plan *p, hipStream_t st, bool timing, unsigned l
     if (p->persistent) {
         if (p->n_emit > 0) {
             HIPCHK(launch_scan(4, 0, 0, p->emit_grid, st, tasks + nt, p->n_emit, p->emit_total, p->d_queues + q,
-                               c->d_binom, c->bstride));
+                               c->d_binom, c->bstride, 0, 1, p->emit_stage));
         }
         ++q;
         if (timing && single) HIPCHK(hipEventRecord(p->ev[2], st));
         for (auto &g : p->groups) {
             HIPCHK(launch_scan(g.np2, g.np3, g.gk, g.grid, st, tasks + g.task_off, (int)g.scans.size(),
-                               std::min(g.total_items, item_cap), p->d_queues + q, c->d_binom, c->bstride));
+                               std::min(g.total_items, item_cap), p->d_queues + q, c->d_binom, c->bstride,
+                               g.tab_cap, g.kmax, g.stage_cap));
             ++q;
         }
         if (timing && single) HIPCHK(hipEventRecord(p->ev[3], st));
@@ -701,14 +751,15 @@ static int plan_enqueue(Ctx *c, Plan *p, hipStream_t st, bool timing, unsigned l
             PlanScan &s = p->scans[i];
             LaunchGroup &g = p->groups[i];
             if (s.desc.order == 3) {
-                const int eg = grid_for(c, 4, 0, 0, s.emit_items);
+                const int es = stage_cap_for(4, 0, std::max(s.ds->w4[0], s.ds->w4[1]));
+                const int eg = grid_for(c, 4, 0, 0, s.emit_items, 0, 1, es);
                 HIPCHK(launch_scan(4, 0, 0, eg, st, tasks + s.emit_task, 1, s.emit_items, p->d_queues + 0,
-                                   c->d_binom, c->bstride));
+                                   c->d_binom, c->bstride, 0, 1, es));
                 HIPCHK(launch_init_counters(st, p->d_queues, 1, nullptr, nullptr, 0));
             }
             if (timing && single) HIPCHK(hipEventRecord(p->ev[2], st));
             HIPCHK(launch_scan(g.np2, g.np3, g.gk, g.grid, st, tasks + i, 1, std::min(s.n_items, item_cap),
-                               p->d_queues + 1, c->d_binom, c->bstride));
+                               p->d_queues + 1, c->d_binom, c->bstride, g.tab_cap, g.kmax, g.stage_cap));
             HIPCHK(launch_init_counters(st, p->d_queues + 1, 1, nullptr, nullptr, 0));
             if (timing && single) HIPCHK(hipEventRecord(p->ev[3], st));
             HIPCHK(launch_merge(1, st, tasks + i, (Cand *)p->d_parts + (size_t)i * kMergeParts * kMaxTopK,

@@ -44,8 +44,9 @@ struct Dataset {
     int id = 0;
     int M = 0, N = 0, n_case = 0, n_ctrl = 0, Mp = 0, shift = 0;
     int w4[2] = {0, 0};
-    void *masks = nullptr, *single = nullptr, *tlog = nullptr, *idx = nullptr, *err = nullptr;
+    void *masks = nullptr, *single = nullptr, *tlog = nullptr, *ftab = nullptr, *idx = nullptr, *err = nullptr;
     long long score_const = 0;
+    float ferr = 0.f;
     uint64_t bytes = 0;
     DsView view{};
 };
@@ -68,7 +69,9 @@ struct PlanScan {
 };
 
 struct LaunchGroup {
-    int np2 = 0, np3 = 0, gk = 0, grid = 1;
+    int np2 = 0, np3 = 0, gk = 0, grid = 1;  // grid: 4-wave workgroups
+    int tab_cap = 0;                         // LDS screening-table entries (0: none)
+    int kmax = 1, stage_cap = 0;
     int task_off = 0;  // first task of the group in the plan's task array
     std::vector<int> scans;
     unsigned long long total_items = 0;
@@ -80,7 +83,8 @@ struct Plan {
     int live_scans = 0;
     std::vector<PlanScan> scans;
     std::vector<LaunchGroup> groups;
-    int n_emit = 0, emit_grid = 1, n_queues = 0;
+    int n_emit = 0, emit_grid = 1, emit_stage = 0, n_queues = 0;
+    constexpr static int kTabMax = 16385;  // screening-table entries that may go to LDS
     unsigned long long emit_total = 0;
     void *d_tasks = nullptr, *d_counters = nullptr, *d_results = nullptr, *d_layout = nullptr, *d_out = nullptr;
     void *d_parts = nullptr;
