@@ -182,6 +182,91 @@ def batched_bench(epi, torch, n_scans, reps):
     }
 
 
+def served_bench(epi, torch, n_requests, rate, seed=7):
+    """Poisson arrivals of scans on a resident dataset pool, served by the
+    continuous-batching server; latency from submission to results ready."""
+    import threading
+
+    import numpy as np
+
+    from synth import make_case_control, served_pool_specs
+
+    pool = served_pool_specs(32)
+    ctx = epi.epi_create(0)
+    t0 = time.perf_counter()
+    dss = []
+    for s in pool:
+        G, y, _ = make_case_control(s["M"], s["N"], s["n_cases"], s["planted"], s["seed"])
+        dss.append(epi.epi_load_genotypes(ctx, G, y))
+    log(f"served: pool of {len(pool)} datasets loaded in {time.perf_counter() - t0:.1f}s")
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for _ in range(n_requests):
+        d = int(rng.integers(len(pool)))
+        reqs.append((d, int(rng.choice(pool[d]["orders"]))))
+    gaps = rng.exponential(1.0 / rate, n_requests)
+    work = [math.comb(pool[d]["M"], o) * pool[d]["N"] for d, o in reqs]
+    K = 100
+    sid = epi.epi_server_start(ctx, max_active=64)
+    # warm-up: one request of each order, not counted
+    for o in (2, 3, 4):
+        w = epi.epi_server_submit(ctx, sid, dss[0], o, K)
+        while epi.epi_server_poll(ctx, sid, w) != 2:
+            time.sleep(0.001)
+        epi.epi_server_results(ctx, sid, w, K, o)
+    pending, lat, done_at = {}, [], []
+    lock = threading.Lock()
+    start = time.perf_counter()
+
+    def submit():
+        t = start
+        for (d, o), g in zip(reqs, gaps):
+            t += g
+            dt = t - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            rid = epi.epi_server_submit(ctx, sid, dss[d], o, K)
+            with lock:
+                pending[rid] = o
+
+    th = threading.Thread(target=submit)
+    th.start()
+    finished = 0
+    while finished < n_requests:
+        with lock:
+            items = list(pending.items())
+        for rid, o in items:
+            if epi.epi_server_poll(ctx, sid, rid) == 2:
+                _, _, _, ms = epi.epi_server_results(ctx, sid, rid, K, o, tables=False)
+                lat.append(ms)
+                done_at.append(time.perf_counter())
+                with lock:
+                    del pending[rid]
+                finished += 1
+        time.sleep(0.0005)
+    th.join()
+    wall = max(done_at) - start
+    stats = epi.epi_server_stats(ctx, sid)
+    epi.epi_server_stop(ctx, sid)
+    for d in dss:
+        epi.epi_unload(ctx, d)
+    epi.epi_destroy(ctx)
+    lat = np.sort(np.asarray(lat))
+    arrivals = float(np.sum(gaps))
+    return {
+        "config": {"workload": f"{n_requests} requests, Poisson {rate}/s, orders 2-4 (order 4 on M<=200), "
+                               f"M in [50,1500], N in [500,16000], pool of {len(pool)} resident datasets, top-100",
+                   "combos_x_samples": int(sum(work))},
+        "value": sum(work) / wall / 1e12,
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "offered_T": sum(work) / arrivals / 1e12,
+        "wall_s": wall,
+        "rounds": stats["rounds"],
+        "peak_active": stats["peak_active"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,6 +278,8 @@ def main():
     ap.add_argument("--batched-scans", type=int, default=64)
     ap.add_argument("--batched-reps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--served-requests", type=int, default=200)
+    ap.add_argument("--served-rate", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (HBM counter calibration)")
@@ -267,6 +354,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(spec, G, y, args.cpu_seconds)
     if not args.no_batched:
         out["batched"] = batched_bench(epi, torch, args.batched_scans, args.batched_reps)
+    if not args.no_served:
+        out["served"] = served_bench(epi, torch, args.served_requests, args.served_rate)
     print(json.dumps(out), flush=True)
 
 

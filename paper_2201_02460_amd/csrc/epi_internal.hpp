@@ -62,6 +62,7 @@ struct Task {
     const unsigned long long *items;  // per-item descriptors: kF3 j<<40 | ib<<20 | mb, kF2 ib<<20 | mb
     unsigned long long n_items;
     unsigned long long item_base;     // first global item of this task in its launch
+    unsigned long long first_item;    // task-local index of the launch's first item of this task
     unsigned long long n_combos;
     long long score_const;            // tlog[N] - tlog[n_case] - tlog[n_ctrl]
     Cand *cand;                       // candidate sink

@@ -758,7 +758,7 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
                 gthr = g > gthr ? g : gthr;
                 fresh = false;
             }
-            const unsigned long long local = item - T.item_base;
+            const unsigned long long local = item - T.item_base + T.first_item;
             const bool lds = loaded != nullptr && T.ds.ftab == loaded;
             switch (T.variant) {
             case kF2:
@@ -1076,6 +1076,18 @@ __global__ void __launch_bounds__(1024) classidx_kernel(const uint8_t *__restric
     }
 }
 
+// After a merge: the best K (results) become the first entries of each
+// task's candidate buffer, so later launches of the same task (serving
+// rounds) add to a compact list.
+__global__ void reseed_kernel(const Task *__restrict__ tasks, const Cand *__restrict__ results) {
+    const Task &t = tasks[blockIdx.x];
+    const Cand *res = results + (long long)blockIdx.x * kMaxTopK;
+    int n = 0;
+    for (int r = 0; r < t.top_k; ++r) n += res[r].key != ~0ull ? 1 : 0;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) t.cand[r] = res[r];
+    if (threadIdx.x == 0) *t.cand_count = (unsigned)n;
+}
+
 // Counters of a launch sequence: queues, candidate counts, thresholds.
 __global__ void init_counters_kernel(unsigned long long *queues, int nq, unsigned *cand_counts,
                                      unsigned long long *thrs, int n_tasks) {
@@ -1162,6 +1174,11 @@ hipError_t launch_init_counters(hipStream_t st, unsigned long long *queues, int 
     int n = nq > n_tasks ? nq : n_tasks;
     hipLaunchKernelGGL(init_counters_kernel, dim3((n + 255) / 256), dim3(256), 0, st, queues, nq, cand_counts, thrs,
                        n_tasks);
+    return hipGetLastError();
+}
+
+hipError_t launch_reseed(int n_tasks, hipStream_t st, const Task *tasks, const Cand *results) {
+    hipLaunchKernelGGL(reseed_kernel, dim3(n_tasks), dim3(64), 0, st, tasks, results);
     return hipGetLastError();
 }
 

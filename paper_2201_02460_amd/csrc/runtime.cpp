@@ -28,21 +28,6 @@
 
 namespace epi {
 
-hipError_t launch_scan(int np2, int np3, int gk, int grid, hipStream_t st, const Task *tasks, int n_tasks,
-                       unsigned long long total_items, unsigned long long *queue, const unsigned long long *binom,
-                       int bstride, int tab_cap, int kmax, int stage_cap);
-size_t scan_lds_bytes(int tab_n, int kmax, int stage_cap);
-hipError_t launch_merge(int n_tasks, hipStream_t st, const Task *tasks, Cand *parts, Cand *results);
-hipError_t scan_attributes(int np2, int np3, int gk, int *vgprs, int *lds_bytes);
-hipError_t launch_finalize(int n_tasks, int max_k, hipStream_t st, const Task *tasks, const Cand *results,
-                           const ResultLayout *layout, char *out);
-hipError_t launch_init_counters(hipStream_t st, unsigned long long *queues, int nq, unsigned *cand_counts,
-                                unsigned long long *thrs, int n_tasks);
-hipError_t launch_pack(hipStream_t st, const uint8_t *geno, long long ld, const int32_t *idx, const DsView &d,
-                       v4u *masks, int *err);
-hipError_t launch_classidx(hipStream_t st, const uint8_t *pheno, int N, int n_case, int32_t *idx, int *err);
-hipError_t launch_singles(hipStream_t st, const DsView &d, uint32_t *single);
-
 // ---------------------------------------------------------------------------
 // errors
 // ---------------------------------------------------------------------------
@@ -140,7 +125,7 @@ void DevAlloc::destroy() {
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
-static uint64_t binom_u64(int64_t n, int64_t k) {
+uint64_t binom_u64(int64_t n, int64_t k) {
     if (k < 0 || n < 0 || k > n) return 0;
     if (k > n - k) k = n - k;
     unsigned __int128 r = 1;
@@ -356,7 +341,7 @@ static void build_f3_items(int M, int np, std::vector<unsigned long long> &out) 
 }
 
 // Descriptor table of a shape, built once per context and cached.
-static int get_items(Ctx *c, int variant, int M, int np, const void **d, unsigned long long *n) {
+int get_items(Ctx *c, int variant, int M, int np, const void **d, unsigned long long *n) {
     std::lock_guard<std::mutex> g(c->items_mu);
     const auto key = std::make_tuple(variant, M, np);
     auto it = c->item_tables.find(key);
@@ -398,7 +383,7 @@ void plan_free(Ctx *c, Plan *p) {
     for (auto &e : p->ev) e = nullptr;
 }
 
-static int check_desc(Ctx *c, const epi_scan_desc &d, Dataset **out) {
+int check_desc(Ctx *c, const epi_scan_desc &d, Dataset **out) {
     auto it = c->datasets.find(d.dataset_id);
     if (it == c->datasets.end()) return fail(EPI_ENOTFOUND, "unknown dataset %d", d.dataset_id);
     Dataset *ds = it->second.get();
@@ -418,7 +403,7 @@ static int check_desc(Ctx *c, const epi_scan_desc &d, Dataset **out) {
 }
 
 // Kernel instantiation for a group of tasks in one persistent launch.
-static void pick_group_kernel(const std::vector<int> &orders, int np3_hint, int *np2, int *np3, int *gk) {
+void pick_group_kernel(const std::vector<int> &orders, int np3_hint, int *np2, int *np3, int *gk) {
     bool has2 = false, has3 = false;
     int gen = 0;
     for (int o : orders) {
@@ -454,7 +439,7 @@ static void pick_group_kernel(const std::vector<int> &orders, int np3_hint, int 
 // at most 8 waves per SIMD) and LDS use (160 KiB per CU).
 // EPI_WAVES_PER_SIMD overrides the register-based count.  Extra workgroups
 // only queue: the work queue drains either way.
-static int grid_for(Ctx *c, int np2, int np3, int gk, unsigned long long items, int tab_cap, int kmax, int stage_cap) {
+int grid_for(Ctx *c, int np2, int np3, int gk, unsigned long long items, int tab_cap, int kmax, int stage_cap) {
     int vgprs = 128, lds_static = 0;
     if (scan_attributes(np2, np3, gk, &vgprs, &lds_static) != hipSuccess) {
         (void)hipGetLastError();
@@ -475,11 +460,12 @@ static int grid_for(Ctx *c, int np2, int np3, int gk, unsigned long long items, 
 
 // Per-wave LDS slot (uint4 entries) for the staged prefix rows: 2 rows per
 // prefix SNP (order 2: NP SNPs, order 3: NP + 1) times the words of one chunk
-// (at most 32 groups of 4 words).
-static int stage_cap_for(int np2, int np3, int w4_max) {
+// (at most 16 groups of 4 words, 2048 individuals of a class, which keeps
+// three 4-wave workgroups per CU next to an 8001-entry screening table).
+int stage_cap_for(int np2, int np3, int w4_max) {
     const int rows = std::max(np2 > 0 ? 2 * np2 : 0, np3 > 0 ? 2 * (np3 + 1) : 0);
     if (rows == 0) return 0;
-    return rows * std::max(1, std::min(w4_max, 32));
+    return rows * std::max(1, std::min(w4_max, 16));
 }
 
 // LDS capacity of a group's float screening table: the largest table among

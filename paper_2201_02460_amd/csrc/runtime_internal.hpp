@@ -134,6 +134,31 @@ struct Ctx {
     std::map<std::tuple<int, int, int>, ItemTable> item_tables;
 };
 
+// kernel launchers (kernels.hip)
+hipError_t launch_scan(int np2, int np3, int gk, int grid, hipStream_t st, const Task *tasks, int n_tasks,
+                       unsigned long long total_items, unsigned long long *queue, const unsigned long long *binom,
+                       int bstride, int tab_cap, int kmax, int stage_cap);
+size_t scan_lds_bytes(int tab_cap, int kmax, int stage_cap);
+hipError_t scan_attributes(int np2, int np3, int gk, int *vgprs, int *lds_bytes);
+hipError_t launch_merge(int n_tasks, hipStream_t st, const Task *tasks, Cand *parts, Cand *results);
+hipError_t launch_finalize(int n_tasks, int max_k, hipStream_t st, const Task *tasks, const Cand *results,
+                           const ResultLayout *layout, char *out);
+hipError_t launch_init_counters(hipStream_t st, unsigned long long *queues, int nq, unsigned *cand_counts,
+                                unsigned long long *thrs, int n_tasks);
+hipError_t launch_reseed(int n_tasks, hipStream_t st, const Task *tasks, const Cand *results);
+hipError_t launch_pack(hipStream_t st, const uint8_t *geno, long long ld, const int32_t *idx, const DsView &d,
+                       v4u *masks, int *err);
+hipError_t launch_classidx(hipStream_t st, const uint8_t *pheno, int N, int n_case, int32_t *idx, int *err);
+hipError_t launch_singles(hipStream_t st, const DsView &d, uint32_t *single);
+
+// runtime helpers shared with the server
+uint64_t binom_u64(int64_t n, int64_t k);
+int get_items(Ctx *c, int variant, int M, int np, const void **d, unsigned long long *n);
+int check_desc(Ctx *c, const epi_scan_desc &d, Dataset **out);
+void pick_group_kernel(const std::vector<int> &orders, int np3_hint, int *np2, int *np3, int *gk);
+int grid_for(Ctx *c, int np2, int np3, int gk, unsigned long long items, int tab_cap, int kmax, int stage_cap);
+int stage_cap_for(int np2, int np3, int w4_max);
+
 Ctx *as_ctx(epi_ctx *c);
 int key_bits_for(int order);
 void load_tune_cache(Ctx *c);

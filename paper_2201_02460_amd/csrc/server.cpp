@@ -1,17 +1,568 @@
-// Serving loop (continuous batching): placeholder until the server lands.
+// Serving: continuous batching of scan requests on resident datasets.
+//
+// A server thread runs launch rounds.  Each round it
+//   1. admits queued requests (first come, first served) while the number of
+//      active requests and the device bytes their buffers need stay within
+//      the configured limits;
+//   2. gives every active request a slice of its remaining work items, sized
+//      so that a round is a few milliseconds of device work, and runs all the
+//      slices in one persistent launch of the scan kernel (order-3 requests
+//      run their pair sub-table pass in the round they are admitted);
+//   3. compacts each request's candidates to its best K on the device, so the
+//      next round adds to a short list;
+//   4. finishes the requests whose work is done: result tables, scores and
+//      combinations are copied to host memory and the request's device
+//      buffers return to the pool, which admits waiting requests next round.
+// Requests that arrive while rounds run join the next round, so their work
+// shares launches with older requests.  Every combination is scored by the
+// same kernel code as a plain scan, so a request's results do not depend on
+// what else was in its rounds.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+
 #include "runtime_internal.hpp"
 
 namespace epi {
-struct Server {};
-void server_shutdown_all(Ctx *c) { c->servers.clear(); }
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+    int id = 0;
+    epi_scan_desc desc{};
+    Dataset *ds = nullptr;
+    int state = 0;  // 0 queued, 1 admitted, 2 done, 3 failed
+    int rc = EPI_OK;
+    std::string err;
+    Clock::time_point t_submit, t_done;
+    int variant = 0, np = 0, slot = -1;
+    const void *items = nullptr, *emit_items = nullptr;
+    unsigned long long n_items = 0, cursor = 0, emit_n = 0, n_combos = 0;
+    bool emit_done = false;
+    void *pairs = nullptr, *cand = nullptr;
+    unsigned cand_cap = 0;
+    uint64_t footprint = 0;
+    std::vector<char> out;  // result block copied from the device
+};
+
+struct Server {
+    Ctx *ctx = nullptr;
+    int id = 0;
+    epi_server_config cfg{};
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    std::thread thread;
+    std::mutex mu;
+    std::condition_variable cv;
+    bool stopping = false;
+    std::deque<std::shared_ptr<Request>> queue;
+    std::map<int, std::shared_ptr<Request>> all;
+    std::vector<std::shared_ptr<Request>> active;
+    std::vector<int> free_slots;
+    int next_req = 1;
+    uint64_t budget = 0, used = 0;
+    int grid_max = 1;
+    // device state: per-slot counters, per-round scratch
+    void *d_counters = nullptr, *d_tasks = nullptr, *d_results = nullptr, *d_parts = nullptr, *d_layout = nullptr,
+         *d_out = nullptr;
+    void *h_tasks = nullptr, *h_out = nullptr, *h_layout = nullptr;
+    unsigned long long *d_queues = nullptr, *d_thr = nullptr;
+    unsigned *d_cand_count = nullptr;
+    long long out_block = 0;
+    int max_round_tasks = 0;
+    // stats
+    uint64_t n_done = 0, rounds = 0, work_done = 0, peak_bytes = 0, peak_active = 0;
+    int fatal = EPI_OK;
+};
+
+static const double kRoundWork = 4e11;  // combos x individuals per round (a few ms)
+
+static void free_request_buffers(Server *S, Request *r) {
+    S->ctx->alloc.release(r->pairs);
+    S->ctx->alloc.release(r->cand);
+    r->pairs = r->cand = nullptr;
+    if (r->slot >= 0) S->free_slots.push_back(r->slot);
+    r->slot = -1;
+    S->used -= r->footprint;
+}
+
+static void fail_request(Server *S, Request *r, int rc, const char *msg) {
+    r->rc = rc;
+    r->err = msg;
+    r->state = 3;
+    r->t_done = Clock::now();
+    free_request_buffers(S, r);
+}
+
+// Footprint and buffers of a request being admitted.
+static int admit(Server *S, Request *r) {
+    Ctx *c = S->ctx;
+    const int o = r->desc.order;
+    r->n_combos = binom_u64(r->ds->M, o);
+    if (o == 2) {
+        r->variant = kF2;
+        r->np = 4;
+    } else if (o == 3) {
+        r->variant = kF3;
+        r->np = 4;
+    } else {
+        r->variant = kGeneric;
+        r->np = kGenRanksHost;
+        r->n_items = (r->n_combos + 64ull * kGenRanksHost - 1) / (64ull * kGenRanksHost);
+    }
+    int rc;
+    if (r->variant != kGeneric && (rc = get_items(c, r->variant, r->ds->M, r->np, &r->items, &r->n_items))) return rc;
+    if (o == 3 && (rc = get_items(c, kF2, r->ds->M, 4, &r->emit_items, &r->emit_n))) return rc;
+    r->cand_cap = (unsigned)((unsigned long long)S->grid_max * 4 * r->desc.top_k + r->desc.top_k + 64);
+    const uint64_t pair_bytes = o == 3 ? binom_u64(r->ds->M, 2) * 32 : 0;
+    r->footprint = pair_bytes + (uint64_t)r->cand_cap * sizeof(Cand);
+    if (S->used + r->footprint > S->budget) return EPI_ENOMEM;
+    if (pair_bytes && (rc = c->alloc.alloc(pair_bytes, &r->pairs))) return rc;
+    if ((rc = c->alloc.alloc((size_t)r->cand_cap * sizeof(Cand), &r->cand))) {
+        c->alloc.release(r->pairs);
+        r->pairs = nullptr;
+        return rc;
+    }
+    S->used += r->footprint;
+    S->peak_bytes = std::max<uint64_t>(S->peak_bytes, S->used);
+    r->slot = S->free_slots.back();
+    S->free_slots.pop_back();
+    r->state = 1;
+    return EPI_OK;
+}
+
+static Task make_task(Server *S, Request *r) {
+    Task t;
+    memset(&t, 0, sizeof t);
+    t.ds = r->ds->view;
+    t.pairs = (uint32_t *)r->pairs;
+    t.items = (const unsigned long long *)r->items;
+    t.n_items = r->n_items;
+    t.n_combos = r->n_combos;
+    t.score_const = r->ds->score_const;
+    t.cand = (Cand *)r->cand;
+    t.cand_count = S->d_cand_count + r->slot;
+    t.thr = S->d_thr + r->slot;
+    t.cand_cap = r->cand_cap;
+    t.variant = r->variant;
+    t.order = r->desc.order;
+    t.top_k = r->desc.top_k;
+    t.np = r->np;
+    t.key_bits = key_bits_for(r->desc.order);
+    return t;
+}
+
+#define SRV_HIPCHK(x)                                                        \
+    do {                                                                     \
+        hipError_t e_ = (x);                                                 \
+        if (e_ != hipSuccess) return fail(EPI_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+// One round: returns EPI_OK or a device error (which stops the server).
+static int run_round(Server *S) {
+    Ctx *c = S->ctx;
+    hipStream_t st = S->stream;
+    // newly admitted requests: zero their counters
+    for (auto &r : S->active)
+        if (!r->emit_done && r->cursor == 0) {
+            SRV_HIPCHK(launch_init_counters(st, nullptr, 0, S->d_cand_count + r->slot, S->d_thr + r->slot, 1));
+        }
+    // slices: finishing requests first (their merge results feed finalize)
+    const double share = kRoundWork / std::max<size_t>(1, S->active.size());
+    std::vector<std::pair<Request *, unsigned long long>> fin, cont;
+    for (auto &r : S->active) {
+        const unsigned long long per_item =
+            (unsigned long long)(r->variant == kGeneric ? 64 * kGenRanksHost : 64 * r->np) * r->ds->N;
+        unsigned long long n = (unsigned long long)std::max(1.0, share / (double)std::max<unsigned long long>(per_item, 1));
+        n = std::min(n, r->n_items - r->cursor);
+        (r->cursor + n >= r->n_items ? fin : cont).push_back({r.get(), n});
+    }
+    std::vector<std::pair<Request *, unsigned long long>> order = fin;
+    order.insert(order.end(), cont.begin(), cont.end());
+    const int nt = (int)order.size();
+    // task array: [main tasks][emit tasks][launch-group copies]
+    Task *ht = (Task *)S->h_tasks;
+    int ti = 0;
+    for (auto &pr : order) ht[ti++] = make_task(S, pr.first);
+    const int emit_off = ti;
+    unsigned long long emit_total = 0;
+    int emit_w4 = 1;
+    for (auto &pr : order) {
+        Request *r = pr.first;
+        if (r->desc.order != 3 || r->emit_done) continue;
+        Task t = make_task(S, r);
+        t.variant = kF2Emit;
+        t.items = (const unsigned long long *)r->emit_items;
+        t.n_items = r->emit_n;
+        t.item_base = emit_total;
+        t.np = 4;
+        t.order = 2;
+        emit_total += r->emit_n;
+        emit_w4 = std::max(emit_w4, std::max(r->ds->w4[0], r->ds->w4[1]));
+        ht[ti++] = t;
+    }
+    const int n_emit = ti - emit_off;
+    // launch groups by kernel instantiation: orders 2-4 together, order 5 apart
+    struct G {
+        int np2, np3, gk, off, n, tab_cap, kmax, stage;
+        unsigned long long total;
+    };
+    std::vector<G> groups;
+    for (int pass = 0; pass < 2; ++pass) {
+        std::vector<int> orders;
+        G g{0, 0, 0, ti, 0, 0, 1, 0, 0};
+        for (int i = 0; i < nt; ++i) {
+            Request *r = order[i].first;
+            if ((r->desc.order == 5) != (pass == 1)) continue;
+            orders.push_back(r->desc.order);
+        }
+        if (orders.empty()) continue;
+        pick_group_kernel(orders, 4, &g.np2, &g.np3, &g.gk);
+        g.stage = stage_cap_for(g.np2, g.np3, 0);
+        for (int i = 0; i < nt; ++i) {
+            Request *r = order[i].first;
+            if ((r->desc.order == 5) != (pass == 1)) continue;
+            Task t = ht[i];
+            t.item_base = g.total;
+            t.first_item = r->cursor;
+            g.total += order[i].second;
+            ht[ti++] = t;
+            g.n++;
+            g.kmax = std::max(g.kmax, r->desc.top_k);
+            g.stage = std::max(g.stage, stage_cap_for(g.np2, g.np3, std::max(r->ds->w4[0], r->ds->w4[1])));
+            if ((r->variant == kF2 || r->variant == kF3) && r->ds->N + 1 <= Plan::kTabMax)
+                g.tab_cap = std::max(g.tab_cap, r->ds->N + 1);
+        }
+        groups.push_back(g);
+    }
+    if (ti > S->max_round_tasks) return fail(EPI_EDEVICE, "server round task array overflow");
+    SRV_HIPCHK(hipMemcpyAsync(S->d_tasks, ht, (size_t)ti * sizeof(Task), hipMemcpyHostToDevice, st));
+    const Task *dt = (const Task *)S->d_tasks;
+    const int nq = 1 + (int)groups.size();
+    SRV_HIPCHK(launch_init_counters(st, S->d_queues, nq, nullptr, nullptr, 0));
+    if (n_emit > 0) {
+        const int es = stage_cap_for(4, 0, emit_w4);
+        const int eg = grid_for(c, 4, 0, 0, emit_total, 0, 1, es);
+        SRV_HIPCHK(launch_scan(4, 0, 0, eg, st, dt + emit_off, n_emit, emit_total, S->d_queues, c->d_binom,
+                               c->bstride, 0, 1, es));
+    }
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const G &g = groups[gi];
+        const int grid = grid_for(c, g.np2, g.np3, g.gk, g.total, g.tab_cap, g.kmax, g.stage);
+        SRV_HIPCHK(launch_scan(g.np2, g.np3, g.gk, std::min(grid, S->grid_max), st, dt + g.off, g.n, g.total,
+                               S->d_queues + 1 + gi, c->d_binom, c->bstride, g.tab_cap, g.kmax, g.stage));
+    }
+    // compact every request's candidates to its best K; finish the done ones
+    SRV_HIPCHK(launch_merge(nt, st, dt, (Cand *)S->d_parts, (Cand *)S->d_results));
+    SRV_HIPCHK(launch_reseed(nt, st, dt, (const Cand *)S->d_results));
+    if (!fin.empty()) {
+        ResultLayout *hl = (ResultLayout *)S->h_layout;
+        int maxk = 1;
+        for (size_t i = 0; i < fin.size(); ++i) {
+            Request *r = fin[i].first;
+            hl[i].offset = (long long)r->slot * S->out_block;
+            hl[i].top_k = r->desc.top_k;
+            hl[i].order = r->desc.order;
+            maxk = std::max(maxk, r->desc.top_k);
+        }
+        SRV_HIPCHK(hipMemcpyAsync(S->d_layout, hl, fin.size() * sizeof(ResultLayout), hipMemcpyHostToDevice, st));
+        SRV_HIPCHK(launch_finalize((int)fin.size(), maxk, st, dt, (const Cand *)S->d_results,
+                                   (const ResultLayout *)S->d_layout, (char *)S->d_out));
+        for (auto &pr : fin) {
+            Request *r = pr.first;
+            const long long off = (long long)r->slot * S->out_block;
+            SRV_HIPCHK(hipMemcpyAsync((char *)S->h_out + off, (char *)S->d_out + off,
+                                      (size_t)result_block_bytes(r->desc.top_k, r->desc.order), hipMemcpyDeviceToHost,
+                                      st));
+        }
+    }
+    SRV_HIPCHK(hipEventRecord(S->ev, st));
+    SRV_HIPCHK(hipEventSynchronize(S->ev));
+    // bookkeeping
+    std::lock_guard<std::mutex> g(S->mu);
+    S->rounds++;
+    for (auto &pr : order) {
+        Request *r = pr.first;
+        r->cursor += pr.second;
+        r->emit_done = true;
+        const unsigned long long per = (unsigned long long)(r->variant == kGeneric ? 64 * kGenRanksHost : 64 * r->np);
+        S->work_done += std::min<unsigned long long>(pr.second * per, r->n_combos) * (unsigned long long)r->ds->N;
+    }
+    for (auto &pr : fin) {
+        Request *r = pr.first;
+        const long long off = (long long)r->slot * S->out_block;
+        const long long bytes = result_block_bytes(r->desc.top_k, r->desc.order);
+        r->out.assign((char *)S->h_out + off, (char *)S->h_out + off + bytes);
+        r->state = 2;
+        r->t_done = Clock::now();
+        free_request_buffers(S, r);
+        S->n_done++;
+    }
+    S->active.erase(std::remove_if(S->active.begin(), S->active.end(),
+                                   [](const std::shared_ptr<Request> &r) { return r->state != 1; }),
+                    S->active.end());
+    return EPI_OK;
+}
+
+static void server_main(Server *S) {
+    (void)hipSetDevice(S->ctx->device);
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv.wait_for(lk, std::chrono::milliseconds(50),
+                           [&] { return S->stopping || !S->queue.empty() || !S->active.empty(); });
+            // admission: first come, first served, by slots and device bytes
+            while (!S->queue.empty() && (int)S->active.size() < S->cfg.max_active && !S->free_slots.empty()) {
+                auto r = S->queue.front();
+                const int rc = admit(S, r.get());
+                if (rc == EPI_ENOMEM && !S->active.empty()) break;  // wait for memory to free up
+                S->queue.pop_front();
+                if (rc != EPI_OK) {
+                    r->rc = rc;
+                    r->err = last_error();
+                    r->state = 3;
+                    r->t_done = Clock::now();
+                    continue;
+                }
+                S->active.push_back(r);
+            }
+            S->peak_active = std::max<uint64_t>(S->peak_active, S->active.size());
+            if (S->active.empty()) {
+                if (S->stopping && S->queue.empty()) return;
+                continue;
+            }
+        }
+        const int rc = run_round(S);
+        if (rc != EPI_OK) {
+            std::lock_guard<std::mutex> g(S->mu);
+            S->fatal = rc;
+            for (auto &r : S->active) fail_request(S, r.get(), rc, "device error in a serving round");
+            S->active.clear();
+            for (auto &r : S->queue) {
+                r->rc = rc;
+                r->state = 3;
+            }
+            S->queue.clear();
+            return;
+        }
+    }
+}
+
+static void server_free(Server *S) {
+    Ctx *c = S->ctx;
+    c->alloc.release(S->d_counters);
+    c->alloc.release(S->d_tasks);
+    c->alloc.release(S->d_results);
+    c->alloc.release(S->d_parts);
+    c->alloc.release(S->d_layout);
+    c->alloc.release(S->d_out);
+    if (S->h_tasks) (void)hipHostFree(S->h_tasks);
+    if (S->h_out) (void)hipHostFree(S->h_out);
+    if (S->h_layout) (void)hipHostFree(S->h_layout);
+    if (S->ev) (void)hipEventDestroy(S->ev);
+    if (S->stream) (void)hipStreamDestroy(S->stream);
+}
+
+static void server_join(Server *S) {
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        S->stopping = true;
+    }
+    S->cv.notify_all();
+    if (S->thread.joinable()) S->thread.join();
+}
+
+void server_shutdown_all(Ctx *c) {
+    for (auto &kv : c->servers) {
+        server_join(kv.second.get());
+        server_free(kv.second.get());
+    }
+    c->servers.clear();
+}
+
+static Server *server_of(Ctx *C, int32_t id) {
+    std::lock_guard<std::mutex> g(C->mu);
+    auto it = C->servers.find(id);
+    return it == C->servers.end() ? nullptr : it->second.get();
+}
+
 }  // namespace epi
 
 using namespace epi;
+
+#define CTX_OR_FAIL(ctx)                                                  \
+    if (!(ctx)) return fail(EPI_EINVAL, "null context");                  \
+    Ctx *C = as_ctx(ctx);                                                 \
+    if (hipSetDevice(C->device) != hipSuccess) return fail(EPI_EDEVICE, "hipSetDevice failed");
+
+#define HIPCHK(x)                                                                        \
+    do {                                                                                 \
+        hipError_t e_ = (x);                                                             \
+        if (e_ != hipSuccess) return fail(EPI_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
 extern "C" {
-int epi_server_start(epi_ctx *, const epi_server_config *, int32_t *) { return fail(EPI_EUNSUPPORTED, "server not built"); }
-int epi_server_submit(epi_ctx *, int32_t, int32_t, int32_t, int32_t, int32_t *) { return fail(EPI_EUNSUPPORTED, "server not built"); }
-int epi_server_poll(epi_ctx *, int32_t, int32_t, int32_t *) { return fail(EPI_EUNSUPPORTED, "server not built"); }
-int epi_server_results(epi_ctx *, int32_t, int32_t, int32_t, int32_t *, float *, uint32_t *, int32_t *, double *) { return fail(EPI_EUNSUPPORTED, "server not built"); }
-int epi_server_stats(epi_ctx *, int32_t, uint64_t *) { return fail(EPI_EUNSUPPORTED, "server not built"); }
-int epi_server_stop(epi_ctx *, int32_t) { return fail(EPI_EUNSUPPORTED, "server not built"); }
+
+int epi_server_start(epi_ctx *ctx, const epi_server_config *cfg, int32_t *server_id) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    if (!cfg || !server_id || cfg->max_active < 1 || cfg->max_active > 4096)
+        return fail(EPI_EINVAL, "bad server configuration");
+    auto S = std::make_shared<Server>();
+    S->ctx = C;
+    S->cfg = *cfg;
+    S->budget = cfg->request_budget ? cfg->request_budget : C->alloc.budget;
+    // the largest persistent grid any round may launch (in 4-wave workgroups)
+    S->grid_max = std::max({grid_for(C, 4, 4, 4, ~0ull >> 8, Plan::kTabMax, EPI_MAX_TOP_K, stage_cap_for(4, 4, 16)),
+                            grid_for(C, 4, 4, 0, ~0ull >> 8, 0, 1, stage_cap_for(4, 4, 16)),
+                            grid_for(C, 0, 0, 5, ~0ull >> 8, 0, 1, 0)});
+    const int A = cfg->max_active;
+    S->max_round_tasks = 3 * A + 4;
+    S->out_block = result_block_bytes(EPI_MAX_TOP_K, EPI_MAX_ORDER);
+    int rc;
+    auto cleanup = [&](int code) {
+        server_free(S.get());
+        return code;
+    };
+    if ((rc = C->alloc.alloc((size_t)8 * 8 + (size_t)A * 8 + (size_t)A * 4, &S->d_counters))) return cleanup(rc);
+    S->d_queues = (unsigned long long *)S->d_counters;
+    S->d_thr = S->d_queues + 8;
+    S->d_cand_count = (unsigned *)(S->d_thr + A);
+    if ((rc = C->alloc.alloc((size_t)S->max_round_tasks * sizeof(Task), &S->d_tasks))) return cleanup(rc);
+    if ((rc = C->alloc.alloc((size_t)A * kMaxTopK * sizeof(Cand), &S->d_results))) return cleanup(rc);
+    if ((rc = C->alloc.alloc((size_t)A * kMergeParts * kMaxTopK * sizeof(Cand), &S->d_parts))) return cleanup(rc);
+    if ((rc = C->alloc.alloc((size_t)A * sizeof(ResultLayout), &S->d_layout))) return cleanup(rc);
+    if ((rc = C->alloc.alloc((size_t)A * S->out_block, &S->d_out))) return cleanup(rc);
+    HIPCHK(hipHostMalloc(&S->h_tasks, (size_t)S->max_round_tasks * sizeof(Task), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc(&S->h_out, (size_t)A * S->out_block, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc(&S->h_layout, (size_t)A * sizeof(ResultLayout), hipHostMallocDefault));
+    HIPCHK(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&S->ev, hipEventDisableTiming));
+    for (int i = A - 1; i >= 0; --i) S->free_slots.push_back(i);
+    {
+        std::lock_guard<std::mutex> g(C->mu);
+        S->id = C->next_id++;
+        C->servers[S->id] = S;
+    }
+    S->thread = std::thread(server_main, S.get());
+    *server_id = S->id;
+    return EPI_OK;
 }
+
+int epi_server_submit(epi_ctx *ctx, int32_t server_id, int32_t dataset_id, int32_t order, int32_t top_k,
+                      int32_t *request_id) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    Server *S = server_of(C, server_id);
+    if (!S) return fail(EPI_ENOTFOUND, "unknown server %d", server_id);
+    if (!request_id) return fail(EPI_EINVAL, "null request_id");
+    epi_scan_desc d{dataset_id, order, top_k, 0};
+    Dataset *ds = nullptr;
+    {
+        std::lock_guard<std::mutex> g(C->mu);
+        int rc = check_desc(C, d, &ds);
+        if (rc) return rc;
+    }
+    auto r = std::make_shared<Request>();
+    r->desc = d;
+    r->ds = ds;
+    r->t_submit = Clock::now();
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        if (S->stopping) return fail(EPI_EINVAL, "server is stopping");
+        if (S->fatal) return fail(S->fatal, "server stopped after a device error");
+        r->id = S->next_req++;
+        S->all[r->id] = r;
+        S->queue.push_back(r);
+    }
+    S->cv.notify_all();
+    *request_id = r->id;
+    return EPI_OK;
+}
+
+int epi_server_poll(epi_ctx *ctx, int32_t server_id, int32_t request_id, int32_t *state) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    Server *S = server_of(C, server_id);
+    if (!S) return fail(EPI_ENOTFOUND, "unknown server %d", server_id);
+    if (!state) return fail(EPI_EINVAL, "null state");
+    std::lock_guard<std::mutex> g(S->mu);
+    auto it = S->all.find(request_id);
+    if (it == S->all.end()) return fail(EPI_ENOTFOUND, "unknown request %d", request_id);
+    if (it->second->state == 3) return fail(it->second->rc, "request failed: %s", it->second->err.c_str());
+    *state = it->second->state;
+    return EPI_OK;
+}
+
+int epi_server_results(epi_ctx *ctx, int32_t server_id, int32_t request_id, int32_t capacity, int32_t *combos,
+                       float *scores, uint32_t *tables, int32_t *n_written, double *latency_ms) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    Server *S = server_of(C, server_id);
+    if (!S) return fail(EPI_ENOTFOUND, "unknown server %d", server_id);
+    if (!n_written || capacity < 0) return fail(EPI_EINVAL, "bad arguments");
+    std::shared_ptr<Request> r;
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        auto it = S->all.find(request_id);
+        if (it == S->all.end()) return fail(EPI_ENOTFOUND, "unknown request %d", request_id);
+        r = it->second;
+        if (r->state == 3) {
+            S->all.erase(it);
+            return fail(r->rc, "request failed: %s", r->err.c_str());
+        }
+        if (r->state != 2) return fail(EPI_ENOTREADY, "request %d not finished", request_id);
+        S->all.erase(it);
+    }
+    const int K = r->desc.top_k, k = r->desc.order, cells = pow3i(k);
+    const char *blk = r->out.data();
+    const int32_t nv = *(const int32_t *)blk;
+    const int32_t *hc = (const int32_t *)(blk + 16);
+    const float *hs = (const float *)(blk + 16 + (size_t)K * k * 4);
+    const uint32_t *ht = (const uint32_t *)(blk + 16 + (size_t)K * k * 4 + (size_t)K * 4);
+    const int n = std::min(capacity, nv);
+    if (n > 0 && (!combos || !scores)) return fail(EPI_EINVAL, "null combos/scores buffer");
+    for (int i = 0; i < n; ++i) {
+        memcpy(combos + (size_t)i * k, hc + (size_t)i * k, (size_t)k * 4);
+        scores[i] = hs[i];
+        if (tables) memcpy(tables + (size_t)i * 2 * cells, ht + (size_t)i * 2 * cells, (size_t)2 * cells * 4);
+    }
+    *n_written = n;
+    if (latency_ms) *latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+    return EPI_OK;
+}
+
+int epi_server_stats(epi_ctx *ctx, int32_t server_id, uint64_t out[5]) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    Server *S = server_of(C, server_id);
+    if (!S) return fail(EPI_ENOTFOUND, "unknown server %d", server_id);
+    if (!out) return fail(EPI_EINVAL, "null out");
+    std::lock_guard<std::mutex> g(S->mu);
+    out[0] = S->n_done;
+    out[1] = S->rounds;
+    out[2] = S->work_done;
+    out[3] = S->peak_bytes;
+    out[4] = S->peak_active;
+    return EPI_OK;
+}
+
+int epi_server_stop(epi_ctx *ctx, int32_t server_id) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    std::shared_ptr<Server> S;
+    {
+        std::lock_guard<std::mutex> g(C->mu);
+        auto it = C->servers.find(server_id);
+        if (it == C->servers.end()) return fail(EPI_ENOTFOUND, "unknown server %d", server_id);
+        S = it->second;
+        C->servers.erase(it);
+    }
+    server_join(S.get());
+    const int fatal = S->fatal;
+    server_free(S.get());
+    if (fatal) return fail(fatal, "server stopped after a device error");
+    return EPI_OK;
+}
+
+}  // extern "C"
