@@ -113,15 +113,18 @@ def cpu_baseline(spec, G, y, seconds):
     order, N = spec["order"], spec["N"]
     # the host share of one GPU is 16 cores, whatever the machine reports
     threads = min(16, len(os.sched_getaffinity(0)))
-    probe = max(1000, int(2e8 / N))
-    t0 = time.perf_counter()
-    r = o.scan(G, y, order, spec["top_k"], 0, probe, nthreads=threads, tables=False)
-    t_probe = time.perf_counter() - t0
-    n = max(probe, int(probe * seconds / max(t_probe, 1e-3)))
-    n = min(n, o.binomial(spec["M"], order))
-    t0 = time.perf_counter()
-    r = o.scan(G, y, order, spec["top_k"], 0, n, nthreads=threads, tables=False)
-    dt = time.perf_counter() - t0
+    total = o.binomial(spec["M"], order)
+    # a probe of about half a second sizes the sample; a sample that still
+    # ran short of half the requested time is sized again from its own rate
+    n = min(total, max(1000, int(4e9 / N)))
+    for _ in range(3):
+        t0 = time.perf_counter()
+        r = o.scan(G, y, order, spec["top_k"], 0, n, nthreads=threads, tables=False)
+        dt = time.perf_counter() - t0
+        want = min(total, max(n, int(n * seconds / max(dt, 1e-3))))
+        if dt >= 0.5 * seconds or n == total:
+            break
+        n = want
     return {
         "value": n * N / dt / 1e12,
         "unit": UNIT,
@@ -282,7 +285,7 @@ def main():
     ap.add_argument("--served-rate", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-copy-mib", type=int, default=0,
-                    help="also run a plain device copy of this many MiB (HBM counter calibration)")
+                    help="also run an elementwise kernel over this many MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the scan is built and measured for a single MI355X; "
@@ -302,11 +305,13 @@ def main():
     log(f"workload {args.workload}: C({M},{order}) = {n_combos} combinations x {N} individuals")
 
     if args.profile_copy_mib:
-        a = torch.empty(args.profile_copy_mib << 20, dtype=torch.uint8, device="cuda")
-        b = torch.empty_like(a)
+        # a plain elementwise kernel that reads and writes exactly this many
+        # bytes: the reference for scaling the HBM byte counters
+        a = torch.zeros(args.profile_copy_mib << 20, dtype=torch.uint8, device="cuda")
         for _ in range(3):
-            b.copy_(a)
+            b = a + 1
         torch.cuda.synchronize()
+        del b
 
     dt, mains, alls, res, sinfo, tuned = plain_bench(epi, torch, spec, G, y, args.steps, args.warmup)
     combos, scores, tables = res
