@@ -660,9 +660,10 @@ EPI_DEV void item_generic(const Task &t, unsigned long long local, TopK &tk, Can
 }
 
 // ---------------------------------------------------------------------------
-// Persistent scan kernel: one wave per workgroup; waves pop work items from a
-// device queue (one atomic per item) that runs over the concatenated item
-// spaces of all tasks of the launch, in task order.
+// Persistent scan kernel: four independent waves per workgroup.  The
+// workgroup pops chunks of work items from a device queue that runs over the
+// concatenated item spaces of all tasks of the launch, in task order; each
+// wave keeps its own best-K list and prefix-row slot in LDS.
 // ---------------------------------------------------------------------------
 // Register budget per instantiation: enough waves per SIMD to hide load
 // latency; the accumulators (16 per prefix for order 3, 8 for order 2) set the
