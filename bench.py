@@ -14,7 +14,10 @@ main counting kernel against the integer-VALU peak (HIP events on the scan's
 stream); ``cpu_baseline`` is the CPU oracle timed on a bounded slice of the
 same workload; ``batched`` compares one persistent, graph-captured launch of
 64 uneven scans with 64 back-to-back plain launches; ``served`` runs the
-continuous-batching server on Poisson arrivals.
+continuous-batching server on Poisson arrivals and, for capacity, on the same
+requests submitted at once against back-to-back plain scans;
+``pcie_inclusive_value`` is the same step with the genotypes handed over from
+host memory; ``orders`` times the other named workloads (orders 2, 4, 5).
 """
 from __future__ import annotations
 
@@ -55,7 +58,14 @@ def ops_per_unit_3k(order):
 
 
 def kernel_hash():
-    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    """Hash of the kernel source with comments and blank lines removed, so a
+    comment edit does not invalidate counters taken on the same code."""
+    code = []
+    for line in open(KERNEL_SOURCE).read().splitlines():
+        line = line.split("//", 1)[0].rstrip()
+        if line:
+            code.append(line)
+    return hashlib.sha256("\n".join(code).encode()).hexdigest()[:16]
 
 
 def load_traffic():
@@ -135,6 +145,64 @@ def cpu_baseline(spec, G, y, seconds):
     }
 
 
+def pcie_bench(epi, spec, G, y, steps):
+    """Same steps with the genotypes handed over from host memory: load
+    (host-to-device copy + packing) + scan + results + unload."""
+    order, K = spec["order"], spec["top_k"]
+    ctx = epi.epi_create(0)
+    times = []
+    for i in range(steps + 1):
+        t0 = time.perf_counter()
+        ds = epi.epi_load_genotypes(ctx, G, y)
+        sid = epi.epi_scan(ctx, ds, order, K)
+        epi.epi_wait(ctx, sid)
+        epi.epi_results(ctx, sid, K, order)
+        epi.epi_release(ctx, sid)
+        epi.epi_unload(ctx, ds)
+        if i:
+            times.append(time.perf_counter() - t0)
+    epi.epi_destroy(ctx)
+    return math.comb(spec["M"], order) * spec["N"] * len(times) / sum(times) / 1e12
+
+
+def orders_bench(epi, torch, names, steps):
+    """Plain scans of the other named workloads (one per order), for the
+    per-order rate and roofline fraction of their counting kernels."""
+    from synth import make_workload
+
+    out = {}
+    ctx = epi.epi_create(0)
+    for name in names:
+        G, y, spec, _ = make_workload(name)
+        order, K = spec["order"], spec["top_k"]
+        work = math.comb(spec["M"], order) * spec["N"]
+        ds = epi.epi_load_genotypes(ctx, G, y)
+        epi.epi_autotune(ctx, ds, order)
+        walls, mains = [], []
+        for i in range(steps + 2):
+            t0 = time.perf_counter()
+            sid = epi.epi_scan(ctx, ds, order, K)
+            epi.epi_wait(ctx, sid)
+            epi.epi_results(ctx, sid, K, order)
+            ms = epi.epi_scan_timing(ctx, sid)
+            info = epi.epi_scan_info(ctx, sid)
+            epi.epi_release(ctx, sid)
+            if i >= 2:
+                walls.append(time.perf_counter() - t0)
+                mains.append(ms[2])
+        epi.epi_unload(ctx, ds)
+        kms = sorted(mains)[len(mains) // 2]
+        # reduced-cell variants count 2^k cells, the generic one all 3^k
+        opu = ops_per_unit(order) if info["variant"] in (1, 2) else ops_per_unit_3k(order)
+        out[name] = {"value": work * len(walls) / sum(walls) / 1e12, "kernel_ms": kms,
+                     "kernel_value": work / (kms * 1e-3) / 1e12, "variant": info["variant"],
+                     "ops_per_unit": opu, "frac": work * opu / (kms * 1e-3) / 1e12 / VALU_PEAK_TOPS,
+                     "frac_3k_cells": work * ops_per_unit_3k(order) / (kms * 1e-3) / 1e12 / VALU_PEAK_TOPS}
+        log(f"{name}: kernel {kms:.3f} ms, {out[name]['kernel_value']:.2f} T, frac {out[name]['frac']:.3f}")
+    epi.epi_destroy(ctx)
+    return out
+
+
 def batched_bench(epi, torch, n_scans, reps):
     """One persistent graph-captured launch of n uneven scans vs n back-to-back plain launches."""
     from synth import batched_specs, make_case_control
@@ -185,28 +253,76 @@ def batched_bench(epi, torch, n_scans, reps):
     }
 
 
-def served_bench(epi, torch, n_requests, rate, seed=7):
-    """Poisson arrivals of scans on a resident dataset pool, served by the
-    continuous-batching server; latency from submission to results ready."""
-    import threading
-
-    import numpy as np
-
+def served_pool(epi, ctx):
+    """Resident dataset pool of the serving workload (loaded once)."""
     from synth import make_case_control, served_pool_specs
 
     pool = served_pool_specs(32)
-    ctx = epi.epi_create(0)
     t0 = time.perf_counter()
     dss = []
     for s in pool:
         G, y, _ = make_case_control(s["M"], s["N"], s["n_cases"], s["planted"], s["seed"])
         dss.append(epi.epi_load_genotypes(ctx, G, y))
     log(f"served: pool of {len(pool)} datasets loaded in {time.perf_counter() - t0:.1f}s")
+    return pool, dss
+
+
+def served_requests(pool, n, seed=7):
+    """Request stream: (dataset, order) uniform over the pool and its orders."""
+    import numpy as np
+
     rng = np.random.default_rng(seed)
     reqs = []
-    for _ in range(n_requests):
+    for _ in range(n):
         d = int(rng.integers(len(pool)))
         reqs.append((d, int(rng.choice(pool[d]["orders"]))))
+    return reqs, rng
+
+
+def served_capacity(epi, ctx, pool, dss, cap, K=100):
+    """The same requests submitted at once to a fresh server, against the same
+    requests as back-to-back plain scans (scan, wait, results)."""
+    work = sum(math.comb(pool[d]["M"], o) * pool[d]["N"] for d, o in cap)
+    sid = epi.epi_server_start(ctx, max_active=64)
+    t0 = time.perf_counter()
+    ids = [(epi.epi_server_submit(ctx, sid, dss[d], o, K), o) for d, o in cap]
+    served_top = []
+    for rid, o in ids:
+        while epi.epi_server_poll(ctx, sid, rid) != 2:
+            time.sleep(0.0005)
+        c, s_, _, _ = epi.epi_server_results(ctx, sid, rid, K, o, tables=False)
+        served_top.append((tuple(c[0]), float(s_[0])))
+    burst_s = time.perf_counter() - t0
+    stats = epi.epi_server_stats(ctx, sid)
+    epi.epi_server_stop(ctx, sid)
+    t0 = time.perf_counter()
+    plain_top = []
+    for d, o in cap:
+        q = epi.epi_scan(ctx, dss[d], o, K)
+        epi.epi_wait(ctx, q)
+        c, s_, _ = epi.epi_results(ctx, q, K, o, tables=False)
+        epi.epi_release(ctx, q)
+        plain_top.append((tuple(c[0]), float(s_[0])))
+    b2b_s = time.perf_counter() - t0
+    log(f"served capacity: {len(cap)} requests at once {burst_s:.3f}s ({stats['rounds']} rounds) "
+        f"vs back-to-back plain {b2b_s:.3f}s")
+    return {"requests": len(cap), "combos_x_samples": int(work), "value": work / burst_s / 1e12,
+            "back_to_back_value": work / b2b_s / 1e12, "speedup": b2b_s / burst_s, "rounds": stats["rounds"],
+            "identical_top1": served_top == plain_top}
+
+
+def served_bench(epi, torch, n_requests, rate, burst, seed=7):
+    """Poisson arrivals of scans on a resident dataset pool, served by the
+    continuous-batching server; latency from submission to results ready."""
+    import threading
+
+    import numpy as np
+
+    ctx = epi.epi_create(0)
+    pool, dss = served_pool(epi, ctx)
+    reqs, rng = served_requests(pool, max(n_requests, burst), seed)
+    cap = reqs[:burst]
+    reqs = reqs[:n_requests]
     gaps = rng.exponential(1.0 / rate, n_requests)
     work = [math.comb(pool[d]["M"], o) * pool[d]["N"] for d, o in reqs]
     K = 100
@@ -251,6 +367,7 @@ def served_bench(epi, torch, n_requests, rate, seed=7):
     wall = max(done_at) - start
     stats = epi.epi_server_stats(ctx, sid)
     epi.epi_server_stop(ctx, sid)
+    capacity = served_capacity(epi, ctx, pool, dss, cap, K)
     for d in dss:
         epi.epi_unload(ctx, d)
     epi.epi_destroy(ctx)
@@ -267,6 +384,7 @@ def served_bench(epi, torch, n_requests, rate, seed=7):
         "wall_s": wall,
         "rounds": stats["rounds"],
         "peak_active": stats["peak_active"],
+        "capacity": capacity,
     }
 
 
@@ -283,6 +401,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--served-requests", type=int, default=200)
     ap.add_argument("--served-rate", type=float, default=20.0)
+    ap.add_argument("--served-burst", type=int, default=100,
+                    help="requests of the served capacity comparison (all submitted at once)")
+    ap.add_argument("--no-orders", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-copy-mib", type=int, default=0,
                     help="also run an elementwise kernel over this many MiB (HBM counter calibration)")
@@ -355,12 +476,16 @@ def main():
         "top1": {"combo": [int(v) for v in combos[0]], "mi": float(scores[0]), "planted": list(spec["planted"]),
                  "planted_rank": planted_rank, "achieved_h2": info["h2"]},
     }
+    out["pcie_inclusive_value"] = round(pcie_bench(epi, spec, G, y, 5), 4)
+    if not args.no_orders:
+        others = [n for n in ("order2_M200_N1000", "order4_M200_N2000", "order5_M60_N2000") if n != args.workload]
+        out["orders"] = orders_bench(epi, torch, others, 5)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(spec, G, y, args.cpu_seconds)
     if not args.no_batched:
         out["batched"] = batched_bench(epi, torch, args.batched_scans, args.batched_reps)
     if not args.no_served:
-        out["served"] = served_bench(epi, torch, args.served_requests, args.served_rate)
+        out["served"] = served_bench(epi, torch, args.served_requests, args.served_rate, args.served_burst)
     print(json.dumps(out), flush=True)
 
 

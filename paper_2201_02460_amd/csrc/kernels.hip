@@ -1116,8 +1116,7 @@ static const ScanKernelEntry kScanKernels[] = {
     EPI_K(2, 0, 0), EPI_K(4, 0, 0), EPI_K(8, 0, 0),                   // order 2 / pair sub-table
     EPI_K(0, 1, 0), EPI_K(0, 2, 0), EPI_K(0, 4, 0), EPI_K(0, 8, 0),   // order 3
     EPI_K(0, 0, 2), EPI_K(0, 0, 3), EPI_K(0, 0, 4), EPI_K(0, 0, 5),   // per-combination kernel
-    EPI_K(4, 2, 0), EPI_K(4, 4, 0),                                   // persistent orders 2-3
-    EPI_K(4, 2, 4), EPI_K(4, 4, 4),                                   // persistent orders 2-4
+    EPI_K(4, 2, 0), EPI_K(4, 4, 0), EPI_K(4, 8, 0),                   // persistent orders 2-3
 };
 #undef EPI_K
 

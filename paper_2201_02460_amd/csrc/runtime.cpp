@@ -306,14 +306,20 @@ static int load_common(Ctx *c, const uint8_t *d_geno, int64_t ld, const uint8_t 
 // ---------------------------------------------------------------------------
 // plans
 // ---------------------------------------------------------------------------
-static int tuned_np(Ctx *c, int order, const Dataset *d) {
+int tuned_np_lookup(Ctx *c, int order, const Dataset *d) {
     const int words = (d->w4[0] + d->w4[1]) * 4;
     int bucket = 0;
     while ((1 << bucket) < words) ++bucket;
     std::lock_guard<std::mutex> g(c->tune_mu);
     auto it = c->tuned.find(TuneKey{order, bucket});
-    if (it != c->tuned.end()) return it->second;
-    return order == 2 ? 4 : (order == 3 ? 4 : kGenRanksHost);
+    return it != c->tuned.end() ? it->second : 0;
+}
+
+static int tuned_np(Ctx *c, int order, const Dataset *d) {
+    if (order == 3) return default_np3(c, d);
+    const int t = tuned_np_lookup(c, order, d);
+    if (t > 0) return t;
+    return order == 2 ? 4 : kGenRanksHost;
 }
 
 // Work items of the order-2 kernels: (i-block ib of np SNPs, block mb of 64
@@ -411,27 +417,28 @@ void pick_group_kernel(const std::vector<int> &orders, int np3_hint, int *np2, i
         else if (o == 3) has3 = true;
         else gen = o;
     }
-    if (gen == 5) {
-        *np2 = 0;
-        *np3 = 0;
-        *gk = 5;
-        return;
-    }
-    if (!has3 && gen == 0) {
-        *np2 = 4;
-        *np3 = 0;
-        *gk = 0;
-        return;
-    }
-    if (!has2 && !has3) {
-        *np2 = 0;
-        *np3 = 0;
+    *np2 = 0;
+    *np3 = 0;
+    *gk = 0;
+    if (gen) {  // a generic order runs in a group of its own
         *gk = gen;
         return;
     }
-    *np2 = 4;
-    *np3 = np3_hint <= 2 ? 2 : 4;
-    *gk = gen == 4 ? 4 : 0;
+    const int h = np3_hint <= 2 ? 2 : (np3_hint <= 4 ? 4 : 8);
+    if (has2) *np2 = 4;
+    if (has3) *np3 = has2 ? h : np3_hint;
+}
+
+// Launch-group key of an order: orders 2 and 3 share the reduced-cell kernel,
+// each generic order has its own instantiation.
+int group_of_order(int order) { return order <= 3 ? 0 : order; }
+
+// Prefix block of an order-3 scan: the autotuned value for the dataset's
+// size bucket if there is one, else 4 (the best measured choice over uneven
+// mixes of M and N; 8 wins only on large M and N).
+int default_np3(Ctx *c, const Dataset *d) {
+    const int t = tuned_np_lookup(c, 3, d);
+    return t > 0 ? t : 4;
 }
 
 // Persistent grid, in 4-wave workgroups (one wave per SIMD each): as many as
@@ -523,28 +530,26 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
     }
     // launch groups
     if (persistent) {
-        // main groups by kernel instantiation (order 5 runs in a group of its own)
-        std::vector<int> orders_a, orders_b;
-        int np3_hint = 4;
-        for (auto &s : p->scans) {
-            if (s.desc.order == 5) orders_b.push_back(5);
-            else orders_a.push_back(s.desc.order);
-            if (s.desc.order == 3) np3_hint = s.np;
-        }
-        if (!orders_a.empty()) {
+        // one launch group per kernel instantiation: orders 2-3 together (the
+        // order-3 prefix block is the one most of their work is tuned for),
+        // each generic order apart
+        for (int key : {0, 4, 5}) {
+            std::vector<int> orders;
+            std::map<int, unsigned long long> np3_work;
             LaunchGroup g;
-            pick_group_kernel(orders_a, np3_hint, &g.np2, &g.np3, &g.gk);
-            for (int i = 0; i < n; ++i)
-                if (p->scans[i].desc.order != 5) g.scans.push_back(i);
-            p->groups.push_back(g);
-        }
-        if (!orders_b.empty()) {
-            LaunchGroup g;
-            g.np2 = 0;
-            g.np3 = 0;
-            g.gk = 5;
-            for (int i = 0; i < n; ++i)
-                if (p->scans[i].desc.order == 5) g.scans.push_back(i);
+            for (int i = 0; i < n; ++i) {
+                const PlanScan &s = p->scans[i];
+                if (group_of_order(s.desc.order) != key) continue;
+                orders.push_back(s.desc.order);
+                if (s.desc.order == 3) np3_work[s.np] += s.n_combos * (unsigned long long)s.ds->N;
+                g.scans.push_back(i);
+            }
+            if (orders.empty()) continue;
+            int np3_hint = 4;
+            unsigned long long best = 0;
+            for (auto &kv : np3_work)
+                if (kv.second > best) best = kv.second, np3_hint = kv.first;
+            pick_group_kernel(orders, np3_hint, &g.np2, &g.np3, &g.gk);
             p->groups.push_back(g);
         }
         for (auto &g : p->groups)

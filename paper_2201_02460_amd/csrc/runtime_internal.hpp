@@ -156,6 +156,9 @@ uint64_t binom_u64(int64_t n, int64_t k);
 int get_items(Ctx *c, int variant, int M, int np, const void **d, unsigned long long *n);
 int check_desc(Ctx *c, const epi_scan_desc &d, Dataset **out);
 void pick_group_kernel(const std::vector<int> &orders, int np3_hint, int *np2, int *np3, int *gk);
+int group_of_order(int order);
+int tuned_np_lookup(Ctx *c, int order, const Dataset *d);
+int default_np3(Ctx *c, const Dataset *d);
 int grid_for(Ctx *c, int np2, int np3, int gk, unsigned long long items, int tab_cap, int kmax, int stage_cap);
 int stage_cap_for(int np2, int np3, int w4_max);
 

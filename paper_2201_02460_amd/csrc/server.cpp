@@ -75,7 +75,19 @@ struct Server {
     int fatal = EPI_OK;
 };
 
-static const double kRoundWork = 4e11;  // combos x individuals per round (a few ms)
+// Device work of a round, in combos x individuals: about 8 ms with up to four
+// active requests, so a new arrival joins within a few milliseconds; with
+// more requests in flight each still gets a useful slice per round, up to
+// eight times that.
+static const double kRoundWork = 4e11;
+
+// Launch group of a request within a round, one per kernel instantiation:
+// order 2, order 3 per prefix block (its work items are built for that
+// block), and each generic order.
+static int round_group(const Request *r) {
+    if (r->desc.order == 3) return 30 + r->np;
+    return r->desc.order;
+}
 
 static void free_request_buffers(Server *S, Request *r) {
     S->ctx->alloc.release(r->pairs);
@@ -104,7 +116,7 @@ static int admit(Server *S, Request *r) {
         r->np = 4;
     } else if (o == 3) {
         r->variant = kF3;
-        r->np = 4;
+        r->np = default_np3(c, r->ds);
     } else {
         r->variant = kGeneric;
         r->np = kGenRanksHost;
@@ -168,7 +180,8 @@ static int run_round(Server *S) {
             SRV_HIPCHK(launch_init_counters(st, nullptr, 0, S->d_cand_count + r->slot, S->d_thr + r->slot, 1));
         }
     // slices: finishing requests first (their merge results feed finalize)
-    const double share = kRoundWork / std::max<size_t>(1, S->active.size());
+    const double na = (double)std::max<size_t>(1, S->active.size());
+    const double share = kRoundWork * std::min(8.0, std::max(1.0, na / 4.0)) / na;
     std::vector<std::pair<Request *, unsigned long long>> fin, cont;
     for (auto &r : S->active) {
         const unsigned long long per_item =
@@ -202,26 +215,26 @@ static int run_round(Server *S) {
         ht[ti++] = t;
     }
     const int n_emit = ti - emit_off;
-    // launch groups by kernel instantiation: orders 2-4 together, order 5 apart
+    // launch groups by kernel instantiation
     struct G {
         int np2, np3, gk, off, n, tab_cap, kmax, stage;
         unsigned long long total;
     };
     std::vector<G> groups;
-    for (int pass = 0; pass < 2; ++pass) {
+    for (int key : {38, 34, 32, 31, 2, 4, 5}) {
         std::vector<int> orders;
         G g{0, 0, 0, ti, 0, 0, 1, 0, 0};
         for (int i = 0; i < nt; ++i) {
             Request *r = order[i].first;
-            if ((r->desc.order == 5) != (pass == 1)) continue;
+            if (round_group(r) != key) continue;
             orders.push_back(r->desc.order);
         }
         if (orders.empty()) continue;
-        pick_group_kernel(orders, 4, &g.np2, &g.np3, &g.gk);
+        pick_group_kernel(orders, key > 30 ? key - 30 : 4, &g.np2, &g.np3, &g.gk);
         g.stage = stage_cap_for(g.np2, g.np3, 0);
         for (int i = 0; i < nt; ++i) {
             Request *r = order[i].first;
-            if ((r->desc.order == 5) != (pass == 1)) continue;
+            if (round_group(r) != key) continue;
             Task t = ht[i];
             t.item_base = g.total;
             t.first_item = r->cursor;
@@ -413,9 +426,11 @@ int epi_server_start(epi_ctx *ctx, const epi_server_config *cfg, int32_t *server
     S->cfg = *cfg;
     S->budget = cfg->request_budget ? cfg->request_budget : C->alloc.budget;
     // the largest persistent grid any round may launch (in 4-wave workgroups)
-    S->grid_max = std::max({grid_for(C, 4, 4, 4, ~0ull >> 8, Plan::kTabMax, EPI_MAX_TOP_K, stage_cap_for(4, 4, 16)),
-                            grid_for(C, 4, 4, 0, ~0ull >> 8, 0, 1, stage_cap_for(4, 4, 16)),
-                            grid_for(C, 0, 0, 5, ~0ull >> 8, 0, 1, 0)});
+    S->grid_max = 1;
+    for (const int *k : {(const int[]){4, 0, 0}, (const int[]){0, 1, 0}, (const int[]){0, 2, 0}, (const int[]){0, 4, 0},
+                         (const int[]){0, 8, 0}, (const int[]){0, 0, 4}, (const int[]){0, 0, 5}})
+        S->grid_max = std::max(S->grid_max,
+                               grid_for(C, k[0], k[1], k[2], ~0ull >> 8, 0, 1, stage_cap_for(k[0], k[1], 1)));
     const int A = cfg->max_active;
     S->max_round_tasks = 3 * A + 4;
     S->out_block = result_block_bytes(EPI_MAX_TOP_K, EPI_MAX_ORDER);
