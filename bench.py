@@ -36,8 +36,14 @@ METRIC = "tera combos×samples/s at order k, batched vs plain, counts bit-exact 
 UNIT = "tera combos×samples/s"
 # Integer VALU peak of MI355X: 256 CUs x 4 SIMD x 16 lanes per clock x 2.4 GHz.
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# Dense 4-bit-float matrix-core peak of MI355X (published), TFLOP/s.
+MFMA_FP4_PEAK_TFLOPS = 10.1e3
+# Dense 8-bit integer matrix-core peak of MI355X (published), TOP/s.
+MFMA_I8_PEAK_TOPS = 5.0e3
+BLOCK_MFMA_FP4 = 16
+BLOCK_MFMA_I8 = 32
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2201_02460_amd", "csrc", "kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_scan_order3_M1000_N4000.json")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def log(*a):
@@ -49,6 +55,12 @@ def ops_per_unit(order):
     kernels: 2^order directly counted cells (all genotypes in {0,1}), one
     three-input AND and one popcount-accumulate per cell per 32 individuals."""
     return 2.0 * 2**order / 32.0
+
+
+def mfma_flops_per_unit(order):
+    """Algorithmic matrix-core work per combination x individual of the
+    matrix-core kernel: one multiply-add (2 flops) per counted cell."""
+    return 2.0 * 2**order
 
 
 def ops_per_unit_3k(order):
@@ -68,9 +80,11 @@ def kernel_hash():
     return hashlib.sha256("\n".join(code).encode()).hexdigest()[:16]
 
 
-def load_traffic():
+def load_traffic(kernel_tag, workload):
+    """HBM bytes per launch from the committed counter summary of this kernel
+    and workload, or None if there is none or the kernel code has changed."""
     try:
-        doc = json.load(open(TRAFFIC_FILE))
+        doc = json.load(open(os.path.join(PROFILES, f"traffic_{kernel_tag}_{workload}.json")))
     except (OSError, ValueError):
         return None
     if doc.get("kernel_sha") != kernel_hash():
@@ -78,14 +92,19 @@ def load_traffic():
     return doc.get("hbm_bytes_per_launch")
 
 
-def plain_bench(epi, torch, spec, G, y, steps, warmup):
-    """Timed steps of repack + scan + results on one resident dataset."""
+def plain_bench(epi, torch, spec, G, y, steps, warmup, block=None):
+    """Timed steps of repack + scan + results on one resident dataset; the
+    counting kernel is the autotuner's choice unless `block` pins one."""
     dG = torch.from_numpy(G).cuda()
     dy = torch.from_numpy(y).cuda()
     stream = torch.cuda.current_stream()
     ctx = epi.epi_create(0)
     ds = epi.epi_load_genotypes_device(ctx, dG, dy, stream)
-    tuned = epi.epi_autotune(ctx, ds, spec["order"])
+    if block is None:
+        tuned = epi.epi_autotune(ctx, ds, spec["order"])
+    else:
+        epi.epi_set_prefix_block(ctx, ds, spec["order"], block)
+        tuned = block
     order, K = spec["order"], spec["top_k"]
     mains, alls = [], []
     res = None
@@ -404,6 +423,7 @@ def main():
     ap.add_argument("--served-burst", type=int, default=100,
                     help="requests of the served capacity comparison (all submitted at once)")
     ap.add_argument("--no-orders", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the comparison with the other counting kernels")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-copy-mib", type=int, default=0,
                     help="also run an elementwise kernel over this many MiB (HBM counter calibration)")
@@ -439,9 +459,31 @@ def main():
     value = n_combos * N * args.steps / dt / 1e12
     ms_main = sum(mains) / len(mains)
     ms_scan = sum(alls) / len(alls)
-    achieved = n_combos * N * ops_per_unit(order) / (ms_main * 1e-3) / 1e12
-    achieved_3k = n_combos * N * ops_per_unit_3k(order) / (ms_main * 1e-3) / 1e12
-    traffic = load_traffic()
+    work = n_combos * N
+    mfma = sinfo["prefix_block"] == BLOCK_MFMA_FP4
+    if mfma:
+        roofline = {
+            "bound": "mfma",
+            "achieved": round(work * mfma_flops_per_unit(order) / (ms_main * 1e-3) / 1e12, 3),
+            "peak": MFMA_FP4_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "kernel": "scan_persistent<0,16,0> (order-3 reduced cells as fp4 0/1 matrix products)",
+            "flops_per_unit": mfma_flops_per_unit(order),
+            "traffic": load_traffic("scan_mfma", args.workload),
+        }
+    else:
+        roofline = {
+            "bound": "alu",
+            "achieved": round(work * ops_per_unit(order) / (ms_main * 1e-3) / 1e12, 3),
+            "peak": round(VALU_PEAK_TOPS, 3),
+            "unit": "TOP/s",
+            "kernel": "scan_persistent (reduced-cell popcount variant)",
+            "ops_per_unit": ops_per_unit(order),
+            "traffic": load_traffic("scan_popcount", args.workload),
+        }
+    roofline["frac"] = round(roofline["achieved"] / roofline["peak"], 4)
+    roofline["kernel_ms"] = round(ms_main, 4)
+    roofline["frac_valu_3k_cells"] = round(work * ops_per_unit_3k(order) / (ms_main * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4)
     planted_rank = next((i + 1 for i, c in enumerate(combos.tolist()) if tuple(c) == tuple(spec["planted"])), None)
     out = {
         "metric": METRIC,
@@ -459,23 +501,27 @@ def main():
         "config": {"workload": args.workload, "order": order, "M": M, "N": N, "n_cases": spec["n_cases"],
                    "top_k": spec["top_k"], "n_combinations": n_combos, "parallelism": "single GPU",
                    "variant": sinfo["variant"], "prefix_block": sinfo["prefix_block"], "autotuned": tuned},
-        "roofline": {
-            "bound": "alu",
-            "achieved": round(achieved, 3),
-            "peak": round(VALU_PEAK_TOPS, 3),
-            "unit": "TOP/s",
-            "frac": round(achieved / VALU_PEAK_TOPS, 4),
-            "traffic": traffic,
-            "kernel": "scan_persistent (order-3 reduced-cell variant)",
-            "kernel_ms": round(ms_main, 4),
-            "ops_per_unit": ops_per_unit(order),
-            "ops_per_unit_3k_cells": ops_per_unit_3k(order),
-            "frac_3k_cells": round(achieved_3k / VALU_PEAK_TOPS, 4),
-        },
+        "roofline": roofline,
         "scan_ms": round(ms_scan, 4),
         "top1": {"combo": [int(v) for v in combos[0]], "mi": float(scores[0]), "planted": list(spec["planted"]),
                  "planted_rank": planted_rank, "achieved_h2": info["h2"]},
     }
+    if order == 3 and not args.no_compare:
+        # the same step with the other counting kernels pinned: popcount
+        # (prefix block 8) and the 8-bit integer matrix-core products
+        for name, block, bound, opu, peak, unit, tag in (
+                ("popcount_kernel", 8, "alu", ops_per_unit(order), VALU_PEAK_TOPS, "TOP/s", "scan_popcount"),
+                ("mfma_int8_kernel", BLOCK_MFMA_I8, "mfma", mfma_flops_per_unit(order), MFMA_I8_PEAK_TOPS, "TOP/s",
+                 "scan_mfma_i8")):
+            pdt, pm, _, pres, _, _ = plain_bench(epi, torch, spec, G, y, max(3, args.steps // 4), 2, block=block)
+            pk = sum(pm) / len(pm)
+            achieved = work * opu / (pk * 1e-3) / 1e12
+            out[name] = {
+                "value": round(work * len(pm) / pdt / 1e12, 4), "kernel_ms": round(pk, 4), "bound": bound,
+                "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": unit,
+                "frac": round(achieved / peak, 4), "traffic": load_traffic(tag, args.workload),
+                "identical_results": bool((pres[0] == combos).all() and (pres[1] == scores).all()),
+            }
     out["pcie_inclusive_value"] = round(pcie_bench(epi, spec, G, y, 5), 4)
     if not args.no_orders:
         others = [n for n in ("order2_M200_N1000", "order4_M200_N2000", "order5_M60_N2000") if n != args.workload]

@@ -194,13 +194,38 @@ int epi_batch_destroy(epi_ctx *ctx, int32_t batch_id);
 
 /* ---- autotuner ----------------------------------------------------------- */
 
-/* Time the kernel variants (prefix block, word unroll) for `order` on a
- * bounded slice of the dataset's combination space and remember the fastest
- * for datasets of the same words-per-individual bucket.  The choice is also
- * written to the cache file named by EPI_TUNE_CACHE (if set).  Scans use
- * tuned choices automatically; untuned shapes use built-in defaults.
- * *choice receives the chosen prefix block. */
+/* Counting kernels by prefix block (the number of first SNPs a work item
+ * shares; Section 2.4 reuses such prefixes of the enumeration):
+ *   order 2: 2, 4, 8 -- popcount kernels;
+ *   order 3: 1, 2, 4, 8 -- popcount kernels (Section 2.2: AND + popcount);
+ *            16 (EPI_BLOCK_MFMA_FP4) -- the reduced cells as 0/1 matrix
+ *            products on the matrix cores, 4-bit float operands (1.0 = 0x2),
+ *            exact float32 sums (datasets with fewer than 2^24 individuals);
+ *            32 (EPI_BLOCK_MFMA_I8) -- the same products with 8-bit integer
+ *            operands and int32 sums (never chosen by the autotuner: it
+ *            moves twice the operand bytes of the 4-bit form for the same
+ *            products).
+ * Every kernel produces the same integers and therefore the same results. */
+#define EPI_BLOCK_MFMA_FP4 16
+#define EPI_BLOCK_MFMA_I8 32
+
+/* Time the counting kernels above for `order` on a bounded slice of the
+ * dataset's combination space and remember the fastest for datasets of the
+ * same words-per-individual bucket.  The choice is also written to the cache
+ * file named by EPI_TUNE_CACHE (if set).  Scans use tuned choices
+ * automatically; untuned shapes use built-in defaults (order 3: the
+ * matrix-core kernel where available).  *choice receives the chosen prefix
+ * block. */
 int epi_autotune(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t *choice);
+
+/* Pin the counting kernel for `order` (2 or 3) on datasets of the same
+ * bucket as `dataset_id`, as if the autotuner had chosen `block` (one of the
+ * blocks listed above).  EPI_BLOCK_MFMA_I8 builds the dataset's integer
+ * operand copies on the context stream and waits for them (no other work on
+ * the dataset may be in flight).  EPI_EINVAL for a block not listed for the
+ * order, EPI_EUNSUPPORTED for a matrix-core block on a dataset with 2^24
+ * individuals or more, EPI_ENOMEM if the copies do not fit. */
+int epi_set_prefix_block(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t block);
 
 /* ---- serving: continuous batching -------------------------------------- */
 

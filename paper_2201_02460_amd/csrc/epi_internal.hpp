@@ -12,7 +12,20 @@
 //             class size and SNPs s >= M are zero.  Class 0 = cases.
 //   single  : u32 [Mp][2 classes][2 genotypes] per-SNP class counts of
 //             genotypes 0 and 1.
-//   tlog    : i64 [N + 1], tlog[n] = round(n * ln(n) * 2^shift).
+//   tlog    : i64 [2N + 1], tlog[n] = round(n * ln(n) * 2^shift).
+//   qa, qb  : the same genotype-0/1 rows as 4-bit floats (e2m1: 0x2 = 1.0,
+//             0x0 = 0), in the operand order of the 32x32x64 matrix-core
+//             product: one 16-byte entry per lane = 32 individuals of one row.
+//             KS = ks[0] + ks[1] steps of 64 individuals (class 0 first, each
+//             class zero-padded to a multiple of kQStepMultiple steps); half h
+//             of a step holds its
+//             individuals 32h .. 32h+31, two per byte, low nibble first.
+//             qa [((s / 16) * KS + step) * 64 + 32 h + 2 (s % 16) + g]
+//             qb [(((s / 32) * 2 + g) * KS + step) * 64 + 32 h + s % 32]
+//   qa8, qb8: the same with 8-bit integer operands (1 = 0x01) for the
+//             32x32x32 integer product: steps of 32 individuals (ks8 per
+//             class, padded alike), half h = individuals 16h .. 16h+15, one
+//             per byte; built only when the integer kernel is selected.
 //
 // Lanes of a wave read 16 consecutive bytes each of 64 consecutive SNPs, so a
 // wave-wide load of one mask row group is one contiguous 1 KiB segment.
@@ -29,6 +42,9 @@ constexpr int kWave = 64;
 constexpr int kMergeSlots = 4096;      // LDS entries of the top-K merge
 constexpr int kMergeParts = 32;        // first-stage merge workgroups per task
 constexpr int kMaxBinomOrder = 8;
+constexpr int kNpMfma = 16;            // order-3 block counted by matrix cores, 4-bit float operands
+constexpr int kNpMfmaI8 = 32;          // the same with 8-bit integer operands
+constexpr int kQStepMultiple = 4;      // qa / qb: steps per class padded to a multiple of this
 
 enum Variant : int32_t {
     kGeneric = 0,  // one combination per lane, all 3^k cells counted
@@ -42,11 +58,15 @@ struct DsView {
     const uint32_t *single;
     const long long *tlog;
     const float *ftab;     // float(n ln n), n = 0 .. N (screening table)
+    const v4u *qa, *qb;    // 4-bit-float operand copies of the masks
+    const v4u *qa8, *qb8;  // 8-bit-integer operand copies (null until selected)
     float ferr;            // bound on the float screening sum error
     int32_t M, Mp, N, shift;
     int32_t ncls[2];
     int32_t w4[2];
     int32_t wbase[2];
+    int32_t ks[2];         // 64-individual steps per class in qa / qb
+    int32_t ks8[2];        // 32-individual steps per class in qa8 / qb8
 };
 
 // One top-K candidate: larger num is better; on equal num the smaller key
@@ -60,6 +80,7 @@ struct Task {
     DsView ds;
     uint32_t *pairs;                  // lex-ordered pair sub-table, 8 u32 per pair
     const unsigned long long *items;  // per-item descriptors: kF3 j<<40 | ib<<20 | mb, kF2 ib<<20 | mb
+                                      // (kF3 with np = kNpMfma: 16-SNP i-block ib, 32-SNP m-block mb)
     unsigned long long n_items;
     unsigned long long item_base;     // first global item of this task in its launch
     unsigned long long first_item;    // task-local index of the launch's first item of this task

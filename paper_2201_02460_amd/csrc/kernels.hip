@@ -543,6 +543,221 @@ EPI_DEV void item_f3(const Task &t, unsigned long long local, TopK &tk, Cand *li
 }
 
 // ---------------------------------------------------------------------------
+// kF3 with np = kNpMfma: order 3 counted by matrix cores.  A work item is
+// (j, block of 16 SNPs i, block of 32 SNPs m); every (i, j, m) with i < j < m
+// in it is one triplet.  Counts of individuals with genotypes (a, b, d) at
+// (i, j, m) are dot products of 0/1 indicator rows, so the reduced cells of a
+// class are the products (X_i . x_{j,b})^T X_m over its individuals, one
+// matrix-core product per step of individuals, b and d: rows (i, a) are A,
+// the rows of genotype b of SNP j mask A, rows (m, d) are B.  With 4-bit
+// float operands (1.0 = 0x2; v_mfma_scale_f32_32x32x64_f8f6f4, 64
+// individuals per step) products are 0 or 1 and sums stay below 2^24, so the
+// float accumulators hold the exact counts; 8-bit integer operands
+// (v_mfma_i32_32x32x32_i8, 32 per step) give the same integers.  In the 32 x 32 result,
+// lane l holds column l % 32 (SNP m) and rows 8 (r / 4) + 4 (l / 32) + r % 4
+// of its 16 registers r, i.e. both genotypes a of eight SNPs i; the epilogue
+// is that of the popcount kernel.
+// ---------------------------------------------------------------------------
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// Descriptor word 3 of a raw (untyped, unswizzled) gfx9 buffer.
+constexpr int kBufWord3 = 0x00020000;
+// Steps of 64 individuals in flight per operand stream.
+constexpr int kQDepth = kQStepMultiple;
+
+EPI_DEV v4u qload(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+// Operand format of the matrix-core order-3 kernel.
+//   I8 = false: 4-bit floats, 64 individuals per step, float32 sums;
+//   I8 = true:  8-bit integers, 32 individuals per step, int32 sums.
+template <bool I8>
+struct QFmt;
+
+template <>
+struct QFmt<false> {
+    typedef v16f acc_t;
+    static EPI_DEV const v4u *qa(const DsView &d) { return d.qa; }
+    static EPI_DEV const v4u *qb(const DsView &d) { return d.qb; }
+    static EPI_DEV int ks(const DsView &d, int c) { return d.ks[c]; }
+    static EPI_DEV acc_t mma(v4u a, v4u b, acc_t c) {
+        const v8i a8 = {(int)a[0], (int)a[1], (int)a[2], (int)a[3], 0, 0, 0, 0};
+        const v8i b8 = {(int)b[0], (int)b[1], (int)b[2], (int)b[3], 0, 0, 0, 0};
+        // formats 4 / 4: e2m1 for both operands; scales 127 = 2^0
+        return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, c, 4, 4, 0, 127, 0, 127);
+    }
+};
+
+template <>
+struct QFmt<true> {
+    typedef v16i acc_t;
+    static EPI_DEV const v4u *qa(const DsView &d) { return d.qa8; }
+    static EPI_DEV const v4u *qb(const DsView &d) { return d.qb8; }
+    static EPI_DEV int ks(const DsView &d, int c) { return d.ks8[c]; }
+    static EPI_DEV acc_t mma(v4u a, v4u b, acc_t c) {
+        return __builtin_amdgcn_mfma_i32_32x32x32_i8(__builtin_bit_cast(v4i, a), __builtin_bit_cast(v4i, b), c, 0, 0,
+                                                     0);
+    }
+};
+
+template <bool LDS, bool I8>
+EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr,
+                      const float *tab) {
+    typedef QFmt<I8> Q;
+    const DsView d = t.ds;
+    const unsigned long long dsc = t.items[local];
+    const int j = uni((int)((dsc >> 40) & 0xfffffu));
+    const int ib = uni((int)((dsc >> 20) & 0xfffffu));
+    const int mb = uni((int)(dsc & 0xfffffu));
+    const int lane = lane_id(), h = lane >> 5;
+    const int m = mb * 32 + (lane & 31);
+    const bool mv = m > j && m < d.M;
+    const int m_ld = mv ? m : j + 1;
+
+    // sub-table rows the epilogue needs, issued before the counting loop
+    const v4u *single4 = (const v4u *)d.single;
+    const v4u *pair4 = (const v4u *)t.pairs;
+    const v4u sm = single4[m_ld];
+    const v4u sj = single4[j];
+    const unsigned long long rjm = lexpair(j, m_ld, d.M);
+    const v4u pjm0 = pair4[2 * rjm], pjm1 = pair4[2 * rjm + 1];
+
+    // operands through buffer descriptors (scalar registers): a lane adds
+    // its own constant byte offset and a step adds a scalar one, so a step
+    // costs no vector address arithmetic
+    const int KS = Q::ks(d, 0) + Q::ks(d, 1);
+    const int blk = KS * 1024;  // bytes of one row block
+    const v4u *qa = Q::qa(d), *qb = Q::qb(d);
+    const __amdgpu_buffer_rsrc_t rA =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(qa + (long long)ib * KS * 64), 0, blk, kBufWord3);
+    const __amdgpu_buffer_rsrc_t rJ =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(qa + (long long)(j >> 4) * KS * 64), 0, blk, kBufWord3);
+    const __amdgpu_buffer_rsrc_t rB0 =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(qb + (long long)(2 * mb) * KS * 64), 0, blk, kBufWord3);
+    const __amdgpu_buffer_rsrc_t rB1 =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(qb + (long long)(2 * mb + 1) * KS * 64), 0, blk, kBufWord3);
+    const int vo = lane * 16, vj = (32 * h + 2 * (j & 15)) * 16;
+    typename Q::acc_t acc[2][2][2];
+    #pragma unroll
+    for (int c = 0; c < 2; ++c)
+        #pragma unroll
+        for (int b = 0; b < 2; ++b)
+            #pragma unroll
+            for (int e = 0; e < 2; ++e) acc[c][b][e] = (typename Q::acc_t){};
+    // software pipeline: the operands of kQDepth steps are in flight while a
+    // step is multiplied (a step's products take far less time than a load
+    // from L2).  Each class has a multiple of kQDepth steps (zero-padded).
+    #pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int s0 = c == 0 ? 0 : Q::ks(d, 0);
+        const int n = Q::ks(d, c);
+        v4u bA[kQDepth], bJ0[kQDepth], bJ1[kQDepth], bB0[kQDepth], bB1[kQDepth];
+        #pragma unroll
+        for (int u = 0; u < kQDepth; ++u) {
+            const int so = (s0 + u) * 1024;
+            bA[u] = qload(rA, vo, so);
+            bJ0[u] = qload(rJ, vj, so);
+            bJ1[u] = qload(rJ, vj + 16, so);
+            bB0[u] = qload(rB0, vo, so);
+            bB1[u] = qload(rB1, vo, so);
+        }
+        #pragma unroll 1
+        for (int k = 0; k < n; k += kQDepth) {
+            #pragma unroll
+            for (int u = 0; u < kQDepth; ++u) {
+                const v4u A0 = bA[u] & bJ0[u], A1 = bA[u] & bJ1[u];
+                acc[c][0][0] = Q::mma(A0, bB0[u], acc[c][0][0]);
+                acc[c][0][1] = Q::mma(A0, bB1[u], acc[c][0][1]);
+                acc[c][1][0] = Q::mma(A1, bB0[u], acc[c][1][0]);
+                acc[c][1][1] = Q::mma(A1, bB1[u], acc[c][1][1]);
+                // refill the slot (the last steps re-read the class's last step)
+                const int so = (s0 + min(k + u + kQDepth, n - 1)) * 1024;
+                bA[u] = qload(rA, vo, so);
+                bJ0[u] = qload(rJ, vj, so);
+                bJ1[u] = qload(rJ, vj + 16, so);
+                bB0[u] = qload(rB0, vo, so);
+                bB1[u] = qload(rB1, vo, so);
+            }
+        }
+    }
+
+    // the lane's eight SNPs i: i_local = 4 (u / 2) + 2 h + u % 2, genotype a in
+    // register 4 (u / 2) + 2 (u % 2) + a
+    const int i_base = ib * 16 + 2 * h;
+    unsigned long long rim = lexpair(min(i_base, j - 1), m_ld, d.M);
+    v4u pim_n0 = pair4[2 * rim], pim_n1 = pair4[2 * rim + 1];
+    #pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int i = i_base + 4 * (u >> 1) + (u & 1);
+        const int i_ld = min(i, j - 1);
+        const bool valid = mv && i < j;
+        const v4u pim0 = pim_n0, pim1 = pim_n1;
+        if (u + 1 < 8) {
+            // next SNP's pair row, in flight while this one is scored
+            const int in = min(i_base + 4 * ((u + 1) >> 1) + ((u + 1) & 1), j - 1);
+            rim = lexpair(in, m_ld, d.M);
+            pim_n0 = pair4[2 * rim];
+            pim_n1 = pair4[2 * rim + 1];
+        }
+        const v4u si = single4[i_ld];
+        const unsigned long long rij = lexpair(i_ld, j, d.M);
+        const int r0 = 4 * (u >> 1) + 2 * (u & 1);
+        int F[2][27];
+        #pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const v4u pij = pair4[2 * rij + c];
+            const v4u pim = c == 0 ? pim0 : pim1;
+            const v4u pjm = c == 0 ? pjm0 : pjm1;
+            // F[a*9 + b*3 + e]; index 2 on an axis = marginal over that SNP
+            #pragma unroll
+            for (int a = 0; a < 2; ++a)
+                #pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    #pragma unroll
+                    for (int e = 0; e < 2; ++e) F[c][9 * a + 3 * b + e] = (int)acc[c][b][e][r0 + a];
+            #pragma unroll
+            for (int a = 0; a < 2; ++a)
+                #pragma unroll
+                for (int b = 0; b < 2; ++b) F[c][9 * a + 3 * b + 2] = pij[2 * a + b];
+            #pragma unroll
+            for (int a = 0; a < 2; ++a)
+                #pragma unroll
+                for (int e = 0; e < 2; ++e) F[c][9 * a + 6 + e] = pim[2 * a + e];
+            #pragma unroll
+            for (int b = 0; b < 2; ++b)
+                #pragma unroll
+                for (int e = 0; e < 2; ++e) F[c][18 + 3 * b + e] = pjm[2 * b + e];
+            F[c][9 * 0 + 8] = si[2 * c + 0];
+            F[c][9 * 1 + 8] = si[2 * c + 1];
+            F[c][18 + 2] = sj[2 * c + 0];
+            F[c][18 + 5] = sj[2 * c + 1];
+            F[c][24] = sm[2 * c + 0];
+            F[c][25] = sm[2 * c + 1];
+            F[c][26] = d.ncls[c];
+            mobius3(F[c]);
+        }
+        bool pass = valid;
+        if constexpr (LDS) {
+            const float sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.ferr);
+            pass = pass && screen_sum<27>(tab, F[0], F[1]) >= sb;
+        }
+        if (__ballot(pass)) {
+            long long num = t.score_const;
+            #pragma unroll
+            for (int x = 0; x < 27; ++x) num += cell_term(d.tlog, F[0][x], F[1][x], (unsigned)d.N);
+            const unsigned long long key =
+                ((unsigned long long)i << 42) | ((unsigned long long)j << 21) | (unsigned long long)m;
+            tk_offer(tk, list, pass, num, key, gthr);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // kGeneric: any order K.  A work item is 64 * kGenRanks consecutive colex
 // ranks; lane l takes ranks l, l + 64, ...  Each lane counts all 3^K cells of
 // its own combination, 27 cells (the last three SNPs) at a time for each
@@ -666,8 +881,8 @@ EPI_DEV void item_generic(const Task &t, unsigned long long local, TopK &tk, Can
 // wave keeps its own best-K list and prefix-row slot in LDS.
 // ---------------------------------------------------------------------------
 // Register budget per instantiation: enough waves per SIMD to hide load
-// latency; the accumulators (16 per prefix for order 3, 8 for order 2) set the
-// floor.
+// latency; the accumulators (16 per prefix for order 3, 8 for order 2, 128
+// for the matrix-core order-3 kernel) set the floor.
 template <int NP2, int NP3, int GK>
 constexpr int scan_waves_per_eu() {
     return GK >= 4 ? 2 : (GK == 3 ? 3 : (NP3 >= 8 ? 2 : (NP3 >= 4 ? 3 : (NP3 >= 2 ? 4 : (NP2 >= 8 ? 3 : 4)))));
@@ -773,7 +988,11 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
                     item_f2<NP2, true, false>(T, local, tk, s_list, gthr, T.ds.ftab, s_stage, stage_cap);
                 break;
             case kF3:
-                if constexpr (NP3 > 0) {
+                if constexpr (NP3 == kNpMfma || NP3 == kNpMfmaI8) {
+                    constexpr bool i8 = NP3 == kNpMfmaI8;
+                    if (lds) item_f3m<true, i8>(T, local, tk, s_list, gthr, s_tab);
+                    else item_f3m<false, i8>(T, local, tk, s_list, gthr, T.ds.ftab);
+                } else if constexpr (NP3 > 0) {
                     if (lds) item_f3<NP3, true>(T, local, tk, s_list, gthr, s_tab, s_stage, stage_cap);
                     else item_f3<NP3, false>(T, local, tk, s_list, gthr, T.ds.ftab, s_stage, stage_cap);
                 }
@@ -1033,6 +1252,73 @@ __global__ void singles_kernel(DsView d, uint32_t *__restrict__ single) {
     single[(s * 2 + cl) * 2 + 1] = n1;
 }
 
+// Matrix-core operand copies of the genotype-0/1 rows: one thread per (SNP,
+// genotype, 64-individual step, half); each 32-individual mask word becomes
+// 32 4-bit floats (bit set -> 0x2 = 1.0), low nibble first.
+__global__ void qpack_kernel(DsView d, v4u *__restrict__ qa, v4u *__restrict__ qb) {
+    const long long KS = d.ks[0] + d.ks[1];
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= (long long)d.Mp * 2 * KS * 2) return;
+    const int s = (int)(tid % d.Mp);
+    long long rest = tid / d.Mp;
+    const int g = (int)(rest & 1);
+    rest >>= 1;
+    const int h = (int)(rest & 1);
+    const long long step = rest >> 1;
+    const int c = step < d.ks[0] ? 0 : 1;
+    const int widx = 2 * (int)(step - (c == 0 ? 0 : d.ks[0])) + h;  // 32-bit word within the class
+    unsigned word = 0;
+    if ((widx >> 2) < d.w4[c]) {
+        gv4u *gm = (gv4u *)d.masks;
+        word = gm[((long long)(d.wbase[c] + (widx >> 2)) * 2 + g) * d.Mp + s][widx & 3];
+    }
+    v4u out;
+    #pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        unsigned x = 0;
+        #pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const unsigned b = (word >> (8 * k + 2 * t)) & 3u;
+            x |= (((b & 1u) << 1) | ((b >> 1) << 5)) << (8 * t);
+        }
+        out[k] = x;
+    }
+    qa[((long long)(s >> 4) * KS + step) * 64 + 32 * h + 2 * (s & 15) + g] = out;
+    qb[(((long long)(s >> 5) * 2 + g) * KS + step) * 64 + 32 * h + (s & 31)] = out;
+}
+
+// Integer operand copies: one thread per (SNP, genotype, 32-individual step,
+// half); each 16-individual half word becomes 16 bytes of 0 / 1.
+__global__ void qpack8_kernel(DsView d, v4u *__restrict__ qa8, v4u *__restrict__ qb8) {
+    const long long KS = d.ks8[0] + d.ks8[1];
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= (long long)d.Mp * 2 * KS * 2) return;
+    const int s = (int)(tid % d.Mp);
+    long long rest = tid / d.Mp;
+    const int g = (int)(rest & 1);
+    rest >>= 1;
+    const int h = (int)(rest & 1);
+    const long long step = rest >> 1;
+    const int c = step < d.ks8[0] ? 0 : 1;
+    const int widx = (int)(step - (c == 0 ? 0 : d.ks8[0]));  // 32-bit word within the class
+    unsigned word = 0;
+    if ((widx >> 2) < d.w4[c]) {
+        gv4u *gm = (gv4u *)d.masks;
+        word = gm[((long long)(d.wbase[c] + (widx >> 2)) * 2 + g) * d.Mp + s][widx & 3];
+    }
+    const unsigned half = word >> (16 * h);
+    v4u out;
+    #pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        unsigned x = 0;
+        #pragma unroll
+        for (int t = 0; t < 4; ++t) x |= ((half >> (4 * k + t)) & 1u) << (8 * t);
+        out[k] = x;
+    }
+    qa8[((long long)(s >> 4) * KS + step) * 64 + 32 * h + 2 * (s & 15) + g] = out;
+    qb8[(((long long)(s >> 5) * 2 + g) * KS + step) * 64 + 32 * h + (s & 31)] = out;
+}
+
 // Class index map: idx[0 .. n_case) = input positions of the cases in input
 // order, idx[n_case .. N) = those of the controls.  One 1024-thread
 // workgroup; a phenotype outside {0,1} raises *err.
@@ -1116,7 +1402,7 @@ static const ScanKernelEntry kScanKernels[] = {
     EPI_K(2, 0, 0), EPI_K(4, 0, 0), EPI_K(8, 0, 0),                   // order 2 / pair sub-table
     EPI_K(0, 1, 0), EPI_K(0, 2, 0), EPI_K(0, 4, 0), EPI_K(0, 8, 0),   // order 3
     EPI_K(0, 0, 2), EPI_K(0, 0, 3), EPI_K(0, 0, 4), EPI_K(0, 0, 5),   // per-combination kernel
-    EPI_K(4, 2, 0), EPI_K(4, 4, 0), EPI_K(4, 8, 0),                   // persistent orders 2-3
+    EPI_K(0, kNpMfma, 0), EPI_K(0, kNpMfmaI8, 0),                    // order 3, matrix cores
 };
 #undef EPI_K
 
@@ -1191,6 +1477,18 @@ hipError_t launch_pack(hipStream_t st, const uint8_t *geno, long long ld, const 
 
 hipError_t launch_classidx(hipStream_t st, const uint8_t *pheno, int N, int n_case, int32_t *idx, int *err) {
     hipLaunchKernelGGL(classidx_kernel, dim3(1), dim3(1024), 0, st, pheno, N, n_case, idx, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_qpack(hipStream_t st, const DsView &d, v4u *qa, v4u *qb) {
+    const long long n = (long long)d.Mp * 2 * (d.ks[0] + d.ks[1]) * 2;
+    hipLaunchKernelGGL(qpack_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, d, qa, qb);
+    return hipGetLastError();
+}
+
+hipError_t launch_qpack8(hipStream_t st, const DsView &d, v4u *qa8, v4u *qb8) {
+    const long long n = (long long)d.Mp * 2 * (d.ks8[0] + d.ks8[1]) * 2;
+    hipLaunchKernelGGL(qpack8_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, d, qa8, qb8);
     return hipGetLastError();
 }
 

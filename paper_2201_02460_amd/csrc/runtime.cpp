@@ -198,7 +198,11 @@ static void ds_free(Ctx *c, Dataset *d) {
     c->alloc.release(d->ftab);
     c->alloc.release(d->idx);
     c->alloc.release(d->err);
-    d->masks = d->single = d->tlog = d->ftab = d->idx = d->err = nullptr;
+    c->alloc.release(d->qa);
+    c->alloc.release(d->qb);
+    c->alloc.release(d->qa8);
+    c->alloc.release(d->qb8);
+    d->masks = d->single = d->tlog = d->ftab = d->idx = d->err = d->qa = d->qb = d->qa8 = d->qb8 = nullptr;
 }
 
 static int ds_layout(Dataset *d, int M, int N, int n_case) {
@@ -209,6 +213,12 @@ static int ds_layout(Dataset *d, int M, int N, int n_case) {
     d->Mp = (M + 63) / 64 * 64;
     d->w4[0] = (d->n_case + 127) / 128;
     d->w4[1] = (d->n_ctrl + 127) / 128;
+    const int q = 64 * kQStepMultiple;
+    d->ks[0] = (d->n_case + q - 1) / q * kQStepMultiple;
+    d->ks[1] = (d->n_ctrl + q - 1) / q * kQStepMultiple;
+    const int q8 = 32 * kQStepMultiple;
+    d->ks8[0] = (d->n_case + q8 - 1) / q8 * kQStepMultiple;
+    d->ks8[1] = (d->n_ctrl + q8 - 1) / q8 * kQStepMultiple;
     d->shift = choose_shift(N);
     return EPI_OK;
 }
@@ -230,7 +240,21 @@ static void ds_view(Dataset *d) {
     v.w4[1] = d->w4[1];
     v.wbase[0] = 0;
     v.wbase[1] = d->w4[0];
+    v.qa = (const v4u *)d->qa;
+    v.qb = (const v4u *)d->qb;
+    v.ks[0] = d->ks[0];
+    v.ks[1] = d->ks[1];
+    v.qa8 = (const v4u *)d->qa8;
+    v.qb8 = (const v4u *)d->qb8;
+    v.ks8[0] = d->ks8[0];
+    v.ks8[1] = d->ks8[1];
 }
+
+// Bytes of each integer operand copy.
+static size_t qop8_bytes(const Dataset *d) { return (size_t)d->Mp * 2 * (d->ks8[0] + d->ks8[1]) * 32; }
+
+// Bytes of each matrix-core operand copy (qa and qb hold the same rows).
+static size_t qop_bytes(const Dataset *d) { return (size_t)d->Mp * 2 * (d->ks[0] + d->ks[1]) * 32; }
 
 static int ds_alloc(Ctx *c, Dataset *d) {
     const size_t mask_bytes = (size_t)(d->w4[0] + d->w4[1]) * 2 * d->Mp * 16;
@@ -242,6 +266,13 @@ static int ds_alloc(Ctx *c, Dataset *d) {
     if ((rc = c->alloc.alloc(((size_t)d->N + 1) * 4, &d->ftab))) return rc;
     if ((rc = c->alloc.alloc(256, &d->err))) return rc;
     d->bytes = mask_bytes + (size_t)d->Mp * 16 + ((size_t)2 * d->N + 1) * 8 + (size_t)d->N * 4;
+    // float accumulation of 0/1 products is exact while a class count stays
+    // below 2^24
+    if (d->N < (1 << 24)) {
+        if ((rc = c->alloc.alloc(qop_bytes(d), &d->qa))) return rc;
+        if ((rc = c->alloc.alloc(qop_bytes(d), &d->qb))) return rc;
+        d->bytes += 2 * qop_bytes(d);
+    }
     ds_view(d);
     std::vector<long long> tl;
     build_tlog(d->N, d->shift, tl);
@@ -263,6 +294,26 @@ static int ds_pack(Dataset *d, const uint8_t *d_geno, int64_t ld, const uint8_t 
     HIPCHK(launch_classidx(st, d_pheno, d->N, d->n_case, (int32_t *)d->idx, (int *)d->err));
     HIPCHK(launch_pack(st, d_geno, ld, (const int32_t *)d->idx, d->view, (v4u *)d->masks, (int *)d->err));
     HIPCHK(launch_singles(st, d->view, (uint32_t *)d->single));
+    if (d->qa) HIPCHK(launch_qpack(st, d->view, (v4u *)d->qa, (v4u *)d->qb));
+    if (d->qa8) HIPCHK(launch_qpack8(st, d->view, (v4u *)d->qa8, (v4u *)d->qb8));
+    return EPI_OK;
+}
+
+// Integer operand copies of a dataset, built the first time the integer
+// matrix-core kernel is selected for it (synchronous on the context stream).
+static int ds_ensure_i8(Ctx *c, Dataset *d) {
+    if (d->qa8) return EPI_OK;
+    int rc;
+    if ((rc = c->alloc.alloc(qop8_bytes(d), &d->qa8))) return rc;
+    if ((rc = c->alloc.alloc(qop8_bytes(d), &d->qb8))) {
+        c->alloc.release(d->qa8);
+        d->qa8 = nullptr;
+        return rc;
+    }
+    d->bytes += 2 * qop8_bytes(d);
+    ds_view(d);
+    HIPCHK(launch_qpack8(c->stream, d->view, (v4u *)d->qa8, (v4u *)d->qb8));
+    HIPCHK(hipStreamSynchronize(c->stream));
     return EPI_OK;
 }
 
@@ -335,8 +386,22 @@ static void build_f2_items(int M, int np, std::vector<unsigned long long> &out) 
 
 // Work items of the order-3 kernel: (j, block ib of np SNPs i < j, block mb
 // of 64 SNPs m > j), descriptor j << 40 | ib << 20 | mb.
+//
+// Matrix-core blocks (np = kNpMfma): (16-SNP block ib of i, 32-SNP block mb of
+// m, j) for every j with some i < j < m in the blocks; j runs fastest, so
+// neighbouring items read the same i and m operand blocks.
 static void build_f3_items(int M, int np, std::vector<unsigned long long> &out) {
     out.clear();
+    if (np == kNpMfma || np == kNpMfmaI8) {
+        for (int ib = 0; ib * 16 < M; ++ib)
+            for (int mb = 0; mb * 32 < M; ++mb) {
+                const int j0 = std::max(1, ib * 16 + 1);
+                const int j1 = std::min(std::min(mb * 32 + 31, M - 1) - 1, M - 2);
+                for (int j = j0; j <= j1; ++j)
+                    out.push_back(((unsigned long long)j << 40) | ((unsigned long long)ib << 20) | (unsigned)mb);
+            }
+        return;
+    }
     for (int j = 1; j <= M - 2; ++j) {
         const int ni = (j + np - 1) / np;
         const int nm = (M - 1 - j + 63) / 64;
@@ -429,16 +494,16 @@ void pick_group_kernel(const std::vector<int> &orders, int np3_hint, int *np2, i
     if (has3) *np3 = has2 ? h : np3_hint;
 }
 
-// Launch-group key of an order: orders 2 and 3 share the reduced-cell kernel,
-// each generic order has its own instantiation.
-int group_of_order(int order) { return order <= 3 ? 0 : order; }
+// Launch-group key of an order (order 3 is further split by prefix block).
+int group_of_order(int order) { return order; }
 
 // Prefix block of an order-3 scan: the autotuned value for the dataset's
-// size bucket if there is one, else 4 (the best measured choice over uneven
-// mixes of M and N; 8 wins only on large M and N).
+// size bucket if there is one, else the matrix-core kernel when the dataset
+// has its operand copies, else 4.
 int default_np3(Ctx *c, const Dataset *d) {
     const int t = tuned_np_lookup(c, 3, d);
-    return t > 0 ? t : 4;
+    if (t > 0 && (t != kNpMfma || d->qa) && (t != kNpMfmaI8 || d->qa8)) return t;
+    return d->qa ? kNpMfma : 4;
 }
 
 // Persistent grid, in 4-wave workgroups (one wave per SIMD each): as many as
@@ -470,7 +535,8 @@ int grid_for(Ctx *c, int np2, int np3, int gk, unsigned long long items, int tab
 // (at most 16 groups of 4 words, 2048 individuals of a class, which keeps
 // three 4-wave workgroups per CU next to an 8001-entry screening table).
 int stage_cap_for(int np2, int np3, int w4_max) {
-    const int rows = std::max(np2 > 0 ? 2 * np2 : 0, np3 > 0 ? 2 * (np3 + 1) : 0);
+    const bool mfma = np3 == kNpMfma || np3 == kNpMfmaI8;
+    const int rows = std::max(np2 > 0 ? 2 * np2 : 0, np3 > 0 && !mfma ? 2 * (np3 + 1) : 0);
     if (rows == 0) return 0;
     return rows * std::max(1, std::min(w4_max, 16));
 }
@@ -530,31 +596,18 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
     }
     // launch groups
     if (persistent) {
-        // one launch group per kernel instantiation: orders 2-3 together (the
-        // order-3 prefix block is the one most of their work is tuned for),
-        // each generic order apart
-        for (int key : {0, 4, 5}) {
-            std::vector<int> orders;
-            std::map<int, unsigned long long> np3_work;
-            LaunchGroup g;
-            for (int i = 0; i < n; ++i) {
-                const PlanScan &s = p->scans[i];
-                if (group_of_order(s.desc.order) != key) continue;
-                orders.push_back(s.desc.order);
-                if (s.desc.order == 3) np3_work[s.np] += s.n_combos * (unsigned long long)s.ds->N;
-                g.scans.push_back(i);
-            }
-            if (orders.empty()) continue;
-            int np3_hint = 4;
-            unsigned long long best = 0;
-            for (auto &kv : np3_work)
-                if (kv.second > best) best = kv.second, np3_hint = kv.first;
-            pick_group_kernel(orders, np3_hint, &g.np2, &g.np3, &g.gk);
-            p->groups.push_back(g);
+        // one launch group per kernel instantiation: order 2, order 3 per
+        // prefix block, each generic order
+        std::map<int, LaunchGroup> by_key;
+        for (int i = 0; i < n; ++i) {
+            const PlanScan &s = p->scans[i];
+            const int key = s.desc.order == 3 ? 30 + s.np : group_of_order(s.desc.order);
+            LaunchGroup &g = by_key[key];
+            g.scans.push_back(i);
+            std::vector<int> orders{s.desc.order};
+            pick_group_kernel(orders, s.np, &g.np2, &g.np3, &g.gk);
         }
-        for (auto &g : p->groups)
-            for (int i : g.scans)
-                if (p->scans[i].desc.order == 3) p->scans[i].np = g.np3;
+        for (auto &kv : by_key) p->groups.push_back(kv.second);
     } else {
         for (int i = 0; i < n; ++i) {
             LaunchGroup g;
@@ -854,7 +907,10 @@ int autotune(Ctx *c, int ds_id, int order, int *choice) {
     }
     std::vector<int> cands;
     if (order == 2) cands = {2, 4, 8};
-    else if (order == 3) cands = {1, 2, 4, 8};
+    else if (order == 3) {
+        cands = {1, 2, 4, 8};
+        if (ds->qa) cands.push_back(kNpMfma);
+    }
     else {
         *choice = kGenRanksHost;
         return EPI_OK;
@@ -1249,6 +1305,38 @@ int epi_batch_destroy(epi_ctx *ctx, int32_t batch_id) {
     }
     if (dead->ran) (void)hipEventSynchronize(dead->ev[4]);
     plan_free(C, dead.get());
+    return EPI_OK;
+}
+
+int epi_set_prefix_block(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t block) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    Dataset *d;
+    {
+        std::lock_guard<std::mutex> g(C->mu);
+        auto it = C->datasets.find(dataset_id);
+        if (it == C->datasets.end()) return fail(EPI_ENOTFOUND, "unknown dataset %d", dataset_id);
+        d = it->second.get();
+    }
+    const bool ok2 = order == 2 && (block == 2 || block == 4 || block == 8);
+    const bool ok3 = order == 3 && (block == 1 || block == 2 || block == 4 || block == 8 || block == kNpMfma ||
+                                    block == kNpMfmaI8);
+    if (!ok2 && !ok3) return fail(EPI_EINVAL, "prefix block %d is not a kernel of order %d", block, order);
+    if (block == kNpMfma && !d->qa)
+        return fail(EPI_EUNSUPPORTED, "dataset %d has no matrix-core operands (2^24 individuals or more)", dataset_id);
+    if (block == kNpMfmaI8) {
+        if (d->N >= (1 << 24))
+            return fail(EPI_EUNSUPPORTED, "dataset %d: 2^24 individuals or more for the integer kernel", dataset_id);
+        int rc = ds_ensure_i8(C, d);
+        if (rc) return rc;
+    }
+    const int words = (d->w4[0] + d->w4[1]) * 4;
+    int bucket = 0;
+    while ((1 << bucket) < words) ++bucket;
+    {
+        std::lock_guard<std::mutex> g(C->tune_mu);
+        C->tuned[TuneKey{order, bucket}] = block;
+    }
     return EPI_OK;
 }
 

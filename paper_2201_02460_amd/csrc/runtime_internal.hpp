@@ -45,6 +45,10 @@ struct Dataset {
     int M = 0, N = 0, n_case = 0, n_ctrl = 0, Mp = 0, shift = 0;
     int w4[2] = {0, 0};
     void *masks = nullptr, *single = nullptr, *tlog = nullptr, *ftab = nullptr, *idx = nullptr, *err = nullptr;
+    int ks[2] = {0, 0};                   // 64-individual steps per class of qa / qb
+    void *qa = nullptr, *qb = nullptr;    // matrix-core operand copies (null: order 3 by popcount only)
+    int ks8[2] = {0, 0};                  // 32-individual steps per class of qa8 / qb8
+    void *qa8 = nullptr, *qb8 = nullptr;  // integer operand copies, built on first selection
     long long score_const = 0;
     float ferr = 0.f;
     uint64_t bytes = 0;
@@ -150,6 +154,8 @@ hipError_t launch_pack(hipStream_t st, const uint8_t *geno, long long ld, const 
                        v4u *masks, int *err);
 hipError_t launch_classidx(hipStream_t st, const uint8_t *pheno, int N, int n_case, int32_t *idx, int *err);
 hipError_t launch_singles(hipStream_t st, const DsView &d, uint32_t *single);
+hipError_t launch_qpack(hipStream_t st, const DsView &d, v4u *qa, v4u *qb);
+hipError_t launch_qpack8(hipStream_t st, const DsView &d, v4u *qa8, v4u *qb8);
 
 // runtime helpers shared with the server
 uint64_t binom_u64(int64_t n, int64_t k);

@@ -80,6 +80,7 @@ struct Server {
 // more requests in flight each still gets a useful slice per round, up to
 // eight times that.
 static const double kRoundWork = 4e11;
+static const int kQueues = 16;
 
 // Launch group of a request within a round, one per kernel instantiation:
 // order 2, order 3 per prefix block (its work items are built for that
@@ -221,7 +222,7 @@ static int run_round(Server *S) {
         unsigned long long total;
     };
     std::vector<G> groups;
-    for (int key : {38, 34, 32, 31, 2, 4, 5}) {
+    for (int key : {30 + kNpMfma, 30 + kNpMfmaI8, 38, 34, 32, 31, 2, 4, 5}) {
         std::vector<int> orders;
         G g{0, 0, 0, ti, 0, 0, 1, 0, 0};
         for (int i = 0; i < nt; ++i) {
@@ -252,6 +253,7 @@ static int run_round(Server *S) {
     SRV_HIPCHK(hipMemcpyAsync(S->d_tasks, ht, (size_t)ti * sizeof(Task), hipMemcpyHostToDevice, st));
     const Task *dt = (const Task *)S->d_tasks;
     const int nq = 1 + (int)groups.size();
+    if (nq > kQueues) return fail(EPI_EDEVICE, "server round has too many launch groups");
     SRV_HIPCHK(launch_init_counters(st, S->d_queues, nq, nullptr, nullptr, 0));
     if (n_emit > 0) {
         const int es = stage_cap_for(4, 0, emit_w4);
@@ -426,9 +428,10 @@ int epi_server_start(epi_ctx *ctx, const epi_server_config *cfg, int32_t *server
     S->cfg = *cfg;
     S->budget = cfg->request_budget ? cfg->request_budget : C->alloc.budget;
     // the largest persistent grid any round may launch (in 4-wave workgroups)
+    static const int kRoundKernels[][3] = {{4, 0, 0}, {0, 1, 0}, {0, 2, 0}, {0, 4, 0},
+                                           {0, 8, 0}, {0, kNpMfma, 0}, {0, kNpMfmaI8, 0}, {0, 0, 4}, {0, 0, 5}};
     S->grid_max = 1;
-    for (const int *k : {(const int[]){4, 0, 0}, (const int[]){0, 1, 0}, (const int[]){0, 2, 0}, (const int[]){0, 4, 0},
-                         (const int[]){0, 8, 0}, (const int[]){0, 0, 4}, (const int[]){0, 0, 5}})
+    for (const auto &k : kRoundKernels)
         S->grid_max = std::max(S->grid_max,
                                grid_for(C, k[0], k[1], k[2], ~0ull >> 8, 0, 1, stage_cap_for(k[0], k[1], 1)));
     const int A = cfg->max_active;
@@ -439,9 +442,11 @@ int epi_server_start(epi_ctx *ctx, const epi_server_config *cfg, int32_t *server
         server_free(S.get());
         return code;
     };
-    if ((rc = C->alloc.alloc((size_t)8 * 8 + (size_t)A * 8 + (size_t)A * 4, &S->d_counters))) return cleanup(rc);
+    // queue counters: one for the pair pass and one per launch group (at most
+    // eight groups: order 2, order 3 per prefix block, orders 4 and 5)
+    if ((rc = C->alloc.alloc((size_t)kQueues * 8 + (size_t)A * 8 + (size_t)A * 4, &S->d_counters))) return cleanup(rc);
     S->d_queues = (unsigned long long *)S->d_counters;
-    S->d_thr = S->d_queues + 8;
+    S->d_thr = S->d_queues + kQueues;
     S->d_cand_count = (unsigned *)(S->d_thr + A);
     if ((rc = C->alloc.alloc((size_t)S->max_round_tasks * sizeof(Task), &S->d_tasks))) return cleanup(rc);
     if ((rc = C->alloc.alloc((size_t)A * kMaxTopK * sizeof(Cand), &S->d_results))) return cleanup(rc);

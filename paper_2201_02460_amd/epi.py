@@ -26,6 +26,8 @@ EPI_ENOTREADY = -5
 EPI_ENOTFOUND = -6
 EPI_MIN_ORDER = 2
 EPI_MAX_ORDER = 5
+EPI_BLOCK_MFMA_FP4 = 16
+EPI_BLOCK_MFMA_I8 = 32
 EPI_MAX_TOP_K = 256
 
 # Every function the header declares, with (restype, argtypes).
@@ -68,6 +70,7 @@ SIGNATURES = {
     "epi_batch_timing": (_c.c_int, [_vp, _i32, _P(_c.c_float)]),
     "epi_batch_destroy": (_c.c_int, [_vp, _i32]),
     "epi_autotune": (_c.c_int, [_vp, _i32, _i32, _P(_i32)]),
+    "epi_set_prefix_block": (_c.c_int, [_vp, _i32, _i32, _i32]),
     "epi_server_start": (_c.c_int, [_vp, _P(ServerConfig), _P(_i32)]),
     "epi_server_submit": (_c.c_int, [_vp, _i32, _i32, _i32, _i32, _P(_i32)]),
     "epi_server_poll": (_c.c_int, [_vp, _i32, _i32, _P(_i32)]),
@@ -292,6 +295,10 @@ def epi_autotune(ctx, dataset_id, order):
     out = _i32()
     _check(lib().epi_autotune(ctx, dataset_id, order, ctypes.byref(out)))
     return out.value
+
+
+def epi_set_prefix_block(ctx, dataset_id, order, block):
+    _check(lib().epi_set_prefix_block(ctx, dataset_id, order, block))
 
 
 def epi_server_start(ctx, max_active=64, round_items=0, request_budget=0):

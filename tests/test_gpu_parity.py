@@ -220,8 +220,39 @@ def test_autotune_keeps_results(cx, orc):
     ds = cx.load(G, y)
     before = cx.scan(ds, 3, 20)
     choice = epi.epi_autotune(cx.ctx, ds, 3)
-    assert choice in (1, 2, 4, 8)
+    assert choice in (1, 2, 4, 8, 16)  # 16: the matrix-core kernel
     after = cx.scan(ds, 3, 20)
     assert np.array_equal(before["combos"], after["combos"]) and np.array_equal(before["scores"], after["scores"])
     check_topk(orc, G, y, 3, 20, after["combos"], after["scores"], after["tables"])
+    epi.epi_unload(cx.ctx, ds)
+
+
+def test_counting_kernels_agree(cx, orc):
+    """Every order-3 counting kernel (popcount prefix blocks, 4-bit float and
+    8-bit integer matrix-core products) gives the same results."""
+    from paper_2201_02460_amd import epi
+
+    G, y = random_genotypes(150, 1100, seed=31, case_fraction=0.35)
+    ds = cx.load(G, y)
+    ref = None
+    for block in (1, 2, 4, 8, epi.EPI_BLOCK_MFMA_FP4, epi.EPI_BLOCK_MFMA_I8):
+        say("prefix block", block)
+        epi.epi_set_prefix_block(cx.ctx, ds, 3, block)
+        res = cx.scan(ds, 3, 30)
+        assert res["prefix_block"] == block
+        if ref is None:
+            check_topk(orc, G, y, 3, 30, res["combos"], res["scores"], res["tables"])
+            ref = res
+        else:
+            assert np.array_equal(res["combos"], ref["combos"])
+            assert np.array_equal(res["scores"], ref["scores"])
+            assert np.array_equal(res["tables"], ref["tables"])
+    for bad in (3, 0, 64):
+        with pytest.raises(epi.EpiError) as e:
+            epi.epi_set_prefix_block(cx.ctx, ds, 3, bad)
+        assert e.value.code == epi.EPI_EINVAL
+    with pytest.raises(epi.EpiError):
+        epi.epi_set_prefix_block(cx.ctx, ds, 2, epi.EPI_BLOCK_MFMA_FP4)
+    # the choice holds for every dataset of the same size bucket: restore the default
+    epi.epi_set_prefix_block(cx.ctx, ds, 3, epi.EPI_BLOCK_MFMA_FP4)
     epi.epi_unload(cx.ctx, ds)
