@@ -200,7 +200,7 @@ int epi_batch_destroy(epi_ctx *ctx, int32_t batch_id);
  *   order 3: 1, 2, 4, 8 -- popcount kernels (Section 2.2: AND + popcount);
  *            16 (EPI_BLOCK_MFMA_FP4) -- the reduced cells as 0/1 matrix
  *            products on the matrix cores, 4-bit float operands (1.0 = 0x2),
- *            exact float32 sums (datasets with fewer than 2^24 individuals);
+ *            exact float32 sums (datasets with fewer than 2^22 individuals);
  *            32 (EPI_BLOCK_MFMA_I8) -- the same products with 8-bit integer
  *            operands and int32 sums (never chosen by the autotuner: it
  *            moves twice the operand bytes of the 4-bit form for the same
@@ -223,7 +223,7 @@ int epi_autotune(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t *choic
  * blocks listed above).  EPI_BLOCK_MFMA_I8 builds the dataset's integer
  * operand copies on the context stream and waits for them (no other work on
  * the dataset may be in flight).  EPI_EINVAL for a block not listed for the
- * order, EPI_EUNSUPPORTED for a matrix-core block on a dataset with 2^24
+ * order, EPI_EUNSUPPORTED for a matrix-core block on a dataset with 2^22
  * individuals or more, EPI_ENOMEM if the copies do not fit. */
 int epi_set_prefix_block(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t block);
 

@@ -13,8 +13,8 @@
 //   single  : u32 [Mp][2 classes][2 genotypes] per-SNP class counts of
 //             genotypes 0 and 1.
 //   tlog    : i64 [2N + 1], tlog[n] = round(n * ln(n) * 2^shift).
-//   qa, qb  : the same genotype-0/1 rows as 4-bit floats (e2m1: 0x2 = 1.0,
-//             0x0 = 0), in the operand order of the 32x32x64 matrix-core
+//   qa, qb  : the same genotype-0/1 rows as 4-bit floats (e2m1: qa 0x2 = 1.0,
+//             qb 0x6 = 4.0, 0x0 = 0), in the operand order of the 32x32x64 matrix-core
 //             product: one 16-byte entry per lane = 32 individuals of one row.
 //             KS = ks[0] + ks[1] steps of 64 individuals (class 0 first, each
 //             class zero-padded to a multiple of kQStepMultiple steps); half h
@@ -22,7 +22,7 @@
 //             individuals 32h .. 32h+31, two per byte, low nibble first.
 //             qa [((s / 16) * KS + step) * 64 + 32 h + 2 (s % 16) + g]
 //             qb [(((s / 32) * 2 + g) * KS + step) * 64 + 32 h + s % 32]
-//   qa8, qb8: the same with 8-bit integer operands (1 = 0x01) for the
+//   qa8, qb8: the same with 8-bit integer operands (qa8 1, qb8 4) for the
 //             32x32x32 integer product: steps of 32 individuals (ks8 per
 //             class, padded alike), half h = individuals 16h .. 16h+15, one
 //             per byte; built only when the integer kernel is selected.
@@ -45,6 +45,7 @@ constexpr int kMaxBinomOrder = 8;
 constexpr int kNpMfma = 16;            // order-3 block counted by matrix cores, 4-bit float operands
 constexpr int kNpMfmaI8 = 32;          // the same with 8-bit integer operands
 constexpr int kQStepMultiple = 4;      // qa / qb: steps per class padded to a multiple of this
+constexpr int kQStageSteps = 64;       // matrix-core kernels: steps of j-mask rows staged in LDS
 
 enum Variant : int32_t {
     kGeneric = 0,  // one combination per lane, all 3^k cells counted
@@ -94,8 +95,13 @@ struct Task {
     int32_t np;                       // prefix block (kF2/kF3) or ranks per lane (kGeneric)
     int32_t n_blocks;                 // number of prefix blocks (kF2: i-blocks, kF3: j values + 1)
     int32_t key_bits;                 // bits per index in the packed key
-    int32_t pad;
+    int32_t cell_shift;               // kF2Emit: pair cells are written as count << cell_shift
 };
+
+// Matrix-core order-3 kernels count 4 x n (their B operand holds 4 for a set
+// bit), so a count is also the byte offset of its float-table entry; their
+// pair sub-tables are written with cell_shift = kQScaleShift to match.
+constexpr int kQScaleShift = 2;
 
 // Per-task result block written by the finalize kernel:
 //   int32 n_valid, int32 pad[3],

@@ -98,6 +98,13 @@ EPI_DEV unsigned long long lexpair(long long x, long long y, long long M) {
     return (unsigned long long)(x * (2 * M - x - 1) / 2 + (y - x - 1));
 }
 
+// Rank of pair (x, x + 1): x (2M - x - 1) / 2.  Both factors stay below 2^24
+// (M < 2^23), which lets the product use the 24-bit multipliers.
+EPI_DEV unsigned long long pair_row(int x, int M) {
+    const unsigned a = (unsigned)x & 0xffffffu, b = (unsigned)(2 * M - x - 1) & 0xffffffu;
+    return ((unsigned long long)a * (unsigned long long)b) >> 1;
+}
+
 // Valid-individual bits of words 4*w4 .. 4*w4+3 of a class of n individuals.
 EPI_DEV v4u valid_mask(int n, int w4) {
     v4u v;
@@ -275,6 +282,17 @@ EPI_DEV float screen_sum(const float *tab, const int (&F0)[CELLS], const int (&F
     return s;
 }
 
+// Same for counts scaled by 4, which are the byte offsets of their entries.
+template <int CELLS>
+EPI_DEV float screen_sum4(const float *tab, const int (&F0)[CELLS], const int (&F1)[CELLS]) {
+    const __attribute__((address_space(3))) char *l = (const __attribute__((address_space(3))) char *)tab;
+    float s = 0.f;
+    #pragma unroll
+    for (int x = 0; x < CELLS; ++x)
+        s += (*(lfloat *)(l + F0[x]) + *(lfloat *)(l + F1[x])) - *(lfloat *)(l + (F0[x] + F1[x]));
+    return s;
+}
+
 // Float bound below which a combination cannot reach `te` (num units).
 EPI_DEV float screen_bound(long long te, long long score_const, int shift, float ferr) {
     if (te == (long long)0x8000000000000000ull) return -__builtin_inff();
@@ -360,8 +378,9 @@ EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *li
             if (valid) {
                 v4u *pv = (v4u *)t.pairs;
                 const unsigned long long r = lexpair(i, m, d.M);
-                pv[2 * r + 0] = v4u{acc[p][0][0], acc[p][0][1], acc[p][0][2], acc[p][0][3]};
-                pv[2 * r + 1] = v4u{acc[p][1][0], acc[p][1][1], acc[p][1][2], acc[p][1][3]};
+                const int sh = t.cell_shift;
+                pv[2 * r + 0] = v4u{acc[p][0][0] << sh, acc[p][0][1] << sh, acc[p][0][2] << sh, acc[p][0][3] << sh};
+                pv[2 * r + 1] = v4u{acc[p][1][0] << sh, acc[p][1][1] << sh, acc[p][1][2] << sh, acc[p][1][3] << sh};
             }
         } else {
             const v4u si = single4[ip[p]];
@@ -551,9 +570,11 @@ EPI_DEV void item_f3(const Task &t, unsigned long long local, TopK &tk, Cand *li
 // matrix-core product per step of individuals, b and d: rows (i, a) are A,
 // the rows of genotype b of SNP j mask A, rows (m, d) are B.  With 4-bit
 // float operands (1.0 = 0x2; v_mfma_scale_f32_32x32x64_f8f6f4, 64
-// individuals per step) products are 0 or 1 and sums stay below 2^24, so the
+// individuals per step) products are 0 or 4 and sums stay below 2^24, so the
 // float accumulators hold the exact counts; 8-bit integer operands
-// (v_mfma_i32_32x32x32_i8, 32 per step) give the same integers.  In the 32 x 32 result,
+// (v_mfma_i32_32x32x32_i8, 32 per step) give the same integers.  B holds 4
+// for a set bit, so the sums are 4 n: a count is then the byte offset of its
+// entry in the float screening table.  In the 32 x 32 result,
 // lane l holds column l % 32 (SNP m) and rows 8 (r / 4) + 4 (l / 32) + r % 4
 // of its 16 registers r, i.e. both genotypes a of eight SNPs i; the epilogue
 // is that of the popcount kernel.
@@ -566,6 +587,8 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 constexpr int kBufWord3 = 0x00020000;
 // Steps of 64 individuals in flight per operand stream.
 constexpr int kQDepth = kQStepMultiple;
+// Steps whose j-mask rows are staged in LDS at a time (4 entries per step).
+constexpr int kQSeg = kQStageSteps;
 
 EPI_DEV v4u qload(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
     return __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
@@ -607,7 +630,7 @@ struct QFmt<true> {
 
 template <bool LDS, bool I8>
 EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr,
-                      const float *tab) {
+                      const float *tab, v4u *stage) {
     typedef QFmt<I8> Q;
     const DsView d = t.ds;
     const unsigned long long dsc = t.items[local];
@@ -619,12 +642,14 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
     const bool mv = m > j && m < d.M;
     const int m_ld = mv ? m : j + 1;
 
-    // sub-table rows the epilogue needs, issued before the counting loop
-    const v4u *single4 = (const v4u *)d.single;
-    const v4u *pair4 = (const v4u *)t.pairs;
-    const v4u sm = single4[m_ld];
-    const v4u sj = single4[j];
-    const unsigned long long rjm = lexpair(j, m_ld, d.M);
+    // sub-table rows the epilogue needs, issued before the counting loop; all
+    // counts below are 4 n (the pair sub-table is written that way, singles
+    // and class sizes are scaled here)
+    gv4u *single4 = (gv4u *)d.single;
+    gv4u *pair4 = (gv4u *)t.pairs;
+    const v4u sm = single4[m_ld] << kQScaleShift;
+    const v4u sj = single4[j] << kQScaleShift;
+    const unsigned long long rjm = pair_row(j, d.M) + (unsigned)(m_ld - j - 1);
     const v4u pjm0 = pair4[2 * rjm], pjm1 = pair4[2 * rjm + 1];
 
     // operands through buffer descriptors (scalar registers): a lane adds
@@ -641,7 +666,7 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
         __builtin_amdgcn_make_buffer_rsrc((void *)(qb + (long long)(2 * mb) * KS * 64), 0, blk, kBufWord3);
     const __amdgpu_buffer_rsrc_t rB1 =
         __builtin_amdgcn_make_buffer_rsrc((void *)(qb + (long long)(2 * mb + 1) * KS * 64), 0, blk, kBufWord3);
-    const int vo = lane * 16, vj = (32 * h + 2 * (j & 15)) * 16;
+    const int vo = lane * 16;
     typename Q::acc_t acc[2][2][2];
     #pragma unroll
     for (int c = 0; c < 2; ++c)
@@ -651,61 +676,82 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
             for (int e = 0; e < 2; ++e) acc[c][b][e] = (typename Q::acc_t){};
     // software pipeline: the operands of kQDepth steps are in flight while a
     // step is multiplied (a step's products take far less time than a load
-    // from L2).  Each class has a multiple of kQDepth steps (zero-padded).
+    // from L2).  The two mask rows of j are the same for every lane of a half
+    // wave: they are staged once per segment of kQSeg steps in the wave's LDS
+    // slot (entry 4 step + 2 h + b) and read back with broadcast loads.  Each
+    // class has a multiple of kQDepth steps (zero-padded).
+    lv4u *slot = (lv4u *)stage;
     #pragma unroll
     for (int c = 0; c < 2; ++c) {
-        const int s0 = c == 0 ? 0 : Q::ks(d, 0);
-        const int n = Q::ks(d, c);
-        v4u bA[kQDepth], bJ0[kQDepth], bJ1[kQDepth], bB0[kQDepth], bB1[kQDepth];
-        #pragma unroll
-        for (int u = 0; u < kQDepth; ++u) {
-            const int so = (s0 + u) * 1024;
-            bA[u] = qload(rA, vo, so);
-            bJ0[u] = qload(rJ, vj, so);
-            bJ1[u] = qload(rJ, vj + 16, so);
-            bB0[u] = qload(rB0, vo, so);
-            bB1[u] = qload(rB1, vo, so);
-        }
+        const int c0 = c == 0 ? 0 : Q::ks(d, 0);
+        const int cn = Q::ks(d, c);
         #pragma unroll 1
-        for (int k = 0; k < n; k += kQDepth) {
+        for (int seg = 0; seg < cn; seg += kQSeg) {
+            const int s0 = c0 + seg;
+            const int n = min(kQSeg, cn - seg);
+            #pragma unroll
+            for (int e0 = 0; e0 < 4 * kQSeg; e0 += kWave) {
+                const int e = e0 + lane;
+                if (e < 4 * n) {
+                    const int vje = (((e >> 2) * 64) + 32 * ((e >> 1) & 1) + 2 * (j & 15) + (e & 1)) * 16;
+                    slot[e] = qload(rJ, vje, s0 * 1024);
+                }
+            }
+            wave_sync();
+            v4u bA[kQDepth], bB0[kQDepth], bB1[kQDepth];
             #pragma unroll
             for (int u = 0; u < kQDepth; ++u) {
-                const v4u A0 = bA[u] & bJ0[u], A1 = bA[u] & bJ1[u];
-                acc[c][0][0] = Q::mma(A0, bB0[u], acc[c][0][0]);
-                acc[c][0][1] = Q::mma(A0, bB1[u], acc[c][0][1]);
-                acc[c][1][0] = Q::mma(A1, bB0[u], acc[c][1][0]);
-                acc[c][1][1] = Q::mma(A1, bB1[u], acc[c][1][1]);
-                // refill the slot (the last steps re-read the class's last step)
-                const int so = (s0 + min(k + u + kQDepth, n - 1)) * 1024;
+                const int so = (s0 + u) * 1024;
                 bA[u] = qload(rA, vo, so);
-                bJ0[u] = qload(rJ, vj, so);
-                bJ1[u] = qload(rJ, vj + 16, so);
                 bB0[u] = qload(rB0, vo, so);
                 bB1[u] = qload(rB1, vo, so);
             }
+            #pragma unroll 1
+            for (int k = 0; k < n; k += kQDepth) {
+                #pragma unroll
+                for (int u = 0; u < kQDepth; ++u) {
+                    const int js = 4 * (k + u) + 2 * h;
+                    const v4u J0 = slot[js], J1 = slot[js + 1];
+                    const v4u A0 = bA[u] & J0, A1 = bA[u] & J1;
+                    acc[c][0][0] = Q::mma(A0, bB0[u], acc[c][0][0]);
+                    acc[c][0][1] = Q::mma(A0, bB1[u], acc[c][0][1]);
+                    acc[c][1][0] = Q::mma(A1, bB0[u], acc[c][1][0]);
+                    acc[c][1][1] = Q::mma(A1, bB1[u], acc[c][1][1]);
+                    // refill the slot (the last steps re-read the segment's last step)
+                    const int so = (s0 + min(k + u + kQDepth, n - 1)) * 1024;
+                    bA[u] = qload(rA, vo, so);
+                    bB0[u] = qload(rB0, vo, so);
+                    bB1[u] = qload(rB1, vo, so);
+                }
+            }
+            wave_sync();  // the slot is rewritten by the next segment
         }
     }
 
     // the lane's eight SNPs i: i_local = 4 (u / 2) + 2 h + u % 2, genotype a in
     // register 4 (u / 2) + 2 (u % 2) + a
     const int i_base = ib * 16 + 2 * h;
-    unsigned long long rim = lexpair(min(i_base, j - 1), m_ld, d.M);
+    int i_n = min(i_base, j - 1);
+    unsigned long long row_n = pair_row(i_n, d.M);
+    unsigned long long rim = row_n + (unsigned)(m_ld - i_n - 1);
     v4u pim_n0 = pair4[2 * rim], pim_n1 = pair4[2 * rim + 1];
     #pragma unroll
     for (int u = 0; u < 8; ++u) {
         const int i = i_base + 4 * (u >> 1) + (u & 1);
-        const int i_ld = min(i, j - 1);
+        const int i_ld = i_n;
+        const unsigned long long row_i = row_n;
         const bool valid = mv && i < j;
         const v4u pim0 = pim_n0, pim1 = pim_n1;
         if (u + 1 < 8) {
             // next SNP's pair row, in flight while this one is scored
-            const int in = min(i_base + 4 * ((u + 1) >> 1) + ((u + 1) & 1), j - 1);
-            rim = lexpair(in, m_ld, d.M);
+            i_n = min(i_base + 4 * ((u + 1) >> 1) + ((u + 1) & 1), j - 1);
+            row_n = pair_row(i_n, d.M);
+            rim = row_n + (unsigned)(m_ld - i_n - 1);
             pim_n0 = pair4[2 * rim];
             pim_n1 = pair4[2 * rim + 1];
         }
-        const v4u si = single4[i_ld];
-        const unsigned long long rij = lexpair(i_ld, j, d.M);
+        const v4u si = single4[i_ld] << kQScaleShift;
+        const unsigned long long rij = row_i + (unsigned)(j - i_ld - 1);
         const int r0 = 4 * (u >> 1) + 2 * (u & 1);
         int F[2][27];
         #pragma unroll
@@ -738,18 +784,19 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
             F[c][18 + 5] = sj[2 * c + 1];
             F[c][24] = sm[2 * c + 0];
             F[c][25] = sm[2 * c + 1];
-            F[c][26] = d.ncls[c];
+            F[c][26] = d.ncls[c] << kQScaleShift;
             mobius3(F[c]);
         }
         bool pass = valid;
         if constexpr (LDS) {
             const float sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.ferr);
-            pass = pass && screen_sum<27>(tab, F[0], F[1]) >= sb;
+            pass = pass && screen_sum4<27>(tab, F[0], F[1]) >= sb;
         }
         if (__ballot(pass)) {
             long long num = t.score_const;
             #pragma unroll
-            for (int x = 0; x < 27; ++x) num += cell_term(d.tlog, F[0][x], F[1][x], (unsigned)d.N);
+            for (int x = 0; x < 27; ++x)
+                num += cell_term(d.tlog, F[0][x] >> kQScaleShift, F[1][x] >> kQScaleShift, (unsigned)d.N);
             const unsigned long long key =
                 ((unsigned long long)i << 42) | ((unsigned long long)j << 21) | (unsigned long long)m;
             tk_offer(tk, list, pass, num, key, gthr);
@@ -990,8 +1037,8 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
             case kF3:
                 if constexpr (NP3 == kNpMfma || NP3 == kNpMfmaI8) {
                     constexpr bool i8 = NP3 == kNpMfmaI8;
-                    if (lds) item_f3m<true, i8>(T, local, tk, s_list, gthr, s_tab);
-                    else item_f3m<false, i8>(T, local, tk, s_list, gthr, T.ds.ftab);
+                    if (lds) item_f3m<true, i8>(T, local, tk, s_list, gthr, s_tab, s_stage);
+                    else item_f3m<false, i8>(T, local, tk, s_list, gthr, T.ds.ftab, s_stage);
                 } else if constexpr (NP3 > 0) {
                     if (lds) item_f3<NP3, true>(T, local, tk, s_list, gthr, s_tab, s_stage, stage_cap);
                     else item_f3<NP3, false>(T, local, tk, s_list, gthr, T.ds.ftab, s_stage, stage_cap);
@@ -1254,7 +1301,8 @@ __global__ void singles_kernel(DsView d, uint32_t *__restrict__ single) {
 
 // Matrix-core operand copies of the genotype-0/1 rows: one thread per (SNP,
 // genotype, 64-individual step, half); each 32-individual mask word becomes
-// 32 4-bit floats (bit set -> 0x2 = 1.0), low nibble first.
+// 32 4-bit floats, low nibble first: 0x2 = 1.0 (qa) or 0x6 = 4.0 (qb) for a
+// set bit.
 __global__ void qpack_kernel(DsView d, v4u *__restrict__ qa, v4u *__restrict__ qb) {
     const long long KS = d.ks[0] + d.ks[1];
     const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1272,6 +1320,7 @@ __global__ void qpack_kernel(DsView d, v4u *__restrict__ qa, v4u *__restrict__ q
         gv4u *gm = (gv4u *)d.masks;
         word = gm[((long long)(d.wbase[c] + (widx >> 2)) * 2 + g) * d.Mp + s][widx & 3];
     }
+    // qa: 1.0 = 0x2 per set bit; qb: 4.0 = 0x6 (counts come out as 4 n)
     v4u out;
     #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -1284,11 +1333,12 @@ __global__ void qpack_kernel(DsView d, v4u *__restrict__ qa, v4u *__restrict__ q
         out[k] = x;
     }
     qa[((long long)(s >> 4) * KS + step) * 64 + 32 * h + 2 * (s & 15) + g] = out;
-    qb[(((long long)(s >> 5) * 2 + g) * KS + step) * 64 + 32 * h + (s & 31)] = out;
+    qb[(((long long)(s >> 5) * 2 + g) * KS + step) * 64 + 32 * h + (s & 31)] = out | (out << 1);
 }
 
 // Integer operand copies: one thread per (SNP, genotype, 32-individual step,
-// half); each 16-individual half word becomes 16 bytes of 0 / 1.
+// half); each 16-individual half word becomes 16 bytes, 1 (qa8) or 4 (qb8)
+// per set bit.
 __global__ void qpack8_kernel(DsView d, v4u *__restrict__ qa8, v4u *__restrict__ qb8) {
     const long long KS = d.ks8[0] + d.ks8[1];
     const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1316,7 +1366,7 @@ __global__ void qpack8_kernel(DsView d, v4u *__restrict__ qa8, v4u *__restrict__
         out[k] = x;
     }
     qa8[((long long)(s >> 4) * KS + step) * 64 + 32 * h + 2 * (s & 15) + g] = out;
-    qb8[(((long long)(s >> 5) * 2 + g) * KS + step) * 64 + 32 * h + (s & 31)] = out;
+    qb8[(((long long)(s >> 5) * 2 + g) * KS + step) * 64 + 32 * h + (s & 31)] = out << 2;  // 4 per set bit
 }
 
 // Class index map: idx[0 .. n_case) = input positions of the cases in input

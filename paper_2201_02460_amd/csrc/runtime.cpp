@@ -266,9 +266,9 @@ static int ds_alloc(Ctx *c, Dataset *d) {
     if ((rc = c->alloc.alloc(((size_t)d->N + 1) * 4, &d->ftab))) return rc;
     if ((rc = c->alloc.alloc(256, &d->err))) return rc;
     d->bytes = mask_bytes + (size_t)d->Mp * 16 + ((size_t)2 * d->N + 1) * 8 + (size_t)d->N * 4;
-    // float accumulation of 0/1 products is exact while a class count stays
-    // below 2^24
-    if (d->N < (1 << 24)) {
+    // float accumulation of 0/1 x 4 products is exact while 4 x a class count
+    // stays below 2^24
+    if (d->N < (1 << 22)) {
         if ((rc = c->alloc.alloc(qop_bytes(d), &d->qa))) return rc;
         if ((rc = c->alloc.alloc(qop_bytes(d), &d->qb))) return rc;
         d->bytes += 2 * qop_bytes(d);
@@ -536,7 +536,8 @@ int grid_for(Ctx *c, int np2, int np3, int gk, unsigned long long items, int tab
 // three 4-wave workgroups per CU next to an 8001-entry screening table).
 int stage_cap_for(int np2, int np3, int w4_max) {
     const bool mfma = np3 == kNpMfma || np3 == kNpMfmaI8;
-    const int rows = std::max(np2 > 0 ? 2 * np2 : 0, np3 > 0 && !mfma ? 2 * (np3 + 1) : 0);
+    if (mfma) return 4 * kQStageSteps;  // j-mask rows: 4 entries per step
+    const int rows = std::max(np2 > 0 ? 2 * np2 : 0, np3 > 0 ? 2 * (np3 + 1) : 0);
     if (rows == 0) return 0;
     return rows * std::max(1, std::min(w4_max, 16));
 }
@@ -735,6 +736,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
             t.np = s.emit_np;
             t.n_blocks = 0;
             t.order = 2;
+            t.cell_shift = (s.np == kNpMfma || s.np == kNpMfmaI8) ? kQScaleShift : 0;
         }
     }
     for (size_t gi = 0; gi < p->groups.size(); ++gi) {
@@ -1323,10 +1325,10 @@ int epi_set_prefix_block(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_
                                     block == kNpMfmaI8);
     if (!ok2 && !ok3) return fail(EPI_EINVAL, "prefix block %d is not a kernel of order %d", block, order);
     if (block == kNpMfma && !d->qa)
-        return fail(EPI_EUNSUPPORTED, "dataset %d has no matrix-core operands (2^24 individuals or more)", dataset_id);
+        return fail(EPI_EUNSUPPORTED, "dataset %d has no matrix-core operands (2^22 individuals or more)", dataset_id);
     if (block == kNpMfmaI8) {
-        if (d->N >= (1 << 24))
-            return fail(EPI_EUNSUPPORTED, "dataset %d: 2^24 individuals or more for the integer kernel", dataset_id);
+        if (d->N >= (1 << 22))
+            return fail(EPI_EUNSUPPORTED, "dataset %d: 2^22 individuals or more for the integer kernel", dataset_id);
         int rc = ds_ensure_i8(C, d);
         if (rc) return rc;
     }

@@ -211,6 +211,7 @@ static int run_round(Server *S) {
         t.item_base = emit_total;
         t.np = 4;
         t.order = 2;
+        t.cell_shift = (r->np == kNpMfma || r->np == kNpMfmaI8) ? kQScaleShift : 0;
         emit_total += r->emit_n;
         emit_w4 = std::max(emit_w4, std::max(r->ds->w4[0], r->ds->w4[1]));
         ht[ti++] = t;
