@@ -387,19 +387,25 @@ static void build_f2_items(int M, int np, std::vector<unsigned long long> &out) 
 // Work items of the order-3 kernel: (j, block ib of np SNPs i < j, block mb
 // of 64 SNPs m > j), descriptor j << 40 | ib << 20 | mb.
 //
-// Matrix-core blocks (np = kNpMfma): (16-SNP block ib of i, 32-SNP block mb of
-// m, j) for every j with some i < j < m in the blocks; j runs fastest, so
-// neighbouring items read the same i and m operand blocks.
+// Matrix-core blocks (np = kNpMfma, kNpMfmaI8): (16-SNP block ib of i, 32-SNP
+// block mb of m, j) for every j with some i < j < m in the blocks.  j runs
+// fastest, so neighbouring items read the same i and m operand blocks, and
+// the (ib, mb) blocks go in tiles of 4 x 4, so the items in flight across the
+// device share a few operand blocks in L2.
 static void build_f3_items(int M, int np, std::vector<unsigned long long> &out) {
     out.clear();
     if (np == kNpMfma || np == kNpMfmaI8) {
-        for (int ib = 0; ib * 16 < M; ++ib)
-            for (int mb = 0; mb * 32 < M; ++mb) {
-                const int j0 = std::max(1, ib * 16 + 1);
-                const int j1 = std::min(std::min(mb * 32 + 31, M - 1) - 1, M - 2);
-                for (int j = j0; j <= j1; ++j)
-                    out.push_back(((unsigned long long)j << 40) | ((unsigned long long)ib << 20) | (unsigned)mb);
-            }
+        const int T = 4;
+        for (int mt = 0; mt * 32 * T < M; ++mt)
+            for (int it = 0; it * 16 * T < M; ++it)
+                for (int mb = mt * T; mb < mt * T + T && mb * 32 < M; ++mb)
+                    for (int ib = it * T; ib < it * T + T && ib * 16 < M; ++ib) {
+                        const int j0 = std::max(1, ib * 16 + 1);
+                        const int j1 = std::min(std::min(mb * 32 + 31, M - 1) - 1, M - 2);
+                        for (int j = j0; j <= j1; ++j)
+                            out.push_back(((unsigned long long)j << 40) | ((unsigned long long)ib << 20) |
+                                          (unsigned)mb);
+                    }
         return;
     }
     for (int j = 1; j <= M - 2; ++j) {
