@@ -52,6 +52,8 @@ enum Variant : int32_t {
     kF2 = 1,       // order 2, reduced cells, prefix block of i's
     kF3 = 2,       // order 3, reduced cells, prefix block of i's sharing j
     kF2Emit = 3,   // order-2 reduced cells written to the pair sub-table
+    kF3Emit = 4,   // order-3 reduced cells written to the triplet sub-table (matrix cores)
+    kR4 = 5,       // order 4, reduced cells per lane, other cells from the sub-tables
 };
 
 struct DsView {
@@ -80,6 +82,7 @@ struct Cand {
 struct Task {
     DsView ds;
     uint32_t *pairs;                  // lex-ordered pair sub-table, 8 u32 per pair
+    uint32_t *triples;                // colex-ordered triplet sub-table, 16 u32 per triplet (kR4, kF3Emit)
     const unsigned long long *items;  // per-item descriptors: kF3 j<<40 | ib<<20 | mb, kF2 ib<<20 | mb
                                       // (kF3 with np = kNpMfma: 16-SNP i-block ib, 32-SNP m-block mb)
     unsigned long long n_items;

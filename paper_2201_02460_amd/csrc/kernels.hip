@@ -136,6 +136,23 @@ EPI_DEV void mobius3(int (&R)[27]) {
     for (int ab = 0; ab < 9; ++ab) R[3 * ab + 2] -= R[3 * ab] + R[3 * ab + 1];
 }
 
+EPI_DEV void mobius4(int (&R)[81]) {
+    #pragma unroll
+    for (int st = 27; st >= 1; st /= 3)
+        #pragma unroll
+        for (int x = 0; x < 81; ++x)
+            if ((x / st) % 3 == 2) R[x] -= R[x - 2 * st] + R[x - st];
+}
+
+// Sub-table passes keep no best-K list.
+EPI_DEV bool is_emit(int variant) { return variant == kF2Emit || variant == kF3Emit; }
+
+// Colex rank of x < y < z: C(z,3) + C(y,2) + x (z < 2^21).
+EPI_DEV unsigned long long colex3(int x, int y, int z) {
+    const unsigned long long Z = (unsigned long long)z, Y = (unsigned long long)y;
+    return Z * (Z - 1) * (Z - 2) / 6 + Y * (Y - 1) / 2 + (unsigned long long)x;
+}
+
 // ---------------------------------------------------------------------------
 // Per-wave best-K list in LDS (unsorted) with its current worst entry.
 // ---------------------------------------------------------------------------
@@ -628,7 +645,7 @@ struct QFmt<true> {
     }
 };
 
-template <bool LDS, bool I8>
+template <bool LDS, bool I8, bool EMIT = false>
 EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr,
                       const float *tab, v4u *stage) {
     typedef QFmt<I8> Q;
@@ -726,6 +743,29 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
             }
             wave_sync();  // the slot is rewritten by the next segment
         }
+    }
+
+    if constexpr (EMIT) {
+        // triplet sub-table: the counts (sums are 4 n) of the lane's eight
+        // triplets at their colex ranks, class 0 cells 4a + 2b + d first
+        gv4u *tv = (gv4u *)t.triples;
+        #pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = ib * 16 + 2 * h + 4 * (u >> 1) + (u & 1);
+            const int r0 = 4 * (u >> 1) + 2 * (u & 1);
+            if (mv && i < j) {
+                v4u *dst = (v4u *)(tv + 4 * colex3(i, j, m));
+                #pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    #pragma unroll
+                    for (int a = 0; a < 2; ++a)
+                        dst[2 * c + a] = v4u{(unsigned)acc[c][0][0][r0 + a] >> kQScaleShift,
+                                             (unsigned)acc[c][0][1][r0 + a] >> kQScaleShift,
+                                             (unsigned)acc[c][1][0][r0 + a] >> kQScaleShift,
+                                             (unsigned)acc[c][1][1][r0 + a] >> kQScaleShift};
+            }
+        }
+        return;
     }
 
     // the lane's eight SNPs i: i_local = 4 (u / 2) + 2 h + u % 2, genotype a in
@@ -922,6 +962,145 @@ EPI_DEV void item_generic(const Task &t, unsigned long long local, TopK &tk, Can
 }
 
 // ---------------------------------------------------------------------------
+// kR4: order 4 by reduced cells.  A work item is 64 * kGenRanks consecutive
+// colex ranks; lane l takes ranks l, l + 64, ... (as kGeneric).  A lane counts
+// the 16 cells of its combination whose four genotypes are all 0 or 1 (per 32
+// individuals: 4 pair ANDs, then one three-input AND and one popcount per
+// cell); every other cell follows by inclusion-exclusion from the triplet
+// sub-table (written by the matrix-core kernel), the pair sub-table and the
+// single-SNP counts, as for order 3.
+// ---------------------------------------------------------------------------
+template <bool LDS>
+EPI_DEV void item_r4(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr,
+                     const float *tab, const unsigned long long *binom, int bstride) {
+    const DsView d = t.ds;
+    const int bits = t.key_bits;
+    gv4u *gm = (gv4u *)d.masks;
+    gv4u *single4 = (gv4u *)d.single;
+    gv4u *pair4 = (gv4u *)t.pairs;
+    gv4u *trip4 = (gv4u *)t.triples;
+    const long long Mp = d.Mp;
+    #pragma unroll 1
+    for (int rr = 0; rr < kGenRanks; ++rr) {
+        unsigned long long rank = (local * kGenRanks + rr) * kWave + lane_id();
+        const bool valid = rank < t.n_combos;
+        rank = valid ? rank : 0ull;
+        int c[4];
+        colex_unrank<4>(rank, d.M, binom, bstride, c);
+        unsigned acc[2][16];
+        #pragma unroll
+        for (int cl = 0; cl < 2; ++cl) {
+            #pragma unroll
+            for (int x = 0; x < 16; ++x) acc[cl][x] = 0;
+            const int W = d.w4[cl];
+            long long off = (long long)d.wbase[cl] * 2 * Mp;
+            #pragma unroll 1
+            for (int w = 0; w < W; ++w, off += 2 * Mp) {
+                v4u r[4][2];
+                #pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    r[u][0] = gm[off + c[u]];
+                    r[u][1] = gm[off + Mp + c[u]];
+                }
+                #pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    unsigned p[4];
+                    #pragma unroll
+                    for (int ab = 0; ab < 4; ++ab) p[ab] = r[0][ab >> 1][q] & r[1][ab & 1][q];
+                    #pragma unroll
+                    for (int ab = 0; ab < 4; ++ab)
+                        #pragma unroll
+                        for (int ce = 0; ce < 4; ++ce)
+                            acc[cl][4 * ab + ce] =
+                                bcnt_acc(p[ab] & r[2][ce >> 1][q] & r[3][ce & 1][q], acc[cl][4 * ab + ce]);
+                }
+            }
+        }
+        // F[27 a + 9 b + 3 g + e]; digit 2 = marginal over that SNP
+        int F[2][81];
+        #pragma unroll
+        for (int x = 0; x < 81; ++x) {
+            const int a = x / 27, b = (x / 9) % 3, g = (x / 3) % 3, e = x % 3;
+            if (a < 2 && b < 2 && g < 2 && e < 2) {
+                F[0][x] = acc[0][8 * a + 4 * b + 2 * g + e];
+                F[1][x] = acc[1][8 * a + 4 * b + 2 * g + e];
+            }
+        }
+        // triplets: drop one SNP (its digit 2), cells 4a' + 2b' + d' of the rest
+        #pragma unroll
+        for (int drop = 0; drop < 4; ++drop) {
+            int s3[3], k = 0;
+            #pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (u != drop) s3[k++] = c[u];
+            const unsigned long long tr = colex3(s3[0], s3[1], s3[2]);
+            #pragma unroll
+            for (int cl = 0; cl < 2; ++cl) {
+                const v4u lo = trip4[4 * tr + 2 * cl], hi = trip4[4 * tr + 2 * cl + 1];
+                #pragma unroll
+                for (int y = 0; y < 8; ++y) {
+                    int dig[4], k2 = 0;
+                    #pragma unroll
+                    for (int u = 0; u < 4; ++u) dig[u] = u == drop ? 2 : (y >> (2 - k2++)) & 1;
+                    F[cl][27 * dig[0] + 9 * dig[1] + 3 * dig[2] + dig[3]] = y < 4 ? lo[y] : hi[y - 4];
+                }
+            }
+        }
+        // pairs: keep two SNPs
+        #pragma unroll
+        for (int u0 = 0; u0 < 4; ++u0)
+            #pragma unroll
+            for (int u1 = u0 + 1; u1 < 4; ++u1) {
+                const unsigned long long pr = lexpair(c[u0], c[u1], d.M);
+                #pragma unroll
+                for (int cl = 0; cl < 2; ++cl) {
+                    const v4u pv = pair4[2 * pr + cl];
+                    #pragma unroll
+                    for (int y = 0; y < 4; ++y) {
+                        int dig[4];
+                        #pragma unroll
+                        for (int u = 0; u < 4; ++u) dig[u] = u == u0 ? (y >> 1) : (u == u1 ? (y & 1) : 2);
+                        F[cl][27 * dig[0] + 9 * dig[1] + 3 * dig[2] + dig[3]] = pv[y];
+                    }
+                }
+            }
+        // singles and the class sizes
+        #pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const v4u sv = single4[c[u]];
+            #pragma unroll
+            for (int cl = 0; cl < 2; ++cl)
+                #pragma unroll
+                for (int g = 0; g < 2; ++g) {
+                    int dig[4];
+                    #pragma unroll
+                    for (int v = 0; v < 4; ++v) dig[v] = v == u ? g : 2;
+                    F[cl][27 * dig[0] + 9 * dig[1] + 3 * dig[2] + dig[3]] = sv[2 * cl + g];
+                }
+        }
+        F[0][80] = d.ncls[0];
+        F[1][80] = d.ncls[1];
+        mobius4(F[0]);
+        mobius4(F[1]);
+        bool pass = valid;
+        if constexpr (LDS) {
+            // 81 cells: at most 485 roundings, twice the 27-cell bound
+            const float sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, 2.f * d.ferr);
+            pass = pass && screen_sum<81>(tab, F[0], F[1]) >= sb;
+        }
+        if (__ballot(pass)) {
+            long long num = t.score_const;
+            #pragma unroll
+            for (int x = 0; x < 81; ++x) num += cell_term(d.tlog, F[0][x], F[1][x], (unsigned)d.N);
+            unsigned long long key = 0;
+            #pragma unroll
+            for (int u = 0; u < 4; ++u) key = (key << bits) | (unsigned long long)c[u];
+            tk_offer(tk, list, pass, num, key, gthr);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Persistent scan kernel: four independent waves per workgroup.  The
 // workgroup pops chunks of work items from a device queue that runs over the
 // concatenated item spaces of all tasks of the launch, in task order; each
@@ -986,7 +1165,7 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
                 if (tasks[mid].item_base <= first) lo = mid; else hi = mid - 1;
             }
             const Task &T0 = tasks[lo];
-            const bool want = (T0.variant == kF2 || T0.variant == kF3) && T0.ds.N + 1 <= tab_cap;
+            const bool want = (T0.variant == kF2 || T0.variant == kF3 || T0.variant == kR4) && T0.ds.N + 1 <= tab_cap;
             if (want && loaded != T0.ds.ftab) {
                 #pragma unroll 1
                 for (int x = threadIdx.x; x <= T0.ds.N; x += blockDim.x) s_tab[x] = T0.ds.ftab[x];
@@ -1003,7 +1182,7 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
                 if (tasks[mid].item_base <= item) lo = mid; else hi = mid - 1;
             }
             if (lo != cur) {
-                if (cur >= 0 && tasks[cur].variant != kF2Emit) {
+                if (cur >= 0 && !is_emit(tasks[cur].variant)) {
                     if (tk.n == tk.K && tk.wn > gthr && lane_id() == 0) atomicMax(tasks[cur].thr, bias(tk.wn));
                     tk_flush(tk, s_list, tasks[cur]);
                 }
@@ -1014,7 +1193,7 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
                 fresh = true;
             }
             const Task &T = tasks[cur];
-            if (fresh && T.variant != kF2Emit) {
+            if (fresh && !is_emit(T.variant)) {
                 long long g = 0;
                 if (lane_id() == 0) g = load_thr(T.thr);
                 g = (long long)rfl64((unsigned long long)g);
@@ -1034,6 +1213,15 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
                 if constexpr (NP2 > 0)
                     item_f2<NP2, true, false>(T, local, tk, s_list, gthr, T.ds.ftab, s_stage, stage_cap);
                 break;
+            case kF3Emit:
+                if constexpr (NP3 == kNpMfma) item_f3m<false, false, true>(T, local, tk, s_list, gthr, T.ds.ftab, s_stage);
+                break;
+            case kR4:
+                if constexpr (GK == 4) {
+                    if (lds) item_r4<true>(T, local, tk, s_list, gthr, s_tab, binom, bstride);
+                    else item_r4<false>(T, local, tk, s_list, gthr, T.ds.ftab, binom, bstride);
+                }
+                break;
             case kF3:
                 if constexpr (NP3 == kNpMfma || NP3 == kNpMfmaI8) {
                     constexpr bool i8 = NP3 == kNpMfmaI8;
@@ -1049,12 +1237,12 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
                 break;
             }
         }
-        if (cur >= 0 && tasks[cur].variant != kF2Emit && tk.n == tk.K && tk.wn > gthr) {
+        if (cur >= 0 && !is_emit(tasks[cur].variant) && tk.n == tk.K && tk.wn > gthr) {
             if (lane_id() == 0) atomicMax(tasks[cur].thr, bias(tk.wn));
             gthr = tk.wn;
         }
     }
-    if (cur >= 0 && tasks[cur].variant != kF2Emit) tk_flush(tk, s_list, tasks[cur]);
+    if (cur >= 0 && !is_emit(tasks[cur].variant)) tk_flush(tk, s_list, tasks[cur]);
 }
 
 // ---------------------------------------------------------------------------

@@ -445,6 +445,7 @@ void plan_free(Ctx *c, Plan *p) {
     p->graph = nullptr;
     for (auto &s : p->scans) {
         c->alloc.release(s.pairs);
+        c->alloc.release(s.triples);
         c->alloc.release(s.cand);
     }
     c->alloc.release(p->d_parts);
@@ -560,10 +561,17 @@ static void pick_tab_cap(const Plan *p, LaunchGroup &g) {
         const PlanScan &s = p->scans[i];
         g.kmax = std::max(g.kmax, s.desc.top_k);
         g.stage_cap = std::max(g.stage_cap, stage_cap_for(g.np2, g.np3, std::max(s.ds->w4[0], s.ds->w4[1])));
-        if ((s.variant == kF2 || s.variant == kF3) && s.ds->N + 1 <= Plan::kTabMax)
+        if ((s.variant == kF2 || s.variant == kF3 || s.variant == kR4) && s.ds->N + 1 <= Plan::kTabMax)
             g.tab_cap = std::max(g.tab_cap, s.ds->N + 1);
     }
 }
+
+// Order 4 by reduced cells needs the dataset's matrix-core operands (for the
+// triplet sub-table pass) and a triplet sub-table of C(M,3) x 64 bytes; larger
+// ones take the per-combination kernel.
+static constexpr unsigned long long kMaxTripleBytes = 8ull << 30;
+bool r4_fits(const Dataset *d) { return d->qa && binom_u64(d->M, 3) <= kMaxTripleBytes / 64; }
+static bool needs_pairs(const PlanScan &s) { return s.desc.order == 3 || s.variant == kR4; }
 
 int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool graph, Plan **out,
                int force_np) {
@@ -596,7 +604,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
             s.variant = kF3;
             s.np = force_np > 0 ? force_np : tuned_np(c, 3, s.ds);
         } else {
-            s.variant = kGeneric;
+            s.variant = o == 4 && r4_fits(s.ds) ? kR4 : kGeneric;
             s.np = kGenRanksHost;
             s.n_items = (s.n_combos + 64ull * kGenRanksHost - 1) / (64ull * kGenRanksHost);
         }
@@ -641,18 +649,27 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         if (s.variant == kF2 || s.variant == kF3) {
             if ((rc = get_items(c, s.variant, s.ds->M, s.np, &s.items, &s.n_items))) return cleanup(rc);
         }
-        if (s.desc.order == 3) {
+        if (needs_pairs(s)) {
             s.emit_np = 4;
             if ((rc = get_items(c, kF2, s.ds->M, s.emit_np, &s.emit_items_d, &s.emit_items))) return cleanup(rc);
             const size_t pb = (size_t)binom_u64(s.ds->M, 2) * 32;
             if ((rc = c->alloc.alloc(std::max<size_t>(pb, 32), &s.pairs))) return cleanup(rc);
         }
+        if (s.variant == kR4) {
+            if ((rc = get_items(c, kF3, s.ds->M, kNpMfma, &s.t3_items_d, &s.t3_items))) return cleanup(rc);
+            const size_t tb = (size_t)binom_u64(s.ds->M, 3) * 64;
+            if ((rc = c->alloc.alloc(std::max<size_t>(tb, 64), &s.triples))) return cleanup(rc);
+        }
     }
-    // tasks: [main tasks in scan order][emit tasks]
+    // tasks: [main tasks in scan order][pair passes][triplet passes]
     const int nt = n;
-    int n_emit = 0;
-    for (auto &s : p->scans) n_emit += s.desc.order == 3 ? 1 : 0;
+    int n_emit = 0, n_t3 = 0;
+    for (auto &s : p->scans) {
+        n_emit += needs_pairs(s) ? 1 : 0;
+        n_t3 += s.variant == kR4 ? 1 : 0;
+    }
     p->n_emit = n_emit;
+    p->n_t3 = n_t3;
     for (auto &g : p->groups) {
         unsigned long long tot = 0;
         for (int i : g.scans) tot += p->scans[i].n_items;
@@ -660,14 +677,20 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         pick_tab_cap(p.get(), g);
         g.grid = grid_for(c, g.np2, g.np3, g.gk, tot, g.tab_cap, g.kmax, g.stage_cap);
     }
-    // emit launch shape (kernel <4,0,0>)
-    unsigned long long emit_total = 0;
-    for (auto &s : p->scans) emit_total += s.desc.order == 3 ? s.emit_items : 0;
+    // pair-pass launch shape (kernel <4,0,0>) and triplet-pass shape (<0,kNpMfma,0>)
+    unsigned long long emit_total = 0, t3_total = 0;
+    for (auto &s : p->scans) {
+        emit_total += needs_pairs(s) ? s.emit_items : 0;
+        t3_total += s.variant == kR4 ? s.t3_items : 0;
+    }
     int emit_w4 = 1;
     for (auto &s : p->scans)
-        if (s.desc.order == 3) emit_w4 = std::max(emit_w4, std::max(s.ds->w4[0], s.ds->w4[1]));
+        if (needs_pairs(s)) emit_w4 = std::max(emit_w4, std::max(s.ds->w4[0], s.ds->w4[1]));
     p->emit_stage = stage_cap_for(4, 0, emit_w4);
     p->emit_grid = grid_for(c, 4, 0, 0, std::max<unsigned long long>(emit_total, 1), 0, 1, p->emit_stage);
+    p->t3_total = t3_total;
+    p->t3_stage = stage_cap_for(0, kNpMfma, 0);
+    p->t3_grid = grid_for(c, 0, kNpMfma, 0, std::max<unsigned long long>(t3_total, 1), 0, 1, p->t3_stage);
     // candidate buffers and result layout
     long long out_bytes = 0;
     for (int i = 0; i < n; ++i) {
@@ -686,7 +709,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         out_bytes += result_block_bytes(s.desc.top_k, s.desc.order);
     }
     p->out_bytes = out_bytes;
-    const int nq = (int)p->groups.size() + 1;
+    const int nq = (int)p->groups.size() + 2;  // pair pass, triplet pass, groups
     p->n_queues = nq;
     const size_t cnt_bytes = (size_t)nq * 8 + (size_t)nt * 8 + (size_t)nt * 4;
     if ((rc = c->alloc.alloc(cnt_bytes, &p->d_counters))) return cleanup(rc);
@@ -701,14 +724,16 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
     std::vector<ResultLayout> lay(nt);
     for (int i = 0; i < nt; ++i) lay[i] = p->scans[i].lay;
     HIPCHK(hipMemcpy(p->d_layout, lay.data(), nt * sizeof(ResultLayout), hipMemcpyHostToDevice));
-    // task array: [main tasks in scan order][emit tasks][per-group launch copies (persistent)]
-    std::vector<Task> tasks(nt + n_emit);
+    // task array: [main tasks in scan order][pair passes][triplet passes]
+    //             [per-group launch copies (persistent)]
+    std::vector<Task> tasks(nt + n_emit + n_t3);
     for (int i = 0; i < nt; ++i) {
         PlanScan &s = p->scans[i];
         Task &t = tasks[i];
         memset(&t, 0, sizeof t);
         t.ds = s.ds->view;
         t.pairs = (uint32_t *)s.pairs;
+        t.triples = (uint32_t *)s.triples;
         t.items = (const unsigned long long *)s.items;
         t.n_items = s.n_items;
         t.item_base = 0;
@@ -730,7 +755,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         unsigned long long base = 0;
         for (int i = 0; i < nt; ++i) {
             PlanScan &s = p->scans[i];
-            if (s.desc.order != 3) continue;
+            if (!needs_pairs(s)) continue;
             s.emit_task = e;
             Task &t = tasks[e++];
             t = tasks[i];
@@ -742,7 +767,22 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
             t.np = s.emit_np;
             t.n_blocks = 0;
             t.order = 2;
-            t.cell_shift = (s.np == kNpMfma || s.np == kNpMfmaI8) ? kQScaleShift : 0;
+            t.cell_shift = s.desc.order == 3 && (s.np == kNpMfma || s.np == kNpMfmaI8) ? kQScaleShift : 0;
+        }
+        base = 0;
+        for (int i = 0; i < nt; ++i) {
+            PlanScan &s = p->scans[i];
+            if (s.variant != kR4) continue;
+            s.t3_task = e;
+            Task &t = tasks[e++];
+            t = tasks[i];
+            t.variant = kF3Emit;
+            t.items = (const unsigned long long *)s.t3_items_d;
+            t.n_items = s.t3_items;
+            t.item_base = persistent ? base : 0;
+            base += s.t3_items;
+            t.np = kNpMfma;
+            t.order = 3;
         }
     }
     for (size_t gi = 0; gi < p->groups.size(); ++gi) {
@@ -784,6 +824,11 @@ static int plan_enqueue(Ctx *c, Plan *p, hipStream_t st, bool timing, unsigned l
                                c->d_binom, c->bstride, 0, 1, p->emit_stage));
         }
         ++q;
+        if (p->n_t3 > 0) {
+            HIPCHK(launch_scan(0, kNpMfma, 0, p->t3_grid, st, tasks + nt + p->n_emit, p->n_t3, p->t3_total,
+                               p->d_queues + q, c->d_binom, c->bstride, 0, 1, p->t3_stage));
+        }
+        ++q;
         if (timing && single) HIPCHK(hipEventRecord(p->ev[2], st));
         for (auto &g : p->groups) {
             HIPCHK(launch_scan(g.np2, g.np3, g.gk, g.grid, st, tasks + g.task_off, (int)g.scans.size(),
@@ -802,11 +847,18 @@ static int plan_enqueue(Ctx *c, Plan *p, hipStream_t st, bool timing, unsigned l
         for (int i = 0; i < nt; ++i) {
             PlanScan &s = p->scans[i];
             LaunchGroup &g = p->groups[i];
-            if (s.desc.order == 3) {
+            if (needs_pairs(s)) {
                 const int es = stage_cap_for(4, 0, std::max(s.ds->w4[0], s.ds->w4[1]));
                 const int eg = grid_for(c, 4, 0, 0, s.emit_items, 0, 1, es);
                 HIPCHK(launch_scan(4, 0, 0, eg, st, tasks + s.emit_task, 1, s.emit_items, p->d_queues + 0,
                                    c->d_binom, c->bstride, 0, 1, es));
+                HIPCHK(launch_init_counters(st, p->d_queues, 1, nullptr, nullptr, 0));
+            }
+            if (s.variant == kR4) {
+                const int ts = stage_cap_for(0, kNpMfma, 0);
+                const int tg = grid_for(c, 0, kNpMfma, 0, s.t3_items, 0, 1, ts);
+                HIPCHK(launch_scan(0, kNpMfma, 0, tg, st, tasks + s.t3_task, 1, s.t3_items, p->d_queues + 0,
+                                   c->d_binom, c->bstride, 0, 1, ts));
                 HIPCHK(launch_init_counters(st, p->d_queues, 1, nullptr, nullptr, 0));
             }
             if (timing && single) HIPCHK(hipEventRecord(p->ev[2], st));

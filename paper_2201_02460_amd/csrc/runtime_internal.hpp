@@ -66,6 +66,11 @@ struct PlanScan {
     unsigned long long emit_items = 0;
     const void *emit_items_d = nullptr;
     void *pairs = nullptr;
+    // order 4 by reduced cells: triplet sub-table pass
+    void *triples = nullptr;
+    int t3_task = -1;
+    unsigned long long t3_items = 0;
+    const void *t3_items_d = nullptr;
     void *cand = nullptr;
     unsigned cand_cap = 0;
     ResultLayout lay{};
@@ -90,6 +95,8 @@ struct Plan {
     int n_emit = 0, emit_grid = 1, emit_stage = 0, n_queues = 0;
     constexpr static int kTabMax = 16385;  // screening-table entries that may go to LDS
     unsigned long long emit_total = 0;
+    int n_t3 = 0, t3_grid = 1, t3_stage = 0;  // triplet sub-table pass (order 4 by reduced cells)
+    unsigned long long t3_total = 0;
     void *d_tasks = nullptr, *d_counters = nullptr, *d_results = nullptr, *d_layout = nullptr, *d_out = nullptr;
     void *d_parts = nullptr;
     void *h_out = nullptr;
@@ -163,6 +170,7 @@ int get_items(Ctx *c, int variant, int M, int np, const void **d, unsigned long 
 int check_desc(Ctx *c, const epi_scan_desc &d, Dataset **out);
 void pick_group_kernel(const std::vector<int> &orders, int np3_hint, int *np2, int *np3, int *gk);
 int group_of_order(int order);
+bool r4_fits(const Dataset *d);
 int tuned_np_lookup(Ctx *c, int order, const Dataset *d);
 int default_np3(Ctx *c, const Dataset *d);
 int grid_for(Ctx *c, int np2, int np3, int gk, unsigned long long items, int tab_cap, int kmax, int stage_cap);

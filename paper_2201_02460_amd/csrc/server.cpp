@@ -36,10 +36,10 @@ struct Request {
     std::string err;
     Clock::time_point t_submit, t_done;
     int variant = 0, np = 0, slot = -1;
-    const void *items = nullptr, *emit_items = nullptr;
-    unsigned long long n_items = 0, cursor = 0, emit_n = 0, n_combos = 0;
+    const void *items = nullptr, *emit_items = nullptr, *t3_items = nullptr;
+    unsigned long long n_items = 0, cursor = 0, emit_n = 0, t3_n = 0, n_combos = 0;
     bool emit_done = false;
-    void *pairs = nullptr, *cand = nullptr;
+    void *pairs = nullptr, *triples = nullptr, *cand = nullptr;
     unsigned cand_cap = 0;
     uint64_t footprint = 0;
     std::vector<char> out;  // result block copied from the device
@@ -92,8 +92,9 @@ static int round_group(const Request *r) {
 
 static void free_request_buffers(Server *S, Request *r) {
     S->ctx->alloc.release(r->pairs);
+    S->ctx->alloc.release(r->triples);
     S->ctx->alloc.release(r->cand);
-    r->pairs = r->cand = nullptr;
+    r->pairs = r->triples = r->cand = nullptr;
     if (r->slot >= 0) S->free_slots.push_back(r->slot);
     r->slot = -1;
     S->used -= r->footprint;
@@ -119,23 +120,30 @@ static int admit(Server *S, Request *r) {
         r->variant = kF3;
         r->np = default_np3(c, r->ds);
     } else {
-        r->variant = kGeneric;
+        r->variant = o == 4 && r4_fits(r->ds) ? kR4 : kGeneric;
         r->np = kGenRanksHost;
         r->n_items = (r->n_combos + 64ull * kGenRanksHost - 1) / (64ull * kGenRanksHost);
     }
+    const bool sub = o == 3 || r->variant == kR4;  // pair sub-table pass
     int rc;
-    if (r->variant != kGeneric && (rc = get_items(c, r->variant, r->ds->M, r->np, &r->items, &r->n_items))) return rc;
-    if (o == 3 && (rc = get_items(c, kF2, r->ds->M, 4, &r->emit_items, &r->emit_n))) return rc;
-    r->cand_cap = (unsigned)((unsigned long long)S->grid_max * 4 * r->desc.top_k + r->desc.top_k + 64);
-    const uint64_t pair_bytes = o == 3 ? binom_u64(r->ds->M, 2) * 32 : 0;
-    r->footprint = pair_bytes + (uint64_t)r->cand_cap * sizeof(Cand);
-    if (S->used + r->footprint > S->budget) return EPI_ENOMEM;
-    if (pair_bytes && (rc = c->alloc.alloc(pair_bytes, &r->pairs))) return rc;
-    if ((rc = c->alloc.alloc((size_t)r->cand_cap * sizeof(Cand), &r->cand))) {
-        c->alloc.release(r->pairs);
-        r->pairs = nullptr;
+    if ((r->variant == kF2 || r->variant == kF3) && (rc = get_items(c, r->variant, r->ds->M, r->np, &r->items, &r->n_items)))
         return rc;
-    }
+    if (sub && (rc = get_items(c, kF2, r->ds->M, 4, &r->emit_items, &r->emit_n))) return rc;
+    if (r->variant == kR4 && (rc = get_items(c, kF3, r->ds->M, kNpMfma, &r->t3_items, &r->t3_n))) return rc;
+    r->cand_cap = (unsigned)((unsigned long long)S->grid_max * 4 * r->desc.top_k + r->desc.top_k + 64);
+    const uint64_t pair_bytes = sub ? binom_u64(r->ds->M, 2) * 32 : 0;
+    const uint64_t trip_bytes = r->variant == kR4 ? binom_u64(r->ds->M, 3) * 64 : 0;
+    r->footprint = pair_bytes + trip_bytes + (uint64_t)r->cand_cap * sizeof(Cand);
+    if (S->used + r->footprint > S->budget) return EPI_ENOMEM;
+    auto undo = [&](int code) {
+        c->alloc.release(r->pairs);
+        c->alloc.release(r->triples);
+        r->pairs = r->triples = nullptr;
+        return code;
+    };
+    if (pair_bytes && (rc = c->alloc.alloc(pair_bytes, &r->pairs))) return undo(rc);
+    if (trip_bytes && (rc = c->alloc.alloc(trip_bytes, &r->triples))) return undo(rc);
+    if ((rc = c->alloc.alloc((size_t)r->cand_cap * sizeof(Cand), &r->cand))) return undo(rc);
     S->used += r->footprint;
     S->peak_bytes = std::max<uint64_t>(S->peak_bytes, S->used);
     r->slot = S->free_slots.back();
@@ -149,6 +157,7 @@ static Task make_task(Server *S, Request *r) {
     memset(&t, 0, sizeof t);
     t.ds = r->ds->view;
     t.pairs = (uint32_t *)r->pairs;
+    t.triples = (uint32_t *)r->triples;
     t.items = (const unsigned long long *)r->items;
     t.n_items = r->n_items;
     t.n_combos = r->n_combos;
@@ -203,7 +212,7 @@ static int run_round(Server *S) {
     int emit_w4 = 1;
     for (auto &pr : order) {
         Request *r = pr.first;
-        if (r->desc.order != 3 || r->emit_done) continue;
+        if ((r->desc.order != 3 && r->variant != kR4) || r->emit_done) continue;
         Task t = make_task(S, r);
         t.variant = kF2Emit;
         t.items = (const unsigned long long *)r->emit_items;
@@ -211,12 +220,29 @@ static int run_round(Server *S) {
         t.item_base = emit_total;
         t.np = 4;
         t.order = 2;
-        t.cell_shift = (r->np == kNpMfma || r->np == kNpMfmaI8) ? kQScaleShift : 0;
+        t.cell_shift = r->desc.order == 3 && (r->np == kNpMfma || r->np == kNpMfmaI8) ? kQScaleShift : 0;
         emit_total += r->emit_n;
         emit_w4 = std::max(emit_w4, std::max(r->ds->w4[0], r->ds->w4[1]));
         ht[ti++] = t;
     }
     const int n_emit = ti - emit_off;
+    // triplet sub-table passes of new reduced order-4 requests (matrix cores)
+    const int t3_off = ti;
+    unsigned long long t3_total = 0;
+    for (auto &pr : order) {
+        Request *r = pr.first;
+        if (r->variant != kR4 || r->emit_done) continue;
+        Task t = make_task(S, r);
+        t.variant = kF3Emit;
+        t.items = (const unsigned long long *)r->t3_items;
+        t.n_items = r->t3_n;
+        t.item_base = t3_total;
+        t.np = kNpMfma;
+        t.order = 3;
+        t3_total += r->t3_n;
+        ht[ti++] = t;
+    }
+    const int n_t3 = ti - t3_off;
     // launch groups by kernel instantiation
     struct G {
         int np2, np3, gk, off, n, tab_cap, kmax, stage;
@@ -245,7 +271,7 @@ static int run_round(Server *S) {
             g.n++;
             g.kmax = std::max(g.kmax, r->desc.top_k);
             g.stage = std::max(g.stage, stage_cap_for(g.np2, g.np3, std::max(r->ds->w4[0], r->ds->w4[1])));
-            if ((r->variant == kF2 || r->variant == kF3) && r->ds->N + 1 <= Plan::kTabMax)
+            if ((r->variant == kF2 || r->variant == kF3 || r->variant == kR4) && r->ds->N + 1 <= Plan::kTabMax)
                 g.tab_cap = std::max(g.tab_cap, r->ds->N + 1);
         }
         groups.push_back(g);
@@ -253,7 +279,7 @@ static int run_round(Server *S) {
     if (ti > S->max_round_tasks) return fail(EPI_EDEVICE, "server round task array overflow");
     SRV_HIPCHK(hipMemcpyAsync(S->d_tasks, ht, (size_t)ti * sizeof(Task), hipMemcpyHostToDevice, st));
     const Task *dt = (const Task *)S->d_tasks;
-    const int nq = 1 + (int)groups.size();
+    const int nq = 2 + (int)groups.size();
     if (nq > kQueues) return fail(EPI_EDEVICE, "server round has too many launch groups");
     SRV_HIPCHK(launch_init_counters(st, S->d_queues, nq, nullptr, nullptr, 0));
     if (n_emit > 0) {
@@ -262,11 +288,17 @@ static int run_round(Server *S) {
         SRV_HIPCHK(launch_scan(4, 0, 0, eg, st, dt + emit_off, n_emit, emit_total, S->d_queues, c->d_binom,
                                c->bstride, 0, 1, es));
     }
+    if (n_t3 > 0) {
+        const int ts = stage_cap_for(0, kNpMfma, 0);
+        const int tg = grid_for(c, 0, kNpMfma, 0, t3_total, 0, 1, ts);
+        SRV_HIPCHK(launch_scan(0, kNpMfma, 0, tg, st, dt + t3_off, n_t3, t3_total, S->d_queues + 1, c->d_binom,
+                               c->bstride, 0, 1, ts));
+    }
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         const G &g = groups[gi];
         const int grid = grid_for(c, g.np2, g.np3, g.gk, g.total, g.tab_cap, g.kmax, g.stage);
         SRV_HIPCHK(launch_scan(g.np2, g.np3, g.gk, std::min(grid, S->grid_max), st, dt + g.off, g.n, g.total,
-                               S->d_queues + 1 + gi, c->d_binom, c->bstride, g.tab_cap, g.kmax, g.stage));
+                               S->d_queues + 2 + gi, c->d_binom, c->bstride, g.tab_cap, g.kmax, g.stage));
     }
     // compact every request's candidates to its best K; finish the done ones
     SRV_HIPCHK(launch_merge(nt, st, dt, (Cand *)S->d_parts, (Cand *)S->d_results));
@@ -436,7 +468,7 @@ int epi_server_start(epi_ctx *ctx, const epi_server_config *cfg, int32_t *server
         S->grid_max = std::max(S->grid_max,
                                grid_for(C, k[0], k[1], k[2], ~0ull >> 8, 0, 1, stage_cap_for(k[0], k[1], 1)));
     const int A = cfg->max_active;
-    S->max_round_tasks = 3 * A + 4;
+    S->max_round_tasks = 4 * A + 4;  // main, pair passes, triplet passes, group copies
     S->out_block = result_block_bytes(EPI_MAX_TOP_K, EPI_MAX_ORDER);
     int rc;
     auto cleanup = [&](int code) {
