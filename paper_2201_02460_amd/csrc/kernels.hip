@@ -291,22 +291,27 @@ EPI_DEV void stage_rows(lv4u *slot, gv4u *gm, long long Mp, int wbase, int w0, i
 
 template <int CELLS>
 EPI_DEV float screen_sum(const float *tab, const int (&F0)[CELLS], const int (&F1)[CELLS]) {
-    // LDS reads cannot fault; the counts of valid lanes are always in range
-    lfloat *l = (lfloat *)tab;
+    // LDS reads cannot fault; the counts of valid lanes are always in range.
+    // The table sits at LDS address 0 (checked when it is loaded), so an
+    // entry's address is 4 n with no base to add.
+    (void)tab;
     float s = 0.f;
     #pragma unroll
-    for (int x = 0; x < CELLS; ++x) s += (l[F0[x]] + l[F1[x]]) - l[F0[x] + F1[x]];
+    for (int x = 0; x < CELLS; ++x)
+        s += (*(lfloat *)(uintptr_t)(4u * (unsigned)F0[x]) + *(lfloat *)(uintptr_t)(4u * (unsigned)F1[x])) -
+             *(lfloat *)(uintptr_t)(4u * (unsigned)(F0[x] + F1[x]));
     return s;
 }
 
 // Same for counts scaled by 4, which are the byte offsets of their entries.
 template <int CELLS>
 EPI_DEV float screen_sum4(const float *tab, const int (&F0)[CELLS], const int (&F1)[CELLS]) {
-    const __attribute__((address_space(3))) char *l = (const __attribute__((address_space(3))) char *)tab;
+    (void)tab;  // at LDS address 0: a scaled count is its entry's address
     float s = 0.f;
     #pragma unroll
     for (int x = 0; x < CELLS; ++x)
-        s += (*(lfloat *)(l + F0[x]) + *(lfloat *)(l + F1[x])) - *(lfloat *)(l + (F0[x] + F1[x]));
+        s += (*(lfloat *)(uintptr_t)(unsigned)F0[x] + *(lfloat *)(uintptr_t)(unsigned)F1[x]) -
+             *(lfloat *)(uintptr_t)(unsigned)(F0[x] + F1[x]);
     return s;
 }
 
@@ -1119,15 +1124,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(scan_w
 scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long total_items,
                 unsigned long long *__restrict__ queue, const unsigned long long *__restrict__ binom, int bstride,
                 int tab_cap, int kmax, int stage_cap) {
-    // dynamic LDS: [tab_cap floats: screening table of the current dataset]
-    //              [4 x kmax best-K lists][4 x stage_cap uint4: staged prefix rows]
+    // dynamic LDS (the kernel has no static LDS, so the screening table
+    // starts at LDS address 0 and a count's byte offset is its address):
+    //   [tab_cap floats: screening table of the current dataset]
+    //   [4 x kmax best-K lists][4 x stage_cap uint4: staged rows][2 x u64: queue chunk]
     extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
-    __shared__ unsigned long long s_chunk[2];
     float *s_tab = (float *)s_dyn;
     const int wave = uni((int)(threadIdx.x >> 6));  // wave index in the workgroup (uniform per wave)
-    Cand *s_list = (Cand *)(s_dyn + (((long long)tab_cap * 4 + 15) & ~15LL)) + wave * kmax;
-    v4u *s_stage = (v4u *)(s_dyn + (((long long)tab_cap * 4 + 15) & ~15LL) + (long long)4 * kmax * sizeof(Cand)) +
-                   wave * stage_cap;
+    const long long lists_off = ((long long)tab_cap * 4 + 15) & ~15LL;
+    const long long stage_off = lists_off + (long long)4 * kmax * sizeof(Cand);
+    Cand *s_list = (Cand *)(s_dyn + lists_off) + wave * kmax;
+    v4u *s_stage = (v4u *)(s_dyn + stage_off) + wave * stage_cap;
+    unsigned long long *s_chunk = (unsigned long long *)(s_dyn + stage_off + (long long)4 * stage_cap * sizeof(v4u));
     TopK tk;
     tk.n = 0;
     tk.K = 1;
@@ -1165,7 +1173,9 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
                 if (tasks[mid].item_base <= first) lo = mid; else hi = mid - 1;
             }
             const Task &T0 = tasks[lo];
-            const bool want = (T0.variant == kF2 || T0.variant == kF3 || T0.variant == kR4) && T0.ds.N + 1 <= tab_cap;
+            // the screening reads address the table from LDS address 0
+            const bool want = (T0.variant == kF2 || T0.variant == kF3 || T0.variant == kR4) &&
+                              T0.ds.N + 1 <= tab_cap && (unsigned)(uintptr_t)(lfloat *)s_tab == 0u;
             if (want && loaded != T0.ds.ftab) {
                 #pragma unroll 1
                 for (int x = threadIdx.x; x <= T0.ds.N; x += blockDim.x) s_tab[x] = T0.ds.ftab[x];
@@ -1646,7 +1656,7 @@ static const ScanKernelEntry kScanKernels[] = {
 
 size_t scan_lds_bytes(int tab_cap, int kmax, int stage_cap) {
     return (((size_t)tab_cap * 4 + 15) & ~(size_t)15) + (size_t)4 * kmax * sizeof(Cand) +
-           (size_t)4 * stage_cap * sizeof(v4u);
+           (size_t)4 * stage_cap * sizeof(v4u) + 2 * sizeof(unsigned long long);
 }
 
 ScanKernelFn find_scan_kernel(int np2, int np3, int gk) {
