@@ -93,6 +93,7 @@ struct Task {
     Cand *cand;                       // candidate sink
     unsigned int *cand_count;
     unsigned long long *thr;          // running lower bound of the K-th best num (sign-flipped int64)
+    unsigned int *hist;               // score histogram, kHistWords counters (null: none)
     unsigned int cand_cap;
     int32_t variant, order, top_k;
     int32_t np;                       // prefix block (kF2/kF3) or ranks per lane (kGeneric)
@@ -100,6 +101,14 @@ struct Task {
     int32_t key_bits;                 // bits per index in the packed key
     int32_t cell_shift;               // kF2Emit: pair cells are written as count << cell_shift
 };
+
+// Score histogram of a task: how many distinct combinations entered some
+// wave's best-K list, by the position of the leading bit of their num and the
+// next kHistFineBits bits (64 x 2^kHistFineBits counters).  It turns the
+// lists of all waves into one lower bound of the task's K-th best.
+constexpr int kHistFineBits = 5;
+constexpr int kHistFine = 1 << kHistFineBits;
+constexpr int kHistWords = 64 * kHistFine;
 
 // Matrix-core order-3 kernels count 4 x n (their B operand holds 4 for a set
 // bit), so a count is also the byte offset of its float-table entry; their

@@ -93,6 +93,61 @@ EPI_DEV bool better(long long an, unsigned long long ak, long long bn, unsigned 
     return an > bn || (an == bn && ak < bk);
 }
 
+// ---------------------------------------------------------------------------
+// Score histogram (layout in epi_internal.hpp).  A combination whose exact num
+// enters a wave's list is counted once, in the bin of its leading bit and the
+// next kHistFineBits bits; a bin's lower edge is at most the num of everything
+// counted in it.  Each combination is scored by one wave only, so K counts at
+// or above an edge are K distinct combinations at least that good: nothing
+// below the edge can be in the best K.  Counts read while other waves add to
+// them are never above the true ones, and leaving bins out only lowers a sum,
+// so a bound taken from any part of the histogram is valid.
+// ---------------------------------------------------------------------------
+EPI_DEV int hist_bin(long long num) {  // num > 0
+    const unsigned long long v = (unsigned long long)num;
+    const int e = 63 - __builtin_clzll(v);
+    const unsigned f = e >= kHistFineBits ? (unsigned)(v >> (e - kHistFineBits)) : (unsigned)(v << (kHistFineBits - e));
+    return e * kHistFine + (int)(f & (kHistFine - 1));
+}
+
+EPI_DEV long long hist_edge(int bin) {
+    const int e = bin / kHistFine;
+    const unsigned long long top = (unsigned long long)(kHistFine + bin % kHistFine);
+    return (long long)(e >= kHistFineBits ? top << (e - kHistFineBits) : top >> (kHistFineBits - e));
+}
+
+EPI_DEV unsigned wave_scan_incl(unsigned v) {
+    const int lane = lane_id();
+    #pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const unsigned o = __shfl_up(v, off);
+        if (lane >= off) v += o;
+    }
+    return v;
+}
+
+// Largest lower edge with at least K counted combinations at or above it, or
+// INT64_MIN.  The sum starts one leading-bit position above `top` (the
+// highest bin this wave has counted) and runs down over at most two windows
+// of 64 bins: a few round trips, however the scores are scaled.
+EPI_DEV long long hist_bound(const unsigned *h, int K, int top) {
+    const int lane = lane_id();
+    int start = top + kHistFine;
+    start = start < kHistWords - 1 ? start : kHistWords - 1;
+    unsigned carry = 0;
+    #pragma unroll 1
+    for (int w = 0; w < 2; ++w, start -= kWave) {
+        const int b = start - lane;
+        const unsigned c = b >= 0 ? __hip_atomic_load(h + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+        const unsigned cs = wave_scan_incl(c) + carry;
+        const unsigned long long m = __ballot(cs >= (unsigned)K);
+        if (m) return hist_edge(start - (int)__builtin_ctzll(m));
+        carry = (unsigned)__builtin_amdgcn_readlane((int)cs, kWave - 1);
+        if (start < kWave) break;
+    }
+    return (long long)0x8000000000000000ull;
+}
+
 // Rank of pair (x, y), x < y, in the lexicographic order of the pairs of M.
 EPI_DEV unsigned long long lexpair(long long x, long long y, long long M) {
     return (unsigned long long)(x * (2 * M - x - 1) / 2 + (y - x - 1));
@@ -160,7 +215,29 @@ struct TopK {
     int n, K, wi;
     long long wn;
     unsigned long long wk;
+    unsigned *hist;  // the task's score histogram (null: none)
+    int added;       // combinations counted since the bound was last taken
+    int top;         // highest histogram bin this wave has counted (-1: none)
 };
+
+// Count the combinations of the lanes with `counted` set: one atomic per
+// distinct bin of the wave, with the number of its lanes in that bin.
+EPI_DEV void hist_add(TopK &t, bool counted, long long num) {
+    counted = counted && num > 0;
+    unsigned long long pend = __ballot(counted);
+    if (!pend) return;
+    const int b = counted ? hist_bin(num) : -1;
+    t.added = 1;
+    while (pend) {
+        const int src = (int)__builtin_ctzll(pend);
+        const int bs = __builtin_amdgcn_readlane(b, src);
+        const unsigned long long same = pend & __ballot(b == bs);
+        if (lane_id() == src)
+            __hip_atomic_fetch_add(t.hist + bs, (unsigned)__popcll(same), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        t.top = bs > t.top ? bs : t.top;
+        pend &= ~same;
+    }
+}
 
 EPI_DEV void tk_recompute(TopK &t, const Cand *list) {
     const int lane = lane_id();
@@ -194,6 +271,9 @@ EPI_DEV void tk_recompute(TopK &t, const Cand *list) {
 EPI_DEV void tk_offer(TopK &t, Cand *list, bool valid, long long num, unsigned long long key, long long gthr) {
     bool want = valid && num >= gthr && (t.n < t.K || better(num, key, t.wn, t.wk));
     unsigned long long mask = __ballot(want);
+    // counted once the list is full or a bound exists: the unbounded filling
+    // of the lists at the start would only add contention
+    if (mask && t.hist && (t.n == t.K || gthr != (long long)0x8000000000000000ull)) hist_add(t, want, num);
     while (mask) {
         const int src = __builtin_ctzll(mask);
         const long long cn = (long long)readlane64((unsigned long long)num, src);
@@ -1142,6 +1222,9 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
     tk.wi = 0;
     tk.wn = 0;
     tk.wk = 0;
+    tk.hist = nullptr;
+    tk.added = 0;
+    tk.top = -1;
     int cur = -1;
     long long gthr = (long long)0x8000000000000000ull;
     const float *loaded = nullptr;  // dataset whose screening table is in s_tab
@@ -1183,7 +1266,6 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
                 loaded = T0.ds.ftab;
             }
         }
-        bool fresh = true;
         #pragma unroll 1
         for (unsigned long long item = first + wave; item < end; item += 4) {
             int lo = 0, hi = n_tasks - 1;
@@ -1199,16 +1281,18 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
                 cur = lo;
                 tk.n = 0;
                 tk.K = tasks[cur].top_k;
+                tk.hist = is_emit(tasks[cur].variant) ? nullptr : tasks[cur].hist;
+                tk.added = 0;
+                tk.top = -1;
                 gthr = (long long)0x8000000000000000ull;
-                fresh = true;
             }
             const Task &T = tasks[cur];
-            if (fresh && !is_emit(T.variant)) {
+            if (!is_emit(T.variant)) {
+                // the bound other waves have published, before every item
                 long long g = 0;
                 if (lane_id() == 0) g = load_thr(T.thr);
                 g = (long long)rfl64((unsigned long long)g);
                 gthr = g > gthr ? g : gthr;
-                fresh = false;
             }
             const unsigned long long local = item - T.item_base + T.first_item;
             const bool lds = loaded != nullptr && T.ds.ftab == loaded;
@@ -1245,6 +1329,15 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
             default:
                 if constexpr (GK > 0) item_generic<GK>(T, local, tk, s_list, gthr, binom, bstride);
                 break;
+            }
+            if (tk.added) {
+                // combinations were counted: raise and publish the bound
+                tk.added = 0;
+                const long long hb = hist_bound(tk.hist, tk.K, tk.top);
+                if (hb > gthr) {
+                    gthr = hb;
+                    if (lane_id() == 0) atomicMax(T.thr, bias(hb));
+                }
             }
         }
         if (cur >= 0 && !is_emit(tasks[cur].variant) && tk.n == tk.K && tk.wn > gthr) {
@@ -1625,13 +1718,14 @@ __global__ void reseed_kernel(const Task *__restrict__ tasks, const Cand *__rest
 
 // Counters of a launch sequence: queues, candidate counts, thresholds.
 __global__ void init_counters_kernel(unsigned long long *queues, int nq, unsigned *cand_counts,
-                                     unsigned long long *thrs, int n_tasks) {
-    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+                                     unsigned long long *thrs, int n_tasks, unsigned *hist) {
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (tid < nq) queues[tid] = 0;
     if (tid < n_tasks) {
         cand_counts[tid] = 0;
         thrs[tid] = 0;  // bias(INT64_MIN)
     }
+    if (hist && tid < (long long)n_tasks * kHistWords) hist[tid] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1704,10 +1798,11 @@ hipError_t launch_finalize(int n_tasks, int max_k, hipStream_t st, const Task *t
 }
 
 hipError_t launch_init_counters(hipStream_t st, unsigned long long *queues, int nq, unsigned *cand_counts,
-                                unsigned long long *thrs, int n_tasks) {
-    int n = nq > n_tasks ? nq : n_tasks;
-    hipLaunchKernelGGL(init_counters_kernel, dim3((n + 255) / 256), dim3(256), 0, st, queues, nq, cand_counts, thrs,
-                       n_tasks);
+                                unsigned long long *thrs, int n_tasks, unsigned *hist) {
+    long long n = nq > n_tasks ? nq : n_tasks;
+    if (hist && (long long)n_tasks * kHistWords > n) n = (long long)n_tasks * kHistWords;
+    hipLaunchKernelGGL(init_counters_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, queues, nq,
+                       cand_counts, thrs, n_tasks, hist);
     return hipGetLastError();
 }
 

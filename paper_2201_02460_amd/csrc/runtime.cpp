@@ -711,11 +711,12 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
     p->out_bytes = out_bytes;
     const int nq = (int)p->groups.size() + 2;  // pair pass, triplet pass, groups
     p->n_queues = nq;
-    const size_t cnt_bytes = (size_t)nq * 8 + (size_t)nt * 8 + (size_t)nt * 4;
+    const size_t cnt_bytes = (size_t)nq * 8 + (size_t)nt * 8 + (size_t)nt * 4 + (size_t)nt * kHistWords * 4;
     if ((rc = c->alloc.alloc(cnt_bytes, &p->d_counters))) return cleanup(rc);
     p->d_queues = (unsigned long long *)p->d_counters;
     p->d_thr = p->d_queues + nq;
     p->d_cand_count = (unsigned *)(p->d_thr + nt);
+    p->d_hist = p->d_cand_count + nt;
     if ((rc = c->alloc.alloc((size_t)nt * kMaxTopK * sizeof(Cand), &p->d_results))) return cleanup(rc);
     if ((rc = c->alloc.alloc((size_t)nt * kMergeParts * kMaxTopK * sizeof(Cand), &p->d_parts))) return cleanup(rc);
     if ((rc = c->alloc.alloc((size_t)nt * sizeof(ResultLayout), &p->d_layout))) return cleanup(rc);
@@ -742,6 +743,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         t.cand = (Cand *)s.cand;
         t.cand_count = p->d_cand_count + i;
         t.thr = p->d_thr + i;
+        t.hist = p->d_hist + (size_t)i * kHistWords;
         t.cand_cap = s.cand_cap;
         t.variant = s.variant;
         t.order = s.desc.order;
@@ -814,7 +816,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
 static int plan_enqueue(Ctx *c, Plan *p, hipStream_t st, bool timing, unsigned long long item_cap) {
     const Task *tasks = (const Task *)p->d_tasks;
     const int nt = (int)p->scans.size();
-    HIPCHK(launch_init_counters(st, p->d_queues, p->n_queues, p->d_cand_count, p->d_thr, nt));
+    HIPCHK(launch_init_counters(st, p->d_queues, p->n_queues, p->d_cand_count, p->d_thr, nt, p->d_hist));
     int q = 0;
     const bool single = nt == 1 && !p->persistent;
     if (timing && single) HIPCHK(hipEventRecord(p->ev[1], st));
@@ -852,19 +854,19 @@ static int plan_enqueue(Ctx *c, Plan *p, hipStream_t st, bool timing, unsigned l
                 const int eg = grid_for(c, 4, 0, 0, s.emit_items, 0, 1, es);
                 HIPCHK(launch_scan(4, 0, 0, eg, st, tasks + s.emit_task, 1, s.emit_items, p->d_queues + 0,
                                    c->d_binom, c->bstride, 0, 1, es));
-                HIPCHK(launch_init_counters(st, p->d_queues, 1, nullptr, nullptr, 0));
+                HIPCHK(launch_init_counters(st, p->d_queues, 1, nullptr, nullptr, 0, nullptr));
             }
             if (s.variant == kR4) {
                 const int ts = stage_cap_for(0, kNpMfma, 0);
                 const int tg = grid_for(c, 0, kNpMfma, 0, s.t3_items, 0, 1, ts);
                 HIPCHK(launch_scan(0, kNpMfma, 0, tg, st, tasks + s.t3_task, 1, s.t3_items, p->d_queues + 0,
                                    c->d_binom, c->bstride, 0, 1, ts));
-                HIPCHK(launch_init_counters(st, p->d_queues, 1, nullptr, nullptr, 0));
+                HIPCHK(launch_init_counters(st, p->d_queues, 1, nullptr, nullptr, 0, nullptr));
             }
             if (timing && single) HIPCHK(hipEventRecord(p->ev[2], st));
             HIPCHK(launch_scan(g.np2, g.np3, g.gk, g.grid, st, tasks + i, 1, std::min(s.n_items, item_cap),
                                p->d_queues + 1, c->d_binom, c->bstride, g.tab_cap, g.kmax, g.stage_cap));
-            HIPCHK(launch_init_counters(st, p->d_queues + 1, 1, nullptr, nullptr, 0));
+            HIPCHK(launch_init_counters(st, p->d_queues + 1, 1, nullptr, nullptr, 0, nullptr));
             if (timing && single) HIPCHK(hipEventRecord(p->ev[3], st));
             HIPCHK(launch_merge(1, st, tasks + i, (Cand *)p->d_parts + (size_t)i * kMergeParts * kMaxTopK,
                                 (Cand *)p->d_results + (size_t)i * kMaxTopK));

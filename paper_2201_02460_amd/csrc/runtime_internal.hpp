@@ -102,6 +102,7 @@ struct Plan {
     void *h_out = nullptr;
     unsigned long long *d_queues = nullptr, *d_thr = nullptr;
     unsigned *d_cand_count = nullptr;
+    unsigned *d_hist = nullptr;  // kHistWords per scan
     long long out_bytes = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -155,7 +156,7 @@ hipError_t launch_merge(int n_tasks, hipStream_t st, const Task *tasks, Cand *pa
 hipError_t launch_finalize(int n_tasks, int max_k, hipStream_t st, const Task *tasks, const Cand *results,
                            const ResultLayout *layout, char *out);
 hipError_t launch_init_counters(hipStream_t st, unsigned long long *queues, int nq, unsigned *cand_counts,
-                                unsigned long long *thrs, int n_tasks);
+                                unsigned long long *thrs, int n_tasks, unsigned *hist);
 hipError_t launch_reseed(int n_tasks, hipStream_t st, const Task *tasks, const Cand *results);
 hipError_t launch_pack(hipStream_t st, const uint8_t *geno, long long ld, const int32_t *idx, const DsView &d,
                        v4u *masks, int *err);

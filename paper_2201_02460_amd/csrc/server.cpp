@@ -67,6 +67,7 @@ struct Server {
          *d_out = nullptr;
     void *h_tasks = nullptr, *h_out = nullptr, *h_layout = nullptr;
     unsigned long long *d_queues = nullptr, *d_thr = nullptr;
+    unsigned *d_hist = nullptr;  // kHistWords per slot
     unsigned *d_cand_count = nullptr;
     long long out_block = 0;
     int max_round_tasks = 0;
@@ -165,6 +166,7 @@ static Task make_task(Server *S, Request *r) {
     t.cand = (Cand *)r->cand;
     t.cand_count = S->d_cand_count + r->slot;
     t.thr = S->d_thr + r->slot;
+    t.hist = S->d_hist + (size_t)r->slot * kHistWords;
     t.cand_cap = r->cand_cap;
     t.variant = r->variant;
     t.order = r->desc.order;
@@ -187,7 +189,8 @@ static int run_round(Server *S) {
     // newly admitted requests: zero their counters
     for (auto &r : S->active)
         if (!r->emit_done && r->cursor == 0) {
-            SRV_HIPCHK(launch_init_counters(st, nullptr, 0, S->d_cand_count + r->slot, S->d_thr + r->slot, 1));
+            SRV_HIPCHK(launch_init_counters(st, nullptr, 0, S->d_cand_count + r->slot, S->d_thr + r->slot, 1,
+                                            S->d_hist + (size_t)r->slot * kHistWords));
         }
     // slices: finishing requests first (their merge results feed finalize)
     const double na = (double)std::max<size_t>(1, S->active.size());
@@ -281,7 +284,7 @@ static int run_round(Server *S) {
     const Task *dt = (const Task *)S->d_tasks;
     const int nq = 2 + (int)groups.size();
     if (nq > kQueues) return fail(EPI_EDEVICE, "server round has too many launch groups");
-    SRV_HIPCHK(launch_init_counters(st, S->d_queues, nq, nullptr, nullptr, 0));
+    SRV_HIPCHK(launch_init_counters(st, S->d_queues, nq, nullptr, nullptr, 0, nullptr));
     if (n_emit > 0) {
         const int es = stage_cap_for(4, 0, emit_w4);
         const int eg = grid_for(c, 4, 0, 0, emit_total, 0, 1, es);
@@ -477,10 +480,13 @@ int epi_server_start(epi_ctx *ctx, const epi_server_config *cfg, int32_t *server
     };
     // queue counters: one for the pair pass and one per launch group (at most
     // eight groups: order 2, order 3 per prefix block, orders 4 and 5)
-    if ((rc = C->alloc.alloc((size_t)kQueues * 8 + (size_t)A * 8 + (size_t)A * 4, &S->d_counters))) return cleanup(rc);
+    if ((rc = C->alloc.alloc((size_t)kQueues * 8 + (size_t)A * 8 + (size_t)A * 4 + (size_t)A * kHistWords * 4,
+                             &S->d_counters)))
+        return cleanup(rc);
     S->d_queues = (unsigned long long *)S->d_counters;
     S->d_thr = S->d_queues + kQueues;
     S->d_cand_count = (unsigned *)(S->d_thr + A);
+    S->d_hist = S->d_cand_count + A;
     if ((rc = C->alloc.alloc((size_t)S->max_round_tasks * sizeof(Task), &S->d_tasks))) return cleanup(rc);
     if ((rc = C->alloc.alloc((size_t)A * kMaxTopK * sizeof(Cand), &S->d_results))) return cleanup(rc);
     if ((rc = C->alloc.alloc((size_t)A * kMergeParts * kMaxTopK * sizeof(Cand), &S->d_parts))) return cleanup(rc);
