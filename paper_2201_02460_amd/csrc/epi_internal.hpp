@@ -13,6 +13,10 @@
 //   single  : u32 [Mp][2 classes][2 genotypes] per-SNP class counts of
 //             genotypes 0 and 1.
 //   tlog    : i64 [2N + 1], tlog[n] = round(n * ln(n) * 2^shift).
+//   itab    : u32 [2N + 2], t(n) = round(n * ln(n) * 2^tq) mod 2^32 at entries
+//             n = 0 .. N and again at entries 2N + 1 - n (the screening table;
+//             copied to LDS address 0, t(n) is at byte 4n and at byte
+//             q3_bias(N) - 4n).
 //   qa, qb  : the same genotype-0/1 rows as 4-bit floats (e2m1: qa 0x2 = 1.0,
 //             qb 0x6 = 4.0, 0x0 = 0), in the operand order of the 32x32x64 matrix-core
 //             product: one 16-byte entry per lane = 32 individuals of one row.
@@ -60,10 +64,11 @@ struct DsView {
     const v4u *masks;
     const uint32_t *single;
     const long long *tlog;
-    const float *ftab;     // float(n ln n), n = 0 .. N (screening table)
+    const uint32_t *itab;  // screening table: t(n) = round(n ln n 2^tq) mod 2^32 for
+                           // n = 0 .. N, then the same values for n = N .. 0
     const v4u *qa, *qb;    // 4-bit-float operand copies of the masks
     const v4u *qa8, *qb8;  // 8-bit-integer operand copies (null until selected)
-    float ferr;            // bound on the float screening sum error
+    int32_t tq;            // fixed-point scale of itab (2^tq per unit of n ln n)
     int32_t M, Mp, N, shift;
     int32_t ncls[2];
     int32_t w4[2];
@@ -100,6 +105,7 @@ struct Task {
     int32_t n_blocks;                 // number of prefix blocks (kF2: i-blocks, kF3: j values + 1)
     int32_t key_bits;                 // bits per index in the packed key
     int32_t cell_shift;               // kF2Emit: pair cells are written as count << cell_shift
+    uint32_t cell_bias;               // kF2Emit: if nonzero, as cell_bias - (count << cell_shift)
 };
 
 // Score histogram of a task: how many distinct combinations entered some
@@ -111,9 +117,15 @@ constexpr int kHistFine = 1 << kHistFineBits;
 constexpr int kHistWords = 64 * kHistFine;
 
 // Matrix-core order-3 kernels count 4 x n (their B operand holds 4 for a set
-// bit), so a count is also the byte offset of its float-table entry; their
-// pair sub-tables are written with cell_shift = kQScaleShift to match.
+// bit), so a count is also the byte offset of its screening-table entry;
+// their pair sub-tables are written as q3_bias(N) - 4 n (cell_shift =
+// kQScaleShift, cell_bias = q3_bias(N)): the cell form their inclusion-
+// exclusion works in.
 constexpr int kQScaleShift = 2;
+
+// Byte offset just past the screening table's two halves (2N + 2 entries):
+// t(n) of the second half sits at q3_bias(N) - 4 n.
+constexpr uint32_t q3_bias(int N) { return 8u * (uint32_t)N + 4u; }
 
 // Per-task result block written by the finalize kernel:
 //   int32 n_valid, int32 pad[3],

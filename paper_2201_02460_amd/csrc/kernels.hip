@@ -51,6 +51,14 @@ EPI_DEV unsigned bcnt_acc(unsigned x, unsigned acc) {
     return r;
 }
 
+// a + b + c as one v_add3_u32 (the compiler splits sums with a subtracted
+// term into two-operand adds and subtracts).
+EPI_DEV unsigned add3(unsigned a, unsigned b, unsigned c) {
+    unsigned r;
+    asm("v_add3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
 EPI_DEV unsigned long long rfl64(unsigned long long v) {
     unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
     unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
@@ -199,6 +207,25 @@ EPI_DEV void mobius4(int (&R)[81]) {
             if ((x / st) % 3 == 2) R[x] -= R[x - 2 * st] + R[x - st];
 }
 
+// Cells with an odd number of digits 2 (index 9a + 3b + e), held as B - 4n
+// by the matrix-core order-3 epilogue.
+constexpr bool odd_twos3(int x) { return ((x / 9 == 2) + ((x / 3) % 3 == 2) + (x % 3 == 2)) & 1; }
+
+// mobius3 on the signed cell form (B - 4n for odd_twos3 cells, 4n for the
+// others, each marginal input offset so that the result comes out in that
+// form): a genotype-2 cell is its marginal minus the genotype-0 and -1 cells,
+// which the form turns into one sum of three.
+EPI_DEV void mobius3_signed(unsigned (&R)[27]) {
+    #pragma unroll
+    for (int r = 0; r < 9; ++r) R[18 + r] += R[r] + R[9 + r];
+    #pragma unroll
+    for (int a = 0; a < 3; ++a)
+        #pragma unroll
+        for (int e = 0; e < 3; ++e) R[9 * a + 6 + e] += R[9 * a + e] + R[9 * a + 3 + e];
+    #pragma unroll
+    for (int ab = 0; ab < 9; ++ab) R[3 * ab + 2] += R[3 * ab] + R[3 * ab + 1];
+}
+
 // Sub-table passes keep no best-K list.
 EPI_DEV bool is_emit(int variant) { return variant == kF2Emit || variant == kF3Emit; }
 
@@ -341,15 +368,22 @@ EPI_DEV long long cell_term_counted(const long long *T, unsigned n0, unsigned n1
 // ---------------------------------------------------------------------------
 // Score screening.  A combination can only enter a wave's best-K list if its
 // score reaches te (the task's global bound, or the list's current worst once
-// the list is full).  A float sum of the same cell terms from the float table
-// (the workgroup's LDS copy, reloaded when a chunk of work starts a dataset
-// whose table fits) differs from the exact score by at most ds.ferr,
-// so combinations whose float sum is below the bound minus that margin skip
-// the exact int64 sum; the exact path is unchanged.  Datasets whose table is
-// not in LDS take the exact path for every combination.
+// the list is full).  The same cell terms summed from the 32-bit table t(n) =
+// round(n ln n 2^tq) (the workgroup's LDS copy, reloaded when a chunk of work
+// starts a dataset whose table fits) give the score to within one unit of
+// 2^-tq per table value read, so combinations whose sum is below the bound
+// by more than that skip the exact int64 sum; the exact path is unchanged.
+// The sums are taken modulo 2^32: only the result, at most 2^30 in size,
+// needs to fit.  Datasets whose table is not in LDS take the exact path for
+// every combination.
 // ---------------------------------------------------------------------------
-typedef __attribute__((address_space(3))) const float lfloat;
+typedef __attribute__((address_space(3))) const unsigned lu32;
 typedef __attribute__((address_space(3))) v4u lv4u;
+
+// The table sits at LDS address 0 (checked when it is loaded), so an entry's
+// address is its byte offset with no base to add.  LDS reads cannot fault;
+// the counts of valid lanes are always in range.
+EPI_DEV unsigned ltab(unsigned byte) { return *(lu32 *)(uintptr_t)byte; }
 
 // Stage the genotype-0/1 rows of `nsnp` wave-uniform SNPs (snp_of(r) for row
 // pair r) over words [w0, w0 + wn) of class c into the wave's LDS slot:
@@ -369,37 +403,68 @@ EPI_DEV void stage_rows(lv4u *slot, gv4u *gm, long long Mp, int wbase, int w0, i
     wave_sync();
 }
 
+// Screening sum of CELLS cells of plain counts (entry n at byte 4n).
 template <int CELLS>
-EPI_DEV float screen_sum(const float *tab, const int (&F0)[CELLS], const int (&F1)[CELLS]) {
-    // LDS reads cannot fault; the counts of valid lanes are always in range.
-    // The table sits at LDS address 0 (checked when it is loaded), so an
-    // entry's address is 4 n with no base to add.
-    (void)tab;
-    float s = 0.f;
+EPI_DEV int screen_sum(const int (&F0)[CELLS], const int (&F1)[CELLS]) {
+    unsigned p = 0, q = 0;
     #pragma unroll
-    for (int x = 0; x < CELLS; ++x)
-        s += (*(lfloat *)(uintptr_t)(4u * (unsigned)F0[x]) + *(lfloat *)(uintptr_t)(4u * (unsigned)F1[x])) -
-             *(lfloat *)(uintptr_t)(4u * (unsigned)(F0[x] + F1[x]));
-    return s;
+    for (int x = 0; x < CELLS; ++x) {
+        p += ltab(4u * (unsigned)F0[x]) + ltab(4u * (unsigned)F1[x]);
+        q += ltab(4u * (unsigned)(F0[x] + F1[x]));
+    }
+    return (int)(p - q);
 }
 
 // Same for counts scaled by 4, which are the byte offsets of their entries.
 template <int CELLS>
-EPI_DEV float screen_sum4(const float *tab, const int (&F0)[CELLS], const int (&F1)[CELLS]) {
-    (void)tab;  // at LDS address 0: a scaled count is its entry's address
-    float s = 0.f;
+EPI_DEV int screen_sum4(const int (&F0)[CELLS], const int (&F1)[CELLS]) {
+    unsigned p = 0, q = 0;
     #pragma unroll
-    for (int x = 0; x < CELLS; ++x)
-        s += (*(lfloat *)(uintptr_t)(unsigned)F0[x] + *(lfloat *)(uintptr_t)(unsigned)F1[x]) -
-             *(lfloat *)(uintptr_t)(unsigned)(F0[x] + F1[x]);
-    return s;
+    for (int x = 0; x < CELLS; ++x) {
+        p += ltab((unsigned)F0[x]) + ltab((unsigned)F1[x]);
+        q += ltab((unsigned)(F0[x] + F1[x]));
+    }
+    return (int)(p - q);
 }
 
-// Float bound below which a combination cannot reach `te` (num units).
-EPI_DEV float screen_bound(long long te, long long score_const, int shift, float ferr) {
-    if (te == (long long)0x8000000000000000ull) return -__builtin_inff();
-    const double v = ldexp((double)(te - score_const), -shift);
-    return (float)v - 2.0f * ferr - 1e-3f;
+// Same for the signed cell form of the matrix-core order-3 epilogue; with
+// REV the table's second half is in LDS and a B - 4n cell is its address
+// there, else it is turned back into 4n.
+template <bool REV>
+EPI_DEV int screen_sum_q3(const unsigned (&F0)[27], const unsigned (&F1)[27], unsigned B) {
+    const unsigned nB = 0u - B;
+    unsigned p = 0, q = 0, qh = 0;
+    #pragma unroll
+    for (int x = 0; x < 27; ++x) {
+        unsigned a0 = F0[x], a1 = F1[x], s;
+        if (odd_twos3(x)) {
+            if constexpr (REV) {
+                s = add3(a0, a1, nB);  // B - 4 (n0 + n1)
+            } else {
+                a0 = B - a0;
+                a1 = B - a1;
+                s = a0 + a1;
+            }
+        } else {
+            s = a0 + a1;
+        }
+        p = add3(p, ltab(a0), ltab(a1));
+        // the subtracted terms in pairs
+        if (x & 1) q = add3(q, qh, ltab(s));
+        else qh = ltab(s);
+    }
+    return (int)(p - q - qh);
+}
+
+// Smallest screening sum of a combination whose num can reach te, for sums
+// of `reads` table values.  Each table value and each exact term is within
+// 1/2 of its scaled n ln n, so a sum and the num it screens for differ by at
+// most reads units of 2^-tq (tq <= shift); one more unit covers the rounding
+// of the scaled bound.
+EPI_DEV int screen_bound(long long te, long long score_const, int shift, int tq, int reads) {
+    if (te == (long long)0x8000000000000000ull) return (int)0x80000000u;
+    const double v = ldexp((double)(te - score_const), tq - shift);
+    return (int)floor(v) - reads - 1;
 }
 
 EPI_DEV long long entry_bound(const TopK &tk, long long gthr) {
@@ -411,8 +476,8 @@ EPI_DEV long long entry_bound(const TopK &tk, long long gthr) {
 // SNPs m > i); lane = m.  Reduced cells (a, d) in {0,1}^2 per class.
 // ---------------------------------------------------------------------------
 template <int NP, bool EMIT, bool LDS>
-EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr,
-                     const float *tab, v4u *stage, int stage_cap) {
+EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr, v4u *stage,
+                     int stage_cap) {
     const DsView d = t.ds;
     const unsigned long long dsc = t.items[local];
     const int ib = uni((int)((dsc >> 20) & 0xfffffu));
@@ -481,8 +546,14 @@ EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *li
                 v4u *pv = (v4u *)t.pairs;
                 const unsigned long long r = lexpair(i, m, d.M);
                 const int sh = t.cell_shift;
-                pv[2 * r + 0] = v4u{acc[p][0][0] << sh, acc[p][0][1] << sh, acc[p][0][2] << sh, acc[p][0][3] << sh};
-                pv[2 * r + 1] = v4u{acc[p][1][0] << sh, acc[p][1][1] << sh, acc[p][1][2] << sh, acc[p][1][3] << sh};
+                v4u c0 = v4u{acc[p][0][0] << sh, acc[p][0][1] << sh, acc[p][0][2] << sh, acc[p][0][3] << sh};
+                v4u c1 = v4u{acc[p][1][0] << sh, acc[p][1][1] << sh, acc[p][1][2] << sh, acc[p][1][3] << sh};
+                if (t.cell_bias) {
+                    c0 = t.cell_bias - c0;
+                    c1 = t.cell_bias - c1;
+                }
+                pv[2 * r + 0] = c0;
+                pv[2 * r + 1] = c1;
             }
         } else {
             const v4u si = single4[ip[p]];
@@ -502,8 +573,8 @@ EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *li
             }
             bool pass = valid;
             if constexpr (LDS) {
-                const float sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.ferr);
-                pass = pass && screen_sum<9>(tab, F[0], F[1]) >= sb;
+                const int sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.tq, 27);
+                pass = pass && screen_sum<9>(F[0], F[1]) >= sb;
             }
             if (__ballot(pass)) {
                 long long num = t.score_const;
@@ -522,8 +593,8 @@ EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *li
 // other cell comes from the pair sub-table and the single-SNP counts.
 // ---------------------------------------------------------------------------
 template <int NP, bool LDS>
-EPI_DEV void item_f3(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr,
-                     const float *tab, v4u *stage, int stage_cap) {
+EPI_DEV void item_f3(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr, v4u *stage,
+                     int stage_cap) {
     const DsView d = t.ds;
     const unsigned long long dsc = t.items[local];
     const int j = uni((int)((dsc >> 40) & 0xfffffu));
@@ -649,8 +720,8 @@ EPI_DEV void item_f3(const Task &t, unsigned long long local, TopK &tk, Cand *li
         }
         bool pass = valid;
         if constexpr (LDS) {
-            const float sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.ferr);
-            pass = pass && screen_sum<27>(tab, F[0], F[1]) >= sb;
+            const int sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.tq, 81);
+            pass = pass && screen_sum<27>(F[0], F[1]) >= sb;
         }
         if (__ballot(pass)) {
             long long num = t.score_const;
@@ -730,9 +801,8 @@ struct QFmt<true> {
     }
 };
 
-template <bool LDS, bool I8, bool EMIT = false>
-EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr,
-                      const float *tab, v4u *stage) {
+template <bool LDS, bool REV, bool I8, bool EMIT = false>
+EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr, v4u *stage) {
     typedef QFmt<I8> Q;
     const DsView d = t.ds;
     const unsigned long long dsc = t.items[local];
@@ -745,12 +815,16 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
     const int m_ld = mv ? m : j + 1;
 
     // sub-table rows the epilogue needs, issued before the counting loop; all
-    // counts below are 4 n (the pair sub-table is written that way, singles
-    // and class sizes are scaled here)
+    // counts below are 4 n, in the signed form of the epilogue (the pair
+    // sub-table is written that way, singles and class sizes are put in it
+    // here)
     gv4u *single4 = (gv4u *)d.single;
     gv4u *pair4 = (gv4u *)t.pairs;
-    const v4u sm = single4[m_ld] << kQScaleShift;
-    const v4u sj = single4[j] << kQScaleShift;
+    const unsigned B = q3_bias(d.N), B4 = 4u * B;
+    const v4u sm = (single4[m_ld] << kQScaleShift) - B4;
+    const v4u sj = (single4[j] << kQScaleShift) - B4;
+    const unsigned nall[2] = {13u * B - ((unsigned)d.ncls[0] << kQScaleShift),
+                              13u * B - ((unsigned)d.ncls[1] << kQScaleShift)};
     const unsigned long long rjm = pair_row(j, d.M) + (unsigned)(m_ld - j - 1);
     const v4u pjm0 = pair4[2 * rjm], pjm1 = pair4[2 * rjm + 1];
 
@@ -853,13 +927,23 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
         return;
     }
 
-    // the lane's eight SNPs i: i_local = 4 (u / 2) + 2 h + u % 2, genotype a in
-    // register 4 (u / 2) + 2 (u % 2) + a
+    // Cells F[c][9a + 3b + e] (digit 2: marginal over that SNP, genotype 2
+    // once the inclusion-exclusion has run) in the signed form: a cell with
+    // an odd number of digits 2 is held as B - 4n, the others as 4n (B =
+    // q3_bias(N)).  Each inclusion-exclusion step is then one three-input add
+    // (mobius3_signed), and both forms are byte addresses of the LDS table,
+    // which holds t(n) at 4n and at B - 4n.  The marginal inputs come in the
+    // forms that make the steps come out so: pair cells B - 4n (as the pair
+    // pass writes them), single-SNP cells 4n - 4B, the class size 13B - 4n.
+    // The lane's eight SNPs i: i_local = 4 (u / 2) + 2 h + u % 2, genotype a
+    // in register 4 (u / 2) + 2 (u % 2) + a.
     const int i_base = ib * 16 + 2 * h;
     int i_n = min(i_base, j - 1);
     unsigned long long row_n = pair_row(i_n, d.M);
     unsigned long long rim = row_n + (unsigned)(m_ld - i_n - 1);
     v4u pim_n0 = pair4[2 * rim], pim_n1 = pair4[2 * rim + 1];
+    int sb = 0;
+    if constexpr (LDS) sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.tq, 81);
     #pragma unroll
     for (int u = 0; u < 8; ++u) {
         const int i = i_base + 4 * (u >> 1) + (u & 1);
@@ -875,22 +959,21 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
             pim_n0 = pair4[2 * rim];
             pim_n1 = pair4[2 * rim + 1];
         }
-        const v4u si = single4[i_ld] << kQScaleShift;
+        const v4u si = (single4[i_ld] << kQScaleShift) - B4;
         const unsigned long long rij = row_i + (unsigned)(j - i_ld - 1);
         const int r0 = 4 * (u >> 1) + 2 * (u & 1);
-        int F[2][27];
+        unsigned F[2][27];
         #pragma unroll
         for (int c = 0; c < 2; ++c) {
             const v4u pij = pair4[2 * rij + c];
             const v4u pim = c == 0 ? pim0 : pim1;
             const v4u pjm = c == 0 ? pjm0 : pjm1;
-            // F[a*9 + b*3 + e]; index 2 on an axis = marginal over that SNP
             #pragma unroll
             for (int a = 0; a < 2; ++a)
                 #pragma unroll
                 for (int b = 0; b < 2; ++b)
                     #pragma unroll
-                    for (int e = 0; e < 2; ++e) F[c][9 * a + 3 * b + e] = (int)acc[c][b][e][r0 + a];
+                    for (int e = 0; e < 2; ++e) F[c][9 * a + 3 * b + e] = (unsigned)(int)acc[c][b][e][r0 + a];
             #pragma unroll
             for (int a = 0; a < 2; ++a)
                 #pragma unroll
@@ -909,22 +992,23 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
             F[c][18 + 5] = sj[2 * c + 1];
             F[c][24] = sm[2 * c + 0];
             F[c][25] = sm[2 * c + 1];
-            F[c][26] = d.ncls[c] << kQScaleShift;
-            mobius3(F[c]);
+            F[c][26] = nall[c];
+            mobius3_signed(F[c]);
         }
         bool pass = valid;
-        if constexpr (LDS) {
-            const float sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.ferr);
-            pass = pass && screen_sum4<27>(tab, F[0], F[1]) >= sb;
-        }
+        if constexpr (LDS) pass = pass && screen_sum_q3<REV>(F[0], F[1], B) >= sb;
         if (__ballot(pass)) {
             long long num = t.score_const;
             #pragma unroll
-            for (int x = 0; x < 27; ++x)
-                num += cell_term(d.tlog, F[0][x] >> kQScaleShift, F[1][x] >> kQScaleShift, (unsigned)d.N);
+            for (int x = 0; x < 27; ++x) {
+                const unsigned n0 = (odd_twos3(x) ? B - F[0][x] : F[0][x]) >> kQScaleShift;
+                const unsigned n1 = (odd_twos3(x) ? B - F[1][x] : F[1][x]) >> kQScaleShift;
+                num += cell_term(d.tlog, (int)n0, (int)n1, (unsigned)d.N);
+            }
             const unsigned long long key =
                 ((unsigned long long)i << 42) | ((unsigned long long)j << 21) | (unsigned long long)m;
             tk_offer(tk, list, pass, num, key, gthr);
+            if constexpr (LDS) sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.tq, 81);
         }
     }
 }
@@ -1057,7 +1141,7 @@ EPI_DEV void item_generic(const Task &t, unsigned long long local, TopK &tk, Can
 // ---------------------------------------------------------------------------
 template <bool LDS>
 EPI_DEV void item_r4(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr,
-                     const float *tab, const unsigned long long *binom, int bstride) {
+                     const unsigned long long *binom, int bstride) {
     const DsView d = t.ds;
     const int bits = t.key_bits;
     gv4u *gm = (gv4u *)d.masks;
@@ -1169,9 +1253,8 @@ EPI_DEV void item_r4(const Task &t, unsigned long long local, TopK &tk, Cand *li
         mobius4(F[1]);
         bool pass = valid;
         if constexpr (LDS) {
-            // 81 cells: at most 485 roundings, twice the 27-cell bound
-            const float sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, 2.f * d.ferr);
-            pass = pass && screen_sum<81>(tab, F[0], F[1]) >= sb;
+            const int sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.tq, 243);
+            pass = pass && screen_sum<81>(F[0], F[1]) >= sb;
         }
         if (__ballot(pass)) {
             long long num = t.score_const;
@@ -1209,7 +1292,7 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
     //   [tab_cap floats: screening table of the current dataset]
     //   [4 x kmax best-K lists][4 x stage_cap uint4: staged rows][2 x u64: queue chunk]
     extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
-    float *s_tab = (float *)s_dyn;
+    unsigned *s_tab = (unsigned *)s_dyn;
     const int wave = uni((int)(threadIdx.x >> 6));  // wave index in the workgroup (uniform per wave)
     const long long lists_off = ((long long)tab_cap * 4 + 15) & ~15LL;
     const long long stage_off = lists_off + (long long)4 * kmax * sizeof(Cand);
@@ -1227,7 +1310,8 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
     tk.top = -1;
     int cur = -1;
     long long gthr = (long long)0x8000000000000000ull;
-    const float *loaded = nullptr;  // dataset whose screening table is in s_tab
+    const uint32_t *loaded = nullptr;  // dataset whose screening table is in s_tab
+    bool loaded_rev = false;           // both halves of it (else the first)
     // Guided self-scheduling, one queue atomic per chunk of 4 x `per` items for
     // the whole workgroup; the chunk shrinks with the remaining work (estimated
     // from the last chunk).  Wave w takes items first + w, first + w + 4, ...
@@ -1256,14 +1340,19 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
                 if (tasks[mid].item_base <= first) lo = mid; else hi = mid - 1;
             }
             const Task &T0 = tasks[lo];
-            // the screening reads address the table from LDS address 0
-            const bool want = (T0.variant == kF2 || T0.variant == kF3 || T0.variant == kR4) &&
-                              T0.ds.N + 1 <= tab_cap && (unsigned)(uintptr_t)(lfloat *)s_tab == 0u;
-            if (want && loaded != T0.ds.ftab) {
+            // the screening reads address the table from LDS address 0; both
+            // halves when they fit, else the first
+            const int ent_fwd = T0.ds.N + 1, ent_rev = 2 * T0.ds.N + 2;
+            const bool want = (T0.variant == kF2 || T0.variant == kF3 || T0.variant == kR4) && ent_fwd <= tab_cap &&
+                              (unsigned)(uintptr_t)(lu32 *)s_tab == 0u;
+            const bool rev = want && ent_rev <= tab_cap;
+            if (want && (loaded != T0.ds.itab || loaded_rev != rev)) {
+                const int ent = rev ? ent_rev : ent_fwd;
                 #pragma unroll 1
-                for (int x = threadIdx.x; x <= T0.ds.N; x += blockDim.x) s_tab[x] = T0.ds.ftab[x];
+                for (int x = threadIdx.x; x < ent; x += blockDim.x) s_tab[x] = T0.ds.itab[x];
                 __syncthreads();
-                loaded = T0.ds.ftab;
+                loaded = T0.ds.itab;
+                loaded_rev = rev;
             }
         }
         #pragma unroll 1
@@ -1295,35 +1384,36 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
                 gthr = g > gthr ? g : gthr;
             }
             const unsigned long long local = item - T.item_base + T.first_item;
-            const bool lds = loaded != nullptr && T.ds.ftab == loaded;
+            const bool lds = loaded != nullptr && T.ds.itab == loaded;
             switch (T.variant) {
             case kF2:
                 if constexpr (NP2 > 0) {
-                    if (lds) item_f2<NP2, false, true>(T, local, tk, s_list, gthr, s_tab, s_stage, stage_cap);
-                    else item_f2<NP2, false, false>(T, local, tk, s_list, gthr, T.ds.ftab, s_stage, stage_cap);
+                    if (lds) item_f2<NP2, false, true>(T, local, tk, s_list, gthr, s_stage, stage_cap);
+                    else item_f2<NP2, false, false>(T, local, tk, s_list, gthr, s_stage, stage_cap);
                 }
                 break;
             case kF2Emit:
                 if constexpr (NP2 > 0)
-                    item_f2<NP2, true, false>(T, local, tk, s_list, gthr, T.ds.ftab, s_stage, stage_cap);
+                    item_f2<NP2, true, false>(T, local, tk, s_list, gthr, s_stage, stage_cap);
                 break;
             case kF3Emit:
-                if constexpr (NP3 == kNpMfma) item_f3m<false, false, true>(T, local, tk, s_list, gthr, T.ds.ftab, s_stage);
+                if constexpr (NP3 == kNpMfma) item_f3m<false, false, false, true>(T, local, tk, s_list, gthr, s_stage);
                 break;
             case kR4:
                 if constexpr (GK == 4) {
-                    if (lds) item_r4<true>(T, local, tk, s_list, gthr, s_tab, binom, bstride);
-                    else item_r4<false>(T, local, tk, s_list, gthr, T.ds.ftab, binom, bstride);
+                    if (lds) item_r4<true>(T, local, tk, s_list, gthr, binom, bstride);
+                    else item_r4<false>(T, local, tk, s_list, gthr, binom, bstride);
                 }
                 break;
             case kF3:
                 if constexpr (NP3 == kNpMfma || NP3 == kNpMfmaI8) {
                     constexpr bool i8 = NP3 == kNpMfmaI8;
-                    if (lds) item_f3m<true, i8>(T, local, tk, s_list, gthr, s_tab, s_stage);
-                    else item_f3m<false, i8>(T, local, tk, s_list, gthr, T.ds.ftab, s_stage);
+                    if (lds && loaded_rev) item_f3m<true, true, i8>(T, local, tk, s_list, gthr, s_stage);
+                    else if (lds) item_f3m<true, false, i8>(T, local, tk, s_list, gthr, s_stage);
+                    else item_f3m<false, false, i8>(T, local, tk, s_list, gthr, s_stage);
                 } else if constexpr (NP3 > 0) {
-                    if (lds) item_f3<NP3, true>(T, local, tk, s_list, gthr, s_tab, s_stage, stage_cap);
-                    else item_f3<NP3, false>(T, local, tk, s_list, gthr, T.ds.ftab, s_stage, stage_cap);
+                    if (lds) item_f3<NP3, true>(T, local, tk, s_list, gthr, s_stage, stage_cap);
+                    else item_f3<NP3, false>(T, local, tk, s_list, gthr, s_stage, stage_cap);
                 }
                 break;
             default:

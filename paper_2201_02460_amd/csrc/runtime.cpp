@@ -183,6 +183,18 @@ static int choose_shift(int N) {
     return std::min(40, std::max(8, s));
 }
 
+// Scale of the 32-bit screening table: a combination's screening sum is
+// 2^tq times its score minus the class-split constant, which lies in
+// [-N ln 2, 0] (Eq. 2: minus the entropy of the class within each cell,
+// summed over the cells); 2^tq (N ln 2 + 1) <= 2^30 keeps it, with the
+// rounding of the table values, inside int32, and the sum may wrap on the
+// way there.  tq <= shift keeps the screening margin at one unit per value.
+static int choose_tq(int N, int shift) {
+    const double span = (double)N * std::log(2.0) + 1.0;
+    const int q = (int)std::floor(30.0 - std::log2(span));
+    return std::max(0, std::min(q, shift));
+}
+
 // round(n ln n * 2^shift) for n = 0 .. 2N (entries past N keep clamped
 // lookups in bounds; valid tables never reach them).
 static void build_tlog(int N, int shift, std::vector<long long> &out) {
@@ -195,14 +207,14 @@ static void ds_free(Ctx *c, Dataset *d) {
     c->alloc.release(d->masks);
     c->alloc.release(d->single);
     c->alloc.release(d->tlog);
-    c->alloc.release(d->ftab);
+    c->alloc.release(d->itab);
     c->alloc.release(d->idx);
     c->alloc.release(d->err);
     c->alloc.release(d->qa);
     c->alloc.release(d->qb);
     c->alloc.release(d->qa8);
     c->alloc.release(d->qb8);
-    d->masks = d->single = d->tlog = d->ftab = d->idx = d->err = d->qa = d->qb = d->qa8 = d->qb8 = nullptr;
+    d->masks = d->single = d->tlog = d->itab = d->idx = d->err = d->qa = d->qb = d->qa8 = d->qb8 = nullptr;
 }
 
 static int ds_layout(Dataset *d, int M, int N, int n_case) {
@@ -220,6 +232,7 @@ static int ds_layout(Dataset *d, int M, int N, int n_case) {
     d->ks8[0] = (d->n_case + q8 - 1) / q8 * kQStepMultiple;
     d->ks8[1] = (d->n_ctrl + q8 - 1) / q8 * kQStepMultiple;
     d->shift = choose_shift(N);
+    d->tq = choose_tq(N, d->shift);
     return EPI_OK;
 }
 
@@ -228,8 +241,8 @@ static void ds_view(Dataset *d) {
     v.masks = (const v4u *)d->masks;
     v.single = (const uint32_t *)d->single;
     v.tlog = (const long long *)d->tlog;
-    v.ftab = (const float *)d->ftab;
-    v.ferr = d->ferr;
+    v.itab = (const uint32_t *)d->itab;
+    v.tq = d->tq;
     v.M = d->M;
     v.Mp = d->Mp;
     v.N = d->N;
@@ -263,7 +276,7 @@ static int ds_alloc(Ctx *c, Dataset *d) {
     if ((rc = c->alloc.alloc((size_t)d->Mp * 16, &d->single))) return rc;
     if ((rc = c->alloc.alloc(((size_t)2 * d->N + 1) * 8, &d->tlog))) return rc;
     if ((rc = c->alloc.alloc((size_t)d->N * 4, &d->idx))) return rc;
-    if ((rc = c->alloc.alloc(((size_t)d->N + 1) * 4, &d->ftab))) return rc;
+    if ((rc = c->alloc.alloc(((size_t)2 * d->N + 2) * 4, &d->itab))) return rc;
     if ((rc = c->alloc.alloc(256, &d->err))) return rc;
     d->bytes = mask_bytes + (size_t)d->Mp * 16 + ((size_t)2 * d->N + 1) * 8 + (size_t)d->N * 4;
     // float accumulation of 0/1 x 4 products is exact while 4 x a class count
@@ -277,14 +290,16 @@ static int ds_alloc(Ctx *c, Dataset *d) {
     std::vector<long long> tl;
     build_tlog(d->N, d->shift, tl);
     HIPCHK(hipMemcpy(d->tlog, tl.data(), tl.size() * 8, hipMemcpyHostToDevice));
-    // float screening table and a bound on its 27-cell sum error: each cell
-    // term costs 3 rounded table values and 2 roundings of magnitude <= N ln N,
-    // the cell sum 26 more (215 roundings in all); 256 of 2^-24 covers it.
-    std::vector<float> ft((size_t)d->N + 1, 0.f);
-    for (int n = 2; n <= d->N; ++n) ft[n] = (float)((long double)n * logl((long double)n));
-    HIPCHK(hipMemcpy(d->ftab, ft.data(), ft.size() * 4, hipMemcpyHostToDevice));
-    d->ferr = (float)(256.0 * std::ldexp(1.0, -24) * (double)d->N * std::log((double)std::max(d->N, 2)));
-    d->view.ferr = d->ferr;
+    // screening table: t(n) = round(n ln n 2^tq) mod 2^32, n = 0 .. N, then
+    // the same values for n = N .. 0 (layout in epi_internal.hpp)
+    std::vector<uint32_t> it((size_t)2 * d->N + 2, 0u);
+    const long double tsc = std::ldexp((long double)1.0, d->tq);
+    for (int n = 2; n <= d->N; ++n) {
+        const uint32_t t = (uint32_t)(unsigned long long)llroundl((long double)n * logl((long double)n) * tsc);
+        it[n] = t;
+        it[(size_t)2 * d->N + 1 - n] = t;
+    }
+    HIPCHK(hipMemcpy(d->itab, it.data(), it.size() * 4, hipMemcpyHostToDevice));
     d->score_const = tl[d->N] - tl[d->n_case] - tl[d->n_ctrl];
     return EPI_OK;
 }
@@ -549,10 +564,17 @@ int stage_cap_for(int np2, int np3, int w4_max) {
     return rows * std::max(1, std::min(w4_max, 16));
 }
 
-// LDS capacity of a group's float screening table: the largest table among
-// its order-2/3 datasets that fits (kTabMax entries); a workgroup reloads the
-// table when a chunk of work starts another dataset.  Larger datasets take
-// the exact score path for every combination.
+// Screening-table entries a scan takes in LDS: both halves (2N + 2) when
+// they fit in kTabMax entries, the first half (N + 1) when only that fits,
+// else none (the exact score path for every combination).
+int tab_entries_for(const Dataset *d, int variant) {
+    if (variant != kF2 && variant != kF3 && variant != kR4) return 0;
+    if (2 * d->N + 2 <= Plan::kTabMax) return 2 * d->N + 2;
+    return d->N + 1 <= Plan::kTabMax ? d->N + 1 : 0;
+}
+
+// LDS capacity of a group's screening table: the largest among its scans; a
+// workgroup reloads the table when a chunk of work starts another dataset.
 static void pick_tab_cap(const Plan *p, LaunchGroup &g) {
     g.tab_cap = 0;
     g.kmax = 1;
@@ -561,8 +583,7 @@ static void pick_tab_cap(const Plan *p, LaunchGroup &g) {
         const PlanScan &s = p->scans[i];
         g.kmax = std::max(g.kmax, s.desc.top_k);
         g.stage_cap = std::max(g.stage_cap, stage_cap_for(g.np2, g.np3, std::max(s.ds->w4[0], s.ds->w4[1])));
-        if ((s.variant == kF2 || s.variant == kF3 || s.variant == kR4) && s.ds->N + 1 <= Plan::kTabMax)
-            g.tab_cap = std::max(g.tab_cap, s.ds->N + 1);
+        g.tab_cap = std::max(g.tab_cap, tab_entries_for(s.ds, s.variant));
     }
 }
 
@@ -769,7 +790,9 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
             t.np = s.emit_np;
             t.n_blocks = 0;
             t.order = 2;
-            t.cell_shift = s.desc.order == 3 && (s.np == kNpMfma || s.np == kNpMfmaI8) ? kQScaleShift : 0;
+            const bool q3 = s.desc.order == 3 && (s.np == kNpMfma || s.np == kNpMfmaI8);
+            t.cell_shift = q3 ? kQScaleShift : 0;
+            t.cell_bias = q3 ? q3_bias(s.ds->N) : 0u;
         }
         base = 0;
         for (int i = 0; i < nt; ++i) {

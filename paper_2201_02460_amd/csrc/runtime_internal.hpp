@@ -44,13 +44,13 @@ struct Dataset {
     int id = 0;
     int M = 0, N = 0, n_case = 0, n_ctrl = 0, Mp = 0, shift = 0;
     int w4[2] = {0, 0};
-    void *masks = nullptr, *single = nullptr, *tlog = nullptr, *ftab = nullptr, *idx = nullptr, *err = nullptr;
+    void *masks = nullptr, *single = nullptr, *tlog = nullptr, *itab = nullptr, *idx = nullptr, *err = nullptr;
     int ks[2] = {0, 0};                   // 64-individual steps per class of qa / qb
     void *qa = nullptr, *qb = nullptr;    // matrix-core operand copies (null: order 3 by popcount only)
     int ks8[2] = {0, 0};                  // 32-individual steps per class of qa8 / qb8
     void *qa8 = nullptr, *qb8 = nullptr;  // integer operand copies, built on first selection
     long long score_const = 0;
-    float ferr = 0.f;
+    int tq = 0;
     uint64_t bytes = 0;
     DsView view{};
 };
@@ -93,7 +93,7 @@ struct Plan {
     std::vector<PlanScan> scans;
     std::vector<LaunchGroup> groups;
     int n_emit = 0, emit_grid = 1, emit_stage = 0, n_queues = 0;
-    constexpr static int kTabMax = 16385;  // screening-table entries that may go to LDS
+    constexpr static int kTabMax = 16386;  // screening-table entries that may go to LDS
     unsigned long long emit_total = 0;
     int n_t3 = 0, t3_grid = 1, t3_stage = 0;  // triplet sub-table pass (order 4 by reduced cells)
     unsigned long long t3_total = 0;
@@ -176,6 +176,7 @@ int tuned_np_lookup(Ctx *c, int order, const Dataset *d);
 int default_np3(Ctx *c, const Dataset *d);
 int grid_for(Ctx *c, int np2, int np3, int gk, unsigned long long items, int tab_cap, int kmax, int stage_cap);
 int stage_cap_for(int np2, int np3, int w4_max);
+int tab_entries_for(const Dataset *d, int variant);
 
 Ctx *as_ctx(epi_ctx *c);
 int key_bits_for(int order);

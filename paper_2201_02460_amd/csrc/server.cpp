@@ -223,7 +223,9 @@ static int run_round(Server *S) {
         t.item_base = emit_total;
         t.np = 4;
         t.order = 2;
-        t.cell_shift = r->desc.order == 3 && (r->np == kNpMfma || r->np == kNpMfmaI8) ? kQScaleShift : 0;
+        const bool q3 = r->desc.order == 3 && (r->np == kNpMfma || r->np == kNpMfmaI8);
+        t.cell_shift = q3 ? kQScaleShift : 0;
+        t.cell_bias = q3 ? q3_bias(r->ds->N) : 0u;
         emit_total += r->emit_n;
         emit_w4 = std::max(emit_w4, std::max(r->ds->w4[0], r->ds->w4[1]));
         ht[ti++] = t;
@@ -274,8 +276,7 @@ static int run_round(Server *S) {
             g.n++;
             g.kmax = std::max(g.kmax, r->desc.top_k);
             g.stage = std::max(g.stage, stage_cap_for(g.np2, g.np3, std::max(r->ds->w4[0], r->ds->w4[1])));
-            if ((r->variant == kF2 || r->variant == kF3 || r->variant == kR4) && r->ds->N + 1 <= Plan::kTabMax)
-                g.tab_cap = std::max(g.tab_cap, r->ds->N + 1);
+            g.tab_cap = std::max(g.tab_cap, tab_entries_for(r->ds, r->variant));
         }
         groups.push_back(g);
     }

@@ -227,6 +227,24 @@ def test_autotune_keeps_results(cx, orc):
     epi.epi_unload(cx.ctx, ds)
 
 
+@pytest.mark.parametrize("N", [9000, 17000])
+def test_large_n_screening_paths(cx, orc, N):
+    """Orders 2-4 where the screening table's two halves do not fit in LDS
+    together (N = 9000: the first half only) and where neither does (N =
+    17000: every combination takes the exact score)."""
+    from paper_2201_02460_amd import epi
+
+    G, y = random_genotypes(40, N, seed=N, case_fraction=0.45)
+    ds = cx.load(G, y)
+    try:
+        for order, K in ((2, 15), (3, 20), (4, 10)):
+            say("N", N, "order", order)
+            res = cx.scan(ds, order, K)
+            check_topk(orc, G, y, order, K, res["combos"], res["scores"], res["tables"])
+    finally:
+        epi.epi_unload(cx.ctx, ds)
+
+
 def test_counting_kernels_agree(cx, orc):
     """Every order-3 counting kernel (popcount prefix blocks, 4-bit float and
     8-bit integer matrix-core products) gives the same results."""
