@@ -852,7 +852,10 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
             for (int e = 0; e < 2; ++e) acc[c][b][e] = (typename Q::acc_t){};
     // software pipeline: the operands of kQDepth steps are in flight while a
     // step is multiplied (a step's products take far less time than a load
-    // from L2).  The two mask rows of j are the same for every lane of a half
+    // from L2).  Scheduling barriers keep the loads in step order, each
+    // step's refills right after its products: left alone, the scheduler
+    // sinks all refills to the end of the unrolled block, and the loop then
+    // waits for every load in flight at its top.  The two mask rows of j are the same for every lane of a half
     // wave: they are staged once per segment of kQSeg steps in the wave's LDS
     // slot (entry 4 step + 2 h + b) and read back with broadcast loads.  Each
     // class has a multiple of kQDepth steps (zero-padded).
@@ -881,6 +884,7 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
                 bA[u] = qload(rA, vo, so);
                 bB0[u] = qload(rB0, vo, so);
                 bB1[u] = qload(rB1, vo, so);
+                __builtin_amdgcn_sched_barrier(0);
             }
             #pragma unroll 1
             for (int k = 0; k < n; k += kQDepth) {
@@ -898,6 +902,7 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
                     bA[u] = qload(rA, vo, so);
                     bB0[u] = qload(rB0, vo, so);
                     bB1[u] = qload(rB1, vo, so);
+                    __builtin_amdgcn_sched_barrier(0);
                 }
             }
             wave_sync();  // the slot is rewritten by the next segment
