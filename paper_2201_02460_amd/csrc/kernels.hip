@@ -1345,13 +1345,14 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
                 if (tasks[mid].item_base <= first) lo = mid; else hi = mid - 1;
             }
             const Task &T0 = tasks[lo];
-            // the screening reads address the table from LDS address 0; both
-            // halves when they fit, else the first
+            // the screening reads address the table from LDS address 0; the
+            // mirrored half too for the matrix-core order-3 kernel when it fits
             const int ent_fwd = T0.ds.N + 1, ent_rev = 2 * T0.ds.N + 2;
             const bool want = (T0.variant == kF2 || T0.variant == kF3 || T0.variant == kR4) && ent_fwd <= tab_cap &&
                               (unsigned)(uintptr_t)(lu32 *)s_tab == 0u;
-            const bool rev = want && ent_rev <= tab_cap;
-            if (want && (loaded != T0.ds.itab || loaded_rev != rev)) {
+            const bool q3 = T0.variant == kF3 && (T0.np == kNpMfma || T0.np == kNpMfmaI8);
+            const bool rev = want && q3 && ent_rev <= tab_cap;  // the mirrored half is read only by q3
+            if (want && (loaded != T0.ds.itab || (rev && !loaded_rev))) {
                 const int ent = rev ? ent_rev : ent_fwd;
                 #pragma unroll 1
                 for (int x = threadIdx.x; x < ent; x += blockDim.x) s_tab[x] = T0.ds.itab[x];
@@ -1379,15 +1380,18 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
                 tk.added = 0;
                 tk.top = -1;
                 gthr = (long long)0x8000000000000000ull;
+                if (!is_emit(tasks[cur].variant)) {
+                    // a new task starts from the bound published so far
+                    long long g = 0;
+                    if (lane_id() == 0) g = load_thr(tasks[cur].thr);
+                    gthr = (long long)rfl64((unsigned long long)g);
+                }
             }
             const Task &T = tasks[cur];
-            if (!is_emit(T.variant)) {
-                // the bound other waves have published, before every item
-                long long g = 0;
-                if (lane_id() == 0) g = load_thr(T.thr);
-                g = (long long)rfl64((unsigned long long)g);
-                gthr = g > gthr ? g : gthr;
-            }
+            // the bound other waves have published: read before every item,
+            // taken up after it (the item's own waits cover the load)
+            long long g_pub = (long long)0x8000000000000000ull;
+            if (!is_emit(T.variant) && lane_id() == 0) g_pub = load_thr(T.thr);
             const unsigned long long local = item - T.item_base + T.first_item;
             const bool lds = loaded != nullptr && T.ds.itab == loaded;
             switch (T.variant) {
@@ -1424,6 +1428,10 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
             default:
                 if constexpr (GK > 0) item_generic<GK>(T, local, tk, s_list, gthr, binom, bstride);
                 break;
+            }
+            if (!is_emit(T.variant)) {
+                const long long g = (long long)rfl64((unsigned long long)g_pub);
+                gthr = g > gthr ? g : gthr;
             }
             if (tk.added) {
                 // combinations were counted: raise and publish the bound

@@ -533,7 +533,7 @@ int default_np3(Ctx *c, const Dataset *d) {
 // at most 8 waves per SIMD) and LDS use (160 KiB per CU).
 // EPI_WAVES_PER_SIMD overrides the register-based count.  Extra workgroups
 // only queue: the work queue drains either way.
-int grid_for(Ctx *c, int np2, int np3, int gk, unsigned long long items, int tab_cap, int kmax, int stage_cap) {
+static int wgs_per_cu(int np2, int np3, int gk, int tab_cap, int kmax, int stage_cap) {
     int vgprs = 128, lds_static = 0;
     if (scan_attributes(np2, np3, gk, &vgprs, &lds_static) != hipSuccess) {
         (void)hipGetLastError();
@@ -545,8 +545,11 @@ int grid_for(Ctx *c, int np2, int np3, int gk, unsigned long long items, int tab
     if (const char *e = getenv("EPI_WAVES_PER_SIMD")) waves = std::max(1, std::min(16, atoi(e)));
     const size_t lds = scan_lds_bytes(tab_cap, kmax, stage_cap) + (size_t)lds_static;
     const int by_lds = (int)std::max<size_t>(1, (160 * 1024) / std::max<size_t>(lds, 1));
-    const int wgs_per_cu = std::max(1, std::min(waves, by_lds));
-    long long g = (long long)wgs_per_cu * c->n_cu;
+    return std::max(1, std::min(waves, by_lds));
+}
+
+int grid_for(Ctx *c, int np2, int np3, int gk, unsigned long long items, int tab_cap, int kmax, int stage_cap) {
+    long long g = (long long)wgs_per_cu(np2, np3, gk, tab_cap, kmax, stage_cap) * c->n_cu;
     const long long need = (long long)((items + 3) / 4);
     if (g > need) g = std::max(1LL, need);
     return (int)g;
@@ -564,27 +567,41 @@ int stage_cap_for(int np2, int np3, int w4_max) {
     return rows * std::max(1, std::min(w4_max, 16));
 }
 
-// Screening-table entries a scan takes in LDS: both halves (2N + 2) when
-// they fit in kTabMax entries, the first half (N + 1) when only that fits,
-// else none (the exact score path for every combination).
-int tab_entries_for(const Dataset *d, int variant) {
+// Screening-table entries a scan takes in LDS: the first half (N + 1) when
+// it fits in kTabMax entries, else none (the exact score path for every
+// combination); with `both`, the matrix-core order-3 kernel takes the
+// mirrored half too (2N + 2 in all) when that fits.
+int tab_entries_for(const Dataset *d, int variant, int np, bool both) {
     if (variant != kF2 && variant != kF3 && variant != kR4) return 0;
-    if (2 * d->N + 2 <= Plan::kTabMax) return 2 * d->N + 2;
+    const bool q3 = variant == kF3 && (np == kNpMfma || np == kNpMfmaI8);
+    if (both && q3 && 2 * d->N + 2 <= Plan::kTabMax) return 2 * d->N + 2;
     return d->N + 1 <= Plan::kTabMax ? d->N + 1 : 0;
 }
 
-// LDS capacity of a group's screening table: the largest among its scans; a
-// workgroup reloads the table when a chunk of work starts another dataset.
+// A group's LDS table capacity from the largest tables of its scans with
+// (cap_both) and without (cap_first) mirrored halves: the former only if it
+// keeps as many workgroups per CU.  A workgroup reloads the table when a
+// chunk of work starts another dataset, and takes the mirrored half for the
+// chunks that use it when it fits the capacity.
+int group_tab_cap(int np2, int np3, int gk, int cap_both, int cap_first, int kmax, int stage_cap) {
+    if (cap_both <= cap_first) return cap_first;
+    const int w_both = wgs_per_cu(np2, np3, gk, cap_both, kmax, stage_cap);
+    const int w_first = wgs_per_cu(np2, np3, gk, cap_first, kmax, stage_cap);
+    return w_both >= w_first ? cap_both : cap_first;
+}
+
 static void pick_tab_cap(const Plan *p, LaunchGroup &g) {
-    g.tab_cap = 0;
+    int cap_both = 0, cap_first = 0;
     g.kmax = 1;
     g.stage_cap = stage_cap_for(g.np2, g.np3, 0);
     for (int i : g.scans) {
         const PlanScan &s = p->scans[i];
         g.kmax = std::max(g.kmax, s.desc.top_k);
         g.stage_cap = std::max(g.stage_cap, stage_cap_for(g.np2, g.np3, std::max(s.ds->w4[0], s.ds->w4[1])));
-        g.tab_cap = std::max(g.tab_cap, tab_entries_for(s.ds, s.variant));
+        cap_both = std::max(cap_both, tab_entries_for(s.ds, s.variant, s.np, true));
+        cap_first = std::max(cap_first, tab_entries_for(s.ds, s.variant, s.np, false));
     }
+    g.tab_cap = group_tab_cap(g.np2, g.np3, g.gk, cap_both, cap_first, g.kmax, g.stage_cap);
 }
 
 // Order 4 by reduced cells needs the dataset's matrix-core operands (for the

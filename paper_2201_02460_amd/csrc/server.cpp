@@ -265,6 +265,7 @@ static int run_round(Server *S) {
         if (orders.empty()) continue;
         pick_group_kernel(orders, key > 30 ? key - 30 : 4, &g.np2, &g.np3, &g.gk);
         g.stage = stage_cap_for(g.np2, g.np3, 0);
+        int cap_both = 0, cap_first = 0;
         for (int i = 0; i < nt; ++i) {
             Request *r = order[i].first;
             if (round_group(r) != key) continue;
@@ -276,8 +277,10 @@ static int run_round(Server *S) {
             g.n++;
             g.kmax = std::max(g.kmax, r->desc.top_k);
             g.stage = std::max(g.stage, stage_cap_for(g.np2, g.np3, std::max(r->ds->w4[0], r->ds->w4[1])));
-            g.tab_cap = std::max(g.tab_cap, tab_entries_for(r->ds, r->variant));
+            cap_both = std::max(cap_both, tab_entries_for(r->ds, r->variant, r->np, true));
+            cap_first = std::max(cap_first, tab_entries_for(r->ds, r->variant, r->np, false));
         }
+        g.tab_cap = group_tab_cap(g.np2, g.np3, g.gk, cap_both, cap_first, g.kmax, g.stage);
         groups.push_back(g);
     }
     if (ti > S->max_round_tasks) return fail(EPI_EDEVICE, "server round task array overflow");
