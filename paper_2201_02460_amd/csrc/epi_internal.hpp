@@ -104,8 +104,9 @@ struct Task {
     int32_t np;                       // prefix block (kF2/kF3) or ranks per lane (kGeneric)
     int32_t n_blocks;                 // number of prefix blocks (kF2: i-blocks, kF3: j values + 1)
     int32_t key_bits;                 // bits per index in the packed key
-    int32_t cell_shift;               // kF2Emit: pair cells are written as count << cell_shift
-    uint32_t cell_bias;               // kF2Emit: if nonzero, as cell_bias - (count << cell_shift)
+    int32_t cell_shift;               // kF2Emit: pair cells are written as (count << cell_shift)
+    uint32_t cell_bias;               //   + cell_bias, or with cell_neg as cell_bias - (count << cell_shift)
+    int32_t cell_neg;
 };
 
 // Score histogram of a task: how many distinct combinations entered some
@@ -117,10 +118,15 @@ constexpr int kHistFine = 1 << kHistFineBits;
 constexpr int kHistWords = 64 * kHistFine;
 
 // Matrix-core order-3 kernels count 4 x n (their B operand holds 4 for a set
-// bit), so a count is also the byte offset of its screening-table entry;
-// their pair sub-tables are written as q3_bias(N) - 4 n (cell_shift =
-// kQScaleShift, cell_bias = q3_bias(N)): the cell form their inclusion-
-// exclusion works in.
+// bit), so a count is also the byte offset of its screening-table entry.
+// Their epilogue, and that of order 4 by reduced cells, hold a cell with an
+// odd number of marginal SNPs as q3_bias(N) - 4n and the others as 4n, and
+// take their marginal inputs with offsets that keep that form through the
+// inclusion-exclusion (a multiple o_t of q3_bias(N) for t marginal SNPs:
+// 1, -4, 13, -40 for t = 1 .. 4, sign (-1)^t on the 4n).  So the pair
+// sub-table is written with cell_shift = kQScaleShift and (order 3)
+// cell_bias = q3_bias(N), cell_neg = 1, or (order 4) cell_bias =
+// -4 q3_bias(N), cell_neg = 0; the triplet sub-table as q3_bias(N) - 4n.
 constexpr int kQScaleShift = 2;
 
 // Byte offset just past the screening table's two halves (2N + 2 entries):

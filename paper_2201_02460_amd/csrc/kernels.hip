@@ -207,11 +207,11 @@ EPI_DEV void mobius4(int (&R)[81]) {
             if ((x / st) % 3 == 2) R[x] -= R[x - 2 * st] + R[x - st];
 }
 
-// Cells with an odd number of digits 2 (index 9a + 3b + e), held as B - 4n
-// by the matrix-core order-3 epilogue.
-constexpr bool odd_twos3(int x) { return ((x / 9 == 2) + ((x / 3) % 3 == 2) + (x % 3 == 2)) & 1; }
+// Cells whose base-3 index has an odd number of digits 2, held as B - 4n in
+// the signed cell form.
+constexpr bool odd_twos(int x) { return x == 0 ? false : ((x % 3 == 2) != odd_twos(x / 3)); }
 
-// mobius3 on the signed cell form (B - 4n for odd_twos3 cells, 4n for the
+// mobius3 on the signed cell form (B - 4n for odd_twos cells, 4n for the
 // others, each marginal input offset so that the result comes out in that
 // form): a genotype-2 cell is its marginal minus the genotype-0 and -1 cells,
 // which the form turns into one sum of three.
@@ -224,6 +224,15 @@ EPI_DEV void mobius3_signed(unsigned (&R)[27]) {
         for (int e = 0; e < 3; ++e) R[9 * a + 6 + e] += R[9 * a + e] + R[9 * a + 3 + e];
     #pragma unroll
     for (int ab = 0; ab < 9; ++ab) R[3 * ab + 2] += R[3 * ab] + R[3 * ab + 1];
+}
+
+// mobius4 on the signed cell form.
+EPI_DEV void mobius4_signed(unsigned (&R)[81]) {
+    #pragma unroll
+    for (int st = 27; st >= 1; st /= 3)
+        #pragma unroll
+        for (int x = 0; x < 81; ++x)
+            if ((x / st) % 3 == 2) R[x] += R[x - 2 * st] + R[x - st];
 }
 
 // Sub-table passes keep no best-K list.
@@ -427,17 +436,17 @@ EPI_DEV int screen_sum4(const int (&F0)[CELLS], const int (&F1)[CELLS]) {
     return (int)(p - q);
 }
 
-// Same for the signed cell form of the matrix-core order-3 epilogue; with
-// REV the table's second half is in LDS and a B - 4n cell is its address
-// there, else it is turned back into 4n.
-template <bool REV>
-EPI_DEV int screen_sum_q3(const unsigned (&F0)[27], const unsigned (&F1)[27], unsigned B) {
+// Same for the signed cell form (matrix-core order 3, order 4 by reduced
+// cells); with REV the table's mirrored half is in LDS and a B - 4n cell is
+// its address there, else it is turned back into 4n.
+template <int CELLS, bool REV>
+EPI_DEV int screen_sum_signed(const unsigned (&F0)[CELLS], const unsigned (&F1)[CELLS], unsigned B) {
     const unsigned nB = 0u - B;
     unsigned p = 0, q = 0, qh = 0;
     #pragma unroll
-    for (int x = 0; x < 27; ++x) {
+    for (int x = 0; x < CELLS; ++x) {
         unsigned a0 = F0[x], a1 = F1[x], s;
-        if (odd_twos3(x)) {
+        if (odd_twos(x)) {
             if constexpr (REV) {
                 s = add3(a0, a1, nB);  // B - 4 (n0 + n1)
             } else {
@@ -548,9 +557,12 @@ EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *li
                 const int sh = t.cell_shift;
                 v4u c0 = v4u{acc[p][0][0] << sh, acc[p][0][1] << sh, acc[p][0][2] << sh, acc[p][0][3] << sh};
                 v4u c1 = v4u{acc[p][1][0] << sh, acc[p][1][1] << sh, acc[p][1][2] << sh, acc[p][1][3] << sh};
-                if (t.cell_bias) {
+                if (t.cell_neg) {
                     c0 = t.cell_bias - c0;
                     c1 = t.cell_bias - c1;
+                } else {
+                    c0 += t.cell_bias;
+                    c1 += t.cell_bias;
                 }
                 pv[2 * r + 0] = c0;
                 pv[2 * r + 1] = c1;
@@ -910,9 +922,11 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
     }
 
     if constexpr (EMIT) {
-        // triplet sub-table: the counts (sums are 4 n) of the lane's eight
-        // triplets at their colex ranks, class 0 cells 4a + 2b + d first
+        // triplet sub-table: the cells of the lane's eight triplets at their
+        // colex ranks, class 0 cells 4a + 2b + d first, as q3_bias(N) - 4n
+        // (the sums are 4n; the signed form of order 4 by reduced cells)
         gv4u *tv = (gv4u *)t.triples;
+        const unsigned Bt = q3_bias(d.N);
         #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int i = ib * 16 + 2 * h + 4 * (u >> 1) + (u & 1);
@@ -923,10 +937,10 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
                 for (int c = 0; c < 2; ++c)
                     #pragma unroll
                     for (int a = 0; a < 2; ++a)
-                        dst[2 * c + a] = v4u{(unsigned)acc[c][0][0][r0 + a] >> kQScaleShift,
-                                             (unsigned)acc[c][0][1][r0 + a] >> kQScaleShift,
-                                             (unsigned)acc[c][1][0][r0 + a] >> kQScaleShift,
-                                             (unsigned)acc[c][1][1][r0 + a] >> kQScaleShift};
+                        dst[2 * c + a] = v4u{Bt - (unsigned)(int)acc[c][0][0][r0 + a],
+                                             Bt - (unsigned)(int)acc[c][0][1][r0 + a],
+                                             Bt - (unsigned)(int)acc[c][1][0][r0 + a],
+                                             Bt - (unsigned)(int)acc[c][1][1][r0 + a]};
             }
         }
         return;
@@ -1001,13 +1015,13 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
             mobius3_signed(F[c]);
         }
         bool pass = valid;
-        if constexpr (LDS) pass = pass && screen_sum_q3<REV>(F[0], F[1], B) >= sb;
+        if constexpr (LDS) pass = pass && screen_sum_signed<27, REV>(F[0], F[1], B) >= sb;
         if (__ballot(pass)) {
             long long num = t.score_const;
             #pragma unroll
             for (int x = 0; x < 27; ++x) {
-                const unsigned n0 = (odd_twos3(x) ? B - F[0][x] : F[0][x]) >> kQScaleShift;
-                const unsigned n1 = (odd_twos3(x) ? B - F[1][x] : F[1][x]) >> kQScaleShift;
+                const unsigned n0 = (odd_twos(x) ? B - F[0][x] : F[0][x]) >> kQScaleShift;
+                const unsigned n1 = (odd_twos(x) ? B - F[1][x] : F[1][x]) >> kQScaleShift;
                 num += cell_term(d.tlog, (int)n0, (int)n1, (unsigned)d.N);
             }
             const unsigned long long key =
@@ -1144,10 +1158,13 @@ EPI_DEV void item_generic(const Task &t, unsigned long long local, TopK &tk, Can
 // sub-table (written by the matrix-core kernel), the pair sub-table and the
 // single-SNP counts, as for order 3.
 // ---------------------------------------------------------------------------
-template <bool LDS>
+template <bool LDS, bool REV>
 EPI_DEV void item_r4(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr,
                      const unsigned long long *binom, int bstride) {
     const DsView d = t.ds;
+    const unsigned B = q3_bias(d.N), B13 = 13u * B, B40 = 40u * B;
+    int sb = 0;
+    if constexpr (LDS) sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.tq, 243);
     const int bits = t.key_bits;
     gv4u *gm = (gv4u *)d.masks;
     gv4u *single4 = (gv4u *)d.single;
@@ -1189,15 +1206,24 @@ EPI_DEV void item_r4(const Task &t, unsigned long long local, TopK &tk, Cand *li
                                 bcnt_acc(p[ab] & r[2][ce >> 1][q] & r[3][ce & 1][q], acc[cl][4 * ab + ce]);
                 }
             }
+            // (keeps the scaling below out of the loop, where the compiler
+            // would otherwise redo it every iteration)
+            #pragma unroll
+            for (int x = 0; x < 16; ++x) asm volatile("" : "+v"(acc[cl][x]));
         }
-        // F[27 a + 9 b + 3 g + e]; digit 2 = marginal over that SNP
-        int F[2][81];
+        // F[27 a + 9 b + 3 g + e]; digit 2 = marginal over that SNP, genotype
+        // 2 once the inclusion-exclusion has run.  Signed cell form (as in
+        // item_f3m): cells with an odd number of digits 2 held as B - 4n, the
+        // others as 4n; the marginal inputs carry the offsets o_t B for t
+        // digits 2 (1, -4, 13, -40) with sign (-1)^t on the 4n, which the
+        // sub-table passes write in and the singles and class sizes get here.
+        unsigned F[2][81];
         #pragma unroll
         for (int x = 0; x < 81; ++x) {
             const int a = x / 27, b = (x / 9) % 3, g = (x / 3) % 3, e = x % 3;
             if (a < 2 && b < 2 && g < 2 && e < 2) {
-                F[0][x] = acc[0][8 * a + 4 * b + 2 * g + e];
-                F[1][x] = acc[1][8 * a + 4 * b + 2 * g + e];
+                F[0][x] = acc[0][8 * a + 4 * b + 2 * g + e] << kQScaleShift;
+                F[1][x] = acc[1][8 * a + 4 * b + 2 * g + e] << kQScaleShift;
             }
         }
         // triplets: drop one SNP (its digit 2), cells 4a' + 2b' + d' of the rest
@@ -1238,7 +1264,7 @@ EPI_DEV void item_r4(const Task &t, unsigned long long local, TopK &tk, Cand *li
                     }
                 }
             }
-        // singles and the class sizes
+        // singles (13B - 4n) and the class sizes (4n - 40B)
         #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const v4u sv = single4[c[u]];
@@ -1249,26 +1275,28 @@ EPI_DEV void item_r4(const Task &t, unsigned long long local, TopK &tk, Cand *li
                     int dig[4];
                     #pragma unroll
                     for (int v = 0; v < 4; ++v) dig[v] = v == u ? g : 2;
-                    F[cl][27 * dig[0] + 9 * dig[1] + 3 * dig[2] + dig[3]] = sv[2 * cl + g];
+                    F[cl][27 * dig[0] + 9 * dig[1] + 3 * dig[2] + dig[3]] = B13 - (sv[2 * cl + g] << kQScaleShift);
                 }
         }
-        F[0][80] = d.ncls[0];
-        F[1][80] = d.ncls[1];
-        mobius4(F[0]);
-        mobius4(F[1]);
+        F[0][80] = ((unsigned)d.ncls[0] << kQScaleShift) - B40;
+        F[1][80] = ((unsigned)d.ncls[1] << kQScaleShift) - B40;
+        mobius4_signed(F[0]);
+        mobius4_signed(F[1]);
         bool pass = valid;
-        if constexpr (LDS) {
-            const int sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.tq, 243);
-            pass = pass && screen_sum<81>(F[0], F[1]) >= sb;
-        }
+        if constexpr (LDS) pass = pass && screen_sum_signed<81, REV>(F[0], F[1], B) >= sb;
         if (__ballot(pass)) {
             long long num = t.score_const;
             #pragma unroll
-            for (int x = 0; x < 81; ++x) num += cell_term(d.tlog, F[0][x], F[1][x], (unsigned)d.N);
+            for (int x = 0; x < 81; ++x) {
+                const unsigned n0 = (odd_twos(x) ? B - F[0][x] : F[0][x]) >> kQScaleShift;
+                const unsigned n1 = (odd_twos(x) ? B - F[1][x] : F[1][x]) >> kQScaleShift;
+                num += cell_term(d.tlog, (int)n0, (int)n1, (unsigned)d.N);
+            }
             unsigned long long key = 0;
             #pragma unroll
             for (int u = 0; u < 4; ++u) key = (key << bits) | (unsigned long long)c[u];
             tk_offer(tk, list, pass, num, key, gthr);
+            if constexpr (LDS) sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.tq, 243);
         }
     }
 }
@@ -1346,12 +1374,13 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
             }
             const Task &T0 = tasks[lo];
             // the screening reads address the table from LDS address 0; the
-            // mirrored half too for the matrix-core order-3 kernel when it fits
+            // mirrored half too for the kernels in the signed cell form, when
+            // it fits
             const int ent_fwd = T0.ds.N + 1, ent_rev = 2 * T0.ds.N + 2;
             const bool want = (T0.variant == kF2 || T0.variant == kF3 || T0.variant == kR4) && ent_fwd <= tab_cap &&
                               (unsigned)(uintptr_t)(lu32 *)s_tab == 0u;
-            const bool q3 = T0.variant == kF3 && (T0.np == kNpMfma || T0.np == kNpMfmaI8);
-            const bool rev = want && q3 && ent_rev <= tab_cap;  // the mirrored half is read only by q3
+            const bool sgn = (T0.variant == kF3 && (T0.np == kNpMfma || T0.np == kNpMfmaI8)) || T0.variant == kR4;
+            const bool rev = want && sgn && ent_rev <= tab_cap;  // read only in the signed cell form
             if (want && (loaded != T0.ds.itab || (rev && !loaded_rev))) {
                 const int ent = rev ? ent_rev : ent_fwd;
                 #pragma unroll 1
@@ -1410,8 +1439,9 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
                 break;
             case kR4:
                 if constexpr (GK == 4) {
-                    if (lds) item_r4<true>(T, local, tk, s_list, gthr, binom, bstride);
-                    else item_r4<false>(T, local, tk, s_list, gthr, binom, bstride);
+                    if (lds && loaded_rev) item_r4<true, true>(T, local, tk, s_list, gthr, binom, bstride);
+                    else if (lds) item_r4<true, false>(T, local, tk, s_list, gthr, binom, bstride);
+                    else item_r4<false, false>(T, local, tk, s_list, gthr, binom, bstride);
                 }
                 break;
             case kF3:

@@ -567,14 +567,25 @@ int stage_cap_for(int np2, int np3, int w4_max) {
     return rows * std::max(1, std::min(w4_max, 16));
 }
 
+// Cell form of the pair sub-table a scan's pair pass writes (the consumers'
+// signed cell form, layout in epi_internal.hpp).
+void set_pair_form(Task &t, const Dataset *d, int order, int variant, int np) {
+    const bool q3 = order == 3 && (np == kNpMfma || np == kNpMfmaI8);
+    const bool r4 = variant == kR4;
+    t.cell_shift = q3 || r4 ? kQScaleShift : 0;
+    t.cell_bias = q3 ? q3_bias(d->N) : (r4 ? 0u - 4u * q3_bias(d->N) : 0u);
+    t.cell_neg = q3 ? 1 : 0;
+}
+
 // Screening-table entries a scan takes in LDS: the first half (N + 1) when
 // it fits in kTabMax entries, else none (the exact score path for every
-// combination); with `both`, the matrix-core order-3 kernel takes the
-// mirrored half too (2N + 2 in all) when that fits.
+// combination); with `both`, the kernels in the signed cell form (matrix-core
+// order 3, order 4 by reduced cells) take the mirrored half too (2N + 2 in
+// all) when that fits.
 int tab_entries_for(const Dataset *d, int variant, int np, bool both) {
     if (variant != kF2 && variant != kF3 && variant != kR4) return 0;
-    const bool q3 = variant == kF3 && (np == kNpMfma || np == kNpMfmaI8);
-    if (both && q3 && 2 * d->N + 2 <= Plan::kTabMax) return 2 * d->N + 2;
+    const bool sgn = (variant == kF3 && (np == kNpMfma || np == kNpMfmaI8)) || variant == kR4;
+    if (both && sgn && 2 * d->N + 2 <= Plan::kTabMax) return 2 * d->N + 2;
     return d->N + 1 <= Plan::kTabMax ? d->N + 1 : 0;
 }
 
@@ -807,9 +818,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
             t.np = s.emit_np;
             t.n_blocks = 0;
             t.order = 2;
-            const bool q3 = s.desc.order == 3 && (s.np == kNpMfma || s.np == kNpMfmaI8);
-            t.cell_shift = q3 ? kQScaleShift : 0;
-            t.cell_bias = q3 ? q3_bias(s.ds->N) : 0u;
+            set_pair_form(t, s.ds, s.desc.order, s.variant, s.np);
         }
         base = 0;
         for (int i = 0; i < nt; ++i) {

@@ -177,6 +177,7 @@ int default_np3(Ctx *c, const Dataset *d);
 int grid_for(Ctx *c, int np2, int np3, int gk, unsigned long long items, int tab_cap, int kmax, int stage_cap);
 int stage_cap_for(int np2, int np3, int w4_max);
 int tab_entries_for(const Dataset *d, int variant, int np, bool both);
+void set_pair_form(Task &t, const Dataset *d, int order, int variant, int np);
 int group_tab_cap(int np2, int np3, int gk, int cap_both, int cap_first, int kmax, int stage_cap);
 
 Ctx *as_ctx(epi_ctx *c);

@@ -223,9 +223,7 @@ static int run_round(Server *S) {
         t.item_base = emit_total;
         t.np = 4;
         t.order = 2;
-        const bool q3 = r->desc.order == 3 && (r->np == kNpMfma || r->np == kNpMfmaI8);
-        t.cell_shift = q3 ? kQScaleShift : 0;
-        t.cell_bias = q3 ? q3_bias(r->ds->N) : 0u;
+        set_pair_form(t, r->ds, r->desc.order, r->variant, r->np);
         emit_total += r->emit_n;
         emit_w4 = std::max(emit_w4, std::max(r->ds->w4[0], r->ds->w4[1]));
         ht[ti++] = t;
