@@ -34,6 +34,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "epi_internal.hpp"
 
 namespace epi {
@@ -834,7 +836,7 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
     gv4u *pair4 = (gv4u *)t.pairs;
     const unsigned B = q3_bias(d.N), B4 = 4u * B;
     const v4u sm = (single4[m_ld] << kQScaleShift) - B4;
-    const v4u sj = (single4[j] << kQScaleShift) - B4;
+    const v4u sj = (((cv4u *)d.single)[j] << kQScaleShift) - B4;  // uniform: a scalar load
     const unsigned nall[2] = {13u * B - ((unsigned)d.ncls[0] << kQScaleShift),
                               13u * B - ((unsigned)d.ncls[1] << kQScaleShift)};
     const unsigned long long rjm = pair_row(j, d.M) + (unsigned)(m_ld - j - 1);
@@ -862,64 +864,76 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
         for (int b = 0; b < 2; ++b)
             #pragma unroll
             for (int e = 0; e < 2; ++e) acc[c][b][e] = (typename Q::acc_t){};
-    // software pipeline: the operands of kQDepth steps are in flight while a
+    // Software pipeline: the operands of kQDepth steps are in flight while a
     // step is multiplied (a step's products take far less time than a load
-    // from L2).  Scheduling barriers keep the loads in step order, each
-    // step's refills right after its products: left alone, the scheduler
-    // sinks all refills to the end of the unrolled block, and the loop then
-    // waits for every load in flight at its top.  The two mask rows of j are the same for every lane of a half
-    // wave: they are staged once per segment of kQSeg steps in the wave's LDS
-    // slot (entry 4 step + 2 h + b) and read back with broadcast loads.  Each
-    // class has a multiple of kQDepth steps (zero-padded).
+    // from L2).  The steps of both classes form one stream, class 0's first
+    // as in the operand copies (each class has a multiple of kQDepth steps,
+    // zero-padded), so the pipeline runs on across the class boundary and an
+    // item waits for operands only at its start.  Scheduling barriers keep
+    // the loads in step order, each step's refills right after its products:
+    // left alone, the scheduler sinks all refills to the end of the unrolled
+    // block, and the loop then waits for every load in flight at its top.
+    // The two mask rows of j are the same for every lane of a half wave: they
+    // are staged once per segment of kQSeg steps in the wave's LDS slot
+    // (entry 4 step + 2 h + b) and read back with broadcast loads.
     lv4u *slot = (lv4u *)stage;
+    const int ks0 = Q::ks(d, 0);
+    v4u bA[kQDepth], bB0[kQDepth], bB1[kQDepth];
+    #pragma unroll
+    for (int u = 0; u < kQDepth; ++u) {
+        const int so = min(u, KS - 1) * 1024;
+        bA[u] = qload(rA, vo, so);
+        bB0[u] = qload(rB0, vo, so);
+        bB1[u] = qload(rB1, vo, so);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    // mask rows of the segment [base, base + kQSeg) of the stream
+    auto stage_masks = [&](int base) __attribute__((always_inline)) {
+        const int n = min(kQSeg, KS - base);
+        wave_sync();  // the slot's previous rows have been read
+        // all loads issued at once, no branch between them (entries past the
+        // segment repeat its last step's; the slot has room for them)
+        #pragma unroll
+        for (int e0 = 0; e0 < 4 * kQSeg; e0 += kWave) {
+            const int e = min(e0 + lane, 4 * n - 1);
+            const int vje = (((e >> 2) * 64) + 32 * ((e >> 1) & 1) + 2 * (j & 15) + (e & 1)) * 16;
+            slot[e0 + lane] = qload(rJ, vje, base * 1024);
+        }
+        wave_sync();
+    };
+    int seg = 0;
+    stage_masks(0);
     #pragma unroll
     for (int c = 0; c < 2; ++c) {
-        const int c0 = c == 0 ? 0 : Q::ks(d, 0);
+        const int c0 = c == 0 ? 0 : ks0;
         const int cn = Q::ks(d, c);
         #pragma unroll 1
-        for (int seg = 0; seg < cn; seg += kQSeg) {
-            const int s0 = c0 + seg;
-            const int n = min(kQSeg, cn - seg);
-            #pragma unroll
-            for (int e0 = 0; e0 < 4 * kQSeg; e0 += kWave) {
-                const int e = e0 + lane;
-                if (e < 4 * n) {
-                    const int vje = (((e >> 2) * 64) + 32 * ((e >> 1) & 1) + 2 * (j & 15) + (e & 1)) * 16;
-                    slot[e] = qload(rJ, vje, s0 * 1024);
-                }
+        for (int k = 0; k < cn; k += kQDepth) {
+            const int g = c0 + k;  // the group's first step in the stream
+            if (g >= seg + kQSeg) {
+                seg += kQSeg;
+                stage_masks(seg);
             }
-            wave_sync();
-            v4u bA[kQDepth], bB0[kQDepth], bB1[kQDepth];
             #pragma unroll
             for (int u = 0; u < kQDepth; ++u) {
-                const int so = (s0 + u) * 1024;
+                const int js = 4 * (g - seg + u) + 2 * h;
+                const v4u J0 = slot[js], J1 = slot[js + 1];
+                const v4u A0 = bA[u] & J0, A1 = bA[u] & J1;
+                acc[c][0][0] = Q::mma(A0, bB0[u], acc[c][0][0]);
+                acc[c][0][1] = Q::mma(A0, bB1[u], acc[c][0][1]);
+                acc[c][1][0] = Q::mma(A1, bB0[u], acc[c][1][0]);
+                acc[c][1][1] = Q::mma(A1, bB1[u], acc[c][1][1]);
+                // refill with the step kQDepth ahead in the stream (the last
+                // steps re-read the stream's last step)
+                const int so = min(g + u + kQDepth, KS - 1) * 1024;
                 bA[u] = qload(rA, vo, so);
                 bB0[u] = qload(rB0, vo, so);
                 bB1[u] = qload(rB1, vo, so);
                 __builtin_amdgcn_sched_barrier(0);
             }
-            #pragma unroll 1
-            for (int k = 0; k < n; k += kQDepth) {
-                #pragma unroll
-                for (int u = 0; u < kQDepth; ++u) {
-                    const int js = 4 * (k + u) + 2 * h;
-                    const v4u J0 = slot[js], J1 = slot[js + 1];
-                    const v4u A0 = bA[u] & J0, A1 = bA[u] & J1;
-                    acc[c][0][0] = Q::mma(A0, bB0[u], acc[c][0][0]);
-                    acc[c][0][1] = Q::mma(A0, bB1[u], acc[c][0][1]);
-                    acc[c][1][0] = Q::mma(A1, bB0[u], acc[c][1][0]);
-                    acc[c][1][1] = Q::mma(A1, bB1[u], acc[c][1][1]);
-                    // refill the slot (the last steps re-read the segment's last step)
-                    const int so = (s0 + min(k + u + kQDepth, n - 1)) * 1024;
-                    bA[u] = qload(rA, vo, so);
-                    bB0[u] = qload(rB0, vo, so);
-                    bB1[u] = qload(rB1, vo, so);
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-            }
-            wave_sync();  // the slot is rewritten by the next segment
         }
     }
+    wave_sync();  // the slot's rows have been read
 
     if constexpr (EMIT) {
         // triplet sub-table: the cells of the lane's eight triplets at their
