@@ -417,25 +417,15 @@ EPI_DEV void stage_rows(lv4u *slot, gv4u *gm, long long Mp, int wbase, int w0, i
 // Screening sum of CELLS cells of plain counts (entry n at byte 4n).
 template <int CELLS>
 EPI_DEV int screen_sum(const int (&F0)[CELLS], const int (&F1)[CELLS]) {
-    unsigned p = 0, q = 0;
+    unsigned p = 0, q = 0, qh = 0;
     #pragma unroll
     for (int x = 0; x < CELLS; ++x) {
-        p += ltab(4u * (unsigned)F0[x]) + ltab(4u * (unsigned)F1[x]);
-        q += ltab(4u * (unsigned)(F0[x] + F1[x]));
+        p = add3(p, ltab(4u * (unsigned)F0[x]), ltab(4u * (unsigned)F1[x]));
+        // the subtracted terms in pairs
+        if (x & 1) q = add3(q, qh, ltab(4u * (unsigned)(F0[x] + F1[x])));
+        else qh = ltab(4u * (unsigned)(F0[x] + F1[x]));
     }
-    return (int)(p - q);
-}
-
-// Same for counts scaled by 4, which are the byte offsets of their entries.
-template <int CELLS>
-EPI_DEV int screen_sum4(const int (&F0)[CELLS], const int (&F1)[CELLS]) {
-    unsigned p = 0, q = 0;
-    #pragma unroll
-    for (int x = 0; x < CELLS; ++x) {
-        p += ltab((unsigned)F0[x]) + ltab((unsigned)F1[x]);
-        q += ltab((unsigned)(F0[x] + F1[x]));
-    }
-    return (int)(p - q);
+    return (int)(p - q - ((CELLS & 1) ? qh : 0u));
 }
 
 // Same for the signed cell form (matrix-core order 3, order 4 by reduced
