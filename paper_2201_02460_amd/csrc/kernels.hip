@@ -1574,6 +1574,16 @@ __global__ void __launch_bounds__(1024) merge_final_kernel(const Task *__restric
     __syncthreads();
     const long long g = load_thr(t.thr);
     int fill = K;
+    if (K + n_parts * K <= kMergeSlots) {
+        // all lists at once: every load in flight together
+        for (int i = threadIdx.x; i < n_parts * K; i += blockDim.x) {
+            const int p = i / K, r = i - p * K;
+            const Cand c = src[(long long)p * kMaxTopK + r];
+            buf[K + i] = c.num >= g ? c : sentinel;
+        }
+        __syncthreads();
+        fill = K + n_parts * K;
+    } else
     for (int p = 0; p < n_parts; ++p) {
         if (fill + K > kMergeSlots) {
             int P = 64;
