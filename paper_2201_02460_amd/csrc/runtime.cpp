@@ -453,6 +453,69 @@ int get_items(Ctx *c, int variant, int M, int np, const void **d, unsigned long 
     return EPI_OK;
 }
 
+// Pinned host buffer of at least `bytes` (power-of-two capacity) from the
+// context's pool, or new.
+static int host_buf_get(Ctx *c, size_t bytes, void **out, size_t *cap) {
+    size_t n = 4096;
+    while (n < bytes) n <<= 1;
+    {
+        std::lock_guard<std::mutex> g(c->pool_mu);
+        auto it = c->host_pool.find(n);
+        if (it != c->host_pool.end()) {
+            *out = it->second;
+            *cap = n;
+            c->host_pool.erase(it);
+            c->host_pool_bytes -= n;
+            return EPI_OK;
+        }
+    }
+    HIPCHK(hipHostMalloc(out, n, hipHostMallocDefault));
+    *cap = n;
+    return EPI_OK;
+}
+
+// Back to the pool (at most 256 MiB kept; the rest is freed).
+static void host_buf_put(Ctx *c, void *p, size_t cap) {
+    if (!p) return;
+    {
+        std::lock_guard<std::mutex> g(c->pool_mu);
+        if (c->host_pool_bytes + cap <= (256ull << 20)) {
+            c->host_pool.emplace(cap, p);
+            c->host_pool_bytes += cap;
+            return;
+        }
+    }
+    (void)hipHostFree(p);
+}
+
+static int event_get(Ctx *c, hipEvent_t *e) {
+    {
+        std::lock_guard<std::mutex> g(c->pool_mu);
+        if (!c->event_pool.empty()) {
+            *e = c->event_pool.back();
+            c->event_pool.pop_back();
+            return EPI_OK;
+        }
+    }
+    HIPCHK(hipEventCreate(e));
+    return EPI_OK;
+}
+
+static void event_put(Ctx *c, hipEvent_t e) {
+    if (!e) return;
+    std::lock_guard<std::mutex> g(c->pool_mu);
+    c->event_pool.push_back(e);
+}
+
+static void pools_free(Ctx *c) {
+    std::lock_guard<std::mutex> g(c->pool_mu);
+    for (auto &kv : c->host_pool) (void)hipHostFree(kv.second);
+    c->host_pool.clear();
+    c->host_pool_bytes = 0;
+    for (auto e : c->event_pool) (void)hipEventDestroy(e);
+    c->event_pool.clear();
+}
+
 void plan_free(Ctx *c, Plan *p) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
@@ -469,10 +532,10 @@ void plan_free(Ctx *c, Plan *p) {
     c->alloc.release(p->d_results);
     c->alloc.release(p->d_layout);
     c->alloc.release(p->d_out);
-    if (p->h_out) (void)hipHostFree(p->h_out);
-    p->h_out = nullptr;
-    for (auto &e : p->ev)
-        if (e) (void)hipEventDestroy(e);
+    host_buf_put(c, p->h_out, p->h_out_cap);
+    host_buf_put(c, p->h_stage, p->h_stage_cap);
+    p->h_out = p->h_stage = nullptr;
+    for (auto &e : p->ev) event_put(c, e);
     for (auto &e : p->ev) e = nullptr;
 }
 
@@ -770,10 +833,10 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
     if ((rc = c->alloc.alloc((size_t)nt * kMergeParts * kMaxTopK * sizeof(Cand), &p->d_parts))) return cleanup(rc);
     if ((rc = c->alloc.alloc((size_t)nt * sizeof(ResultLayout), &p->d_layout))) return cleanup(rc);
     if ((rc = c->alloc.alloc((size_t)std::max<long long>(out_bytes, 256), &p->d_out))) return cleanup(rc);
-    HIPCHK(hipHostMalloc(&p->h_out, (size_t)std::max<long long>(out_bytes, 256), hipHostMallocDefault));
+    if ((rc = host_buf_get(c, (size_t)std::max<long long>(out_bytes, 256), &p->h_out, &p->h_out_cap)))
+        return cleanup(rc);
     std::vector<ResultLayout> lay(nt);
     for (int i = 0; i < nt; ++i) lay[i] = p->scans[i].lay;
-    HIPCHK(hipMemcpy(p->d_layout, lay.data(), nt * sizeof(ResultLayout), hipMemcpyHostToDevice));
     // task array: [main tasks in scan order][pair passes][triplet passes]
     //             [per-group launch copies (persistent)]
     std::vector<Task> tasks(nt + n_emit + n_t3);
@@ -852,9 +915,17 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         }
     }
     if ((rc = c->alloc.alloc(tasks.size() * sizeof(Task), &p->d_tasks))) return cleanup(rc);
-    HIPCHK(hipMemcpy(p->d_tasks, tasks.data(), tasks.size() * sizeof(Task), hipMemcpyHostToDevice));
+    // layout and task arrays staged in pinned memory; every run uploads them
+    // on its own stream ahead of its kernels (no synchronous copy here)
+    p->stage_layout_bytes = ((size_t)nt * sizeof(ResultLayout) + 255) & ~(size_t)255;
+    p->stage_tasks_bytes = tasks.size() * sizeof(Task);
+    if ((rc = host_buf_get(c, p->stage_layout_bytes + p->stage_tasks_bytes, &p->h_stage, &p->h_stage_cap)))
+        return cleanup(rc);
+    memcpy(p->h_stage, lay.data(), (size_t)nt * sizeof(ResultLayout));
+    memcpy((char *)p->h_stage + p->stage_layout_bytes, tasks.data(), p->stage_tasks_bytes);
     p->emit_total = emit_total;
-    for (auto &ev : p->ev) HIPCHK(hipEventCreate(&ev));
+    for (auto &ev : p->ev)
+        if ((rc = event_get(c, &ev))) return cleanup(rc);
     *out = p.release();
     return EPI_OK;
 }
@@ -865,6 +936,9 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
 static int plan_enqueue(Ctx *c, Plan *p, hipStream_t st, bool timing, unsigned long long item_cap) {
     const Task *tasks = (const Task *)p->d_tasks;
     const int nt = (int)p->scans.size();
+    HIPCHK(hipMemcpyAsync(p->d_layout, p->h_stage, (size_t)nt * sizeof(ResultLayout), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(p->d_tasks, (const char *)p->h_stage + p->stage_layout_bytes, p->stage_tasks_bytes,
+                          hipMemcpyHostToDevice, st));
     HIPCHK(launch_init_counters(st, p->d_queues, p->n_queues, p->d_cand_count, p->d_thr, nt, p->d_hist));
     int q = 0;
     const bool single = nt == 1 && !p->persistent;
@@ -1105,6 +1179,7 @@ int epi_destroy(epi_ctx *ctx) {
     (void)hipDeviceSynchronize();
     for (auto &kv : C->plans) plan_free(C, kv.second.get());
     C->plans.clear();
+    pools_free(C);
     C->item_tables.clear();
     for (auto &kv : C->datasets) ds_free(C, kv.second.get());
     C->datasets.clear();

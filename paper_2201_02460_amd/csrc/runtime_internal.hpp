@@ -99,7 +99,10 @@ struct Plan {
     unsigned long long t3_total = 0;
     void *d_tasks = nullptr, *d_counters = nullptr, *d_results = nullptr, *d_layout = nullptr, *d_out = nullptr;
     void *d_parts = nullptr;
-    void *h_out = nullptr;
+    void *h_out = nullptr;                // pinned, from the context's pool
+    size_t h_out_cap = 0;
+    void *h_stage = nullptr;              // pinned copies of the layout and task arrays, uploaded by every run
+    size_t h_stage_cap = 0, stage_layout_bytes = 0, stage_tasks_bytes = 0;
     unsigned long long *d_queues = nullptr, *d_thr = nullptr;
     unsigned *d_cand_count = nullptr;
     unsigned *d_hist = nullptr;  // kHistWords per scan
@@ -144,6 +147,13 @@ struct Ctx {
     std::map<int, std::shared_ptr<Server>> servers;
     std::mutex items_mu;
     std::map<std::tuple<int, int, int>, ItemTable> item_tables;
+    // pinned host buffers (by capacity) and events kept for later plans:
+    // freeing pinned memory and events per scan costs more than the scan's
+    // own host work
+    std::mutex pool_mu;
+    std::multimap<size_t, void *> host_pool;
+    size_t host_pool_bytes = 0;
+    std::vector<hipEvent_t> event_pool;
 };
 
 // kernel launchers (kernels.hip)
