@@ -212,7 +212,7 @@ def orders_bench(epi, torch, names, steps):
         epi.epi_unload(ctx, ds)
         kms = sorted(mains)[len(mains) // 2]
         # reduced-cell variants count 2^k cells, the generic one all 3^k
-        opu = ops_per_unit(order) if info["variant"] in (1, 2) else ops_per_unit_3k(order)
+        opu = ops_per_unit(order) if info["variant"] in (1, 2, 5) else ops_per_unit_3k(order)
         out[name] = {"value": work * len(walls) / sum(walls) / 1e12, "kernel_ms": kms,
                      "kernel_value": work / (kms * 1e-3) / 1e12, "variant": info["variant"],
                      "ops_per_unit": opu, "frac": work * opu / (kms * 1e-3) / 1e12 / VALU_PEAK_TOPS,
@@ -524,7 +524,8 @@ def main():
             }
     out["pcie_inclusive_value"] = round(pcie_bench(epi, spec, G, y, 5), 4)
     if not args.no_orders:
-        others = [n for n in ("order2_M200_N1000", "order4_M200_N2000", "order5_M60_N2000") if n != args.workload]
+        others = [n for n in ("order2_M200_N1000", "order4_M200_N2000", "order5_M60_N2000", "order8_M23_N2048")
+                  if n != args.workload]
         out["orders"] = orders_bench(epi, torch, others, 5)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(spec, G, y, args.cpu_seconds)

@@ -59,7 +59,10 @@ extern "C" {
 
 /* ---- limits -------------------------------------------------------------- */
 #define EPI_MIN_ORDER 2
-#define EPI_MAX_ORDER 5
+#define EPI_MAX_ORDER 8
+/* Largest order the server accepts (its per-request result blocks are sized
+ * for it). */
+#define EPI_SERVE_MAX_ORDER 5
 #define EPI_MAX_TOP_K 256
 /* A combination is keyed by its indices packed big-endian into 64 bits with
  * floor(64/order) bits each, so M may not exceed 2^floor(64/order)
@@ -241,7 +244,8 @@ typedef struct {
 int epi_server_start(epi_ctx *ctx, const epi_server_config *cfg, int32_t *server_id);
 
 /* Enqueue a scan request on a resident dataset; thread-safe, non-blocking.
- * Same argument checks as epi_scan. */
+ * Same argument checks as epi_scan, and EUNSUPPORTED for an order above
+ * EPI_SERVE_MAX_ORDER. */
 int epi_server_submit(epi_ctx *ctx, int32_t server_id, int32_t dataset_id, int32_t order, int32_t top_k,
                       int32_t *request_id);
 

@@ -1891,6 +1891,7 @@ static const ScanKernelEntry kScanKernels[] = {
     EPI_K(2, 0, 0), EPI_K(4, 0, 0), EPI_K(8, 0, 0),                   // order 2 / pair sub-table
     EPI_K(0, 1, 0), EPI_K(0, 2, 0), EPI_K(0, 4, 0), EPI_K(0, 8, 0),   // order 3
     EPI_K(0, 0, 2), EPI_K(0, 0, 3), EPI_K(0, 0, 4), EPI_K(0, 0, 5),   // per-combination kernel
+    EPI_K(0, 0, 6), EPI_K(0, 0, 7), EPI_K(0, 0, 8),
     EPI_K(0, kNpMfma, 0), EPI_K(0, kNpMfmaI8, 0),                    // order 3, matrix cores
 };
 #undef EPI_K

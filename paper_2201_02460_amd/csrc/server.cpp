@@ -474,7 +474,7 @@ int epi_server_start(epi_ctx *ctx, const epi_server_config *cfg, int32_t *server
                                grid_for(C, k[0], k[1], k[2], ~0ull >> 8, 0, 1, stage_cap_for(k[0], k[1], 1)));
     const int A = cfg->max_active;
     S->max_round_tasks = 4 * A + 4;  // main, pair passes, triplet passes, group copies
-    S->out_block = result_block_bytes(EPI_MAX_TOP_K, EPI_MAX_ORDER);
+    S->out_block = result_block_bytes(EPI_MAX_TOP_K, EPI_SERVE_MAX_ORDER);
     int rc;
     auto cleanup = [&](int code) {
         server_free(S.get());
@@ -522,6 +522,8 @@ int epi_server_submit(epi_ctx *ctx, int32_t server_id, int32_t dataset_id, int32
     {
         std::lock_guard<std::mutex> g(C->mu);
         int rc = check_desc(C, d, &ds);
+        if (rc == EPI_OK && order > EPI_SERVE_MAX_ORDER)
+            rc = fail(EPI_EUNSUPPORTED, "order %d > %d for served requests", order, EPI_SERVE_MAX_ORDER);
         if (rc) return rc;
     }
     auto r = std::make_shared<Request>();

@@ -25,7 +25,8 @@ EPI_EUNSUPPORTED = -4
 EPI_ENOTREADY = -5
 EPI_ENOTFOUND = -6
 EPI_MIN_ORDER = 2
-EPI_MAX_ORDER = 5
+EPI_MAX_ORDER = 8
+EPI_SERVE_MAX_ORDER = 5
 EPI_BLOCK_MFMA_FP4 = 16
 EPI_BLOCK_MFMA_I8 = 32
 EPI_MAX_TOP_K = 256

@@ -153,6 +153,9 @@ WORKLOADS = {
     "order3_M1000_N4000": dict(order=3, M=1000, N=4000, n_cases=2000, planted=(17, 113, 617), seed=0, top_k=100),
     "order4_M200_N2000": dict(order=4, M=200, N=2000, n_cases=600, planted=(17, 59, 113, 171), seed=0, top_k=100),
     "order5_M60_N2000": dict(order=5, M=60, N=2000, n_cases=600, planted=(5, 17, 29, 41, 53), seed=0, top_k=100),
+    # the order-8 row of the paper's Table 2 (23 SNPs, 2048 individuals)
+    "order8_M23_N2048": dict(order=8, M=23, N=2048, n_cases=1024, planted=(1, 4, 7, 10, 13, 16, 19, 22), seed=0,
+                             top_k=10),
 }
 
 

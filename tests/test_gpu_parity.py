@@ -56,6 +56,13 @@ CASES = [
     (5, 5, 33, 16, 1),
     (5, 22, 200, 60, 50),
     (5, 26, 130, 65, 8),
+    (6, 6, 40, 20, 1),
+    (6, 14, 200, 70, 20),
+    (7, 15, 129, 64, 9),
+    (7, 11, 300, 150, 40),
+    (8, 8, 33, 16, 1),
+    (8, 13, 260, 100, 30),
+    (8, 16, 129, 1, 5),
 ]
 
 
@@ -89,9 +96,9 @@ def test_deterministic_planted_ranks_first(cx):
 
 
 def test_more_results_than_combinations(cx, orc):
-    G, y = random_genotypes(6, 90, seed=3)
-    for order in (2, 3, 4, 5):
-        n = math.comb(6, order)
+    G, y = random_genotypes(9, 90, seed=3)
+    for order in (2, 3, 4, 5, 6, 7, 8):
+        n = math.comb(9, order)
         res = run_scan(cx, G, y, order, n + 7)
         assert len(res["combos"]) == n
         check_topk(orc, G, y, order, n + 7, res["combos"], res["scores"], res["tables"])
@@ -125,6 +132,14 @@ def test_invalid_inputs_are_rejected(cx):
     ds = cx.load(G, y)
     for order, K, code in ((1, 5, epi.EPI_EINVAL), (6, 5, epi.EPI_EINVAL), (3, 0, epi.EPI_EINVAL),
                            (3, 257, epi.EPI_EUNSUPPORTED)):
+        with pytest.raises(epi.EpiError) as e:
+            epi.epi_scan(cx.ctx, ds, order, K)
+        assert e.value.code == code
+    epi.epi_unload(cx.ctx, ds)
+    # an order beyond the largest supported one; order 8 keys a SNP in 8 bits (M <= 256)
+    G, y = random_genotypes(300, 40, seed=2)
+    ds = cx.load(G, y)
+    for order, K, code in ((9, 5, epi.EPI_EUNSUPPORTED), (8, 5, epi.EPI_EUNSUPPORTED)):
         with pytest.raises(epi.EpiError) as e:
             epi.epi_scan(cx.ctx, ds, order, K)
         assert e.value.code == code

@@ -77,6 +77,10 @@ def test_served_equals_alone(cx, orc):
     stats = epi.epi_server_stats(cx.ctx, sid)
     say("server stats", stats)
     assert stats["requests_done"] == len(reqs) and stats["peak_active"] <= 4
+    # orders above the served maximum are refused at submission (plain scans take them)
+    with pytest.raises(epi.EpiError) as e:
+        epi.epi_server_submit(cx.ctx, sid, data[4][0], epi.EPI_SERVE_MAX_ORDER + 1, 5)
+    assert e.value.code == epi.EPI_EUNSUPPORTED
     epi.epi_server_stop(cx.ctx, sid)
     # one served result against the oracle as well
     di, order, K = reqs[2]
