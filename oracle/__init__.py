@@ -48,6 +48,9 @@ def _bind(lib):
     lib.oracle_enumerate_count.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.oracle_count_table.restype = ctypes.c_int
     lib.oracle_count_table.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int32, i32p, ctypes.c_int32, u64p]
+    lib.oracle_genotype_rows.restype = ctypes.c_int
+    lib.oracle_genotype_rows.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int32, i32p, ctypes.c_int32,
+                                         ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint32)]
     lib.oracle_mi.restype = ctypes.c_double
     lib.oracle_mi.argtypes = [u64p, ctypes.c_int32]
     lib.oracle_scan.restype = ctypes.c_int
@@ -107,6 +110,21 @@ class Oracle:
                                          G.shape[1], _ptr(c, ctypes.c_int32), k, _ptr(out, ctypes.c_uint64))
         if rc != 0:
             raise ValueError("genotype outside {0,1,2}")
+        return out
+
+    def genotype_rows(self, G, y, combo, words0, words1):
+        """Genotype table, shape (3**k, words0 + words1) uint32: row x holds the
+        cases with genotype combination x as a bitset over the cases (first
+        words0 words), then the controls (words1 words)."""
+        G, y = _as_inputs(G, y)
+        c = np.ascontiguousarray(combo, dtype=np.int32)
+        k = c.shape[0]
+        out = np.zeros((3**k, words0 + words1), np.uint32)
+        rc = self.lib.oracle_genotype_rows(_ptr(G, ctypes.c_uint8), G.shape[1], _ptr(y, ctypes.c_uint8),
+                                           G.shape[1], _ptr(c, ctypes.c_int32), k, int(words0), int(words1),
+                                           _ptr(out, ctypes.c_uint32))
+        if rc != 0:
+            raise ValueError("genotype outside {0,1,2} or a class wider than its words")
         return out
 
     def mi(self, table):

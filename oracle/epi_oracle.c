@@ -139,6 +139,39 @@ int oracle_count_table(const uint8_t *G, int64_t ld, const uint8_t *y, int32_t N
     return 0;
 }
 
+/* Genotype table of a combination (Section 2.1: one row of individuals per
+ * genotype combination, built by Algorithm 1's combine step one SNP at a
+ * time).  Row x of class cls is a bitset over that class's individuals in
+ * input order: bit b of word w stands for the class's individual 32 w + b.
+ * rows[x * (words0 + words1) + (cls ? words0 : 0) + w], words_cls words per
+ * class (at least enough for the class; bits past its size are 0).  Walks the
+ * individuals one at a time.  Returns -1 if a genotype is outside {0,1,2} or
+ * a class does not fit its words. */
+int oracle_genotype_rows(const uint8_t *G, int64_t ld, const uint8_t *y, int32_t N,
+                         const int32_t *combo, int32_t k, int32_t words0, int32_t words1, uint32_t *rows)
+{
+    const int64_t P = pow3(k);
+    const int64_t W = (int64_t)words0 + words1;
+    for (int64_t i = 0; i < P * W; i++)
+        rows[i] = 0;
+    int32_t pos[2] = {0, 0};
+    for (int32_t s = 0; s < N; s++) {
+        int64_t row = 0;
+        for (int32_t t = 0; t < k; t++) {
+            uint8_t geno = G[(int64_t)combo[t] * ld + s];
+            if (geno > 2)
+                return -1;
+            row = 3 * row + geno;
+        }
+        int cl = y[s] ? 0 : 1;
+        int32_t b = pos[cl]++;
+        if (b >= 32 * (cl ? words1 : words0))
+            return -1;
+        rows[row * W + (cl ? words0 : 0) + b / 32] |= (uint32_t)1 << (b % 32);
+    }
+    return 0;
+}
+
 /* ---- mutual information (Equations 1-3) --------------------------------- */
 
 /* MI of a 2 x 3^k table, natural logarithm, probabilities = count / m with m

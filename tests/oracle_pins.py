@@ -282,8 +282,63 @@ def pin_rank_ranges(o, seed=19):
     assert [c for _, c in rows[:20]] == [tuple(c) for c in whole["combos"]]
 
 
+def _row_bits(word_list, n):
+    """First n bits of a row (bit b of word w = individual 32 w + b) as a 0/1 string."""
+    return "".join(str((int(word_list[b // 32]) >> (b % 32)) & 1) for b in range(n))
+
+
+def pin_genotype_rows_fig_example(o):
+    """The combined genotype table of Fig. gt_example: the printed rows, bit for
+    bit (the misprinted control row by the AND of its printed inputs)."""
+    G, y, doc = fig_example_inputs()
+    rows = o.genotype_rows(G, y, [0, 1], 1, 1)
+    assert rows.shape == (9, 2)
+    bad = {(m["i"], m["j"], m["class"]) for m in doc["misprinted_rows"]}
+    for row in doc["combined_printed"]:
+        x = row["i"] * 3 + row["j"]
+        for col, key in ((0, "cases"), (1, "ctrls")):
+            if (row["i"], row["j"], key) in bad:
+                want = int(doc["snp_i"][key][row["i"]], 2) & int(doc["snp_j"][key][row["j"]], 2)
+                want = format(want, "016b")
+            else:
+                want = row[key]
+            assert _row_bits(rows[x, col:col + 1], 16) == want, (row, key)
+    # single-SNP tables are the printed input rows themselves
+    for s, key in enumerate(("snp_i", "snp_j")):
+        r1 = o.genotype_rows(G, y, [s], 1, 1)
+        for g in range(3):
+            assert _row_bits(r1[g, 0:1], 16) == doc[key]["cases"][g]
+            assert _row_bits(r1[g, 1:2], 16) == doc[key]["ctrls"][g]
+
+
+def pin_genotype_rows_invariants(o, seed=20):
+    """Rows of a class partition its individuals, hold nothing past its size,
+    and their popcounts are the contingency table; a row is the AND of the
+    rows of its SNPs (the combine step of Algorithm 1)."""
+    G, y = random_genotypes(6, 150, seed=seed, case_fraction=0.35)
+    n = (int(y.sum()), int((1 - y).sum()))
+    words = (4 * ((n[0] + 127) // 128), 4 * ((n[1] + 127) // 128))
+    for k in (1, 2, 3, 4):
+        for combo in itertools.islice(itertools.combinations(range(6), k), 6):
+            rows = o.genotype_rows(G, y, combo, *words).astype(np.uint64)
+            tab = o.count_table(G, y, combo).astype(np.int64)
+            for cls in (0, 1):
+                part = rows[:, (0 if cls == 0 else words[0]):(words[0] if cls == 0 else words[0] + words[1])]
+                bits = np.unpackbits(part.astype("<u4").view(np.uint8), bitorder="little").reshape(len(part), -1)
+                assert np.array_equal(bits.sum(axis=1), tab[cls])
+                assert np.array_equal(bits.sum(axis=0)[: n[cls]], np.ones(n[cls], np.int64))
+                assert bits[:, n[cls]:].sum() == 0
+            if k > 1:
+                pref = o.genotype_rows(G, y, combo[:-1], *words)
+                last = o.genotype_rows(G, y, combo[-1:], *words)
+                for x in range(3**k):
+                    assert np.array_equal(rows[x].astype(np.uint32), pref[x // 3] & last[x % 3])
+
+
 ALL_PINS = [
     pin_fig_gt_example,
+    pin_genotype_rows_fig_example,
+    pin_genotype_rows_invariants,
     pin_tables_brute_force,
     pin_table_invariants,
     pin_mi_library,

@@ -32,6 +32,12 @@ MUTANTS = {
     "unrank_off_by_one": ("if (rank < block)", "if (rank <= block)"),
     # top-K keeps the worse entry
     "topk_compare": ("return a->mi > b->mi;", "return a->mi < b->mi;"),
+    # genotype-table bits numbered from the other end of the word
+    "gt_bit_order": ("(uint32_t)1 << (b % 32)", "(uint32_t)1 << (31 - b % 32)"),
+    # genotype-table classes in swapped word ranges
+    "gt_class_words": ("(cl ? words0 : 0) + b / 32", "(cl ? 0 : words1) + b / 32"),
+    # genotype-table row index with the SNPs in reverse significance
+    "gt_row_radix": ("row = 3 * row + geno;", "row = row + geno * (t == 0 ? 1 : (t == 1 ? 3 : 9));"),
 }
 
 CHILD = r"""
