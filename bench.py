@@ -222,6 +222,102 @@ def orders_bench(epi, torch, names, steps):
     return out
 
 
+def segmented_bench(epi, names, steps):
+    """The segmented variant (a wave's 64 tables counted into a buffer, then
+    scored: the paper's Algorithm 2) against the fused kernel of each named
+    workload: median kernel times and whether the results are identical."""
+    import numpy as np
+
+    from synth import make_workload
+
+    out = {}
+    ctx = epi.epi_create(0)
+    for name in names:
+        G, y, spec, _ = make_workload(name)
+        order, K = spec["order"], spec["top_k"]
+        work = math.comb(spec["M"], order) * spec["N"]
+        ds = epi.epi_load_genotypes(ctx, G, y)
+        row = {}
+        for form in ("fused", "segmented"):
+            epi.epi_set_prefix_block(ctx, ds, order, epi.EPI_BLOCK_SEGMENTED if form == "segmented" else 0)
+            mains, res = [], None
+            for i in range(steps + 1):
+                sid = epi.epi_scan(ctx, ds, order, K)
+                epi.epi_wait(ctx, sid)
+                r = epi.epi_results(ctx, sid, K, order)
+                ms = epi.epi_scan_timing(ctx, sid)
+                variant = epi.epi_scan_info(ctx, sid)["variant"]
+                epi.epi_release(ctx, sid)
+                if i:
+                    mains.append(ms[2])
+                res = r
+            kms = sorted(mains)[len(mains) // 2]
+            row[form] = {"kernel_ms": kms, "kernel_value": work / (kms * 1e-3) / 1e12, "variant": variant,
+                         "result": res}
+        epi.epi_set_prefix_block(ctx, ds, order, 0)
+        epi.epi_unload(ctx, ds)
+        a, b = row["fused"].pop("result"), row["segmented"].pop("result")
+        row["identical_results"] = bool(all(np.array_equal(u, v) for u, v in zip(a, b)))
+        row["segmented_over_fused_time"] = row["segmented"]["kernel_ms"] / row["fused"]["kernel_ms"]
+        out[name] = row
+        log(f"{name}: fused {row['fused']['kernel_ms']:.3f} ms, segmented {row['segmented']['kernel_ms']:.3f} ms, "
+            f"identical {row['identical_results']}")
+    epi.epi_destroy(ctx)
+    return out
+
+
+def functions_bench(epi, torch, reps=3, out_cap=1 << 30):
+    """The three steps as separate passes over a list of combinations, timed
+    per genotype-table row (both classes), per contingency-table cell (both
+    classes) and per MI cell: order 3 against the number of individuals, and
+    orders 2, 4 and 8 at 2048 individuals (the paper's per-function
+    figures).  Each pass covers the first n lexicographic combinations of 64
+    SNPs (1500 for order 2, so that a pass fills the device), n bounded so
+    that its output stays under out_cap bytes."""
+    import itertools
+
+    import numpy as np
+
+    from synth import random_genotypes
+
+    ctx = epi.epi_create(0)
+    out = {"vs_individuals_order3": {}, "vs_order_N2048": {}}
+    points = [(3, n_ind, "vs_individuals_order3") for n_ind in (128, 256, 512, 1024, 2048, 4096, 8192)]
+    points += [(k, 2048, "vs_order_N2048") for k in (2, 4, 8)]
+    for order, N, key in points:
+        M = 1500 if order == 2 else 64
+        G, y = random_genotypes(M, N, seed=4000 + N + order, case_fraction=0.5)
+        ds = epi.epi_load_genotypes(ctx, G, y)
+        n_case = int(y.sum())
+        W = 4 * ((n_case + 127) // 128) + 4 * ((N - n_case + 127) // 128)
+        P = 3**order
+        n_gt = max(1, min(math.comb(M, order), out_cap // (P * W * 4), 1 << 20))
+        n_ct = max(1, min(math.comb(M, order), out_cap // (P * 8), 1 << 20))
+        combos = np.asarray(list(itertools.islice(itertools.combinations(range(M), order), max(n_gt, n_ct))),
+                            np.int32)
+        dc = torch.from_numpy(combos).cuda()
+        rows = torch.empty((n_gt, P, W), dtype=torch.int32, device="cuda")
+        tabs = torch.empty((n_ct, 2, P), dtype=torch.int32, device="cuda")
+        mi = torch.empty(n_ct, dtype=torch.float64, device="cuda")
+        t_gt, t_ct, t_mi = [], [], []
+        for _ in range(reps + 1):
+            t_gt.append(epi.epi_genotype_tables(ctx, ds, dc[:n_gt], rows))
+            t_ct.append(epi.epi_contingency_tables(ctx, ds, dc[:n_ct], tabs))
+            t_mi.append(epi.epi_mutual_information(ctx, ds, order, tabs, mi))
+        med = lambda v: sorted(v[1:])[len(v[1:]) // 2]  # noqa: E731
+        gt_ms, ct_ms, mi_ms = med(t_gt), med(t_ct), med(t_mi)
+        row = {"order": order, "individuals": N, "gt_combinations": n_gt, "ct_combinations": n_ct,
+               "gt_ns_per_row": gt_ms * 1e6 / (n_gt * P), "gt_write_GBps": n_gt * P * W * 4 / (gt_ms * 1e-3) / 1e9,
+               "ct_ns_per_cell": ct_ms * 1e6 / (n_ct * P), "mi_ns_per_cell": mi_ms * 1e6 / (n_ct * P)}
+        out[key][f"k{order}_N{N}"] = row
+        log(f"functions k={order} N={N}: GT {row['gt_ns_per_row']:.4f} ns/row ({row['gt_write_GBps']:.0f} GB/s), "
+            f"CT {row['ct_ns_per_cell']:.4f} ns/cell, MI {row['mi_ns_per_cell']:.4f} ns/cell")
+        del rows, tabs, mi, dc
+        epi.epi_unload(ctx, ds)
+    epi.epi_destroy(ctx)
+    return out
+
+
 def batched_bench(epi, torch, n_scans, reps):
     """One persistent graph-captured launch of n uneven scans vs n back-to-back plain launches."""
     from synth import batched_specs, make_case_control
@@ -423,6 +519,8 @@ def main():
     ap.add_argument("--served-burst", type=int, default=100,
                     help="requests of the served capacity comparison (all submitted at once)")
     ap.add_argument("--no-orders", action="store_true")
+    ap.add_argument("--no-segmented", action="store_true", help="skip the segmented-vs-fused comparison")
+    ap.add_argument("--no-functions", action="store_true", help="skip the per-step (GT, CT, MI) timings")
     ap.add_argument("--no-compare", action="store_true", help="skip the comparison with the other counting kernels")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-copy-mib", type=int, default=0,
@@ -527,6 +625,11 @@ def main():
         others = [n for n in ("order2_M200_N1000", "order4_M200_N2000", "order5_M60_N2000", "order8_M23_N2048")
                   if n != args.workload]
         out["orders"] = orders_bench(epi, torch, others, 5)
+    if not args.no_functions:
+        out["functions"] = functions_bench(epi, torch)
+    if not args.no_segmented:
+        out["segmented"] = segmented_bench(
+            epi, ["order2_M200_N1000", args.workload, "order4_M200_N2000", "order5_M60_N2000", "order8_M23_N2048"], 3)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(spec, G, y, args.cpu_seconds)
     if not args.no_batched:

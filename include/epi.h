@@ -211,6 +211,13 @@ int epi_batch_destroy(epi_ctx *ctx, int32_t batch_id);
  * Every kernel produces the same integers and therefore the same results. */
 #define EPI_BLOCK_MFMA_FP4 16
 #define EPI_BLOCK_MFMA_I8 32
+/* Any order: the segmented exploration of Section 3.4 (Algorithm 2).  Each
+ * wave counts the full 2 x 3^k tables of a block of 64 combinations into a
+ * device buffer, then scores the block (the fused kernels score each table as
+ * it is counted).  Same results; the buffer takes 2 x 3^k x 256 bytes per
+ * wave of the launch (order 8: 3.4 MB).  Block 0 restores the built-in
+ * choice for the order. */
+#define EPI_BLOCK_SEGMENTED 64
 
 /* Time the counting kernels above for `order` on a bounded slice of the
  * dataset's combination space and remember the fastest for datasets of the
@@ -221,14 +228,52 @@ int epi_batch_destroy(epi_ctx *ctx, int32_t batch_id);
  * block. */
 int epi_autotune(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t *choice);
 
-/* Pin the counting kernel for `order` (2 or 3) on datasets of the same
- * bucket as `dataset_id`, as if the autotuner had chosen `block` (one of the
- * blocks listed above).  EPI_BLOCK_MFMA_I8 builds the dataset's integer
+/* Pin the counting kernel for `order` on datasets of the same bucket as
+ * `dataset_id`, as if the autotuner had chosen `block` (one of the blocks
+ * listed above; orders above 3 take only EPI_BLOCK_SEGMENTED and 0).  EPI_BLOCK_MFMA_I8 builds the dataset's integer
  * operand copies on the context stream and waits for them (no other work on
  * the dataset may be in flight).  EPI_EINVAL for a block not listed for the
  * order, EPI_EUNSUPPORTED for a matrix-core block on a dataset with 2^22
  * individuals or more, EPI_ENOMEM if the copies do not fit. */
 int epi_set_prefix_block(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t block);
+
+/* ---- the steps of the method as separate passes ------------------------- */
+
+/* Each of these takes n combinations of `order` SNP indices of a resident
+ * dataset on the device (int32 [n][order]; any indices in [0, M), in any
+ * order), runs on the context stream and returns when it is done;
+ * *kernel_ms (may be null) receives the kernel's time.  Output buffers are
+ * device memory owned by the caller.  EPI_EINVAL for an order outside the
+ * listed range, a null buffer, or an index outside [0, M) (that
+ * combination's output is left unwritten), EPI_ENOTFOUND for an unknown
+ * dataset, EPI_EDEVICE for a HIP error.  n = 0 does nothing. */
+
+/* Genotype tables (Section 2.1; Algorithm 1 builds them one SNP at a time):
+ * for each combination, row x for each of the 3^order genotype combinations
+ * (x in base 3, the first SNP's genotype the leading digit) is the set of
+ * individuals with those genotypes, cases then controls, as bitsets.
+ * d_rows: uint32 [n][3^order][W], W = W0 + W1 with W0 = 4 ceil(n_cases / 128)
+ * and W1 = 4 ceil(n_controls / 128); bit b of word w < W0 is case 32 w + b,
+ * bit b of word W0 + w is control 32 w + b (each class in input order); bits
+ * past a class's size are 0.  order 1 .. EPI_MAX_ORDER. */
+int epi_genotype_tables(epi_ctx *ctx, int32_t dataset_id, int32_t order, const int32_t *d_combos, uint64_t n,
+                        uint32_t *d_rows, float *kernel_ms);
+
+/* Contingency tables (Section 2.2): d_tables uint32 [n][2][3^order], class 0
+ * = cases, the cell order of the genotype tables (and of epi_results).
+ * order 2 .. EPI_MAX_ORDER. */
+int epi_contingency_tables(epi_ctx *ctx, int32_t dataset_id, int32_t order, const int32_t *d_combos, uint64_t n,
+                           uint32_t *d_tables, float *kernel_ms);
+
+/* Mutual information (Section 2.3, Equation 1, natural logarithm) of n
+ * contingency tables of the dataset, uint32 [n][2][3^order] on the device,
+ * into d_mi (double [n], device).  It is the exact fixed-point sum the scans
+ * rank by, scaled to nats, so it matches a scan's score of the same
+ * combination to the float rounding of that score.  EPI_EINVAL if a table's
+ * classes do not sum to the dataset's class sizes (its d_mi entry is NaN).
+ * order 2 .. EPI_MAX_ORDER. */
+int epi_mutual_information(epi_ctx *ctx, int32_t dataset_id, int32_t order, const uint32_t *d_tables, uint64_t n,
+                           double *d_mi, float *kernel_ms);
 
 /* ---- serving: continuous batching -------------------------------------- */
 

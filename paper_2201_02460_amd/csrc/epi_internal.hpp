@@ -58,7 +58,12 @@ enum Variant : int32_t {
     kF2Emit = 3,   // order-2 reduced cells written to the pair sub-table
     kF3Emit = 4,   // order-3 reduced cells written to the triplet sub-table (matrix cores)
     kR4 = 5,       // order 4, reduced cells per lane, other cells from the sub-tables
+    kSeg = 6,      // any order, segmented: a wave's 64 tables counted to a buffer, then scored
 };
+
+// Kernel instantiation of the segmented variant for order k: generic-order
+// parameter kSegGk + k.
+constexpr int kSegGk = 16;
 
 struct DsView {
     const v4u *masks;
@@ -88,6 +93,8 @@ struct Task {
     DsView ds;
     uint32_t *pairs;                  // lex-ordered pair sub-table, 8 u32 per pair
     uint32_t *triples;                // colex-ordered triplet sub-table, 16 u32 per triplet (kR4, kF3Emit)
+    uint32_t *seg;                    // kSeg: per wave slot of the launch (4 per workgroup), 2 x 3^k x 64 u32
+                                      //   counts, cell-major ([class][cell][lane])
     const unsigned long long *items;  // per-item descriptors: kF3 j<<40 | ib<<20 | mb, kF2 ib<<20 | mb
                                       // (kF3 with np = kNpMfma: 16-SNP i-block ib, 32-SNP m-block mb)
     unsigned long long n_items;

@@ -1061,8 +1061,14 @@ EPI_DEV void colex_unrank(unsigned long long rank, int M, const unsigned long lo
     }
 }
 
-template <int K>
-EPI_DEV long long generic_num(const DsView &d, const int (&c)[K], long long score_const) {
+// Counts every cell of combination c, 27 (order 2: 9) at a time.  The fused
+// form (STORE false) scores each chunk as it is counted and returns the
+// score; with STORE the counts go to out[x * ostride] (class 0) and
+// out[(3^K + x) * ostride] (class 1) instead, x the cell's index in base 3
+// with the genotype of c[0] as the leading digit.
+template <int K, bool STORE = false>
+EPI_DEV long long generic_num(const DsView &d, const int (&c)[K], long long score_const, uint32_t *out = nullptr,
+                              int ostride = kWave) {
     constexpr int NPRE = K > 3 ? K - 3 : 0;
     constexpr int NCH = pow3c(NPRE);
     constexpr int L = K >= 3 ? 3 : 2;
@@ -1128,8 +1134,16 @@ EPI_DEV long long generic_num(const DsView &d, const int (&c)[K], long long scor
                 }
             }
         }
-        #pragma unroll
-        for (int x = 0; x < CELLS; ++x) num += cell_term_counted(d.tlog, acc[0][x], acc[1][x]);
+        if constexpr (STORE) {
+            #pragma unroll
+            for (int x = 0; x < CELLS; ++x) {
+                out[(ch * CELLS + x) * ostride] = acc[0][x];
+                out[(pow3c(K) + ch * CELLS + x) * ostride] = acc[1][x];
+            }
+        } else {
+            #pragma unroll
+            for (int x = 0; x < CELLS; ++x) num += cell_term_counted(d.tlog, acc[0][x], acc[1][x]);
+        }
     }
     return num;
 }
@@ -1146,6 +1160,43 @@ EPI_DEV void item_generic(const Task &t, unsigned long long local, TopK &tk, Can
         int c[K];
         colex_unrank<K>(rank, d.M, binom, bstride, c);
         const long long num = generic_num<K>(d, c, t.score_const);
+        unsigned long long key = 0;
+        #pragma unroll
+        for (int u = 0; u < K; ++u) key = (key << bits) | (unsigned long long)c[u];
+        tk_offer(tk, list, valid, num, key, gthr);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// kSeg: the segmented exploration of Section 3.4 (Algorithm 2) on a wave.  A
+// block of b = 64 combinations (one per lane) first has all 2 x 3^K cells of
+// its contingency tables counted, as kGeneric counts them, into the wave's
+// slot of a device buffer (cell-major, 64 lanes contiguous); only then are
+// the b tables read back and scored.  The item's kGenRanks blocks follow one
+// another through the same slot.  A lane reads back only what it wrote, so
+// program order is the only ordering needed.
+// ---------------------------------------------------------------------------
+template <int K>
+EPI_DEV void item_seg(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr,
+                      const unsigned long long *binom, int bstride, uint32_t *slot) {
+    constexpr int CELLS = pow3c(K);
+    const DsView d = t.ds;
+    const int bits = t.key_bits;
+    const int lane = lane_id();
+    uint32_t *mine = slot + lane;
+    #pragma unroll 1
+    for (int rr = 0; rr < kGenRanks; ++rr) {
+        unsigned long long rank = (local * kGenRanks + rr) * kWave + lane;
+        const bool valid = rank < t.n_combos;
+        rank = valid ? rank : 0ull;
+        int c[K];
+        colex_unrank<K>(rank, d.M, binom, bstride, c);
+        // phase 1: the block's tables
+        (void)generic_num<K, true>(d, c, 0, mine);
+        // phase 2: their scores
+        long long num = t.score_const;
+        #pragma unroll 9
+        for (int x = 0; x < CELLS; ++x) num += cell_term_counted(d.tlog, mine[x * kWave], mine[(CELLS + x) * kWave]);
         unsigned long long key = 0;
         #pragma unroll
         for (int u = 0; u < K; ++u) key = (key << bits) | (unsigned long long)c[u];
@@ -1459,8 +1510,13 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
                     else item_f3<NP3, false>(T, local, tk, s_list, gthr, s_stage, stage_cap);
                 }
                 break;
+            case kSeg:
+                if constexpr (GK > kSegGk)
+                    item_seg<GK - kSegGk>(T, local, tk, s_list, gthr, binom, bstride,
+                                          T.seg + (size_t)(blockIdx.x * 4 + wave) * (2 * kWave * pow3c(GK - kSegGk)));
+                break;
             default:
-                if constexpr (GK > 0) item_generic<GK>(T, local, tk, s_list, gthr, binom, bstride);
+                if constexpr (GK > 0 && GK < kSegGk) item_generic<GK>(T, local, tk, s_list, gthr, binom, bstride);
                 break;
             }
             if (!is_emit(T.variant)) {
@@ -1670,6 +1726,172 @@ __global__ void __launch_bounds__(64) finalize_kernel(const Task *__restrict__ t
             }
             tables[((long long)r * 2 + cl) * cells + x] = cnt;
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The three steps of Section 2 as separate passes over a list of
+// combinations (n x K int32 SNP indices): genotype tables (Section 2.1),
+// contingency tables (Section 2.2) and mutual information (Section 2.3,
+// Equation 1).  An index outside [0, M) or a table that does not fit the
+// dataset sets *err and leaves that combination's output unwritten (tables,
+// rows) or NaN (MI).
+// ---------------------------------------------------------------------------
+
+// Genotype rows, depth-first over the genotypes of SNPs T .. K-1: p is the
+// AND of the rows chosen for SNPs 0 .. T-1 (Algorithm 1's combine step adds
+// one SNP per level); leaves are written W words apart.
+template <int T, int K>
+EPI_DEV void gt_walk(const unsigned (&r)[K][3], unsigned p, uint32_t *&o, int W) {
+    if constexpr (T + 2 >= K) {
+        #pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            const unsigned q = p & r[T][g];
+            if constexpr (T + 1 == K) {
+                *o = q;
+                o += W;
+            } else {
+                gt_walk<T + 1, K>(r, q, o, W);
+            }
+        }
+    } else {
+        #pragma unroll 1
+        for (int g = 0; g < 3; ++g) {
+            const unsigned rg = g == 0 ? r[T][0] : (g == 1 ? r[T][1] : r[T][2]);
+            gt_walk<T + 1, K>(r, p & rg, o, W);
+        }
+    }
+}
+
+// Leading SNPs whose genotypes split a combination's rows over threads.
+template <int K>
+constexpr int gt_split() { return K >= 5 ? 2 : 0; }
+
+// One thread per (combination, genotypes of its first gt_split SNPs, 32-bit
+// word of the two classes' rows): rows [i][x][w], W = 4 (w4[0] + w4[1])
+// words, class 0 first.
+template <int K>
+__global__ void __launch_bounds__(256) gt_kernel(DsView d, const int32_t *__restrict__ combos, unsigned long long n,
+                                                 uint32_t *__restrict__ rows, int *__restrict__ err) {
+    constexpr int P = pow3c(K), S = gt_split<K>(), PS = pow3c(S);
+    const int W0 = 4 * d.w4[0], W = W0 + 4 * d.w4[1];
+    const unsigned *m = (const unsigned *)d.masks;
+    const long long Mp = d.Mp;
+    const unsigned long long total = n * PS * (unsigned long long)W;
+    for (unsigned long long id = blockIdx.x * 256ull + threadIdx.x; id < total;
+         id += (unsigned long long)gridDim.x * 256ull) {
+        const unsigned long long rest = id / (unsigned)W;
+        const int w = (int)(id - rest * (unsigned)W);
+        const unsigned long long i = rest / PS;
+        const int sub = (int)(rest - i * PS);
+        const int cl = w < W0 ? 0 : 1;
+        const int wc = w - (cl ? W0 : 0);
+        const long long g4 = d.wbase[cl] + wc / 4;
+        const int left = d.ncls[cl] - 32 * wc;
+        const unsigned vm = left >= 32 ? ~0u : (left <= 0 ? 0u : ((1u << left) - 1u));
+        unsigned r[K][3];
+        bool bad = false;
+        #pragma unroll
+        for (int t = 0; t < K; ++t) {
+            int sn = combos[i * K + t];
+            bad |= sn < 0 || sn >= d.M;
+            sn = sn < 0 || sn >= d.M ? 0 : sn;
+            r[t][0] = m[((g4 * 2 + 0) * Mp + sn) * 4 + (wc & 3)];
+            r[t][1] = m[((g4 * 2 + 1) * Mp + sn) * 4 + (wc & 3)];
+            r[t][2] = vm & ~(r[t][0] | r[t][1]);
+        }
+        if (bad) {
+            atomicOr(err, 1);
+            continue;
+        }
+        unsigned p = ~0u;
+        #pragma unroll
+        for (int t = 0, x = sub, div = PS / 3; t < S; ++t, div /= 3) {
+            const int g = x / div;
+            x -= g * div;
+            p &= g == 0 ? r[t][0] : (g == 1 ? r[t][1] : r[t][2]);
+        }
+        uint32_t *o = rows + (i * P + (unsigned long long)sub * (P / PS)) * (unsigned long long)W + w;
+        gt_walk<S, K>(r, p, o, W);
+    }
+}
+
+// One thread per combination: its 2 x 3^K counts, tables[i][class][x].
+template <int K>
+__global__ void __launch_bounds__(256) ct_kernel(DsView d, const int32_t *__restrict__ combos, unsigned long long n,
+                                                 uint32_t *__restrict__ tables, int *__restrict__ err) {
+    for (unsigned long long i = blockIdx.x * 256ull + threadIdx.x; i < n; i += (unsigned long long)gridDim.x * 256ull) {
+        int c[K];
+        bool bad = false;
+        #pragma unroll
+        for (int t = 0; t < K; ++t) {
+            const int sn = combos[i * K + t];
+            bad |= sn < 0 || sn >= d.M;
+            c[t] = sn < 0 || sn >= d.M ? 0 : sn;
+        }
+        if (bad) {
+            atomicOr(err, 1);
+            continue;
+        }
+        (void)generic_num<K, true>(d, c, 0, tables + i * (2ull * pow3c(K)), 1);
+    }
+}
+
+// One thread per table: N * MI by Equation 1 from the exact n ln n table, as
+// the scans score a combination, then MI = that / 2^shift / N.  A table whose
+// classes do not sum to the dataset's class sizes is rejected.
+__global__ void __launch_bounds__(256) mi_kernel(DsView d, int P, long long score_const,
+                                                 const uint32_t *__restrict__ tables, unsigned long long n,
+                                                 double *__restrict__ mi, int *__restrict__ err) {
+    for (unsigned long long i = blockIdx.x * 256ull + threadIdx.x; i < n; i += (unsigned long long)gridDim.x * 256ull) {
+        const uint32_t *t = tables + i * 2ull * (unsigned)P;
+        long long num = score_const;
+        unsigned long long s0 = 0, s1 = 0;
+        bool ok = true;
+        for (int x = 0; x < P; ++x) {
+            const unsigned n0 = t[x], n1 = t[P + x];
+            const bool in = n0 <= (unsigned)d.ncls[0] && n1 <= (unsigned)d.ncls[1];
+            ok &= in;
+            s0 += n0;
+            s1 += n1;
+            num += in ? cell_term_counted(d.tlog, n0, n1) : 0;
+        }
+        ok &= s0 == (unsigned long long)d.ncls[0] && s1 == (unsigned long long)d.ncls[1];
+        mi[i] = ok ? ldexp((double)num, -d.shift) / (double)d.N : __builtin_nan("");
+        if (!ok) atomicOr(err, 1);
+    }
+}
+
+template <int K>
+static hipError_t launch_function_k(int fn, hipStream_t st, const DsView &d, const int32_t *combos,
+                                    unsigned long long n, void *out, int *err, int grid) {
+    if (fn == 0) {
+        hipLaunchKernelGGL(gt_kernel<K>, dim3(grid), dim3(256), 0, st, d, combos, n, (uint32_t *)out, err);
+    } else {
+        if constexpr (K < 2) return hipErrorInvalidValue;  // tables start at order 2
+        else hipLaunchKernelGGL(ct_kernel<K>, dim3(grid), dim3(256), 0, st, d, combos, n, (uint32_t *)out, err);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_function(int fn, int order, hipStream_t st, const DsView &d, const int32_t *combos,
+                           const uint32_t *tables, unsigned long long n, void *out, int *err, int grid,
+                           long long score_const) {
+    if (fn == 2) {
+        hipLaunchKernelGGL(mi_kernel, dim3(grid), dim3(256), 0, st, d, pow3i(order), score_const, tables, n,
+                           (double *)out, err);
+        return hipGetLastError();
+    }
+    switch (order) {
+    case 1: return launch_function_k<1>(fn, st, d, combos, n, out, err, grid);
+    case 2: return launch_function_k<2>(fn, st, d, combos, n, out, err, grid);
+    case 3: return launch_function_k<3>(fn, st, d, combos, n, out, err, grid);
+    case 4: return launch_function_k<4>(fn, st, d, combos, n, out, err, grid);
+    case 5: return launch_function_k<5>(fn, st, d, combos, n, out, err, grid);
+    case 6: return launch_function_k<6>(fn, st, d, combos, n, out, err, grid);
+    case 7: return launch_function_k<7>(fn, st, d, combos, n, out, err, grid);
+    case 8: return launch_function_k<8>(fn, st, d, combos, n, out, err, grid);
+    default: return hipErrorInvalidValue;
     }
 }
 
@@ -1892,6 +2114,8 @@ static const ScanKernelEntry kScanKernels[] = {
     EPI_K(0, 1, 0), EPI_K(0, 2, 0), EPI_K(0, 4, 0), EPI_K(0, 8, 0),   // order 3
     EPI_K(0, 0, 2), EPI_K(0, 0, 3), EPI_K(0, 0, 4), EPI_K(0, 0, 5),   // per-combination kernel
     EPI_K(0, 0, 6), EPI_K(0, 0, 7), EPI_K(0, 0, 8),
+    EPI_K(0, 0, kSegGk + 2), EPI_K(0, 0, kSegGk + 3), EPI_K(0, 0, kSegGk + 4),   // segmented (two-phase)
+    EPI_K(0, 0, kSegGk + 5), EPI_K(0, 0, kSegGk + 6), EPI_K(0, 0, kSegGk + 7), EPI_K(0, 0, kSegGk + 8),
     EPI_K(0, kNpMfma, 0), EPI_K(0, kNpMfmaI8, 0),                    // order 3, matrix cores
 };
 #undef EPI_K

@@ -381,6 +381,14 @@ int tuned_np_lookup(Ctx *c, int order, const Dataset *d) {
     return it != c->tuned.end() ? it->second : 0;
 }
 
+bool seg_pinned(Ctx *c, int order, const Dataset *d) {
+    const int words = (d->w4[0] + d->w4[1]) * 4;
+    int bucket = 0;
+    while ((1 << bucket) < words) ++bucket;
+    std::lock_guard<std::mutex> g(c->tune_mu);
+    return c->seg_pins.count(TuneKey{order, bucket}) != 0;
+}
+
 static int tuned_np(Ctx *c, int order, const Dataset *d) {
     if (order == 3) return default_np3(c, d);
     const int t = tuned_np_lookup(c, order, d);
@@ -524,6 +532,7 @@ void plan_free(Ctx *c, Plan *p) {
     for (auto &s : p->scans) {
         c->alloc.release(s.pairs);
         c->alloc.release(s.triples);
+        c->alloc.release(s.seg);
         c->alloc.release(s.cand);
     }
     c->alloc.release(p->d_parts);
@@ -709,7 +718,11 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         s.ds = dss[i];
         s.n_combos = binom_u64(s.ds->M, s.desc.order);
         const int o = s.desc.order;
-        if (o == 2) {
+        if (force_np <= 0 && seg_pinned(c, o, s.ds)) {
+            s.variant = kSeg;
+            s.np = kGenRanksHost;
+            s.n_items = (s.n_combos + 64ull * kGenRanksHost - 1) / (64ull * kGenRanksHost);
+        } else if (o == 2) {
             s.variant = kF2;
             s.np = persistent ? 4 : (force_np > 0 ? force_np : tuned_np(c, 2, s.ds));
         } else if (o == 3) {
@@ -728,18 +741,28 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         std::map<int, LaunchGroup> by_key;
         for (int i = 0; i < n; ++i) {
             const PlanScan &s = p->scans[i];
-            const int key = s.desc.order == 3 ? 30 + s.np : group_of_order(s.desc.order);
+            const bool seg = s.variant == kSeg;
+            const int key = seg ? 200 + s.desc.order
+                                : (s.desc.order == 3 ? 30 + s.np : group_of_order(s.desc.order));
             LaunchGroup &g = by_key[key];
             g.scans.push_back(i);
             std::vector<int> orders{s.desc.order};
             pick_group_kernel(orders, s.np, &g.np2, &g.np3, &g.gk);
+            if (seg) {
+                g.np2 = g.np3 = 0;
+                g.gk = kSegGk + s.desc.order;
+            }
         }
         for (auto &kv : by_key) p->groups.push_back(kv.second);
     } else {
         for (int i = 0; i < n; ++i) {
             LaunchGroup g;
             const PlanScan &s = p->scans[i];
-            if (s.desc.order == 2) {
+            if (s.variant == kSeg) {
+                g.np2 = 0;
+                g.np3 = 0;
+                g.gk = kSegGk + s.desc.order;
+            } else if (s.desc.order == 2) {
                 g.np2 = s.np;
                 g.np3 = 0;
                 g.gk = 0;
@@ -815,6 +838,11 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         s.cand_cap = (unsigned)std::min<unsigned long long>((unsigned long long)grid * 4 * s.desc.top_k + 64,
                                                             0xffffffffull);
         if ((rc = c->alloc.alloc((size_t)s.cand_cap * sizeof(Cand), &s.cand))) return cleanup(rc);
+        if (s.variant == kSeg) {
+            // one block of 64 tables (2 x 3^k counts each) per wave slot of the launch
+            const size_t sb = (size_t)grid * 4 * 64 * 2 * (size_t)pow3i(s.desc.order) * 4;
+            if ((rc = c->alloc.alloc(sb, &s.seg))) return cleanup(rc);
+        }
         s.lay.offset = out_bytes;
         s.lay.top_k = s.desc.top_k;
         s.lay.order = s.desc.order;
@@ -847,6 +875,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         t.ds = s.ds->view;
         t.pairs = (uint32_t *)s.pairs;
         t.triples = (uint32_t *)s.triples;
+        t.seg = (uint32_t *)s.seg;
         t.items = (const unsigned long long *)s.items;
         t.n_items = s.n_items;
         t.item_base = 0;
@@ -1133,6 +1162,7 @@ int autotune(Ctx *c, int ds_id, int order, int *choice) {
     {
         std::lock_guard<std::mutex> g(c->tune_mu);
         c->tuned[TuneKey{order, bucket}] = best;
+        c->seg_pins.erase(TuneKey{order, bucket});
         save_tune_cache(c);
     }
     *choice = best;
@@ -1507,7 +1537,8 @@ int epi_set_prefix_block(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_
     const bool ok2 = order == 2 && (block == 2 || block == 4 || block == 8);
     const bool ok3 = order == 3 && (block == 1 || block == 2 || block == 4 || block == 8 || block == kNpMfma ||
                                     block == kNpMfmaI8);
-    if (!ok2 && !ok3) return fail(EPI_EINVAL, "prefix block %d is not a kernel of order %d", block, order);
+    const bool any = order >= EPI_MIN_ORDER && order <= EPI_MAX_ORDER && (block == 0 || block == EPI_BLOCK_SEGMENTED);
+    if (!ok2 && !ok3 && !any) return fail(EPI_EINVAL, "prefix block %d is not a kernel of order %d", block, order);
     if (block == kNpMfma && !d->qa)
         return fail(EPI_EUNSUPPORTED, "dataset %d has no matrix-core operands (2^22 individuals or more)", dataset_id);
     if (block == kNpMfmaI8) {
@@ -1521,9 +1552,87 @@ int epi_set_prefix_block(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_
     while ((1 << bucket) < words) ++bucket;
     {
         std::lock_guard<std::mutex> g(C->tune_mu);
-        C->tuned[TuneKey{order, bucket}] = block;
+        const TuneKey key{order, bucket};
+        if (block == EPI_BLOCK_SEGMENTED) {
+            C->seg_pins[key] = 1;
+        } else if (block == 0) {
+            C->seg_pins.erase(key);
+            C->tuned.erase(key);
+        } else {
+            C->seg_pins.erase(key);
+            C->tuned[key] = block;
+        }
     }
     return EPI_OK;
+}
+
+// The steps of the method as separate passes (genotype rows, contingency
+// tables, MI) over a device list of combinations or tables; synchronous.
+static int run_function(epi_ctx *ctx, int fn, int32_t dataset_id, int32_t order, const int32_t *d_combos,
+                        const uint32_t *d_tables, uint64_t n, void *d_out, float *kernel_ms) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    Dataset *d;
+    {
+        std::lock_guard<std::mutex> g(C->mu);
+        auto it = C->datasets.find(dataset_id);
+        if (it == C->datasets.end()) return fail(EPI_ENOTFOUND, "unknown dataset %d", dataset_id);
+        d = it->second.get();
+    }
+    const int lo = fn == 0 ? 1 : EPI_MIN_ORDER;
+    if (order < lo || order > EPI_MAX_ORDER)
+        return fail(EPI_EINVAL, "order %d outside %d .. %d", order, lo, EPI_MAX_ORDER);
+    if (kernel_ms) *kernel_ms = 0.f;
+    if (n == 0) return EPI_OK;
+    if (!d_out || (fn < 2 && !d_combos) || (fn == 2 && !d_tables)) return fail(EPI_EINVAL, "null buffer");
+    const unsigned long long words = (unsigned long long)(d->w4[0] + d->w4[1]) * 4;
+    const unsigned long long threads = fn == 0 ? n * words * (order >= 5 ? 9 : 1) : n;
+    const unsigned long long want = (threads + 255) / 256;
+    const int grid = (int)std::min<unsigned long long>(want, (unsigned long long)C->n_cu * 64);
+    void *d_err = nullptr;
+    int rc = C->alloc.alloc(256, &d_err);
+    if (rc) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if ((rc = event_get(C, &e0)) || (rc = event_get(C, &e1))) {
+        event_put(C, e0);
+        C->alloc.release(d_err);
+        return rc;
+    }
+    int h_err = 0;
+    hipError_t he = hipMemsetAsync(d_err, 0, sizeof(int), C->stream);
+    if (he == hipSuccess) he = hipEventRecord(e0, C->stream);
+    if (he == hipSuccess)
+        he = launch_function(fn, order, C->stream, d->view, d_combos, d_tables, n, d_out, (int *)d_err, grid,
+                             d->score_const);
+    if (he == hipSuccess) he = hipEventRecord(e1, C->stream);
+    if (he == hipSuccess) he = hipMemcpyAsync(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost, C->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(C->stream);
+    float ms = 0.f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    event_put(C, e0);
+    event_put(C, e1);
+    C->alloc.release(d_err);
+    if (he != hipSuccess) return fail(EPI_EDEVICE, "device error: %s", hipGetErrorString(he));
+    if (kernel_ms) *kernel_ms = ms;
+    if (h_err)
+        return fail(EPI_EINVAL, fn == 2 ? "a table does not fit the dataset's class sizes"
+                                        : "a SNP index outside [0, %d)", d->M);
+    return EPI_OK;
+}
+
+int epi_genotype_tables(epi_ctx *ctx, int32_t dataset_id, int32_t order, const int32_t *d_combos, uint64_t n,
+                        uint32_t *d_rows, float *kernel_ms) {
+    return run_function(ctx, 0, dataset_id, order, d_combos, nullptr, n, d_rows, kernel_ms);
+}
+
+int epi_contingency_tables(epi_ctx *ctx, int32_t dataset_id, int32_t order, const int32_t *d_combos, uint64_t n,
+                           uint32_t *d_tables, float *kernel_ms) {
+    return run_function(ctx, 1, dataset_id, order, d_combos, nullptr, n, d_tables, kernel_ms);
+}
+
+int epi_mutual_information(epi_ctx *ctx, int32_t dataset_id, int32_t order, const uint32_t *d_tables, uint64_t n,
+                           double *d_mi, float *kernel_ms) {
+    return run_function(ctx, 2, dataset_id, order, nullptr, d_tables, n, d_mi, kernel_ms);
 }
 
 int epi_autotune(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t *choice) {

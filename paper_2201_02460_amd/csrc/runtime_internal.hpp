@@ -69,6 +69,7 @@ struct PlanScan {
     // order 4 by reduced cells: triplet sub-table pass
     void *triples = nullptr;
     int t3_task = -1;
+    void *seg = nullptr;  // segmented variant: the launch's per-wave table blocks
     unsigned long long t3_items = 0;
     const void *t3_items_d = nullptr;
     void *cand = nullptr;
@@ -143,6 +144,7 @@ struct Ctx {
     std::map<int, ScanRef> scan_index;
     std::mutex tune_mu;
     std::map<TuneKey, int> tuned;
+    std::map<TuneKey, int> seg_pins;  // (order, bucket) pinned to the segmented variant
     std::string tune_path;
     std::map<int, std::shared_ptr<Server>> servers;
     std::mutex items_mu;
@@ -167,6 +169,10 @@ hipError_t launch_finalize(int n_tasks, int max_k, hipStream_t st, const Task *t
                            const ResultLayout *layout, char *out);
 hipError_t launch_init_counters(hipStream_t st, unsigned long long *queues, int nq, unsigned *cand_counts,
                                 unsigned long long *thrs, int n_tasks, unsigned *hist);
+// fn 0: genotype rows, 1: contingency tables (of combos), 2: MI (of tables)
+hipError_t launch_function(int fn, int order, hipStream_t st, const DsView &d, const int32_t *combos,
+                           const uint32_t *tables, unsigned long long n, void *out, int *err, int grid,
+                           long long score_const);
 hipError_t launch_reseed(int n_tasks, hipStream_t st, const Task *tasks, const Cand *results);
 hipError_t launch_pack(hipStream_t st, const uint8_t *geno, long long ld, const int32_t *idx, const DsView &d,
                        v4u *masks, int *err);
@@ -183,6 +189,7 @@ void pick_group_kernel(const std::vector<int> &orders, int np3_hint, int *np2, i
 int group_of_order(int order);
 bool r4_fits(const Dataset *d);
 int tuned_np_lookup(Ctx *c, int order, const Dataset *d);
+bool seg_pinned(Ctx *c, int order, const Dataset *d);
 int default_np3(Ctx *c, const Dataset *d);
 int grid_for(Ctx *c, int np2, int np3, int gk, unsigned long long items, int tab_cap, int kmax, int stage_cap);
 int stage_cap_for(int np2, int np3, int w4_max);

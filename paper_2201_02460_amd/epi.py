@@ -29,6 +29,7 @@ EPI_MAX_ORDER = 8
 EPI_SERVE_MAX_ORDER = 5
 EPI_BLOCK_MFMA_FP4 = 16
 EPI_BLOCK_MFMA_I8 = 32
+EPI_BLOCK_SEGMENTED = 64
 EPI_MAX_TOP_K = 256
 
 # Every function the header declares, with (restype, argtypes).
@@ -72,6 +73,9 @@ SIGNATURES = {
     "epi_batch_destroy": (_c.c_int, [_vp, _i32]),
     "epi_autotune": (_c.c_int, [_vp, _i32, _i32, _P(_i32)]),
     "epi_set_prefix_block": (_c.c_int, [_vp, _i32, _i32, _i32]),
+    "epi_genotype_tables": (_c.c_int, [_vp, _i32, _i32, _vp, _u64, _vp, _P(_c.c_float)]),
+    "epi_contingency_tables": (_c.c_int, [_vp, _i32, _i32, _vp, _u64, _vp, _P(_c.c_float)]),
+    "epi_mutual_information": (_c.c_int, [_vp, _i32, _i32, _vp, _u64, _vp, _P(_c.c_float)]),
     "epi_server_start": (_c.c_int, [_vp, _P(ServerConfig), _P(_i32)]),
     "epi_server_submit": (_c.c_int, [_vp, _i32, _i32, _i32, _i32, _P(_i32)]),
     "epi_server_poll": (_c.c_int, [_vp, _i32, _i32, _P(_i32)]),
@@ -300,6 +304,31 @@ def epi_autotune(ctx, dataset_id, order):
 
 def epi_set_prefix_block(ctx, dataset_id, order, block):
     _check(lib().epi_set_prefix_block(ctx, dataset_id, order, block))
+
+
+def epi_genotype_tables(ctx, dataset_id, d_combos, d_rows):
+    """Genotype rows of the combinations in d_combos (device int32 [n][k])
+    into d_rows (device uint32 [n][3^k][W]); returns the kernel time in ms."""
+    n, k = d_combos.shape
+    ms = _c.c_float()
+    _check(lib().epi_genotype_tables(ctx, dataset_id, k, _ptr(d_combos), n, _ptr(d_rows), _c.byref(ms)))
+    return ms.value
+
+
+def epi_contingency_tables(ctx, dataset_id, d_combos, d_tables):
+    """Contingency tables (device uint32 [n][2][3^k]) of d_combos; returns ms."""
+    n, k = d_combos.shape
+    ms = _c.c_float()
+    _check(lib().epi_contingency_tables(ctx, dataset_id, k, _ptr(d_combos), n, _ptr(d_tables), _c.byref(ms)))
+    return ms.value
+
+
+def epi_mutual_information(ctx, dataset_id, order, d_tables, d_mi):
+    """MI (device float64 [n]) of n tables (device uint32 [n][2][3^order]); returns ms."""
+    n = d_tables.shape[0]
+    ms = _c.c_float()
+    _check(lib().epi_mutual_information(ctx, dataset_id, order, _ptr(d_tables), n, _ptr(d_mi), _c.byref(ms)))
+    return ms.value
 
 
 def epi_server_start(ctx, max_active=64, round_items=0, request_budget=0):

@@ -228,6 +228,35 @@ def test_batch_matches_single_scans(cx, orc):
         epi.epi_unload(cx.ctx, d)
 
 
+@pytest.mark.parametrize("order,M,N,nc,K", [(2, 130, 300, 100, 20), (3, 70, 257, 128, 25), (4, 30, 200, 77, 30),
+                                            (5, 21, 385, 200, 12), (6, 14, 130, 40, 9), (7, 12, 96, 48, 5),
+                                            (8, 13, 260, 100, 30)])
+def test_segmented_matches_fused(cx, orc, order, M, N, nc, K):
+    """The segmented variant (tables of a block counted first, then scored)
+    gives the fused kernels' results exactly, and the oracle's."""
+    from paper_2201_02460_amd import epi
+
+    G, y = random_genotypes(M, N, seed=700 + order, case_fraction=nc / N)
+    ds = cx.load(G, y)
+    try:
+        fused = cx.scan(ds, order, K)
+        epi.epi_set_prefix_block(cx.ctx, ds, order, epi.EPI_BLOCK_SEGMENTED)
+        try:
+            seg = cx.scan(ds, order, K)
+        finally:
+            epi.epi_set_prefix_block(cx.ctx, ds, order, 0)
+        say("order", order, "fused variant", fused["variant"], "segmented variant", seg["variant"])
+        assert seg["variant"] == 6 and fused["variant"] != 6
+        assert np.array_equal(seg["combos"], fused["combos"]) and np.array_equal(seg["scores"], fused["scores"])
+        assert np.array_equal(seg["tables"], fused["tables"])
+        check_topk(orc, G, y, order, K, seg["combos"], seg["scores"], seg["tables"])
+        with pytest.raises(epi.EpiError) as e:
+            epi.epi_set_prefix_block(cx.ctx, ds, max(order, 4), 4)
+        assert e.value.code == epi.EPI_EINVAL
+    finally:
+        epi.epi_unload(cx.ctx, ds)
+
+
 def test_autotune_keeps_results(cx, orc):
     from paper_2201_02460_amd import epi
 
@@ -280,12 +309,14 @@ def test_counting_kernels_agree(cx, orc):
             assert np.array_equal(res["combos"], ref["combos"])
             assert np.array_equal(res["scores"], ref["scores"])
             assert np.array_equal(res["tables"], ref["tables"])
-    for bad in (3, 0, 64):
+    for bad in (3, 5, 128, -1):
         with pytest.raises(epi.EpiError) as e:
             epi.epi_set_prefix_block(cx.ctx, ds, 3, bad)
         assert e.value.code == epi.EPI_EINVAL
     with pytest.raises(epi.EpiError):
         epi.epi_set_prefix_block(cx.ctx, ds, 2, epi.EPI_BLOCK_MFMA_FP4)
-    # the choice holds for every dataset of the same size bucket: restore the default
-    epi.epi_set_prefix_block(cx.ctx, ds, 3, epi.EPI_BLOCK_MFMA_FP4)
+    # the choice holds for every dataset of the same size bucket: block 0
+    # restores the built-in default (the 4-bit matrix-core kernel here)
+    epi.epi_set_prefix_block(cx.ctx, ds, 3, 0)
+    assert cx.scan(ds, 3, 30)["prefix_block"] == epi.EPI_BLOCK_MFMA_FP4
     epi.epi_unload(cx.ctx, ds)
