@@ -266,6 +266,53 @@ def segmented_bench(epi, names, steps):
     return out
 
 
+def orders_pass_bench(epi, names, steps):
+    """Every order 2 .. k of a named workload in one pass (epi_scan_orders)
+    against the same scans one after another: end-to-end wall time (launch
+    through results on the host), median of steps runs."""
+    import numpy as np
+
+    from synth import make_workload
+
+    out = {}
+    ctx = epi.epi_create(0)
+    for name in names:
+        G, y, spec, _ = make_workload(name)
+        kmax, K = spec["order"], spec["top_k"]
+        orders = list(range(2, kmax + 1))
+        work = sum(math.comb(spec["M"], o) for o in orders) * spec["N"]
+        ds = epi.epi_load_genotypes(ctx, G, y)
+        t_one, t_sep, res_one, res_sep = [], [], None, None
+        for i in range(steps + 1):
+            t0 = time.perf_counter()
+            ids = epi.epi_scan_orders(ctx, ds, kmax, K)
+            res_one = []
+            for o, sid in zip(orders, ids):
+                epi.epi_wait(ctx, sid)
+                res_one.append(epi.epi_results(ctx, sid, K, o))
+                epi.epi_release(ctx, sid)
+            t1 = time.perf_counter()
+            res_sep = []
+            for o in orders:
+                sid = epi.epi_scan(ctx, ds, o, K)
+                epi.epi_wait(ctx, sid)
+                res_sep.append(epi.epi_results(ctx, sid, K, o))
+                epi.epi_release(ctx, sid)
+            t2 = time.perf_counter()
+            if i:
+                t_one.append(t1 - t0)
+                t_sep.append(t2 - t1)
+        epi.epi_unload(ctx, ds)
+        one, sep = sorted(t_one)[len(t_one) // 2], sorted(t_sep)[len(t_sep) // 2]
+        same = all(np.array_equal(u, v) for a, b in zip(res_one, res_sep) for u, v in zip(a, b))
+        out[name] = {"orders": orders, "one_pass_ms": one * 1e3, "separate_ms": sep * 1e3,
+                     "one_pass_value": work / one / 1e12, "separate_value": work / sep / 1e12,
+                     "speedup": sep / one, "identical_results": bool(same)}
+        log(f"{name} orders {orders}: one pass {one * 1e3:.3f} ms, separate {sep * 1e3:.3f} ms, identical {same}")
+    epi.epi_destroy(ctx)
+    return out
+
+
 def functions_bench(epi, torch, reps=3, out_cap=1 << 30):
     """The three steps as separate passes over a list of combinations, timed
     per genotype-table row (both classes), per contingency-table cell (both
@@ -521,6 +568,7 @@ def main():
     ap.add_argument("--no-orders", action="store_true")
     ap.add_argument("--no-segmented", action="store_true", help="skip the segmented-vs-fused comparison")
     ap.add_argument("--no-functions", action="store_true", help="skip the per-step (GT, CT, MI) timings")
+    ap.add_argument("--no-orders-pass", action="store_true", help="skip the all-orders-in-one-pass comparison")
     ap.add_argument("--no-compare", action="store_true", help="skip the comparison with the other counting kernels")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-copy-mib", type=int, default=0,
@@ -625,6 +673,9 @@ def main():
         others = [n for n in ("order2_M200_N1000", "order4_M200_N2000", "order5_M60_N2000", "order8_M23_N2048")
                   if n != args.workload]
         out["orders"] = orders_bench(epi, torch, others, 5)
+    if not args.no_orders_pass:
+        out["orders_one_pass"] = orders_pass_bench(
+            epi, [args.workload, "order4_M200_N2000", "order5_M60_N2000"], 5)
     if not args.no_functions:
         out["functions"] = functions_bench(epi, torch)
     if not args.no_segmented:

@@ -148,6 +148,16 @@ int epi_scan(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t top_k, voi
  * epi_scan, checked for every descriptor before anything is launched. */
 int epi_scan_batch(epi_ctx *ctx, const epi_scan_desc *descs, int32_t n, void *stream, int32_t *scan_ids);
 
+/* Every order from 2 to max_order in one pass (a search up to a given
+ * combination size): one scan per order, launched together as by
+ * epi_scan_batch; scan_ids[o - 2] receives the scan of order o, each waited
+ * for, read and released on its own.  The order-2 results are scored by the
+ * pair sub-table pass that the order-3 (or order-4) scan runs anyway, so the
+ * pairs are counted once.  Errors as epi_scan for each order (EINVAL for
+ * max_order < 2 or above M, EUNSUPPORTED above EPI_MAX_ORDER). */
+int epi_scan_orders(epi_ctx *ctx, int32_t dataset_id, int32_t max_order, int32_t top_k, void *stream,
+                    int32_t *scan_ids);
+
 /* *done = 1 when the scan's results are ready, else 0. */
 int epi_query(epi_ctx *ctx, int32_t scan_id, int32_t *done);
 

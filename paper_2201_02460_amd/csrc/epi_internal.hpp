@@ -59,6 +59,7 @@ enum Variant : int32_t {
     kF3Emit = 4,   // order-3 reduced cells written to the triplet sub-table (matrix cores)
     kR4 = 5,       // order 4, reduced cells per lane, other cells from the sub-tables
     kSeg = 6,      // any order, segmented: a wave's 64 tables counted to a buffer, then scored
+    kF2Fold = 7,   // order 2 scored by the pair sub-table pass of another scan of the same dataset
 };
 
 // Kernel instantiation of the segmented variant for order k: generic-order

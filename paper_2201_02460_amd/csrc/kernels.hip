@@ -473,10 +473,13 @@ EPI_DEV long long entry_bound(const TopK &tk, long long gthr) {
 }
 
 // ---------------------------------------------------------------------------
-// kF2 / kF2Emit: order 2.  A work item is (block of NP SNPs i, block of 64
-// SNPs m > i); lane = m.  Reduced cells (a, d) in {0,1}^2 per class.
+// kF2 / kF2Emit / kF2Fold: order 2.  A work item is (block of NP SNPs i,
+// block of 64 SNPs m > i); lane = m.  Reduced cells (a, d) in {0,1}^2 per
+// class, scored (kF2), written to the pair sub-table (kF2Emit), or both
+// (kF2Fold: a scan of all orders takes its order-2 results from the pair
+// sub-table pass of its higher orders instead of counting the pairs twice).
 // ---------------------------------------------------------------------------
-template <int NP, bool EMIT, bool LDS>
+template <int NP, bool EMIT, bool LDS, bool SCORE = !EMIT>
 EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr, v4u *stage,
                      int stage_cap) {
     const DsView d = t.ds;
@@ -559,7 +562,8 @@ EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *li
                 pv[2 * r + 0] = c0;
                 pv[2 * r + 1] = c1;
             }
-        } else {
+        }
+        if constexpr (SCORE) {
             const v4u si = single4[ip[p]];
             int F[2][9];
             #pragma unroll
@@ -1432,7 +1436,8 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
             // mirrored half too for the kernels in the signed cell form, when
             // it fits
             const int ent_fwd = T0.ds.N + 1, ent_rev = 2 * T0.ds.N + 2;
-            const bool want = (T0.variant == kF2 || T0.variant == kF3 || T0.variant == kR4) && ent_fwd <= tab_cap &&
+            const bool want = (T0.variant == kF2 || T0.variant == kF2Fold || T0.variant == kF3 || T0.variant == kR4) &&
+                              ent_fwd <= tab_cap &&
                               (unsigned)(uintptr_t)(lu32 *)s_tab == 0u;
             const bool sgn = (T0.variant == kF3 && (T0.np == kNpMfma || T0.np == kNpMfmaI8)) || T0.variant == kR4;
             const bool rev = want && sgn && ent_rev <= tab_cap;  // read only in the signed cell form
@@ -1488,6 +1493,12 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
             case kF2Emit:
                 if constexpr (NP2 > 0)
                     item_f2<NP2, true, false>(T, local, tk, s_list, gthr, s_stage, stage_cap);
+                break;
+            case kF2Fold:
+                if constexpr (NP2 > 0) {
+                    if (lds) item_f2<NP2, true, true, true>(T, local, tk, s_list, gthr, s_stage, stage_cap);
+                    else item_f2<NP2, true, false, true>(T, local, tk, s_list, gthr, s_stage, stage_cap);
+                }
                 break;
             case kF3Emit:
                 if constexpr (NP3 == kNpMfma) item_f3m<false, false, false, true>(T, local, tk, s_list, gthr, s_stage);

@@ -692,7 +692,9 @@ static void pick_tab_cap(const Plan *p, LaunchGroup &g) {
 // ones take the per-combination kernel.
 static constexpr unsigned long long kMaxTripleBytes = 8ull << 30;
 bool r4_fits(const Dataset *d) { return d->qa && binom_u64(d->M, 3) <= kMaxTripleBytes / 64; }
-static bool needs_pairs(const PlanScan &s) { return s.desc.order == 3 || s.variant == kR4; }
+static bool needs_pairs(const PlanScan &s) {
+    return s.variant != kSeg && (s.desc.order == 3 || s.variant == kR4);
+}
 
 int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool graph, Plan **out,
                int force_np) {
@@ -734,6 +736,23 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
             s.n_items = (s.n_combos + 64ull * kGenRanksHost - 1) / (64ull * kGenRanksHost);
         }
     }
+    // Scans of several orders over one dataset count the pairs once: an
+    // order-2 scan is scored by the pair sub-table pass of a higher-order scan
+    // of the same dataset in this plan (kF2Fold) and has no launch of its own.
+    std::vector<int> fold_of(n, -1);  // scan j's pair pass scores scan fold_of[j]
+    if (persistent) {
+        for (int i = 0; i < n; ++i) {
+            PlanScan &s = p->scans[i];
+            if (s.variant != kF2) continue;
+            for (int j = 0; j < n; ++j) {
+                if (j == i || fold_of[j] >= 0 || p->scans[j].ds != s.ds || !needs_pairs(p->scans[j])) continue;
+                fold_of[j] = i;
+                s.variant = kF2Fold;
+                s.n_items = 0;
+                break;
+            }
+        }
+    }
     // launch groups
     if (persistent) {
         // one launch group per kernel instantiation: order 2, order 3 per
@@ -741,6 +760,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         std::map<int, LaunchGroup> by_key;
         for (int i = 0; i < n; ++i) {
             const PlanScan &s = p->scans[i];
+            if (s.variant == kF2Fold) continue;  // runs in the pair pass
             const bool seg = s.variant == kSeg;
             const int key = seg ? 200 + s.desc.order
                                 : (s.desc.order == 3 ? 30 + s.np : group_of_order(s.desc.order));
@@ -822,7 +842,9 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
     for (auto &s : p->scans)
         if (needs_pairs(s)) emit_w4 = std::max(emit_w4, std::max(s.ds->w4[0], s.ds->w4[1]));
     p->emit_stage = stage_cap_for(4, 0, emit_w4);
-    p->emit_grid = grid_for(c, 4, 0, 0, std::max<unsigned long long>(emit_total, 1), 0, 1, p->emit_stage);
+    for (int j = 0; j < n; ++j)
+        if (fold_of[j] >= 0) p->emit_kmax = std::max(p->emit_kmax, p->scans[fold_of[j]].desc.top_k);
+    p->emit_grid = grid_for(c, 4, 0, 0, std::max<unsigned long long>(emit_total, 1), 0, p->emit_kmax, p->emit_stage);
     p->t3_total = t3_total;
     p->t3_stage = stage_cap_for(0, kNpMfma, 0);
     p->t3_grid = grid_for(c, 0, kNpMfma, 0, std::max<unsigned long long>(t3_total, 1), 0, 1, p->t3_stage);
@@ -830,7 +852,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
     long long out_bytes = 0;
     for (int i = 0; i < n; ++i) {
         PlanScan &s = p->scans[i];
-        int grid = 0;
+        int grid = s.variant == kF2Fold ? p->emit_grid : 0;
         for (auto &g : p->groups)
             for (int j : g.scans)
                 if (j == i) grid = g.grid;
@@ -911,6 +933,20 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
             t.n_blocks = 0;
             t.order = 2;
             set_pair_form(t, s.ds, s.desc.order, s.variant, s.np);
+            if (fold_of[i] >= 0) {
+                // this pass also scores the order-2 scan: its best-K state
+                const Task &o2 = tasks[fold_of[i]];
+                t.variant = kF2Fold;
+                t.cand = o2.cand;
+                t.cand_count = o2.cand_count;
+                t.thr = o2.thr;
+                t.hist = o2.hist;
+                t.cand_cap = o2.cand_cap;
+                t.top_k = o2.top_k;
+                t.key_bits = o2.key_bits;
+                t.n_combos = o2.n_combos;
+                t.score_const = o2.score_const;
+            }
         }
         base = 0;
         for (int i = 0; i < nt; ++i) {
@@ -975,7 +1011,7 @@ static int plan_enqueue(Ctx *c, Plan *p, hipStream_t st, bool timing, unsigned l
     if (p->persistent) {
         if (p->n_emit > 0) {
             HIPCHK(launch_scan(4, 0, 0, p->emit_grid, st, tasks + nt, p->n_emit, p->emit_total, p->d_queues + q,
-                               c->d_binom, c->bstride, 0, 1, p->emit_stage));
+                               c->d_binom, c->bstride, 0, p->emit_kmax, p->emit_stage));
         }
         ++q;
         if (p->n_t3 > 0) {
@@ -1356,6 +1392,18 @@ int epi_scan_batch(epi_ctx *ctx, const epi_scan_desc *descs, int32_t n, void *st
     register_plan(C, p, scan_ids);
     p->transient = true;
     return plan_run(C, p, (hipStream_t)stream, ~0ull);
+}
+
+int epi_scan_orders(epi_ctx *ctx, int32_t dataset_id, int32_t max_order, int32_t top_k, void *stream,
+                    int32_t *scan_ids) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    if (!scan_ids) return fail(EPI_EINVAL, "null scan_ids");
+    if (max_order < EPI_MIN_ORDER) return fail(EPI_EINVAL, "max_order %d < %d", max_order, EPI_MIN_ORDER);
+    if (max_order > EPI_MAX_ORDER) return fail(EPI_EUNSUPPORTED, "max_order %d > %d", max_order, EPI_MAX_ORDER);
+    std::vector<epi_scan_desc> descs;
+    for (int o = EPI_MIN_ORDER; o <= max_order; ++o) descs.push_back(epi_scan_desc{dataset_id, o, top_k, 0});
+    return epi_scan_batch(ctx, descs.data(), (int32_t)descs.size(), stream, scan_ids);
 }
 
 int epi_query(epi_ctx *ctx, int32_t scan_id, int32_t *done) {

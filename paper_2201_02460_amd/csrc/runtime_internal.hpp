@@ -94,6 +94,7 @@ struct Plan {
     std::vector<PlanScan> scans;
     std::vector<LaunchGroup> groups;
     int n_emit = 0, emit_grid = 1, emit_stage = 0, n_queues = 0;
+    int emit_kmax = 1;  // best-K list entries per wave of the pair-pass launch (order-2 scans scored there)
     constexpr static int kTabMax = 16386;  // screening-table entries that may go to LDS
     unsigned long long emit_total = 0;
     int n_t3 = 0, t3_grid = 1, t3_stage = 0;  // triplet sub-table pass (order 4 by reduced cells)

@@ -59,6 +59,7 @@ SIGNATURES = {
     "epi_dataset_info": (_c.c_int, [_vp, _i32, _P(_i32), _P(_i32), _P(_i32), _P(_u64)]),
     "epi_scan": (_c.c_int, [_vp, _i32, _i32, _i32, _vp, _P(_i32)]),
     "epi_scan_batch": (_c.c_int, [_vp, _P(ScanDesc), _i32, _vp, _P(_i32)]),
+    "epi_scan_orders": (_c.c_int, [_vp, _i32, _i32, _i32, _vp, _P(_i32)]),
     "epi_query": (_c.c_int, [_vp, _i32, _P(_i32)]),
     "epi_wait": (_c.c_int, [_vp, _i32]),
     "epi_results": (_c.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _P(_i32)]),
@@ -216,6 +217,13 @@ def epi_scan_batch(ctx, descs, stream=None):
     arr = _descs(descs)
     ids = (_i32 * len(descs))()
     _check(lib().epi_scan_batch(ctx, arr, len(descs), _stream(stream), ids))
+    return list(ids)
+
+
+def epi_scan_orders(ctx, dataset_id, max_order, top_k, stream=None):
+    """Scans of every order 2 .. max_order in one pass; list of scan ids (order 2 first)."""
+    ids = (_i32 * (max_order - 1))()
+    _check(lib().epi_scan_orders(ctx, dataset_id, max_order, top_k, _stream(stream), ids))
     return list(ids)
 
 

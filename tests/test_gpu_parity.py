@@ -257,6 +257,62 @@ def test_segmented_matches_fused(cx, orc, order, M, N, nc, K):
         epi.epi_unload(cx.ctx, ds)
 
 
+def test_scan_orders_one_pass(cx, orc):
+    """Every order 2 .. max_order in one pass equals the separate scans; the
+    order-2 scan is scored by the higher orders' pair sub-table pass."""
+    from paper_2201_02460_amd import epi
+
+    G, y = random_genotypes(40, 500, seed=77, case_fraction=0.4)
+    ds = cx.load(G, y)
+    G2, y2 = random_genotypes(50, 300, seed=78, case_fraction=0.5)
+    ds2 = cx.load(G2, y2)
+    try:
+        K = 25
+        single = {o: cx.scan(ds, o, K) for o in range(2, 6)}
+        ids = epi.epi_scan_orders(cx.ctx, ds, 5, K)
+        assert len(ids) == 4
+        for o, sid in zip(range(2, 6), ids):
+            epi.epi_wait(cx.ctx, sid)
+            c, sc, t = epi.epi_results(cx.ctx, sid, K, o)
+            info = epi.epi_scan_info(cx.ctx, sid)
+            say("order", o, "variant", info["variant"])
+            if o == 2:
+                assert info["variant"] == 7  # scored by the pair sub-table pass
+            assert np.array_equal(c, single[o]["combos"]) and np.array_equal(sc, single[o]["scores"])
+            assert np.array_equal(t, single[o]["tables"])
+            epi.epi_release(cx.ctx, sid)
+        check_topk(orc, G, y, 2, K, single[2]["combos"], single[2]["scores"], single[2]["tables"])
+        # order 2 folded into an order-4 pass only, and not across datasets
+        for descs, want in (([(ds, 2, K), (ds, 4, K)], 7), ([(ds2, 2, K), (ds, 3, K)], 1)):
+            ids = epi.epi_scan_batch(cx.ctx, descs)
+            epi.epi_wait(cx.ctx, ids[0])
+            assert epi.epi_scan_info(cx.ctx, ids[0])["variant"] == want
+            c, sc, t = epi.epi_results(cx.ctx, ids[0], K, 2)
+            ref = single[2] if descs[0][0] == ds else cx.scan(ds2, 2, K)
+            assert np.array_equal(c, ref["combos"]) and np.array_equal(sc, ref["scores"])
+            for sid in ids:
+                epi.epi_wait(cx.ctx, sid)
+                epi.epi_release(cx.ctx, sid)
+        with pytest.raises(epi.EpiError) as e:
+            epi.epi_scan_orders(cx.ctx, ds, 9, K)
+        assert e.value.code == epi.EPI_EUNSUPPORTED
+    finally:
+        epi.epi_unload(cx.ctx, ds)
+        epi.epi_unload(cx.ctx, ds2)
+    # up to order 8 on a small dataset
+    G, y = random_genotypes(10, 260, seed=79, case_fraction=0.45)
+    ds = cx.load(G, y)
+    try:
+        ids = epi.epi_scan_orders(cx.ctx, ds, 8, 12)
+        for o, sid in zip(range(2, 9), ids):
+            epi.epi_wait(cx.ctx, sid)
+            c, sc, t = epi.epi_results(cx.ctx, sid, 12, o)
+            epi.epi_release(cx.ctx, sid)
+            check_topk(orc, G, y, o, 12, c, sc, t)
+    finally:
+        epi.epi_unload(cx.ctx, ds)
+
+
 def test_autotune_keeps_results(cx, orc):
     from paper_2201_02460_amd import epi
 
