@@ -396,6 +396,13 @@ typedef __attribute__((address_space(3))) v4u lv4u;
 // the counts of valid lanes are always in range.
 EPI_DEV unsigned ltab(unsigned byte) { return *(lu32 *)(uintptr_t)byte; }
 
+// The per-combination kernels take the exact table round(n ln n 2^shift),
+// n = 0 .. N, at LDS address 0 when it fits: entry n is at byte 8n.
+typedef __attribute__((address_space(3))) const long long lli64;
+EPI_DEV long long cell_term_lds(unsigned n0, unsigned n1) {
+    return *(lli64 *)(uintptr_t)(8u * n0) + *(lli64 *)(uintptr_t)(8u * n1) - *(lli64 *)(uintptr_t)(8u * (n0 + n1));
+}
+
 // Stage the genotype-0/1 rows of `nsnp` wave-uniform SNPs (snp_of(r) for row
 // pair r) over words [w0, w0 + wn) of class c into the wave's LDS slot:
 // slot[(2 * r + g) * cw + w].  One coalesced pass by all lanes; the counting
@@ -1065,14 +1072,112 @@ EPI_DEV void colex_unrank(unsigned long long rank, int M, const unsigned long lo
     }
 }
 
+// Grouped counting for K >= 5: the three 27-cell chunks that differ only in
+// the genotype of the last prefix SNP c[K-4] are counted in one pass over the
+// words, so each word's rows and the AND of the other prefix rows are loaded
+// and formed once for 81 cells instead of once per 27 (a third of the loads;
+// per 32 individuals 81 AND + popcount pairs and 12 other operations).  The
+// 81 class-0 counts wait for class 1 packed two to a register, so classes
+// of up to 65535 individuals only.
+template <int K>
+EPI_DEV void g3_count(const DsView &d, const int (&c)[K], const int *dig, int cl, unsigned (&acc)[81]) {
+    constexpr int NB = K - 4;
+    gv4u *gm = (gv4u *)d.masks;
+    const long long Mp = d.Mp;
+    const int sp = c[NB];
+    #pragma unroll
+    for (int x = 0; x < 81; ++x) acc[x] = 0;
+    const int W = d.w4[cl];
+    long long off = (long long)d.wbase[cl] * 2 * Mp;
+    for (int w = 0; w < W; ++w, off += 2 * Mp) {
+        const v4u vm = valid_mask(d.ncls[cl], w);
+        v4u X = vm;
+        #pragma unroll
+        for (int t = 0; t < NB; ++t) {
+            const v4u r0 = gm[off + c[t]];
+            const v4u r1 = gm[off + Mp + c[t]];
+            X &= dig[t] == 0 ? r0 : (dig[t] == 1 ? r1 : vm & ~(r0 | r1));
+        }
+        const v4u p0 = gm[off + sp], p1 = gm[off + Mp + sp];
+        v4u r0[3], r1[3];
+        #pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            r0[u] = gm[off + c[K - 3 + u]];
+            r1[u] = gm[off + Mp + c[K - 3 + u]];
+        }
+        #pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            unsigned rw[3][3];
+            #pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                rw[u][0] = r0[u][q];
+                rw[u][1] = r1[u][q];
+                rw[u][2] = vm[q] & ~(r0[u][q] | r1[u][q]);
+            }
+            #pragma unroll
+            for (int g = 0; g < 3; ++g) {
+                const unsigned xg = X[q] & (g == 0 ? p0[q] : (g == 1 ? p1[q] : vm[q] & ~(p0[q] | p1[q])));
+                #pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const unsigned xa = xg & rw[0][a];
+                    #pragma unroll
+                    for (int b = 0; b < 3; ++b)
+                        #pragma unroll
+                        for (int e = 0; e < 3; ++e)
+                            acc[27 * g + 9 * a + 3 * b + e] =
+                                bcnt_acc(xa & rw[1][b] & rw[2][e], acc[27 * g + 9 * a + 3 * b + e]);
+                }
+            }
+        }
+    }
+}
+
+template <int K, bool STORE, bool LDT>
+EPI_DEV long long generic_num_g3(const DsView &d, const int (&c)[K], long long score_const, uint32_t *out,
+                                 int ostride) {
+    constexpr int NB = K - 4;       // prefix SNPs fixed within a group
+    constexpr int NG = pow3c(NB);   // groups of 81 cells
+    long long num = score_const;
+    #pragma unroll 1
+    for (int gi = 0; gi < NG; ++gi) {
+        int dig[NB > 0 ? NB : 1];
+        {
+            int x = gi;
+            #pragma unroll
+            for (int t = NB - 1; t >= 0; --t) {
+                dig[t] = x % 3;
+                x /= 3;
+            }
+        }
+        unsigned acc[81], pk[41];
+        g3_count<K>(d, c, dig, 0, acc);
+        #pragma unroll
+        for (int x = 0; x < 41; ++x) pk[x] = acc[2 * x] | (2 * x + 1 < 81 ? acc[2 * x + 1] << 16 : 0u);
+        g3_count<K>(d, c, dig, 1, acc);
+        #pragma unroll
+        for (int x = 0; x < 81; ++x) {
+            const unsigned n0 = x & 1 ? pk[x >> 1] >> 16 : pk[x >> 1] & 0xffffu;
+            if constexpr (STORE) {
+                out[(gi * 81 + x) * ostride] = n0;
+                out[(pow3c(K) + gi * 81 + x) * ostride] = acc[x];
+            } else {
+                num += LDT ? cell_term_lds(n0, acc[x]) : cell_term_counted(d.tlog, n0, acc[x]);
+            }
+        }
+    }
+    return num;
+}
+
 // Counts every cell of combination c, 27 (order 2: 9) at a time.  The fused
 // form (STORE false) scores each chunk as it is counted and returns the
 // score; with STORE the counts go to out[x * ostride] (class 0) and
 // out[(3^K + x) * ostride] (class 1) instead, x the cell's index in base 3
 // with the genotype of c[0] as the leading digit.
-template <int K, bool STORE = false>
+template <int K, bool STORE = false, bool LDT = false>
 EPI_DEV long long generic_num(const DsView &d, const int (&c)[K], long long score_const, uint32_t *out = nullptr,
                               int ostride = kWave) {
+    if constexpr (K >= 5)
+        if (d.ncls[0] <= 0xffff) return generic_num_g3<K, STORE, LDT>(d, c, score_const, out, ostride);
     constexpr int NPRE = K > 3 ? K - 3 : 0;
     constexpr int NCH = pow3c(NPRE);
     constexpr int L = K >= 3 ? 3 : 2;
@@ -1146,13 +1251,14 @@ EPI_DEV long long generic_num(const DsView &d, const int (&c)[K], long long scor
             }
         } else {
             #pragma unroll
-            for (int x = 0; x < CELLS; ++x) num += cell_term_counted(d.tlog, acc[0][x], acc[1][x]);
+            for (int x = 0; x < CELLS; ++x)
+                num += LDT ? cell_term_lds(acc[0][x], acc[1][x]) : cell_term_counted(d.tlog, acc[0][x], acc[1][x]);
         }
     }
     return num;
 }
 
-template <int K>
+template <int K, bool LDT>
 EPI_DEV void item_generic(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr,
                           const unsigned long long *binom, int bstride) {
     const DsView d = t.ds;
@@ -1163,7 +1269,7 @@ EPI_DEV void item_generic(const Task &t, unsigned long long local, TopK &tk, Can
         rank = valid ? rank : 0ull;
         int c[K];
         colex_unrank<K>(rank, d.M, binom, bstride, c);
-        const long long num = generic_num<K>(d, c, t.score_const);
+        const long long num = generic_num<K, false, LDT>(d, c, t.score_const);
         unsigned long long key = 0;
         #pragma unroll
         for (int u = 0; u < K; ++u) key = (key << bits) | (unsigned long long)c[u];
@@ -1180,7 +1286,7 @@ EPI_DEV void item_generic(const Task &t, unsigned long long local, TopK &tk, Can
 // another through the same slot.  A lane reads back only what it wrote, so
 // program order is the only ordering needed.
 // ---------------------------------------------------------------------------
-template <int K>
+template <int K, bool LDT>
 EPI_DEV void item_seg(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr,
                       const unsigned long long *binom, int bstride, uint32_t *slot) {
     constexpr int CELLS = pow3c(K);
@@ -1200,7 +1306,10 @@ EPI_DEV void item_seg(const Task &t, unsigned long long local, TopK &tk, Cand *l
         // phase 2: their scores
         long long num = t.score_const;
         #pragma unroll 9
-        for (int x = 0; x < CELLS; ++x) num += cell_term_counted(d.tlog, mine[x * kWave], mine[(CELLS + x) * kWave]);
+        for (int x = 0; x < CELLS; ++x) {
+            const unsigned n0 = mine[x * kWave], n1 = mine[(CELLS + x) * kWave];
+            num += LDT ? cell_term_lds(n0, n1) : cell_term_counted(d.tlog, n0, n1);
+        }
         unsigned long long key = 0;
         #pragma unroll
         for (int u = 0; u < K; ++u) key = (key << bits) | (unsigned long long)c[u];
@@ -1449,6 +1558,18 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
                 loaded = T0.ds.itab;
                 loaded_rev = rev;
             }
+            // the per-combination kernels: the exact n ln n table, n <= N
+            const int ent_tl = 2 * (T0.ds.N + 1);
+            const bool want_tl = (T0.variant == kGeneric || T0.variant == kSeg) && ent_tl <= tab_cap &&
+                                 (unsigned)(uintptr_t)(lu32 *)s_tab == 0u;
+            if (want_tl && loaded != (const uint32_t *)T0.ds.tlog) {
+                const uint32_t *src = (const uint32_t *)T0.ds.tlog;
+                #pragma unroll 1
+                for (int x = threadIdx.x; x < ent_tl; x += blockDim.x) s_tab[x] = src[x];
+                __syncthreads();
+                loaded = src;
+                loaded_rev = false;
+            }
         }
         #pragma unroll 1
         for (unsigned long long item = first + wave; item < end; item += 4) {
@@ -1483,6 +1604,7 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
             if (!is_emit(T.variant) && lane_id() == 0) g_pub = load_thr(T.thr);
             const unsigned long long local = item - T.item_base + T.first_item;
             const bool lds = loaded != nullptr && T.ds.itab == loaded;
+            const bool ldt = loaded != nullptr && (const uint32_t *)T.ds.tlog == loaded;
             switch (T.variant) {
             case kF2:
                 if constexpr (NP2 > 0) {
@@ -1522,12 +1644,17 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
                 }
                 break;
             case kSeg:
-                if constexpr (GK > kSegGk)
-                    item_seg<GK - kSegGk>(T, local, tk, s_list, gthr, binom, bstride,
-                                          T.seg + (size_t)(blockIdx.x * 4 + wave) * (2 * kWave * pow3c(GK - kSegGk)));
+                if constexpr (GK > kSegGk) {
+                    uint32_t *slot = T.seg + (size_t)(blockIdx.x * 4 + wave) * (2 * kWave * pow3c(GK - kSegGk));
+                    if (ldt) item_seg<GK - kSegGk, true>(T, local, tk, s_list, gthr, binom, bstride, slot);
+                    else item_seg<GK - kSegGk, false>(T, local, tk, s_list, gthr, binom, bstride, slot);
+                }
                 break;
             default:
-                if constexpr (GK > 0 && GK < kSegGk) item_generic<GK>(T, local, tk, s_list, gthr, binom, bstride);
+                if constexpr (GK > 0 && GK < kSegGk) {
+                    if (ldt) item_generic<GK, true>(T, local, tk, s_list, gthr, binom, bstride);
+                    else item_generic<GK, false>(T, local, tk, s_list, gthr, binom, bstride);
+                }
                 break;
             }
             if (!is_emit(T.variant)) {

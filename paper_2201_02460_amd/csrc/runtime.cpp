@@ -655,6 +655,8 @@ void set_pair_form(Task &t, const Dataset *d, int order, int variant, int np) {
 // order 3, order 4 by reduced cells) take the mirrored half too (2N + 2 in
 // all) when that fits.
 int tab_entries_for(const Dataset *d, int variant, int np, bool both) {
+    if (variant == kGeneric || variant == kSeg)  // exact int64 table, n = 0 .. N
+        return 2 * (d->N + 1) <= Plan::kTabMax ? 2 * (d->N + 1) : 0;
     if (variant != kF2 && variant != kF3 && variant != kR4) return 0;
     const bool sgn = (variant == kF3 && (np == kNpMfma || np == kNpMfmaI8)) || variant == kR4;
     if (both && sgn && 2 * d->N + 2 <= Plan::kTabMax) return 2 * d->N + 2;
