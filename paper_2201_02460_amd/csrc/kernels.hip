@@ -1977,10 +1977,21 @@ __global__ void __launch_bounds__(256) ct_kernel(DsView d, const int32_t *__rest
 
 // One thread per table: N * MI by Equation 1 from the exact n ln n table, as
 // the scans score a combination, then MI = that / 2^shift / N.  A table whose
-// classes do not sum to the dataset's class sizes is rejected.
+// classes do not sum to the dataset's class sizes is rejected.  With LDT the
+// table (n = 0 .. N) is first staged at LDS address 0.
+template <bool LDT>
 __global__ void __launch_bounds__(256) mi_kernel(DsView d, int P, long long score_const,
                                                  const uint32_t *__restrict__ tables, unsigned long long n,
                                                  double *__restrict__ mi, int *__restrict__ err) {
+    bool at0 = false;  // the lookups address the staged table from LDS address 0
+    if constexpr (LDT) {
+        extern __shared__ __attribute__((aligned(16))) unsigned char s_mi[];
+        unsigned *s_t = (unsigned *)s_mi;
+        const unsigned *src = (const unsigned *)d.tlog;
+        for (int x = threadIdx.x; x < 2 * (d.N + 1); x += blockDim.x) s_t[x] = src[x];
+        __syncthreads();
+        at0 = (unsigned)(uintptr_t)(lu32 *)s_t == 0u;
+    }
     for (unsigned long long i = blockIdx.x * 256ull + threadIdx.x; i < n; i += (unsigned long long)gridDim.x * 256ull) {
         const uint32_t *t = tables + i * 2ull * (unsigned)P;
         long long num = score_const;
@@ -1992,7 +2003,7 @@ __global__ void __launch_bounds__(256) mi_kernel(DsView d, int P, long long scor
             ok &= in;
             s0 += n0;
             s1 += n1;
-            num += in ? cell_term_counted(d.tlog, n0, n1) : 0;
+            num += in ? (LDT && at0 ? cell_term_lds(n0, n1) : cell_term_counted(d.tlog, n0, n1)) : 0;
         }
         ok &= s0 == (unsigned long long)d.ncls[0] && s1 == (unsigned long long)d.ncls[1];
         mi[i] = ok ? ldexp((double)num, -d.shift) / (double)d.N : __builtin_nan("");
@@ -2016,8 +2027,14 @@ hipError_t launch_function(int fn, int order, hipStream_t st, const DsView &d, c
                            const uint32_t *tables, unsigned long long n, void *out, int *err, int grid,
                            long long score_const) {
     if (fn == 2) {
-        hipLaunchKernelGGL(mi_kernel, dim3(grid), dim3(256), 0, st, d, pow3i(order), score_const, tables, n,
-                           (double *)out, err);
+        // the exact table in LDS when it fits beside two workgroups per CU
+        const size_t tl = (size_t)8 * (d.N + 1);
+        if (tl <= 64 * 1024)
+            hipLaunchKernelGGL(mi_kernel<true>, dim3(grid), dim3(256), tl, st, d, pow3i(order), score_const, tables,
+                               n, (double *)out, err);
+        else
+            hipLaunchKernelGGL(mi_kernel<false>, dim3(grid), dim3(256), 0, st, d, pow3i(order), score_const, tables,
+                               n, (double *)out, err);
         return hipGetLastError();
     }
     switch (order) {

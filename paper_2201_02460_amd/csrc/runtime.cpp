@@ -1638,7 +1638,8 @@ static int run_function(epi_ctx *ctx, int fn, int32_t dataset_id, int32_t order,
     const unsigned long long words = (unsigned long long)(d->w4[0] + d->w4[1]) * 4;
     const unsigned long long threads = fn == 0 ? n * words * (order >= 5 ? 9 : 1) : n;
     const unsigned long long want = (threads + 255) / 256;
-    const int grid = (int)std::min<unsigned long long>(want, (unsigned long long)C->n_cu * 64);
+    // MI stages its n ln n table per workgroup: fewer, longer-lived workgroups
+    const int grid = (int)std::min<unsigned long long>(want, (unsigned long long)C->n_cu * (fn == 2 ? 8 : 64));
     void *d_err = nullptr;
     int rc = C->alloc.alloc(256, &d_err);
     if (rc) return rc;
