@@ -313,14 +313,15 @@ def orders_pass_bench(epi, names, steps):
     return out
 
 
-def functions_bench(epi, torch, reps=3, out_cap=1 << 30):
+def functions_bench(epi, torch, reps=3, out_cap=1 << 30, table_cap=8 << 30):
     """The three steps as separate passes over a list of combinations, timed
     per genotype-table row (both classes), per contingency-table cell (both
     classes) and per MI cell: order 3 against the number of individuals, and
     orders 2, 4 and 8 at 2048 individuals (the paper's per-function
-    figures).  Each pass covers the first n lexicographic combinations of 64
-    SNPs (1500 for order 2, so that a pass fills the device), n bounded so
-    that its output stays under out_cap bytes."""
+    figures).  Each pass covers the first n lexicographic combinations of M
+    SNPs (1500 for order 2, 200 for order 3, else 64), at most 2^20, n bounded
+    so that the genotype rows stay under out_cap bytes and the tables under
+    table_cap bytes; the MI pass reads the tables repeated up to that many."""
     import itertools
 
     import numpy as np
@@ -332,33 +333,41 @@ def functions_bench(epi, torch, reps=3, out_cap=1 << 30):
     points = [(3, n_ind, "vs_individuals_order3") for n_ind in (128, 256, 512, 1024, 2048, 4096, 8192)]
     points += [(k, 2048, "vs_order_N2048") for k in (2, 4, 8)]
     for order, N, key in points:
-        M = 1500 if order == 2 else 64
+        M = {2: 1500, 3: 200}.get(order, 64)
         G, y = random_genotypes(M, N, seed=4000 + N + order, case_fraction=0.5)
         ds = epi.epi_load_genotypes(ctx, G, y)
         n_case = int(y.sum())
         W = 4 * ((n_case + 127) // 128) + 4 * ((N - n_case + 127) // 128)
         P = 3**order
         n_gt = max(1, min(math.comb(M, order), out_cap // (P * W * 4), 1 << 20))
-        n_ct = max(1, min(math.comb(M, order), out_cap // (P * 8), 1 << 20))
+        n_ct = max(1, min(math.comb(M, order), table_cap // (P * 8), 1 << 20))
+        n_mi = max(1, min(table_cap // (P * 8), 1 << 20))
         combos = np.asarray(list(itertools.islice(itertools.combinations(range(M), order), max(n_gt, n_ct))),
                             np.int32)
         dc = torch.from_numpy(combos).cuda()
         rows = torch.empty((n_gt, P, W), dtype=torch.int32, device="cuda")
         tabs = torch.empty((n_ct, 2, P), dtype=torch.int32, device="cuda")
-        mi = torch.empty(n_ct, dtype=torch.float64, device="cuda")
+        mi = torch.empty(n_mi, dtype=torch.float64, device="cuda")
         t_gt, t_ct, t_mi = [], [], []
         for _ in range(reps + 1):
             t_gt.append(epi.epi_genotype_tables(ctx, ds, dc[:n_gt], rows))
             t_ct.append(epi.epi_contingency_tables(ctx, ds, dc[:n_ct], tabs))
-            t_mi.append(epi.epi_mutual_information(ctx, ds, order, tabs, mi))
+            if n_mi > n_ct:
+                big = tabs.repeat(((n_mi + n_ct - 1) // n_ct, 1, 1))[:n_mi].contiguous()
+                t_mi.append(epi.epi_mutual_information(ctx, ds, order, big, mi))
+                del big
+            else:
+                t_mi.append(epi.epi_mutual_information(ctx, ds, order, tabs, mi))
         med = lambda v: sorted(v[1:])[len(v[1:]) // 2]  # noqa: E731
         gt_ms, ct_ms, mi_ms = med(t_gt), med(t_ct), med(t_mi)
-        row = {"order": order, "individuals": N, "gt_combinations": n_gt, "ct_combinations": n_ct,
+        row = {"order": order, "individuals": N, "gt_combinations": n_gt, "ct_combinations": n_ct, "mi_tables": n_mi,
                "gt_ns_per_row": gt_ms * 1e6 / (n_gt * P), "gt_write_GBps": n_gt * P * W * 4 / (gt_ms * 1e-3) / 1e9,
-               "ct_ns_per_cell": ct_ms * 1e6 / (n_ct * P), "mi_ns_per_cell": mi_ms * 1e6 / (n_ct * P)}
+               "ct_ns_per_cell": ct_ms * 1e6 / (n_ct * P), "mi_ns_per_cell": mi_ms * 1e6 / (n_mi * P),
+               "mi_read_GBps": n_mi * P * 8 / (mi_ms * 1e-3) / 1e9}
         out[key][f"k{order}_N{N}"] = row
         log(f"functions k={order} N={N}: GT {row['gt_ns_per_row']:.4f} ns/row ({row['gt_write_GBps']:.0f} GB/s), "
-            f"CT {row['ct_ns_per_cell']:.4f} ns/cell, MI {row['mi_ns_per_cell']:.4f} ns/cell")
+            f"CT {row['ct_ns_per_cell']:.4f} ns/cell, MI {row['mi_ns_per_cell']:.4f} ns/cell "
+            f"({row['mi_read_GBps']:.0f} GB/s)")
         del rows, tabs, mi, dc
         epi.epi_unload(ctx, ds)
     epi.epi_destroy(ctx)

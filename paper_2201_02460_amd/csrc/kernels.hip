@@ -1975,40 +1975,77 @@ __global__ void __launch_bounds__(256) ct_kernel(DsView d, const int32_t *__rest
     }
 }
 
-// One thread per table: N * MI by Equation 1 from the exact n ln n table, as
-// the scans score a combination, then MI = that / 2^shift / N.  A table whose
-// classes do not sum to the dataset's class sizes is rejected.  With LDT the
-// table (n = 0 .. N) is first staged at LDS address 0.
+// N * MI of a table by Equation 1 from the exact n ln n table, as the scans
+// score a combination, then MI = that / 2^shift / N; a table whose classes do
+// not sum to the dataset's class sizes is rejected.  One lane per table, 64
+// tables per wave: the wave stages kMiChunk cells of both classes of each of
+// its tables into its LDS slot (each class's cells read as consecutive
+// words), then every lane sums its own table's terms from there.  With LDT
+// the n ln n table (n = 0 .. N) is staged at LDS address 0 first.
+constexpr int kMiChunk = 16;
+constexpr int kMiRow = 2 * kMiChunk + 1;  // words per table in a slot; the odd stride keeps lanes on distinct banks
+
+EPI_DEV void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <bool LDT>
 __global__ void __launch_bounds__(256) mi_kernel(DsView d, int P, long long score_const,
                                                  const uint32_t *__restrict__ tables, unsigned long long n,
                                                  double *__restrict__ mi, int *__restrict__ err) {
+    // dynamic LDS: [LDT: 2 (N + 1) words of n ln n table][4 waves x 64 x kMiRow words of staged cells]
+    extern __shared__ __attribute__((aligned(16))) unsigned char s_mi[];
+    unsigned *s_t = (unsigned *)s_mi;
+    const int tl_words = LDT ? (2 * (d.N + 1) + 3) & ~3 : 0;
+    unsigned *slot = s_t + tl_words + (threadIdx.x >> 6) * (64 * kMiRow);
     bool at0 = false;  // the lookups address the staged table from LDS address 0
     if constexpr (LDT) {
-        extern __shared__ __attribute__((aligned(16))) unsigned char s_mi[];
-        unsigned *s_t = (unsigned *)s_mi;
         const unsigned *src = (const unsigned *)d.tlog;
         for (int x = threadIdx.x; x < 2 * (d.N + 1); x += blockDim.x) s_t[x] = src[x];
         __syncthreads();
         at0 = (unsigned)(uintptr_t)(lu32 *)s_t == 0u;
     }
-    for (unsigned long long i = blockIdx.x * 256ull + threadIdx.x; i < n; i += (unsigned long long)gridDim.x * 256ull) {
-        const uint32_t *t = tables + i * 2ull * (unsigned)P;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long groups = (n + 63) / 64;
+    const unsigned long long n_waves = (unsigned long long)gridDim.x * 4;
+    for (unsigned long long g = blockIdx.x * 4ull + (threadIdx.x >> 6); g < groups; g += n_waves) {
+        const unsigned long long i0 = g * 64;
+        const int nt = (int)min(64ull, n - i0);
         long long num = score_const;
         unsigned long long s0 = 0, s1 = 0;
         bool ok = true;
-        for (int x = 0; x < P; ++x) {
-            const unsigned n0 = t[x], n1 = t[P + x];
-            const bool in = n0 <= (unsigned)d.ncls[0] && n1 <= (unsigned)d.ncls[1];
-            ok &= in;
-            s0 += n0;
-            s1 += n1;
-            num += in ? (LDT && at0 ? cell_term_lds(n0, n1) : cell_term_counted(d.tlog, n0, n1)) : 0;
+        for (int c0 = 0; c0 < P; c0 += kMiChunk) {
+            const int cw = min(kMiChunk, P - c0), row = 2 * cw;
+            for (int j = lane; j < nt * row; j += 64) {
+                const int t = j / row, r = j - t * row, cl = r >= cw ? 1 : 0, x = r - cl * cw;
+                slot[t * kMiRow + cl * kMiChunk + x] =
+                    tables[(i0 + t) * 2ull * (unsigned)P + (unsigned)(cl * P + c0 + x)];
+            }
+            wave_lds_sync();
+            if (lane < nt) {
+                for (int x = 0; x < cw; ++x) {
+                    const unsigned n0 = slot[lane * kMiRow + x], n1 = slot[lane * kMiRow + kMiChunk + x];
+                    const bool in = n0 <= (unsigned)d.ncls[0] && n1 <= (unsigned)d.ncls[1];
+                    ok &= in;
+                    s0 += n0;
+                    s1 += n1;
+                    num += in ? (LDT && at0 ? cell_term_lds(n0, n1) : cell_term_counted(d.tlog, n0, n1)) : 0;
+                }
+            }
+            wave_lds_sync();
         }
-        ok &= s0 == (unsigned long long)d.ncls[0] && s1 == (unsigned long long)d.ncls[1];
-        mi[i] = ok ? ldexp((double)num, -d.shift) / (double)d.N : __builtin_nan("");
-        if (!ok) atomicOr(err, 1);
+        if (lane < nt) {
+            ok &= s0 == (unsigned long long)d.ncls[0] && s1 == (unsigned long long)d.ncls[1];
+            mi[i0 + lane] = ok ? ldexp((double)num, -d.shift) / (double)d.N : __builtin_nan("");
+            if (!ok) atomicOr(err, 1);
+        }
     }
+}
+
+size_t mi_lds_bytes(int N, bool ldt) {
+    return (ldt ? (size_t)4 * ((2 * (N + 1) + 3) & ~3) : 0) + (size_t)4 * 4 * 64 * kMiRow;
 }
 
 template <int K>
@@ -2028,13 +2065,12 @@ hipError_t launch_function(int fn, int order, hipStream_t st, const DsView &d, c
                            long long score_const) {
     if (fn == 2) {
         // the exact table in LDS when it fits beside two workgroups per CU
-        const size_t tl = (size_t)8 * (d.N + 1);
-        if (tl <= 64 * 1024)
-            hipLaunchKernelGGL(mi_kernel<true>, dim3(grid), dim3(256), tl, st, d, pow3i(order), score_const, tables,
-                               n, (double *)out, err);
+        if ((size_t)8 * (d.N + 1) <= 64 * 1024)
+            hipLaunchKernelGGL(mi_kernel<true>, dim3(grid), dim3(256), mi_lds_bytes(d.N, true), st, d, pow3i(order),
+                               score_const, tables, n, (double *)out, err);
         else
-            hipLaunchKernelGGL(mi_kernel<false>, dim3(grid), dim3(256), 0, st, d, pow3i(order), score_const, tables,
-                               n, (double *)out, err);
+            hipLaunchKernelGGL(mi_kernel<false>, dim3(grid), dim3(256), mi_lds_bytes(d.N, false), st, d,
+                               pow3i(order), score_const, tables, n, (double *)out, err);
         return hipGetLastError();
     }
     switch (order) {

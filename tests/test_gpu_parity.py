@@ -345,6 +345,32 @@ def test_large_n_screening_paths(cx, orc, N):
         epi.epi_unload(cx.ctx, ds)
 
 
+@pytest.mark.parametrize("N,nc", [(9000, 4000), (132000, 66000)])
+def test_per_combination_paths(cx, orc, N, nc):
+    """Orders 5-6 by the per-combination kernel where the n ln n table does
+    not fit in LDS (N = 9000) and where class 0 exceeds 65535 individuals
+    (N = 132000: the 27-cell form instead of the packed 81-cell one), fused
+    and segmented."""
+    from paper_2201_02460_amd import epi
+
+    G, y = random_genotypes(8, N, seed=N + 5, case_fraction=nc / N)
+    ds = cx.load(G, y)
+    try:
+        for order, K in ((5, 12), (6, 9)):
+            say("N", N, "order", order)
+            res = cx.scan(ds, order, K)
+            check_topk(orc, G, y, order, K, res["combos"], res["scores"], res["tables"])
+            epi.epi_set_prefix_block(cx.ctx, ds, order, epi.EPI_BLOCK_SEGMENTED)
+            try:
+                seg = cx.scan(ds, order, K)
+            finally:
+                epi.epi_set_prefix_block(cx.ctx, ds, order, 0)
+            assert np.array_equal(seg["combos"], res["combos"]) and np.array_equal(seg["tables"], res["tables"])
+            assert np.array_equal(seg["scores"], res["scores"])
+    finally:
+        epi.epi_unload(cx.ctx, ds)
+
+
 def test_counting_kernels_agree(cx, orc):
     """Every order-3 counting kernel (popcount prefix blocks, 4-bit float and
     8-bit integer matrix-core products) gives the same results."""
