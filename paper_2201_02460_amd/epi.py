@@ -314,26 +314,58 @@ def epi_set_prefix_block(ctx, dataset_id, order, block):
     _check(lib().epi_set_prefix_block(ctx, dataset_id, order, block))
 
 
+def _device_buffer(t, itemsize, count, what):
+    """Check that a torch tensor is a contiguous device buffer of at least
+    count items of itemsize bytes (the library trusts the pointer it gets)."""
+    if not (hasattr(t, "is_cuda") and t.is_cuda):
+        raise EpiError(EPI_EINVAL, f"{what} must be a device tensor")
+    if not t.is_contiguous():
+        raise EpiError(EPI_EINVAL, f"{what} must be contiguous")
+    if t.element_size() != itemsize or t.numel() < count:
+        raise EpiError(EPI_EINVAL, f"{what} must hold {count} items of {itemsize} bytes")
+
+
+def _combos_arg(d_combos):
+    if d_combos.dim() != 2 or d_combos.dtype != _torch_int32():
+        raise EpiError(EPI_EINVAL, "combinations must be an int32 [n, k] device tensor")
+    n, k = d_combos.shape
+    _device_buffer(d_combos, 4, n * k, "combinations")
+    return n, k
+
+
+def _torch_int32():
+    import torch
+
+    return torch.int32
+
+
 def epi_genotype_tables(ctx, dataset_id, d_combos, d_rows):
     """Genotype rows of the combinations in d_combos (device int32 [n][k])
-    into d_rows (device uint32 [n][3^k][W]); returns the kernel time in ms."""
-    n, k = d_combos.shape
+    into d_rows (device 32-bit [n][3^k][W]); returns the kernel time in ms."""
+    n, k = _combos_arg(d_combos)
+    info = epi_dataset_info(ctx, dataset_id)
+    nc, nt = info["n_cases"], info["N"] - info["n_cases"]
+    W = 4 * ((nc + 127) // 128) + 4 * ((nt + 127) // 128)
+    _device_buffer(d_rows, 4, n * 3**k * W, "rows")
     ms = _c.c_float()
     _check(lib().epi_genotype_tables(ctx, dataset_id, k, _ptr(d_combos), n, _ptr(d_rows), _c.byref(ms)))
     return ms.value
 
 
 def epi_contingency_tables(ctx, dataset_id, d_combos, d_tables):
-    """Contingency tables (device uint32 [n][2][3^k]) of d_combos; returns ms."""
-    n, k = d_combos.shape
+    """Contingency tables (device 32-bit [n][2][3^k]) of d_combos; returns ms."""
+    n, k = _combos_arg(d_combos)
+    _device_buffer(d_tables, 4, n * 2 * 3**k, "tables")
     ms = _c.c_float()
     _check(lib().epi_contingency_tables(ctx, dataset_id, k, _ptr(d_combos), n, _ptr(d_tables), _c.byref(ms)))
     return ms.value
 
 
 def epi_mutual_information(ctx, dataset_id, order, d_tables, d_mi):
-    """MI (device float64 [n]) of n tables (device uint32 [n][2][3^order]); returns ms."""
+    """MI (device float64 [n]) of n tables (device 32-bit [n][2][3^order]); returns ms."""
     n = d_tables.shape[0]
+    _device_buffer(d_tables, 4, n * 2 * 3**order, "tables")
+    _device_buffer(d_mi, 8, n, "mi")
     ms = _c.c_float()
     _check(lib().epi_mutual_information(ctx, dataset_id, order, _ptr(d_tables), n, _ptr(d_mi), _c.byref(ms)))
     return ms.value

@@ -156,6 +156,13 @@ def test_function_errors(cx):
         with pytest.raises(epi.EpiError) as e:
             epi.epi_contingency_tables(cx.ctx, ds, good[:, :1].contiguous(), t1)
         assert e.value.code == epi.EPI_EINVAL
+        # buffers the binding can see are too small, or of the wrong type, never reach the library
+        with pytest.raises(epi.EpiError):
+            epi.epi_contingency_tables(cx.ctx, ds, good, torch.zeros((1, 2, 8), dtype=torch.int32, device="cuda"))
+        with pytest.raises(epi.EpiError):
+            epi.epi_genotype_tables(cx.ctx, ds, good.long(), rows)
+        with pytest.raises(epi.EpiError):
+            epi.epi_mutual_information(cx.ctx, ds, 2, t1, torch.zeros(1, dtype=torch.float32, device="cuda"))
         # nothing to do
         empty = torch.zeros((0, 3), dtype=torch.int32, device="cuda")
         assert epi.epi_contingency_tables(cx.ctx, ds, empty, t1) == 0.0
