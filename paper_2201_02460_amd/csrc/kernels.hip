@@ -1347,31 +1347,66 @@ EPI_DEV void item_r4(const Task &t, unsigned long long local, TopK &tk, Cand *li
         int c[4];
         colex_unrank<4>(rank, d.M, binom, bstride, c);
         unsigned acc[2][16];
+        // consecutive colex ranks share their two last SNPs almost always:
+        // then their rows are wave-uniform scalar loads and their four
+        // pairwise ANDs scalar operations, which halves the vector loads
+        const int c2u = uni(c[2]), c3u = uni(c[3]);
+        const bool u23 = __ballot(c[2] != c2u || c[3] != c3u) == 0ull;
         #pragma unroll
         for (int cl = 0; cl < 2; ++cl) {
             #pragma unroll
             for (int x = 0; x < 16; ++x) acc[cl][x] = 0;
             const int W = d.w4[cl];
             long long off = (long long)d.wbase[cl] * 2 * Mp;
-            #pragma unroll 1
-            for (int w = 0; w < W; ++w, off += 2 * Mp) {
-                v4u r[4][2];
-                #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    r[u][0] = gm[off + c[u]];
-                    r[u][1] = gm[off + Mp + c[u]];
-                }
-                #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    unsigned p[4];
+            if (u23) {
+                cv4u *sm = (cv4u *)d.masks;
+                #pragma unroll 1
+                for (int w = 0; w < W; ++w, off += 2 * Mp) {
+                    v4u r[2][2];
                     #pragma unroll
-                    for (int ab = 0; ab < 4; ++ab) p[ab] = r[0][ab >> 1][q] & r[1][ab & 1][q];
+                    for (int u = 0; u < 2; ++u) {
+                        r[u][0] = gm[off + c[u]];
+                        r[u][1] = gm[off + Mp + c[u]];
+                    }
+                    const v4u s20 = sm[off + c2u], s21 = sm[off + Mp + c2u];
+                    const v4u s30 = sm[off + c3u], s31 = sm[off + Mp + c3u];
                     #pragma unroll
-                    for (int ab = 0; ab < 4; ++ab)
+                    for (int q = 0; q < 4; ++q) {
+                        unsigned p[4], y[4];
                         #pragma unroll
-                        for (int ce = 0; ce < 4; ++ce)
-                            acc[cl][4 * ab + ce] =
-                                bcnt_acc(p[ab] & r[2][ce >> 1][q] & r[3][ce & 1][q], acc[cl][4 * ab + ce]);
+                        for (int ab = 0; ab < 4; ++ab) p[ab] = r[0][ab >> 1][q] & r[1][ab & 1][q];
+                        y[0] = uni(s20[q] & s30[q]);
+                        y[1] = uni(s20[q] & s31[q]);
+                        y[2] = uni(s21[q] & s30[q]);
+                        y[3] = uni(s21[q] & s31[q]);
+                        #pragma unroll
+                        for (int ab = 0; ab < 4; ++ab)
+                            #pragma unroll
+                            for (int ce = 0; ce < 4; ++ce)
+                                acc[cl][4 * ab + ce] = bcnt_acc(p[ab] & y[ce], acc[cl][4 * ab + ce]);
+                    }
+                }
+            } else {
+                #pragma unroll 1
+                for (int w = 0; w < W; ++w, off += 2 * Mp) {
+                    v4u r[4][2];
+                    #pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        r[u][0] = gm[off + c[u]];
+                        r[u][1] = gm[off + Mp + c[u]];
+                    }
+                    #pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        unsigned p[4];
+                        #pragma unroll
+                        for (int ab = 0; ab < 4; ++ab) p[ab] = r[0][ab >> 1][q] & r[1][ab & 1][q];
+                        #pragma unroll
+                        for (int ab = 0; ab < 4; ++ab)
+                            #pragma unroll
+                            for (int ce = 0; ce < 4; ++ce)
+                                acc[cl][4 * ab + ce] =
+                                    bcnt_acc(p[ab] & r[2][ce >> 1][q] & r[3][ce & 1][q], acc[cl][4 * ab + ce]);
+                    }
                 }
             }
             // (keeps the scaling below out of the loop, where the compiler
