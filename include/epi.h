@@ -16,7 +16,13 @@
  *   - score: Section 2.3, Equations 1-3 (MI = H(X) + H(Y) - H(X,Y), natural
  *     logarithm, probabilities over all individuals, empty cells skipped);
  *   - exploration: Section 2.4, Algorithm 1 (every combination of the order
- *     exactly once; only the highest-MI combinations are kept).
+ *     exactly once; only the highest-MI combinations are kept), orders 2-8
+ *     and every order up to a bound in one pass (epi_scan_orders);
+ *   - segmented exploration: Section 3.4, Algorithm 2 (tables of a block
+ *     counted first, then scored; EPI_BLOCK_SEGMENTED);
+ *   - the steps as separate passes (epi_genotype_tables,
+ *     epi_contingency_tables, epi_mutual_information), which Section 4
+ *     times one by one.
  *
  * Conventions shared by every call:
  *   - Every function returns EPI_OK (0) or a negative EPI_E* status; no C++

@@ -1223,7 +1223,7 @@ extern "C" {
 
 const char *epi_last_error(void) { return last_error(); }
 
-const char *epi_version(void) { return "epi-mi355x 0.1 (gfx950)"; }
+const char *epi_version(void) { return "epi-mi355x 0.2 (gfx950)"; }
 
 int epi_create(int32_t device, uint64_t hbm_budget_bytes, epi_ctx **out) {
     clear_error();
