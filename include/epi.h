@@ -232,7 +232,8 @@ int epi_batch_destroy(epi_ctx *ctx, int32_t batch_id);
  * device buffer, then scores the block (the fused kernels score each table as
  * it is counted).  Same results; the buffer takes 2 x 3^k x 256 bytes per
  * wave of the launch (order 8: 3.4 MB).  Block 0 restores the built-in
- * choice for the order. */
+ * choice for the order.  Served requests (epi_server_*) always use the fused
+ * kernels. */
 #define EPI_BLOCK_SEGMENTED 64
 
 /* Time the counting kernels above for `order` on a bounded slice of the
