@@ -2020,12 +2020,6 @@ __global__ void __launch_bounds__(256) ct_kernel(DsView d, const int32_t *__rest
 constexpr int kMiChunk = 16;
 constexpr int kMiRow = 2 * kMiChunk + 1;  // words per table in a slot; the odd stride keeps lanes on distinct banks
 
-EPI_DEV void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 template <bool LDT>
 __global__ void __launch_bounds__(256) mi_kernel(DsView d, int P, long long score_const,
                                                  const uint32_t *__restrict__ tables, unsigned long long n,
@@ -2058,7 +2052,7 @@ __global__ void __launch_bounds__(256) mi_kernel(DsView d, int P, long long scor
                 slot[t * kMiRow + cl * kMiChunk + x] =
                     tables[(i0 + t) * 2ull * (unsigned)P + (unsigned)(cl * P + c0 + x)];
             }
-            wave_lds_sync();
+            wave_sync();
             if (lane < nt) {
                 for (int x = 0; x < cw; ++x) {
                     const unsigned n0 = slot[lane * kMiRow + x], n1 = slot[lane * kMiRow + kMiChunk + x];
@@ -2069,7 +2063,7 @@ __global__ void __launch_bounds__(256) mi_kernel(DsView d, int P, long long scor
                     num += in ? (LDT && at0 ? cell_term_lds(n0, n1) : cell_term_counted(d.tlog, n0, n1)) : 0;
                 }
             }
-            wave_lds_sync();
+            wave_sync();
         }
         if (lane < nt) {
             ok &= s0 == (unsigned long long)d.ncls[0] && s1 == (unsigned long long)d.ncls[1];
