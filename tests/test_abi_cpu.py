@@ -48,3 +48,15 @@ def test_errors_cross_the_abi_as_codes():
     assert rc == epi.EPI_EINVAL
     assert "null" in epi.epi_last_error()
     assert epi.lib().epi_destroy(None) == epi.EPI_OK
+
+
+def test_binding_constants_match_the_header():
+    """Every #define EPI_* integer the header states has the same value in the binding."""
+    from paper_2201_02460_amd import epi
+
+    text = open(HEADER).read()
+    defs = dict(re.findall(r"#define\s+(EPI_[A-Z0-9_]+)\s+\(?(-?\d+)\)?", text))
+    assert "EPI_MAX_ORDER" in defs and "EPI_BLOCK_SEGMENTED" in defs and "EPI_SERVE_MAX_ORDER" in defs
+    for name, value in defs.items():
+        assert hasattr(epi, name), f"binding lacks {name}"
+        assert getattr(epi, name) == int(value), name
