@@ -92,9 +92,11 @@ def load_traffic(kernel_tag, workload):
     return doc.get("hbm_bytes_per_launch")
 
 
-def plain_bench(epi, torch, spec, G, y, steps, warmup, block=None):
+def plain_bench(epi, torch, spec, G, y, steps, warmup, block=None, extra=None):
     """Timed steps of repack + scan + results on one resident dataset; the
-    counting kernel is the autotuner's choice unless `block` pins one."""
+    counting kernel is the autotuner's choice unless `block` pins one.  With
+    `extra` (a dict), the device packing alone is timed after the steps
+    (events on the stream it runs on) into extra["pack_ms"]."""
     dG = torch.from_numpy(G).cuda()
     dy = torch.from_numpy(y).cuda()
     stream = torch.cuda.current_stream()
@@ -129,6 +131,15 @@ def plain_bench(epi, torch, spec, G, y, steps, warmup, block=None):
         alls.append(ms[0])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    if extra is not None:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record(stream)
+        for _ in range(reps):
+            epi.epi_repack_device(ctx, ds, dG, dy, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        extra["pack_ms"] = e0.elapsed_time(e1) / reps
     epi.epi_unload(ctx, ds)
     epi.epi_destroy(ctx)
     return dt, mains, alls, res, info, tuned
@@ -609,7 +620,8 @@ def main():
         torch.cuda.synchronize()
         del b
 
-    dt, mains, alls, res, sinfo, tuned = plain_bench(epi, torch, spec, G, y, args.steps, args.warmup)
+    extra = {}
+    dt, mains, alls, res, sinfo, tuned = plain_bench(epi, torch, spec, G, y, args.steps, args.warmup, extra=extra)
     combos, scores, tables = res
     value = n_combos * N * args.steps / dt / 1e12
     ms_main = sum(mains) / len(mains)
@@ -658,6 +670,7 @@ def main():
                    "variant": sinfo["variant"], "prefix_block": sinfo["prefix_block"], "autotuned": tuned},
         "roofline": roofline,
         "scan_ms": round(ms_scan, 4),
+        "pack_ms": round(extra["pack_ms"], 4),
         "top1": {"combo": [int(v) for v in combos[0]], "mi": float(scores[0]), "planted": list(spec["planted"]),
                  "planted_rank": planted_rank, "achieved_h2": info["h2"]},
     }
