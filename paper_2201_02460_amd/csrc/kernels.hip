@@ -1804,14 +1804,18 @@ __global__ void __launch_bounds__(1024) merge_final_kernel(const Task *__restric
     const long long g = load_thr(t.thr);
     int fill = K;
     if (K + n_parts * K <= kMergeSlots) {
-        // all lists at once: every load in flight together
+        // all lists at once, every load in flight together; only entries
+        // that reach the task's bound are kept, packed behind the first K
+        // slots, so the sort covers those alone
+        if (threadIdx.x == 0) s_ctr = K;
+        __syncthreads();
         for (int i = threadIdx.x; i < n_parts * K; i += blockDim.x) {
             const int p = i / K, r = i - p * K;
             const Cand c = src[(long long)p * kMaxTopK + r];
-            buf[K + i] = c.num >= g ? c : sentinel;
+            if (c.num >= g) buf[atomicAdd(&s_ctr, 1)] = c;
         }
         __syncthreads();
-        fill = K + n_parts * K;
+        fill = s_ctr;
     } else
     for (int p = 0; p < n_parts; ++p) {
         if (fill + K > kMergeSlots) {
@@ -1829,7 +1833,6 @@ __global__ void __launch_bounds__(1024) merge_final_kernel(const Task *__restric
         __syncthreads();
         fill += K;
     }
-    (void)s_ctr;
     int P = 64;
     while (P < fill) P <<= 1;
     bitonic_sort_best_first(buf, P);
