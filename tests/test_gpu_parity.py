@@ -257,6 +257,40 @@ def test_segmented_matches_fused(cx, orc, order, M, N, nc, K):
         epi.epi_unload(cx.ctx, ds)
 
 
+def test_segmented_in_graph_batch(cx, orc):
+    """Segmented scans inside a persistent graph-captured batch (their table
+    buffers shared by a launch's tasks wave slot by wave slot) equal the
+    fused single scans, over several replays."""
+    from paper_2201_02460_amd import epi
+
+    data = [random_genotypes(16, 300, seed=810 + i, case_fraction=0.4) for i in range(2)]
+    dss = [cx.load(G, y) for G, y in data]
+    try:
+        K = 15
+        fused = [cx.scan(ds, 5, K) for ds in dss] + [cx.scan(dss[0], 4, K)]
+        for order in (4, 5):
+            epi.epi_set_prefix_block(cx.ctx, dss[0], order, epi.EPI_BLOCK_SEGMENTED)
+        try:
+            descs = [(dss[0], 5, K), (dss[1], 5, K), (dss[0], 4, K)]
+            bid = epi.epi_batch_create(cx.ctx, descs, persistent=True, use_graph=True)
+            for rep in range(3):
+                say("segmented batch replay", rep)
+                epi.epi_batch_run(cx.ctx, bid)
+                epi.epi_batch_wait(cx.ctx, bid)
+                for i, (ds, order, _) in enumerate(descs):
+                    c, sc, t = epi.epi_batch_results(cx.ctx, bid, i, K, order)
+                    assert np.array_equal(c, fused[i]["combos"]) and np.array_equal(sc, fused[i]["scores"])
+                    assert np.array_equal(t, fused[i]["tables"])
+            epi.epi_batch_destroy(cx.ctx, bid)
+        finally:
+            for order in (4, 5):
+                epi.epi_set_prefix_block(cx.ctx, dss[0], order, 0)
+        check_topk(orc, data[1][0], data[1][1], 5, K, fused[1]["combos"], fused[1]["scores"], fused[1]["tables"])
+    finally:
+        for ds in dss:
+            epi.epi_unload(cx.ctx, ds)
+
+
 def test_scan_orders_one_pass(cx, orc):
     """Every order 2 .. max_order in one pass equals the separate scans; the
     order-2 scan is scored by the higher orders' pair sub-table pass."""
