@@ -1879,6 +1879,43 @@ __global__ void __launch_bounds__(64) finalize_kernel(const Task *__restrict__ t
     for (int u = 0; u < k; ++u) cells *= 3;
     gv4u *gm = (gv4u *)d.masks;
     const long long Mp = d.Mp;
+    if (cells <= 32) {
+        // orders 2-3: lanes that share a cell take every parts-th word of
+        // it, and their counts meet in LDS
+        __shared__ unsigned s_cnt[2][32];
+        const int parts = kWave / cells;
+        s_cnt[threadIdx.x >> 5][threadIdx.x & 31] = 0;
+        __syncthreads();
+        const int x = threadIdx.x % cells, part = threadIdx.x / cells;
+        if (part < parts) {
+            int g[3];
+            for (int u = k - 1, y = x; u >= 0; --u) {
+                g[u] = y % 3;
+                y /= 3;
+            }
+            for (int cl = 0; cl < 2; ++cl) {
+                unsigned cnt = 0;
+                #pragma unroll 2
+                for (int w = part; w < d.w4[cl]; w += parts) {
+                    const long long off = ((long long)d.wbase[cl] + w) * 2 * Mp;
+                    const v4u vm = valid_mask(d.ncls[cl], w);
+                    v4u X = vm;
+                    for (int u = 0; u < k; ++u) {
+                        const v4u r0 = gm[off + c[u]];
+                        const v4u r1 = gm[off + Mp + c[u]];
+                        X &= g[u] == 0 ? r0 : (g[u] == 1 ? r1 : (vm & ~(r0 | r1)));
+                    }
+                    cnt += __builtin_popcount(X[0]) + __builtin_popcount(X[1]) + __builtin_popcount(X[2]) +
+                           __builtin_popcount(X[3]);
+                }
+                atomicAdd(&s_cnt[cl][x], cnt);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < cells)
+            for (int cl = 0; cl < 2; ++cl) tables[((long long)r * 2 + cl) * cells + threadIdx.x] = s_cnt[cl][threadIdx.x];
+        return;
+    }
     for (int x = threadIdx.x; x < cells; x += kWave) {
         int g[kMaxBinomOrder];
         int y = x;
