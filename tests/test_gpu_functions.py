@@ -68,6 +68,36 @@ def test_genotype_tables_vs_oracle(cx, orc, order, M, N, nc):
         epi.epi_unload(cx.ctx, ds)
 
 
+@pytest.mark.parametrize("N,nc", [(129, 64), (256, 128), (300, 1), (1000, 999), (4097, 2048)])
+def test_packing_round_trip(cx, N, nc):
+    """unpack(pack(G)) = G: the order-1 genotype tables of every SNP are the
+    packed rows; in each class every individual is in exactly one of them
+    (its genotype), and bits past the class are zero."""
+    import torch
+
+    from paper_2201_02460_amd import epi
+
+    M = 37
+    G, y = random_genotypes(M, N, seed=N + nc, case_fraction=nc / N)
+    G[5] = 2  # a SNP with one genotype only
+    ds = cx.load(G, y)
+    try:
+        W0, W1 = _words(y)
+        combos = torch.arange(M, dtype=torch.int32, device="cuda").reshape(M, 1)
+        rows = torch.zeros((M, 3, W0 + W1), dtype=torch.int32, device="cuda")
+        epi.epi_genotype_tables(cx.ctx, ds, combos, rows)
+        r = rows.cpu().numpy().view(np.uint32)
+        bits = np.unpackbits(r.astype("<u4").view(np.uint8), bitorder="little").reshape(M, 3, -1)
+        for cls, idx, lo, words in ((0, np.flatnonzero(y == 1), 0, W0), (1, np.flatnonzero(y == 0), W0, W1)):
+            b = bits[:, :, 32 * lo: 32 * (lo + words)]
+            n = len(idx)
+            assert (b.sum(axis=1)[:, :n] == 1).all(), "every individual in exactly one genotype row"
+            assert b[:, :, n:].sum() == 0, "pad bits are zero"
+            assert np.array_equal(b[:, :, :n].argmax(axis=1), G[:, idx]), "rows decode to the genotypes"
+    finally:
+        epi.epi_unload(cx.ctx, ds)
+
+
 CT_CASES = [(2, 40, 1000, 450), (3, 20, 257, 100), (4, 12, 640, 511), (5, 10, 129, 64), (6, 9, 300, 150),
             (7, 9, 200, 80), (8, 10, 385, 129)]
 
