@@ -115,15 +115,24 @@ int epi_load_genotypes(epi_ctx *ctx, const uint8_t *geno, int64_t ld, const uint
 int epi_load_genotypes_device(epi_ctx *ctx, const uint8_t *d_geno, int64_t ld, const uint8_t *d_pheno,
                               int32_t M, int32_t N, void *stream, int32_t *dataset_id);
 
-/* Repack new genotypes and phenotypes of the same shape and class sizes into
- * an existing dataset, from device memory, asynchronously on `stream`
- * (no allocation, no synchronisation).  Values are not validated: they must
- * already be known to lie in {0,1,2} and {0,1} with the dataset's class
- * sizes.  Errors: ENOTFOUND, EINVAL (shape or class sizes differ). */
+/* Repack new genotypes and phenotypes into an existing dataset, from device
+ * memory, asynchronously on `stream` (no allocation, no synchronisation).
+ * d_geno must hold the dataset's M rows of N genotypes (row stride ld >= N)
+ * and d_pheno its N phenotypes with the dataset's number of cases; the
+ * library cannot see the size of a device buffer, so a smaller buffer is
+ * read past its end.  The values are checked on the device while they are
+ * packed: a genotype outside {0,1,2}, a phenotype outside {0,1} or a
+ * different number of cases makes the results call of every scan of the
+ * dataset that runs after this repack (epi_results, epi_batch_results,
+ * epi_server_results) fail with EINVAL, until a repack with valid input.
+ * Errors: ENOTFOUND, EINVAL (null pointer, ld < N). */
 int epi_repack_device(epi_ctx *ctx, int32_t dataset_id, const uint8_t *d_geno, int64_t ld,
                       const uint8_t *d_pheno, void *stream);
 
-/* Free a dataset (waits for scans that still read it). */
+/* Free a dataset: waits for device work of scans and batches that still read
+ * it (a batch that names it can no longer run).  EINVAL while a server
+ * request on it is queued or running (its memory stays valid until the
+ * request is done). */
 int epi_unload(epi_ctx *ctx, int32_t dataset_id);
 
 /* Shape of a dataset and the device bytes it holds. */

@@ -81,6 +81,7 @@ struct DsView {
     int32_t wbase[2];
     int32_t ks[2];         // 64-individual steps per class in qa / qb
     int32_t ks8[2];        // 32-individual steps per class in qa8 / qb8
+    const int *err;        // error bits of the dataset's last packing (0: valid input)
 };
 
 // One top-K candidate: larger num is better; on equal num the smaller key
@@ -142,7 +143,8 @@ constexpr int kQScaleShift = 2;
 constexpr uint32_t q3_bias(int N) { return 8u * (uint32_t)N + 4u; }
 
 // Per-task result block written by the finalize kernel:
-//   int32 n_valid, int32 pad[3],
+//   int32 n_valid, int32 pack_err (the dataset's packing error bits when the
+//   block was written), int32 pad[2],
 //   int32 combos[top_k][order], float scores[top_k],
 //   uint32 tables[top_k][2][3^order]
 struct ResultLayout {

@@ -1865,7 +1865,10 @@ __global__ void __launch_bounds__(64) finalize_kernel(const Task *__restrict__ t
         for (int x = threadIdx.x; x < K; x += kWave) nv += res[x].key != sentinel_key ? 1 : 0;
         #pragma unroll
         for (int off = 32; off > 0; off >>= 1) nv += __shfl_xor(nv, off);
-        if (threadIdx.x == 0) hdr[0] = nv;
+        if (threadIdx.x == 0) {
+            hdr[0] = nv;
+            hdr[1] = *d.err;  // nonzero: the dataset's last packing had invalid input
+        }
     }
     const Cand e = res[r];
     if (e.key == sentinel_key) return;
@@ -2291,13 +2294,18 @@ __global__ void qpack8_kernel(DsView d, v4u *__restrict__ qa8, v4u *__restrict__
 
 // Class index map: idx[0 .. n_case) = input positions of the cases in input
 // order, idx[n_case .. N) = those of the controls.  One 1024-thread
-// workgroup; a phenotype outside {0,1} raises *err.
+// workgroup, the first kernel of a packing: it clears the dataset's error
+// word, then a phenotype outside {0,1} raises bit 2 and a number of cases
+// other than n_case bit 4 (some index then falls outside its class).
 __global__ void __launch_bounds__(1024) classidx_kernel(const uint8_t *__restrict__ pheno, int N, int n_case,
                                                         int32_t *__restrict__ idx, int *__restrict__ err) {
     __shared__ int s_scan[1024];
     __shared__ int s_cases;
     const int tid = threadIdx.x;
-    if (tid == 0) s_cases = 0;
+    if (tid == 0) {
+        s_cases = 0;
+        *err = 0;
+    }
     __syncthreads();
     for (int base = 0; base < N; base += 1024) {
         const int s = base + tid;

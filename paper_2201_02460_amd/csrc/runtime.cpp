@@ -261,6 +261,7 @@ static void ds_view(Dataset *d) {
     v.qb8 = (const v4u *)d->qb8;
     v.ks8[0] = d->ks8[0];
     v.ks8[1] = d->ks8[1];
+    v.err = (const int *)d->err;
 }
 
 // Bytes of each integer operand copy.
@@ -348,16 +349,14 @@ static int load_common(Ctx *c, const uint8_t *d_geno, int64_t ld, const uint8_t 
         ds_free(c, d.get());
         return rc;
     }
-    HIPCHK(hipMemsetAsync(d->err, 0, 4, st));
-    rc = ds_pack(d.get(), d_geno, ld, d_pheno, st);
+    rc = ds_pack(d.get(), d_geno, ld, d_pheno, st);  // the first kernel clears the error word
     int herr = 0;
     if (!rc) {
         hipError_t e = hipMemcpyAsync(&herr, d->err, 4, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) rc = fail(EPI_EDEVICE, "dataset pack: %s", hipGetErrorString(e));
     }
-    if (!rc && (herr & 1)) rc = fail(EPI_EINVAL, "a genotype is outside {0,1,2}");
-    if (!rc && herr) rc = fail(EPI_EINVAL, "phenotype check failed on the device (code %d)", herr);
+    if (!rc && herr) rc = pack_error(herr);
     if (rc) {
         ds_free(c, d.get());
         return rc;
@@ -1106,6 +1105,15 @@ int plan_wait(Plan *p) {
     return EPI_OK;
 }
 
+// Error bits of a dataset's packing (set by the device kernels): 1 a genotype
+// outside {0,1,2}, 2 a phenotype outside {0,1}, 4 class sizes that differ
+// from the dataset's, 8 an individual index out of range.
+int pack_error(int bits) {
+    return fail(EPI_EINVAL, "the dataset's last packing had invalid input (device check bits 0x%x:%s%s%s)", bits,
+                (bits & 1) ? " genotype outside {0,1,2}" : "", (bits & 2) ? " phenotype outside {0,1}" : "",
+                (bits & 12) ? " class sizes differ from the dataset's" : "");
+}
+
 int plan_results(Plan *p, int index, int capacity, int32_t *combos, float *scores, uint32_t *tables,
                  int32_t *n_written) {
     if (index < 0 || index >= (int)p->scans.size()) return fail(EPI_EINVAL, "scan index %d out of range", index);
@@ -1118,6 +1126,8 @@ int plan_results(Plan *p, int index, int capacity, int32_t *combos, float *score
     const int K = s.desc.top_k, k = s.desc.order, cells = pow3i(k);
     const char *blk = (const char *)p->h_out + s.lay.offset;
     const int32_t nv = *(const int32_t *)blk;
+    const int32_t perr = ((const int32_t *)blk)[1];
+    if (perr) return pack_error(perr);
     const int32_t *hc = (const int32_t *)(blk + 16);
     const float *hs = (const float *)(blk + 16 + (size_t)K * k * 4);
     const uint32_t *ht = (const uint32_t *)(blk + 16 + (size_t)K * k * 4 + (size_t)K * 4);
@@ -1326,6 +1336,9 @@ int epi_unload(epi_ctx *ctx, int32_t dataset_id) {
         std::lock_guard<std::mutex> g(C->mu);
         auto it = C->datasets.find(dataset_id);
         if (it == C->datasets.end()) return fail(EPI_ENOTFOUND, "unknown dataset %d", dataset_id);
+        const int users = it->second->users.load();
+        if (users > 0)
+            return fail(EPI_EINVAL, "dataset %d is read by %d queued or running server requests", dataset_id, users);
         d = std::move(it->second);
         C->datasets.erase(it);
     }

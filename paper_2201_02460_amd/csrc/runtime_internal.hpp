@@ -53,6 +53,9 @@ struct Dataset {
     int tq = 0;
     uint64_t bytes = 0;
     DsView view{};
+    // server requests (queued or admitted) that read this dataset; epi_unload
+    // refuses while any do
+    std::atomic<int> users{0};
 };
 
 struct PlanScan {
@@ -206,6 +209,7 @@ int plan_run(Ctx *c, Plan *p, hipStream_t st, unsigned long long item_cap);
 int plan_wait(Plan *p);
 int plan_results(Plan *p, int index, int capacity, int32_t *combos, float *scores, uint32_t *tables,
                  int32_t *n_written);
+int pack_error(int bits);
 void plan_free(Ctx *c, Plan *p);
 void server_shutdown_all(Ctx *c);
 

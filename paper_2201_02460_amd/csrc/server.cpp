@@ -43,7 +43,14 @@ struct Request {
     unsigned cand_cap = 0;
     uint64_t footprint = 0;
     std::vector<char> out;  // result block copied from the device
+    bool holds_ds = false;  // counted in ds->users until the request is done or failed
 };
+
+// The request no longer reads its dataset (done or failed).
+static void drop_dataset(Request *r) {
+    if (r->holds_ds) r->ds->users.fetch_sub(1);
+    r->holds_ds = false;
+}
 
 struct Server {
     Ctx *ctx = nullptr;
@@ -107,6 +114,7 @@ static void fail_request(Server *S, Request *r, int rc, const char *msg) {
     r->state = 3;
     r->t_done = Clock::now();
     free_request_buffers(S, r);
+    drop_dataset(r);
 }
 
 // Footprint and buffers of a request being admitted.
@@ -349,6 +357,7 @@ static int run_round(Server *S) {
         r->state = 2;
         r->t_done = Clock::now();
         free_request_buffers(S, r);
+        drop_dataset(r);
         S->n_done++;
     }
     S->active.erase(std::remove_if(S->active.begin(), S->active.end(),
@@ -375,6 +384,7 @@ static void server_main(Server *S) {
                     r->err = last_error();
                     r->state = 3;
                     r->t_done = Clock::now();
+                    drop_dataset(r.get());
                     continue;
                 }
                 S->active.push_back(r);
@@ -394,6 +404,7 @@ static void server_main(Server *S) {
             for (auto &r : S->queue) {
                 r->rc = rc;
                 r->state = 3;
+                drop_dataset(r.get());
             }
             S->queue.clear();
             return;
@@ -525,15 +536,22 @@ int epi_server_submit(epi_ctx *ctx, int32_t server_id, int32_t dataset_id, int32
         if (rc == EPI_OK && order > EPI_SERVE_MAX_ORDER)
             rc = fail(EPI_EUNSUPPORTED, "order %d > %d for served requests", order, EPI_SERVE_MAX_ORDER);
         if (rc) return rc;
+        // counted while the context lock is held, so epi_unload either sees
+        // the request or has already removed the dataset
+        ds->users.fetch_add(1);
     }
     auto r = std::make_shared<Request>();
     r->desc = d;
     r->ds = ds;
+    r->holds_ds = true;
     r->t_submit = Clock::now();
     {
         std::lock_guard<std::mutex> g(S->mu);
-        if (S->stopping) return fail(EPI_EINVAL, "server is stopping");
-        if (S->fatal) return fail(S->fatal, "server stopped after a device error");
+        if (S->stopping || S->fatal) {
+            drop_dataset(r.get());
+            if (S->stopping) return fail(EPI_EINVAL, "server is stopping");
+            return fail(S->fatal, "server stopped after a device error");
+        }
         r->id = S->next_req++;
         S->all[r->id] = r;
         S->queue.push_back(r);
@@ -580,6 +598,7 @@ int epi_server_results(epi_ctx *ctx, int32_t server_id, int32_t request_id, int3
     const int K = r->desc.top_k, k = r->desc.order, cells = pow3i(k);
     const char *blk = r->out.data();
     const int32_t nv = *(const int32_t *)blk;
+    if (((const int32_t *)blk)[1]) return pack_error(((const int32_t *)blk)[1]);
     const int32_t *hc = (const int32_t *)(blk + 16);
     const float *hs = (const float *)(blk + 16 + (size_t)K * k * 4);
     const uint32_t *ht = (const uint32_t *)(blk + 16 + (size_t)K * k * 4 + (size_t)K * 4);

@@ -167,9 +167,46 @@ def epi_memory(ctx):
     return used.value, budget.value
 
 
+def _host_inputs(geno, pheno):
+    """Genotypes (M, N) and phenotypes (N,) as contiguous uint8 numpy arrays;
+    other dtypes are refused rather than cast (a cast could wrap an invalid
+    value into the valid range)."""
+    g, p = np.asarray(geno), np.asarray(pheno)
+    if g.dtype != np.uint8 or p.dtype != np.uint8:
+        raise EpiError(EPI_EINVAL, "genotypes and phenotypes must be uint8 arrays")
+    if g.ndim != 2 or p.ndim != 1 or p.shape[0] != g.shape[1]:
+        raise EpiError(EPI_EINVAL, f"genotypes must be (M, N) and phenotypes (N,): got {g.shape} and {p.shape}")
+    return np.ascontiguousarray(g), np.ascontiguousarray(p)
+
+
+def _device_inputs(d_geno, d_pheno, shape=None):
+    """Checks of device genotypes (M, N) uint8 with unit stride along the
+    individuals and phenotypes (N,) uint8 contiguous: the library reads M
+    rows of N bytes and N bytes through the raw pointers.  Returns (M, N, ld)."""
+    import torch
+
+    for t, what in ((d_geno, "genotypes"), (d_pheno, "phenotypes")):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda):
+            raise EpiError(EPI_EINVAL, f"{what} must be a device tensor")
+        if t.dtype != torch.uint8:
+            raise EpiError(EPI_EINVAL, f"{what} must be uint8, got {t.dtype}")
+    if d_geno.dim() != 2 or d_pheno.dim() != 1 or d_pheno.shape[0] != d_geno.shape[1]:
+        raise EpiError(EPI_EINVAL, f"genotypes must be (M, N) and phenotypes (N,): got {tuple(d_geno.shape)} and "
+                                   f"{tuple(d_pheno.shape)}")
+    M, N = d_geno.shape
+    if shape is not None and (M, N) != tuple(shape):
+        raise EpiError(EPI_EINVAL, f"genotypes {M} x {N} differ from the dataset's {shape[0]} x {shape[1]}")
+    if N > 1 and d_geno.stride(1) != 1:
+        raise EpiError(EPI_EINVAL, "genotype rows must be contiguous (stride 1 along the individuals)")
+    if M > 1 and d_geno.stride(0) < N:
+        raise EpiError(EPI_EINVAL, "genotype rows overlap (row stride below N)")
+    if not d_pheno.is_contiguous():
+        raise EpiError(EPI_EINVAL, "phenotypes must be contiguous")
+    return M, N, d_geno.stride(0) if M > 1 else N
+
+
 def epi_load_genotypes(ctx, geno, pheno):
-    g = np.ascontiguousarray(geno, dtype=np.uint8)
-    p = np.ascontiguousarray(pheno, dtype=np.uint8)
+    g, p = _host_inputs(geno, pheno)
     M, N = g.shape
     out = _i32()
     _check(lib().epi_load_genotypes(ctx, _ptr(g), N, _ptr(p), M, N, ctypes.byref(out)))
@@ -177,8 +214,7 @@ def epi_load_genotypes(ctx, geno, pheno):
 
 
 def epi_load_genotypes_device(ctx, d_geno, d_pheno, stream=None):
-    M, N = d_geno.shape
-    ld = d_geno.stride(0)
+    M, N, ld = _device_inputs(d_geno, d_pheno)
     out = _i32()
     _check(lib().epi_load_genotypes_device(ctx, _ptr(d_geno), ld, _ptr(d_pheno), M, N, _stream(stream),
                                            ctypes.byref(out)))
@@ -186,7 +222,9 @@ def epi_load_genotypes_device(ctx, d_geno, d_pheno, stream=None):
 
 
 def epi_repack_device(ctx, dataset_id, d_geno, d_pheno, stream=None):
-    _check(lib().epi_repack_device(ctx, dataset_id, _ptr(d_geno), d_geno.stride(0), _ptr(d_pheno), _stream(stream)))
+    info = epi_dataset_info(ctx, dataset_id)
+    _, _, ld = _device_inputs(d_geno, d_pheno, (info["M"], info["N"]))
+    _check(lib().epi_repack_device(ctx, dataset_id, _ptr(d_geno), ld, _ptr(d_pheno), _stream(stream)))
 
 
 def epi_unload(ctx, dataset_id):

@@ -282,6 +282,25 @@ def pin_rank_ranges(o, seed=19):
     assert [c for _, c in rows[:20]] == [tuple(c) for c in whole["combos"]]
 
 
+def pin_score_list(o, seed=21):
+    """Tables and MI of an explicit list of combinations, row by row (every
+    row, not only the first, so a wrong per-row offset of the combinations,
+    tables or scores fails): numpy bincount and scikit-learn, also for lists
+    in non-lexicographic order and with repeated combinations."""
+    rng = np.random.default_rng(seed)
+    for M, N, k, frac in ((9, 70, 2, 0.5), (8, 133, 3, 0.3), (7, 64, 4, 0.55), (6, 41, 5, 0.4)):
+        G, y = random_genotypes(M, N, seed=seed + 10 * M + k, case_fraction=frac)
+        combos = [tuple(sorted(rng.choice(M, k, replace=False).tolist())) for _ in range(9)]
+        combos.append(combos[2])
+        scores, tables = o.score_list(G, y, np.asarray(combos, np.int32))
+        assert scores.shape == (len(combos),) and tables.shape == (len(combos), 2, 3**k)
+        for r, c in enumerate(combos):
+            assert np.array_equal(tables[r].astype(np.int64), bincount_table(G, y, c)), (r, c)
+            ref = sklearn_mi(G, y, c)
+            assert abs(scores[r] - ref) <= 1e-12 + 1e-10 * abs(ref), (r, c, scores[r], ref)
+        assert np.array_equal(tables[2], tables[-1]) and scores[2] == scores[-1]
+
+
 def _row_bits(word_list, n):
     """First n bits of a row (bit b of word w = individual 32 w + b) as a 0/1 string."""
     return "".join(str((int(word_list[b // 32]) >> (b % 32)) & 1) for b in range(n))
@@ -349,6 +368,7 @@ ALL_PINS = [
     pin_topk_lex_ties,
     pin_planted_recovery,
     pin_rank_ranges,
+    pin_score_list,
 ]
 
 

@@ -169,6 +169,50 @@ def test_device_load_and_repack(cx, orc):
     epi.epi_unload(cx.ctx, ds)
 
 
+def test_repack_input_checks(cx, orc):
+    """A repack with invalid values or other class sizes is reported by the
+    results of the scans that follow it (the device checks the values while
+    packing); a repack with valid input clears it.  The binding refuses
+    tensors of the wrong shape, dtype or layout before any call."""
+    import torch
+
+    from paper_2201_02460_amd import epi
+
+    G, y = random_genotypes(60, 300, seed=14, case_fraction=0.4)
+    dG, dy = torch.from_numpy(G).cuda(), torch.from_numpy(y).cuda()
+    ds = epi.epi_load_genotypes_device(cx.ctx, dG, dy)
+    try:
+        y_more = y.copy()
+        y_more[np.nonzero(y == 0)[0][0]] = 1  # one more case than the dataset has
+        G_bad = G.copy()
+        G_bad[7, 100] = 3
+        y_bad = y.copy()
+        y_bad[5] = 2
+        for gg, yy, what in ((G, y_more, "class sizes"), (G_bad, y, "genotype"), (G, y_bad, "phenotype")):
+            say("invalid repack:", what)
+            epi.epi_repack_device(cx.ctx, ds, torch.from_numpy(gg).cuda(), torch.from_numpy(yy).cuda())
+            sid = epi.epi_scan(cx.ctx, ds, 3, 5)
+            epi.epi_wait(cx.ctx, sid)
+            with pytest.raises(epi.EpiError) as e:
+                epi.epi_results(cx.ctx, sid, 5, 3)
+            assert e.value.code == epi.EPI_EINVAL
+            epi.epi_release(cx.ctx, sid)
+        epi.epi_repack_device(cx.ctx, ds, dG, dy)
+        res = cx.scan(ds, 3, 10)
+        check_topk(orc, G, y, 3, 10, res["combos"], res["scores"], res["tables"])
+        for bad_g, bad_y in ((dG[:, :299], dy[:299]), (dG.to(torch.int32), dy), (dG.t().contiguous().t(), dy),
+                             (dG, dy.to(torch.int64)), (torch.from_numpy(G), dy)):
+            with pytest.raises(epi.EpiError) as e:
+                epi.epi_repack_device(cx.ctx, ds, bad_g, bad_y)
+            assert e.value.code == epi.EPI_EINVAL
+        with pytest.raises(epi.EpiError):
+            epi.epi_load_genotypes(cx.ctx, G.astype(np.int64), y)
+        with pytest.raises(epi.EpiError):
+            epi.epi_load_genotypes(cx.ctx, G, y[:-1])
+    finally:
+        epi.epi_unload(cx.ctx, ds)
+
+
 def _golden_names():
     return [n for n in WORKLOADS if os.path.exists(os.path.join(GOLDEN, n + ".json"))]
 

@@ -110,3 +110,35 @@ def test_admission_by_memory_budget(cx):
         epi.epi_server_submit(cx.ctx, sid, data[0][0], 2, 5)
     for d in data:
         epi.epi_unload(cx.ctx, d[0])
+
+
+def test_unload_refused_while_requests_use_dataset(cx, orc):
+    """A dataset named by a queued or running request cannot be unloaded; the
+    requests still finish with the plain scans' results, and the dataset can
+    be unloaded once they are done.  Other datasets unload meanwhile."""
+    from paper_2201_02460_amd import epi
+
+    G, y = random_genotypes(150, 300, seed=330, case_fraction=0.4)
+    ds = cx.load(G, y)
+    G2, y2 = random_genotypes(30, 200, seed=331, case_fraction=0.5)
+    other = cx.load(G2, y2)
+    reqs = [(4, 10), (3, 20), (2, 15), (3, 7)]
+    alone = {r: cx.scan(ds, r[0], r[1]) for r in reqs}
+    sid = epi.epi_server_start(cx.ctx, max_active=1)
+    ids = [(epi.epi_server_submit(cx.ctx, sid, ds, o, K), (o, K)) for o, K in reqs]
+    with pytest.raises(epi.EpiError) as e:
+        epi.epi_unload(cx.ctx, ds)
+    assert e.value.code == epi.EPI_EINVAL
+    say("unload refused:", e.value)
+    epi.epi_unload(cx.ctx, other)
+    for rid, (o, K) in ids:
+        _wait(epi, cx, sid, rid)
+        c, s, t, _ = epi.epi_server_results(cx.ctx, sid, rid, K, o)
+        a = alone[(o, K)]
+        assert np.array_equal(c, a["combos"]) and np.array_equal(s, a["scores"]) and np.array_equal(t, a["tables"])
+    epi.epi_server_stop(cx.ctx, sid)
+    check_topk(orc, G, y, 3, 20, alone[(3, 20)]["combos"], alone[(3, 20)]["scores"], alone[(3, 20)]["tables"])
+    epi.epi_unload(cx.ctx, ds)
+    with pytest.raises(epi.EpiError) as e:
+        cx.scan(ds, 2, 5)
+    assert e.value.code == epi.EPI_ENOTFOUND

@@ -38,6 +38,12 @@ MUTANTS = {
     "gt_class_words": ("(cl ? words0 : 0) + b / 32", "(cl ? 0 : words1) + b / 32"),
     # genotype-table row index with the SNPs in reverse significance
     "gt_row_radix": ("row = 3 * row + geno;", "row = row + geno * (t == 0 ? 1 : (t == 1 ? 3 : 9));"),
+    # score list: per-row table offset of one class instead of two
+    "score_list_table_offset": ("out_tables + (int64_t)i * 2 * P : table;", "out_tables + (int64_t)i * P : table;"),
+    # score list: combinations read one index apart instead of k
+    "score_list_combo_offset": ("combos + (int64_t)i * k, k, t)", "combos + (int64_t)i, k, t)"),
+    # score list: every score written to the first slot
+    "score_list_score_index": ("out_scores[i] = oracle_mi(t, k);", "out_scores[0] = oracle_mi(t, k);"),
 }
 
 CHILD = r"""
