@@ -202,6 +202,31 @@ int epi_scan_info(epi_ctx *ctx, int32_t scan_id, uint64_t *n_combinations, int32
 /* Free a scan's buffers (waits for it first). */
 int epi_release(epi_ctx *ctx, int32_t scan_id);
 
+/* ---- completeness check (Algorithm 1: every combination exactly once;
+ *      Section 2.2: each with its contingency table) ---------------------- */
+
+/* Start a scan exactly as epi_scan does (same kernel choice, same results,
+ * read with epi_wait / epi_results / epi_release), with the checking build
+ * of its counting kernels: they also count every combination they score and
+ * add up a digest of it and its table.  For a combination c_1 < ... < c_k
+ * with table T[class][x] (class 0 = cases, x the cell index of epi_results)
+ *   h = mix64(... mix64(mix64(c_1 + 1) + c_2 + 1) ... + c_k + 1),
+ *   s = sum over class, x of T[class][x] * mix64(2 x + class + 1),
+ *   contribution = mix64(h XOR s),
+ * all modulo 2^64, mix64 being the output function of SplitMix64 (Steele,
+ * Lea and Flood, 2014).  The scan's digest is the sum of the contributions,
+ * independent of the order of the visit, so it can be compared with a
+ * count-and-digest of every combination computed any other way.  Slower
+ * than epi_scan (it is a check, not the production path).  Errors as
+ * epi_scan. */
+int epi_scan_check(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t top_k, void *stream,
+                   int32_t *scan_id);
+
+/* Count of combinations scored and their digest, of a finished scan started
+ * by epi_scan_check.  Errors: ENOTFOUND, ENOTREADY (not finished), EINVAL
+ * (a scan not started by epi_scan_check, null output). */
+int epi_scan_digest(epi_ctx *ctx, int32_t scan_id, uint64_t *n_scored, uint64_t *digest);
+
 /* ---- re-runnable batches ------------------------------------------------- */
 
 /* Build a batch of n scans once: work queue, per-scan buffers and (if
@@ -244,6 +269,13 @@ int epi_batch_destroy(epi_ctx *ctx, int32_t batch_id);
  * choice for the order.  Served requests (epi_server_*) always use the fused
  * kernels. */
 #define EPI_BLOCK_SEGMENTED 64
+/* Orders 4-8: the per-combination kernel that counts all 3^order cells of a
+ * combination's table with AND + popcount (Section 2.2 as written).  It is
+ * the built-in choice from order 5 on; order 4 uses the reduced-cell kernel
+ * (the cells with genotypes 0 and 1 counted, the others by
+ * inclusion-exclusion from the pair and triplet sub-tables) when its
+ * triplet sub-table fits, and this block pins the all-cell kernel instead. */
+#define EPI_BLOCK_ALL_CELLS 81
 
 /* Time the counting kernels above for `order` on a bounded slice of the
  * dataset's combination space and remember the fastest for datasets of the
@@ -256,7 +288,8 @@ int epi_autotune(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t *choic
 
 /* Pin the counting kernel for `order` on datasets of the same bucket as
  * `dataset_id`, as if the autotuner had chosen `block` (one of the blocks
- * listed above; orders above 3 take only EPI_BLOCK_SEGMENTED and 0).  EPI_BLOCK_MFMA_I8 builds the dataset's integer
+ * listed above; orders above 3 take EPI_BLOCK_SEGMENTED, EPI_BLOCK_ALL_CELLS
+ * and 0).  EPI_BLOCK_MFMA_I8 builds the dataset's integer
  * operand copies on the context stream and waits for them (no other work on
  * the dataset may be in flight).  EPI_EINVAL for a block not listed for the
  * order, EPI_EUNSUPPORTED for a matrix-core block on a dataset with 2^22

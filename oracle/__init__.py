@@ -57,6 +57,9 @@ def _bind(lib):
     lib.oracle_scan.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                 ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32,
                                 i32p, f64p, u64p, i32p, i32p]
+    lib.oracle_digest.restype = ctypes.c_int
+    lib.oracle_digest.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32, u64p, u64p]
     lib.oracle_score_list.restype = ctypes.c_int
     lib.oracle_score_list.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int32, ctypes.c_int32, i32p,
                                       ctypes.c_int32, f64p, u64p]
@@ -159,6 +162,21 @@ class Oracle:
         n = n_out.value
         return {"combos": combos[:n], "scores": scores[:n], "tables": tabs[:n] if tables else None,
                 "threads": used.value}
+
+    def digest(self, G, y, order, rank_begin=0, rank_end=None, nthreads=0):
+        """(count, digest) of the combinations of the lexicographic rank range:
+        how many there are and the sum modulo 2^64 of each one's hash with its
+        table (the completeness check of a scan)."""
+        G, y = _as_inputs(G, y)
+        M, N = G.shape
+        total = self.binomial(M, order)
+        end = total if rank_end is None else min(int(rank_end), total)
+        count, dig = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        rc = self.lib.oracle_digest(_ptr(G, ctypes.c_uint8), N, _ptr(y, ctypes.c_uint8), M, N, order,
+                                    int(rank_begin), int(end), int(nthreads), ctypes.byref(count), ctypes.byref(dig))
+        if rc != 0:
+            raise ValueError("oracle_digest rejected its input")
+        return count.value, dig.value
 
     def score_list(self, G, y, combos):
         """Scores (n,) and tables (n, 2, 3**k) of explicit combinations."""

@@ -22,7 +22,12 @@
  *     zero counts contribute nothing;
  *   - the best `top_k` combinations: larger MI first, ties broken by the
  *     lexicographically smaller combination (the paper keeps only the
- *     combinations with the highest MI, Section 2.4).
+ *     combinations with the highest MI, Section 2.4);
+ *   - a completeness digest: the number of combinations of a rank range and
+ *     the sum of a hash of each combination and its table (the definition is
+ *     at oracle_digest), against which a GPU scan that visits the
+ *     combinations in its own order can show that it scored every one of
+ *     them exactly once, each with its table.
  *
  * Inputs: genotypes G (uint8, M rows of N individuals, row stride ld, values
  * 0/1/2 = homozygous dominant / heterozygous / homozygous recessive, the three
@@ -364,6 +369,127 @@ int oracle_scan(const uint8_t *G, int64_t ld, const uint8_t *y, int32_t M, int32
         free(jobs[t].table);
     }
     free(best);
+    free(jobs);
+    free(tids);
+    return rc;
+}
+
+/* ---- completeness digest (Algorithm 1 visits every combination once;
+ *      Section 2.2 gives each its table) --------------------------------- */
+
+/* Output function of SplitMix64 (Steele, Lea and Flood, "Fast splittable
+ * pseudorandom number generators", OOPSLA 2014), arithmetic modulo 2^64. */
+static uint64_t splitmix_out(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * UINT64_C(0xbf58476d1ce4e5b9);
+    z = (z ^ (z >> 27)) * UINT64_C(0x94d049bb133111eb);
+    return z ^ (z >> 31);
+}
+
+/* Contribution of one combination c[0] < ... < c[k-1] with table
+ * table[cls * 3^k + x]: the indices folded one at a time,
+ * h = mix(h + c_t + 1) from h = 0; the counts weighted per cell,
+ * s = sum table[cls][x] * mix(2 x + cls + 1); the contribution mix(h ^ s). */
+static uint64_t digest_term(const int32_t *c, int32_t k, const uint64_t *table)
+{
+    const int64_t P = pow3(k);
+    uint64_t h = 0;
+    for (int32_t t = 0; t < k; t++)
+        h = splitmix_out(h + (uint64_t)c[t] + 1);
+    uint64_t s = 0;
+    for (int cls = 0; cls < 2; cls++)
+        for (int64_t x = 0; x < P; x++)
+            s += table[cls * P + x] * splitmix_out(2 * (uint64_t)x + (uint64_t)cls + 1);
+    return splitmix_out(h ^ s);
+}
+
+typedef struct {
+    const uint8_t *G;
+    int64_t ld;
+    const uint8_t *y;
+    int32_t M, N, k;
+    uint64_t begin, end, count, sum;
+    uint64_t *table;
+    int status;
+} digest_job_t;
+
+static void *digest_range(void *arg)
+{
+    digest_job_t *j = (digest_job_t *)arg;
+    j->count = 0;
+    j->sum = 0;
+    j->status = 0;
+    if (j->begin >= j->end)
+        return NULL;
+    int32_t c[64];
+    lex_unrank(j->begin, j->M, j->k, c);
+    for (uint64_t r = j->begin; r < j->end; r++) {
+        if (oracle_count_table(j->G, j->ld, j->y, j->N, c, j->k, j->table) != 0) {
+            j->status = -1;
+            return NULL;
+        }
+        j->sum += digest_term(c, j->k, j->table);
+        j->count++;
+        if (r + 1 < j->end)
+            lex_next(c, j->M, j->k);
+    }
+    return NULL;
+}
+
+/*
+ * Number of combinations in the lexicographic rank range [rank_begin,
+ * rank_end) (clamped to C(M,k)) and the sum modulo 2^64 of their digest
+ * contributions, each table counted one individual at a time, with
+ * `nthreads` threads (<= 0: all online cores).  Returns 0, or -1 on invalid
+ * arguments / genotype values.
+ */
+int oracle_digest(const uint8_t *G, int64_t ld, const uint8_t *y, int32_t M, int32_t N, int32_t k,
+                  uint64_t rank_begin, uint64_t rank_end, int32_t nthreads, uint64_t *count, uint64_t *digest)
+{
+    *count = 0;
+    *digest = 0;
+    if (k < 1 || k > ORACLE_MAX_ORDER || k > M || N < 1)
+        return -1;
+    uint64_t total = oracle_binomial(M, k);
+    if (rank_end > total)
+        rank_end = total;
+    if (rank_begin >= rank_end)
+        return 0;
+    if (nthreads <= 0)
+        nthreads = (int32_t)sysconf(_SC_NPROCESSORS_ONLN);
+    if (nthreads < 1)
+        nthreads = 1;
+    uint64_t span = rank_end - rank_begin;
+    if ((uint64_t)nthreads > span)
+        nthreads = (int32_t)span;
+    const int64_t P = pow3(k);
+    digest_job_t *jobs = (digest_job_t *)calloc((size_t)nthreads, sizeof(digest_job_t));
+    pthread_t *tids = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+    for (int32_t t = 0; t < nthreads; t++) {
+        digest_job_t *j = &jobs[t];
+        j->G = G;
+        j->ld = ld;
+        j->y = y;
+        j->M = M;
+        j->N = N;
+        j->k = k;
+        j->begin = rank_begin + span * (uint64_t)t / (uint64_t)nthreads;
+        j->end = rank_begin + span * (uint64_t)(t + 1) / (uint64_t)nthreads;
+        j->table = (uint64_t *)calloc((size_t)(2 * P), sizeof(uint64_t));
+    }
+    for (int32_t t = 1; t < nthreads; t++)
+        pthread_create(&tids[t], NULL, digest_range, &jobs[t]);
+    digest_range(&jobs[0]);
+    for (int32_t t = 1; t < nthreads; t++)
+        pthread_join(tids[t], NULL);
+    int rc = 0;
+    for (int32_t t = 0; t < nthreads; t++) {
+        if (jobs[t].status != 0)
+            rc = -1;
+        *count += jobs[t].count;
+        *digest += jobs[t].sum;
+        free(jobs[t].table);
+    }
     free(jobs);
     free(tids);
     return rc;

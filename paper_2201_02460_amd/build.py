@@ -16,16 +16,20 @@ LIB = os.path.join(BUILD, "libepi.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-SOURCES = ["kernels.hip", "runtime.cpp", "server.cpp"]
+# (source, object, extra flags): kernels.hip is compiled a second time with
+# EPI_SCAN_CHECK for the checking instantiations of the scan kernel
+SOURCES = [("kernels.hip", "kernels.o", []), ("kernels.hip", "kernels_check.o", ["-DEPI_SCAN_CHECK"]),
+           ("runtime.cpp", "runtime.o", []), ("server.cpp", "server.o", [])]
 # Packed FP32 VALU instructions are disabled for all device code.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-mcode-object-version=5", "-Xclang",
          "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument", f"-I{INCLUDE}", "-Wall"]
 
 
-def _compile(src):
-    out = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+def _compile(entry):
+    src, obj, extra = entry
+    out = os.path.join(BUILD, obj)
     lang = [] if src.endswith(".hip") else ["-x", "hip"]
-    cmd = [HIPCC, *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", out]
+    cmd = [HIPCC, *FLAGS, *extra, *lang, "-c", os.path.join(CSRC, src), "-o", out]
     subprocess.run(cmd, check=True)
     return out
 

@@ -116,7 +116,28 @@ struct Task {
     int32_t cell_shift;               // kF2Emit: pair cells are written as (count << cell_shift)
     uint32_t cell_bias;               //   + cell_bias, or with cell_neg as cell_bias - (count << cell_shift)
     int32_t cell_neg;
+    unsigned long long *digest;       // checking launches: [0] combinations scored, [1] their digest sum
+                                      //   (null: no check)
 };
+
+// Completeness check of a scan (every combination exactly once, each with
+// its table).  mix64 is the output function of SplitMix64 (Steele, Lea and
+// Flood, "Fast splittable pseudorandom number generators", 2014).  A
+// combination c_1 < ... < c_k with table T[class][x] (class 0 = cases, x the
+// cell index) contributes mix64(h ^ s), where h folds its indices,
+// h = mix64(... mix64(mix64(c_1 + 1) + c_2 + 1) ... + c_k + 1), and s weighs
+// its counts, s = sum T[class][x] * mix64(2 x + class + 1) (all mod 2^64).
+// A scan's digest is the sum of the contributions of the combinations it
+// scored, so it does not depend on the order in which they were visited.
+__host__ __device__ constexpr unsigned long long mix64(unsigned long long z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__host__ __device__ constexpr unsigned long long cell_weight(int cls, int x) {
+    return mix64(2ull * (unsigned long long)x + (unsigned long long)cls + 1ull);
+}
 
 // Score histogram of a task: how many distinct combinations entered some
 // wave's best-K list, by the position of the leading bit of their num and the

@@ -256,7 +256,55 @@ struct TopK {
     unsigned *hist;  // the task's score histogram (null: none)
     int added;       // combinations counted since the bound was last taken
     int top;         // highest histogram bin this wave has counted (-1: none)
+    unsigned long long dsum;  // checking launches: this lane's digest sum and count since the last flush
+    unsigned dn;
 };
+
+// ---------------------------------------------------------------------------
+// Completeness check (checking launches only; definition in
+// epi_internal.hpp): every scored combination adds mix64(h ^ s) to its
+// lane's sum, flushed to the task's two counters when the wave leaves the
+// task.
+// ---------------------------------------------------------------------------
+template <int K>
+EPI_DEV unsigned long long combo_hash(const int (&c)[K]) {
+    unsigned long long h = 0;
+    #pragma unroll
+    for (int t = 0; t < K; ++t) h = mix64(h + (unsigned long long)c[t] + 1ull);
+    return h;
+}
+
+EPI_DEV void digest_add(TopK &t, bool valid, unsigned long long h, unsigned long long s) {
+    if (valid) {
+        t.dsum += mix64(h ^ s);
+        t.dn += 1;
+    }
+}
+
+// Weighted sum of a table held as plain counts F[class][x].
+template <int CELLS, class T>
+EPI_DEV unsigned long long table_sum(const T (&F0)[CELLS], const T (&F1)[CELLS]) {
+    unsigned long long s = 0;
+    #pragma unroll
+    for (int x = 0; x < CELLS; ++x)
+        s += (unsigned long long)(unsigned)F0[x] * cell_weight(0, x) + (unsigned long long)(unsigned)F1[x] * cell_weight(1, x);
+    return s;
+}
+
+EPI_DEV void digest_flush(TopK &t, const Task &task) {
+    unsigned long long s = t.dsum, n = t.dn;
+    #pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        s += __shfl_xor(s, off);
+        n += __shfl_xor(n, off);
+    }
+    if (lane_id() == 0 && task.digest) {
+        atomicAdd(task.digest, n);
+        atomicAdd(task.digest + 1, s);
+    }
+    t.dsum = 0;
+    t.dn = 0;
+}
 
 // Count the combinations of the lanes with `counted` set: one atomic per
 // distinct bin of the wave, with the number of its lanes in that bin.
@@ -486,7 +534,7 @@ EPI_DEV long long entry_bound(const TopK &tk, long long gthr) {
 // (kF2Fold: a scan of all orders takes its order-2 results from the pair
 // sub-table pass of its higher orders instead of counting the pairs twice).
 // ---------------------------------------------------------------------------
-template <int NP, bool EMIT, bool LDS, bool SCORE = !EMIT>
+template <int NP, bool EMIT, bool LDS, bool SCORE = !EMIT, bool CHECK = false>
 EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr, v4u *stage,
                      int stage_cap) {
     const DsView d = t.ds;
@@ -586,6 +634,10 @@ EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *li
                 F[c][8] = d.ncls[c];
                 mobius2(F[c]);
             }
+            if constexpr (CHECK) {
+                const int cc[2] = {i, m};
+                digest_add(tk, valid, combo_hash<2>(cc), table_sum<9>(F[0], F[1]));
+            }
             bool pass = valid;
             if constexpr (LDS) {
                 const int sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.tq, 27);
@@ -607,7 +659,7 @@ EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *li
 // m > j); lane = m.  Reduced cells (a, b, d) in {0,1}^3 per class; every
 // other cell comes from the pair sub-table and the single-SNP counts.
 // ---------------------------------------------------------------------------
-template <int NP, bool LDS>
+template <int NP, bool LDS, bool CHECK = false>
 EPI_DEV void item_f3(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr, v4u *stage,
                      int stage_cap) {
     const DsView d = t.ds;
@@ -733,6 +785,10 @@ EPI_DEV void item_f3(const Task &t, unsigned long long local, TopK &tk, Cand *li
             F[c][26] = d.ncls[c];
             mobius3(F[c]);
         }
+        if constexpr (CHECK) {
+            const int cc[3] = {i, j, m};
+            digest_add(tk, valid, combo_hash<3>(cc), table_sum<27>(F[0], F[1]));
+        }
         bool pass = valid;
         if constexpr (LDS) {
             const int sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.tq, 81);
@@ -816,7 +872,7 @@ struct QFmt<true> {
     }
 };
 
-template <bool LDS, bool REV, bool I8, bool EMIT = false>
+template <bool LDS, bool REV, bool I8, bool EMIT = false, bool CHECK = false>
 EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr, v4u *stage) {
     typedef QFmt<I8> Q;
     const DsView d = t.ds;
@@ -1029,6 +1085,17 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
             F[c][26] = nall[c];
             mobius3_signed(F[c]);
         }
+        if constexpr (CHECK) {
+            unsigned long long sum = 0;
+            #pragma unroll
+            for (int x = 0; x < 27; ++x) {
+                const unsigned n0 = (odd_twos(x) ? B - F[0][x] : F[0][x]) >> kQScaleShift;
+                const unsigned n1 = (odd_twos(x) ? B - F[1][x] : F[1][x]) >> kQScaleShift;
+                sum += (unsigned long long)n0 * cell_weight(0, x) + (unsigned long long)n1 * cell_weight(1, x);
+            }
+            const int cc[3] = {i, j, m};
+            digest_add(tk, valid, combo_hash<3>(cc), sum);
+        }
         bool pass = valid;
         if constexpr (LDS) pass = pass && screen_sum_signed<27, REV>(F[0], F[1], B) >= sb;
         if (__ballot(pass)) {
@@ -1132,9 +1199,9 @@ EPI_DEV void g3_count(const DsView &d, const int (&c)[K], const int *dig, int cl
     }
 }
 
-template <int K, bool STORE, bool LDT>
+template <int K, bool STORE, bool LDT, bool DIG>
 EPI_DEV long long generic_num_g3(const DsView &d, const int (&c)[K], long long score_const, uint32_t *out,
-                                 int ostride) {
+                                 int ostride, unsigned long long *dsum) {
     constexpr int NB = K - 4;       // prefix SNPs fixed within a group
     constexpr int NG = pow3c(NB);   // groups of 81 cells
     long long num = score_const;
@@ -1157,6 +1224,9 @@ EPI_DEV long long generic_num_g3(const DsView &d, const int (&c)[K], long long s
         #pragma unroll
         for (int x = 0; x < 81; ++x) {
             const unsigned n0 = x & 1 ? pk[x >> 1] >> 16 : pk[x >> 1] & 0xffffu;
+            if constexpr (DIG)
+                *dsum += (unsigned long long)n0 * cell_weight(0, gi * 81 + x) +
+                         (unsigned long long)acc[x] * cell_weight(1, gi * 81 + x);
             if constexpr (STORE) {
                 out[(gi * 81 + x) * ostride] = n0;
                 out[(pow3c(K) + gi * 81 + x) * ostride] = acc[x];
@@ -1172,12 +1242,14 @@ EPI_DEV long long generic_num_g3(const DsView &d, const int (&c)[K], long long s
 // form (STORE false) scores each chunk as it is counted and returns the
 // score; with STORE the counts go to out[x * ostride] (class 0) and
 // out[(3^K + x) * ostride] (class 1) instead, x the cell's index in base 3
-// with the genotype of c[0] as the leading digit.
-template <int K, bool STORE = false, bool LDT = false>
+// with the genotype of c[0] as the leading digit.  With DIG the weighted sum
+// of the counts (the table part of the completeness digest) is added to
+// *dsum.
+template <int K, bool STORE = false, bool LDT = false, bool DIG = false>
 EPI_DEV long long generic_num(const DsView &d, const int (&c)[K], long long score_const, uint32_t *out = nullptr,
-                              int ostride = kWave) {
+                              int ostride = kWave, unsigned long long *dsum = nullptr) {
     if constexpr (K >= 5)
-        if (d.ncls[0] <= 0xffff) return generic_num_g3<K, STORE, LDT>(d, c, score_const, out, ostride);
+        if (d.ncls[0] <= 0xffff) return generic_num_g3<K, STORE, LDT, DIG>(d, c, score_const, out, ostride, dsum);
     constexpr int NPRE = K > 3 ? K - 3 : 0;
     constexpr int NCH = pow3c(NPRE);
     constexpr int L = K >= 3 ? 3 : 2;
@@ -1243,6 +1315,12 @@ EPI_DEV long long generic_num(const DsView &d, const int (&c)[K], long long scor
                 }
             }
         }
+        if constexpr (DIG) {
+            #pragma unroll
+            for (int x = 0; x < CELLS; ++x)
+                *dsum += (unsigned long long)acc[0][x] * cell_weight(0, ch * CELLS + x) +
+                         (unsigned long long)acc[1][x] * cell_weight(1, ch * CELLS + x);
+        }
         if constexpr (STORE) {
             #pragma unroll
             for (int x = 0; x < CELLS; ++x) {
@@ -1258,7 +1336,7 @@ EPI_DEV long long generic_num(const DsView &d, const int (&c)[K], long long scor
     return num;
 }
 
-template <int K, bool LDT>
+template <int K, bool LDT, bool CHECK = false>
 EPI_DEV void item_generic(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr,
                           const unsigned long long *binom, int bstride) {
     const DsView d = t.ds;
@@ -1269,7 +1347,9 @@ EPI_DEV void item_generic(const Task &t, unsigned long long local, TopK &tk, Can
         rank = valid ? rank : 0ull;
         int c[K];
         colex_unrank<K>(rank, d.M, binom, bstride, c);
-        const long long num = generic_num<K, false, LDT>(d, c, t.score_const);
+        unsigned long long sum = 0;
+        const long long num = generic_num<K, false, LDT, CHECK>(d, c, t.score_const, nullptr, kWave, &sum);
+        if constexpr (CHECK) digest_add(tk, valid, combo_hash<K>(c), sum);
         unsigned long long key = 0;
         #pragma unroll
         for (int u = 0; u < K; ++u) key = (key << bits) | (unsigned long long)c[u];
@@ -1286,7 +1366,7 @@ EPI_DEV void item_generic(const Task &t, unsigned long long local, TopK &tk, Can
 // another through the same slot.  A lane reads back only what it wrote, so
 // program order is the only ordering needed.
 // ---------------------------------------------------------------------------
-template <int K, bool LDT>
+template <int K, bool LDT, bool CHECK = false>
 EPI_DEV void item_seg(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr,
                       const unsigned long long *binom, int bstride, uint32_t *slot) {
     constexpr int CELLS = pow3c(K);
@@ -1305,11 +1385,15 @@ EPI_DEV void item_seg(const Task &t, unsigned long long local, TopK &tk, Cand *l
         (void)generic_num<K, true>(d, c, 0, mine);
         // phase 2: their scores
         long long num = t.score_const;
+        unsigned long long sum = 0;
         #pragma unroll 9
         for (int x = 0; x < CELLS; ++x) {
             const unsigned n0 = mine[x * kWave], n1 = mine[(CELLS + x) * kWave];
             num += LDT ? cell_term_lds(n0, n1) : cell_term_counted(d.tlog, n0, n1);
+            if constexpr (CHECK)
+                sum += (unsigned long long)n0 * cell_weight(0, x) + (unsigned long long)n1 * cell_weight(1, x);
         }
+        if constexpr (CHECK) digest_add(tk, valid, combo_hash<K>(c), sum);
         unsigned long long key = 0;
         #pragma unroll
         for (int u = 0; u < K; ++u) key = (key << bits) | (unsigned long long)c[u];
@@ -1326,7 +1410,7 @@ EPI_DEV void item_seg(const Task &t, unsigned long long local, TopK &tk, Cand *l
 // sub-table (written by the matrix-core kernel), the pair sub-table and the
 // single-SNP counts, as for order 3.
 // ---------------------------------------------------------------------------
-template <bool LDS, bool REV>
+template <bool LDS, bool REV, bool CHECK = false>
 EPI_DEV void item_r4(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr,
                      const unsigned long long *binom, int bstride) {
     const DsView d = t.ds;
@@ -1485,6 +1569,16 @@ EPI_DEV void item_r4(const Task &t, unsigned long long local, TopK &tk, Cand *li
         F[1][80] = ((unsigned)d.ncls[1] << kQScaleShift) - B40;
         mobius4_signed(F[0]);
         mobius4_signed(F[1]);
+        if constexpr (CHECK) {
+            unsigned long long sum = 0;
+            #pragma unroll
+            for (int x = 0; x < 81; ++x) {
+                const unsigned n0 = (odd_twos(x) ? B - F[0][x] : F[0][x]) >> kQScaleShift;
+                const unsigned n1 = (odd_twos(x) ? B - F[1][x] : F[1][x]) >> kQScaleShift;
+                sum += (unsigned long long)n0 * cell_weight(0, x) + (unsigned long long)n1 * cell_weight(1, x);
+            }
+            digest_add(tk, valid, combo_hash<4>(c), sum);
+        }
         bool pass = valid;
         if constexpr (LDS) pass = pass && screen_sum_signed<81, REV>(F[0], F[1], B) >= sb;
         if (__ballot(pass)) {
@@ -1518,7 +1612,9 @@ constexpr int scan_waves_per_eu() {
     return GK >= 4 ? 2 : (GK == 3 ? 3 : (NP3 >= 8 ? 2 : (NP3 >= 4 ? 3 : (NP3 >= 2 ? 4 : (NP2 >= 8 ? 3 : 4)))));
 }
 
-template <int NP2, int NP3, int GK>
+// CHECK: the checking instantiation, which also adds every scored
+// combination to its task's completeness digest (the same results otherwise).
+template <int NP2, int NP3, int GK, bool CHECK>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<NP2, NP3, GK>())))
 scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long total_items,
                 unsigned long long *__restrict__ queue, const unsigned long long *__restrict__ binom, int bstride,
@@ -1544,6 +1640,8 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
     tk.hist = nullptr;
     tk.added = 0;
     tk.top = -1;
+    tk.dsum = 0;
+    tk.dn = 0;
     int cur = -1;
     long long gthr = (long long)0x8000000000000000ull;
     const uint32_t *loaded = nullptr;  // dataset whose screening table is in s_tab
@@ -1617,6 +1715,7 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
                 if (cur >= 0 && !is_emit(tasks[cur].variant)) {
                     if (tk.n == tk.K && tk.wn > gthr && lane_id() == 0) atomicMax(tasks[cur].thr, bias(tk.wn));
                     tk_flush(tk, s_list, tasks[cur]);
+                    if constexpr (CHECK) digest_flush(tk, tasks[cur]);
                 }
                 cur = lo;
                 tk.n = 0;
@@ -1643,8 +1742,8 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
             switch (T.variant) {
             case kF2:
                 if constexpr (NP2 > 0) {
-                    if (lds) item_f2<NP2, false, true>(T, local, tk, s_list, gthr, s_stage, stage_cap);
-                    else item_f2<NP2, false, false>(T, local, tk, s_list, gthr, s_stage, stage_cap);
+                    if (lds) item_f2<NP2, false, true, true, CHECK>(T, local, tk, s_list, gthr, s_stage, stage_cap);
+                    else item_f2<NP2, false, false, true, CHECK>(T, local, tk, s_list, gthr, s_stage, stage_cap);
                 }
                 break;
             case kF2Emit:
@@ -1653,8 +1752,8 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
                 break;
             case kF2Fold:
                 if constexpr (NP2 > 0) {
-                    if (lds) item_f2<NP2, true, true, true>(T, local, tk, s_list, gthr, s_stage, stage_cap);
-                    else item_f2<NP2, true, false, true>(T, local, tk, s_list, gthr, s_stage, stage_cap);
+                    if (lds) item_f2<NP2, true, true, true, CHECK>(T, local, tk, s_list, gthr, s_stage, stage_cap);
+                    else item_f2<NP2, true, false, true, CHECK>(T, local, tk, s_list, gthr, s_stage, stage_cap);
                 }
                 break;
             case kF3Emit:
@@ -1662,33 +1761,33 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
                 break;
             case kR4:
                 if constexpr (GK == 4) {
-                    if (lds && loaded_rev) item_r4<true, true>(T, local, tk, s_list, gthr, binom, bstride);
-                    else if (lds) item_r4<true, false>(T, local, tk, s_list, gthr, binom, bstride);
-                    else item_r4<false, false>(T, local, tk, s_list, gthr, binom, bstride);
+                    if (lds && loaded_rev) item_r4<true, true, CHECK>(T, local, tk, s_list, gthr, binom, bstride);
+                    else if (lds) item_r4<true, false, CHECK>(T, local, tk, s_list, gthr, binom, bstride);
+                    else item_r4<false, false, CHECK>(T, local, tk, s_list, gthr, binom, bstride);
                 }
                 break;
             case kF3:
                 if constexpr (NP3 == kNpMfma || NP3 == kNpMfmaI8) {
                     constexpr bool i8 = NP3 == kNpMfmaI8;
-                    if (lds && loaded_rev) item_f3m<true, true, i8>(T, local, tk, s_list, gthr, s_stage);
-                    else if (lds) item_f3m<true, false, i8>(T, local, tk, s_list, gthr, s_stage);
-                    else item_f3m<false, false, i8>(T, local, tk, s_list, gthr, s_stage);
+                    if (lds && loaded_rev) item_f3m<true, true, i8, false, CHECK>(T, local, tk, s_list, gthr, s_stage);
+                    else if (lds) item_f3m<true, false, i8, false, CHECK>(T, local, tk, s_list, gthr, s_stage);
+                    else item_f3m<false, false, i8, false, CHECK>(T, local, tk, s_list, gthr, s_stage);
                 } else if constexpr (NP3 > 0) {
-                    if (lds) item_f3<NP3, true>(T, local, tk, s_list, gthr, s_stage, stage_cap);
-                    else item_f3<NP3, false>(T, local, tk, s_list, gthr, s_stage, stage_cap);
+                    if (lds) item_f3<NP3, true, CHECK>(T, local, tk, s_list, gthr, s_stage, stage_cap);
+                    else item_f3<NP3, false, CHECK>(T, local, tk, s_list, gthr, s_stage, stage_cap);
                 }
                 break;
             case kSeg:
                 if constexpr (GK > kSegGk) {
                     uint32_t *slot = T.seg + (size_t)(blockIdx.x * 4 + wave) * (2 * kWave * pow3c(GK - kSegGk));
-                    if (ldt) item_seg<GK - kSegGk, true>(T, local, tk, s_list, gthr, binom, bstride, slot);
-                    else item_seg<GK - kSegGk, false>(T, local, tk, s_list, gthr, binom, bstride, slot);
+                    if (ldt) item_seg<GK - kSegGk, true, CHECK>(T, local, tk, s_list, gthr, binom, bstride, slot);
+                    else item_seg<GK - kSegGk, false, CHECK>(T, local, tk, s_list, gthr, binom, bstride, slot);
                 }
                 break;
             default:
                 if constexpr (GK > 0 && GK < kSegGk) {
-                    if (ldt) item_generic<GK, true>(T, local, tk, s_list, gthr, binom, bstride);
-                    else item_generic<GK, false>(T, local, tk, s_list, gthr, binom, bstride);
+                    if (ldt) item_generic<GK, true, CHECK>(T, local, tk, s_list, gthr, binom, bstride);
+                    else item_generic<GK, false, CHECK>(T, local, tk, s_list, gthr, binom, bstride);
                 }
                 break;
             }
@@ -1711,9 +1810,51 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
             gthr = tk.wn;
         }
     }
-    if (cur >= 0 && !is_emit(tasks[cur].variant)) tk_flush(tk, s_list, tasks[cur]);
+    if (cur >= 0 && !is_emit(tasks[cur].variant)) {
+        tk_flush(tk, s_list, tasks[cur]);
+        if constexpr (CHECK) digest_flush(tk, tasks[cur]);
+    }
 }
 
+typedef void (*ScanKernelFn)(const Task *, int, unsigned long long, unsigned long long *, const unsigned long long *,
+                             int, int, int, int);
+
+struct ScanKernelEntry {
+    int np2, np3, gk;
+    ScanKernelFn fn;
+};
+
+// Every instantiation of the scan kernel, in one table per CHECK value: this
+// file is compiled twice, once as is (everything but the checking
+// instantiations) and once with EPI_SCAN_CHECK defined (only those), so the
+// two large sets of instantiations compile in parallel.
+#define EPI_SCAN_KERNELS(CK)                                                                                     \
+    {2, 0, 0, scan_persistent<2, 0, 0, CK>}, {4, 0, 0, scan_persistent<4, 0, 0, CK>},                             \
+        {8, 0, 0, scan_persistent<8, 0, 0, CK>}, /* order 2 / pair sub-table */                                  \
+        {0, 1, 0, scan_persistent<0, 1, 0, CK>}, {0, 2, 0, scan_persistent<0, 2, 0, CK>},                         \
+        {0, 4, 0, scan_persistent<0, 4, 0, CK>}, {0, 8, 0, scan_persistent<0, 8, 0, CK>}, /* order 3 */          \
+        {0, 0, 4, scan_persistent<0, 0, 4, CK>}, {0, 0, 5, scan_persistent<0, 0, 5, CK>}, /* per combination */ \
+        {0, 0, 6, scan_persistent<0, 0, 6, CK>}, {0, 0, 7, scan_persistent<0, 0, 7, CK>},                         \
+        {0, 0, 8, scan_persistent<0, 0, 8, CK>},                                                                   \
+        {0, 0, kSegGk + 2, scan_persistent<0, 0, kSegGk + 2, CK>}, /* segmented (two-phase) */                   \
+        {0, 0, kSegGk + 3, scan_persistent<0, 0, kSegGk + 3, CK>},                                                 \
+        {0, 0, kSegGk + 4, scan_persistent<0, 0, kSegGk + 4, CK>},                                                 \
+        {0, 0, kSegGk + 5, scan_persistent<0, 0, kSegGk + 5, CK>},                                                 \
+        {0, 0, kSegGk + 6, scan_persistent<0, 0, kSegGk + 6, CK>},                                                 \
+        {0, 0, kSegGk + 7, scan_persistent<0, 0, kSegGk + 7, CK>},                                                 \
+        {0, 0, kSegGk + 8, scan_persistent<0, 0, kSegGk + 8, CK>},                                                 \
+        {0, kNpMfma, 0, scan_persistent<0, kNpMfma, 0, CK>}, /* order 3, matrix cores */                         \
+        {0, kNpMfmaI8, 0, scan_persistent<0, kNpMfmaI8, 0, CK>},
+
+#ifdef EPI_SCAN_CHECK
+static const ScanKernelEntry kScanKernelsCheck[] = {EPI_SCAN_KERNELS(true)};
+
+ScanKernelFn find_scan_kernel_check(int np2, int np3, int gk) {
+    for (const auto &e : kScanKernelsCheck)
+        if (e.np2 == np2 && e.np3 == np3 && e.gk == gk) return e.fn;
+    return nullptr;
+}
+#else
 // ---------------------------------------------------------------------------
 // Best-K selection over a task's candidate buffer: one 1024-thread workgroup
 // per task; candidates below the task's final threshold are dropped, the rest
@@ -2368,25 +2509,9 @@ __global__ void init_counters_kernel(unsigned long long *queues, int nq, unsigne
 // ---------------------------------------------------------------------------
 // Host-side launchers (called by the runtime).
 // ---------------------------------------------------------------------------
-typedef void (*ScanKernelFn)(const Task *, int, unsigned long long, unsigned long long *, const unsigned long long *,
-                             int, int, int, int);
+static const ScanKernelEntry kScanKernels[] = {EPI_SCAN_KERNELS(false)};
 
-struct ScanKernelEntry {
-    int np2, np3, gk;
-    ScanKernelFn fn;
-};
-
-#define EPI_K(a, b, c) {a, b, c, scan_persistent<a, b, c>}
-static const ScanKernelEntry kScanKernels[] = {
-    EPI_K(2, 0, 0), EPI_K(4, 0, 0), EPI_K(8, 0, 0),                   // order 2 / pair sub-table
-    EPI_K(0, 1, 0), EPI_K(0, 2, 0), EPI_K(0, 4, 0), EPI_K(0, 8, 0),   // order 3
-    EPI_K(0, 0, 2), EPI_K(0, 0, 3), EPI_K(0, 0, 4), EPI_K(0, 0, 5),   // per-combination kernel
-    EPI_K(0, 0, 6), EPI_K(0, 0, 7), EPI_K(0, 0, 8),
-    EPI_K(0, 0, kSegGk + 2), EPI_K(0, 0, kSegGk + 3), EPI_K(0, 0, kSegGk + 4),   // segmented (two-phase)
-    EPI_K(0, 0, kSegGk + 5), EPI_K(0, 0, kSegGk + 6), EPI_K(0, 0, kSegGk + 7), EPI_K(0, 0, kSegGk + 8),
-    EPI_K(0, kNpMfma, 0), EPI_K(0, kNpMfmaI8, 0),                    // order 3, matrix cores
-};
-#undef EPI_K
+ScanKernelFn find_scan_kernel_check(int np2, int np3, int gk);  // the EPI_SCAN_CHECK build of this file
 
 size_t scan_lds_bytes(int tab_cap, int kmax, int stage_cap) {
     return (((size_t)tab_cap * 4 + 15) & ~(size_t)15) + (size_t)4 * kmax * sizeof(Cand) +
@@ -2399,11 +2524,11 @@ ScanKernelFn find_scan_kernel(int np2, int np3, int gk) {
     return nullptr;
 }
 
-// grid = number of 4-wave workgroups
+// grid = number of 4-wave workgroups; check: the checking instantiation
 hipError_t launch_scan(int np2, int np3, int gk, int grid, hipStream_t st, const Task *tasks, int n_tasks,
                        unsigned long long total_items, unsigned long long *queue, const unsigned long long *binom,
-                       int bstride, int tab_cap, int kmax, int stage_cap) {
-    ScanKernelFn fn = find_scan_kernel(np2, np3, gk);
+                       int bstride, int tab_cap, int kmax, int stage_cap, bool check) {
+    ScanKernelFn fn = check ? find_scan_kernel_check(np2, np3, gk) : find_scan_kernel(np2, np3, gk);
     if (!fn) return hipErrorInvalidValue;
     const size_t lds = scan_lds_bytes(tab_cap, kmax, stage_cap);
     hipLaunchKernelGGL(fn, dim3(grid), dim3(4 * kWave), lds, st, tasks, n_tasks, total_items, queue, binom, bstride,
@@ -2480,5 +2605,7 @@ hipError_t launch_singles(hipStream_t st, const DsView &d, uint32_t *single) {
     hipLaunchKernelGGL(singles_kernel, dim3((n + 255) / 256), dim3(256), 0, st, d, single);
     return hipGetLastError();
 }
+
+#endif  // EPI_SCAN_CHECK
 
 }  // namespace epi

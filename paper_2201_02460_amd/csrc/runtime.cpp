@@ -693,12 +693,15 @@ static void pick_tab_cap(const Plan *p, LaunchGroup &g) {
 // ones take the per-combination kernel.
 static constexpr unsigned long long kMaxTripleBytes = 8ull << 30;
 bool r4_fits(const Dataset *d) { return d->qa && binom_u64(d->M, 3) <= kMaxTripleBytes / 64; }
+// Order 4 runs by reduced cells when they fit, unless the all-cell kernel is
+// pinned for the dataset's size bucket.
+bool use_r4(Ctx *c, const Dataset *d) { return r4_fits(d) && tuned_np_lookup(c, 4, d) != EPI_BLOCK_ALL_CELLS; }
 static bool needs_pairs(const PlanScan &s) {
     return s.variant != kSeg && (s.desc.order == 3 || s.variant == kR4);
 }
 
 int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool graph, Plan **out,
-               int force_np) {
+               int force_np, bool check) {
     if (n < 1) return fail(EPI_EINVAL, "empty scan list");
     std::vector<Dataset *> dss(n);
     for (int i = 0; i < n; ++i) {
@@ -708,6 +711,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
     auto p = std::make_unique<Plan>();
     p->persistent = persistent;
     p->use_graph = graph;
+    p->check = check;
     p->scans.resize(n);
     int rc = EPI_OK;
     auto cleanup = [&](int code) {
@@ -732,7 +736,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
             s.variant = kF3;
             s.np = force_np > 0 ? force_np : tuned_np(c, 3, s.ds);
         } else {
-            s.variant = o == 4 && r4_fits(s.ds) ? kR4 : kGeneric;
+            s.variant = o == 4 && use_r4(c, s.ds) ? kR4 : kGeneric;
             s.np = kGenRanksHost;
             s.n_items = (s.n_combos + 64ull * kGenRanksHost - 1) / (64ull * kGenRanksHost);
         }
@@ -873,18 +877,25 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
     }
     p->out_bytes = out_bytes;
     const int nq = (int)p->groups.size() + 2;  // pair pass, triplet pass, groups
-    p->n_queues = nq;
-    const size_t cnt_bytes = (size_t)nq * 8 + (size_t)nt * 8 + (size_t)nt * 4 + (size_t)nt * kHistWords * 4;
+    // checking plans: two digest words per scan right after the queues, so
+    // the counter reset clears them with the queues
+    const int ndig = check ? 2 * nt : 0;
+    p->n_queues = nq + ndig;
+    const size_t cnt_bytes =
+        (size_t)(nq + ndig) * 8 + (size_t)nt * 8 + (size_t)nt * 4 + (size_t)nt * kHistWords * 4;
     if ((rc = c->alloc.alloc(cnt_bytes, &p->d_counters))) return cleanup(rc);
     p->d_queues = (unsigned long long *)p->d_counters;
-    p->d_thr = p->d_queues + nq;
+    p->d_digest = check ? p->d_queues + nq : nullptr;
+    p->d_thr = p->d_queues + nq + ndig;
     p->d_cand_count = (unsigned *)(p->d_thr + nt);
     p->d_hist = p->d_cand_count + nt;
     if ((rc = c->alloc.alloc((size_t)nt * kMaxTopK * sizeof(Cand), &p->d_results))) return cleanup(rc);
     if ((rc = c->alloc.alloc((size_t)nt * kMergeParts * kMaxTopK * sizeof(Cand), &p->d_parts))) return cleanup(rc);
     if ((rc = c->alloc.alloc((size_t)nt * sizeof(ResultLayout), &p->d_layout))) return cleanup(rc);
     if ((rc = c->alloc.alloc((size_t)std::max<long long>(out_bytes, 256), &p->d_out))) return cleanup(rc);
-    if ((rc = host_buf_get(c, (size_t)std::max<long long>(out_bytes, 256), &p->h_out, &p->h_out_cap)))
+    // pinned results, then (checking plans) the digest words of every scan
+    if ((rc = host_buf_get(c, (size_t)std::max<long long>(out_bytes, 256) + (size_t)ndig * 8, &p->h_out,
+                           &p->h_out_cap)))
         return cleanup(rc);
     std::vector<ResultLayout> lay(nt);
     for (int i = 0; i < nt; ++i) lay[i] = p->scans[i].lay;
@@ -915,6 +926,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         t.np = s.np;
         t.n_blocks = 0;
         t.key_bits = key_bits_for(s.desc.order);
+        t.digest = check ? p->d_digest + 2 * i : nullptr;
     }
     {
         int e = nt;
@@ -926,6 +938,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
             Task &t = tasks[e++];
             t = tasks[i];
             t.variant = kF2Emit;
+            t.digest = nullptr;
             t.items = (const unsigned long long *)s.emit_items_d;
             t.n_items = s.emit_items;
             t.item_base = persistent ? base : 0;
@@ -947,6 +960,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
                 t.key_bits = o2.key_bits;
                 t.n_combos = o2.n_combos;
                 t.score_const = o2.score_const;
+                t.digest = o2.digest;
             }
         }
         base = 0;
@@ -957,6 +971,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
             Task &t = tasks[e++];
             t = tasks[i];
             t.variant = kF3Emit;
+            t.digest = nullptr;
             t.items = (const unsigned long long *)s.t3_items_d;
             t.n_items = s.t3_items;
             t.item_base = persistent ? base : 0;
@@ -1012,7 +1027,7 @@ static int plan_enqueue(Ctx *c, Plan *p, hipStream_t st, bool timing, unsigned l
     if (p->persistent) {
         if (p->n_emit > 0) {
             HIPCHK(launch_scan(4, 0, 0, p->emit_grid, st, tasks + nt, p->n_emit, p->emit_total, p->d_queues + q,
-                               c->d_binom, c->bstride, 0, p->emit_kmax, p->emit_stage));
+                               c->d_binom, c->bstride, 0, p->emit_kmax, p->emit_stage, p->check));
         }
         ++q;
         if (p->n_t3 > 0) {
@@ -1024,7 +1039,7 @@ static int plan_enqueue(Ctx *c, Plan *p, hipStream_t st, bool timing, unsigned l
         for (auto &g : p->groups) {
             HIPCHK(launch_scan(g.np2, g.np3, g.gk, g.grid, st, tasks + g.task_off, (int)g.scans.size(),
                                std::min(g.total_items, item_cap), p->d_queues + q, c->d_binom, c->bstride,
-                               g.tab_cap, g.kmax, g.stage_cap));
+                               g.tab_cap, g.kmax, g.stage_cap, p->check));
             ++q;
         }
         if (timing && single) HIPCHK(hipEventRecord(p->ev[3], st));
@@ -1054,7 +1069,7 @@ static int plan_enqueue(Ctx *c, Plan *p, hipStream_t st, bool timing, unsigned l
             }
             if (timing && single) HIPCHK(hipEventRecord(p->ev[2], st));
             HIPCHK(launch_scan(g.np2, g.np3, g.gk, g.grid, st, tasks + i, 1, std::min(s.n_items, item_cap),
-                               p->d_queues + 1, c->d_binom, c->bstride, g.tab_cap, g.kmax, g.stage_cap));
+                               p->d_queues + 1, c->d_binom, c->bstride, g.tab_cap, g.kmax, g.stage_cap, p->check));
             HIPCHK(launch_init_counters(st, p->d_queues + 1, 1, nullptr, nullptr, 0, nullptr));
             if (timing && single) HIPCHK(hipEventRecord(p->ev[3], st));
             HIPCHK(launch_merge(1, st, tasks + i, (Cand *)p->d_parts + (size_t)i * kMergeParts * kMaxTopK,
@@ -1064,6 +1079,9 @@ static int plan_enqueue(Ctx *c, Plan *p, hipStream_t st, bool timing, unsigned l
         }
     }
     HIPCHK(hipMemcpyAsync(p->h_out, p->d_out, (size_t)std::max<long long>(p->out_bytes, 256), hipMemcpyDeviceToHost, st));
+    if (p->check)
+        HIPCHK(hipMemcpyAsync((char *)p->h_out + std::max<long long>(p->out_bytes, 256), p->d_digest,
+                              (size_t)nt * 16, hipMemcpyDeviceToHost, st));
     return EPI_OK;
 }
 
@@ -1397,6 +1415,38 @@ int epi_scan(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t top_k, voi
     return plan_run(C, p, (hipStream_t)stream, ~0ull);
 }
 
+int epi_scan_check(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t top_k, void *stream, int32_t *scan_id) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    if (!scan_id) return fail(EPI_EINVAL, "null scan_id");
+    epi_scan_desc d{dataset_id, order, top_k, 0};
+    Plan *p = nullptr;
+    int rc = plan_build(C, &d, 1, false, false, &p, 0, true);
+    if (rc) return rc;
+    register_plan(C, p, scan_id);
+    p->transient = true;
+    return plan_run(C, p, (hipStream_t)stream, ~0ull);
+}
+
+int epi_scan_digest(epi_ctx *ctx, int32_t scan_id, uint64_t *n_scored, uint64_t *digest) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    int idx;
+    Plan *p = plan_of_scan(C, scan_id, &idx);
+    if (!p) return fail(EPI_ENOTFOUND, "unknown scan %d", scan_id);
+    if (!p->check) return fail(EPI_EINVAL, "scan %d was not started by epi_scan_check", scan_id);
+    if (!n_scored || !digest) return fail(EPI_EINVAL, "null output");
+    if (!p->ran) return fail(EPI_ENOTREADY, "scan has not run");
+    hipError_t q = hipEventQuery(p->ev[4]);
+    if (q == hipErrorNotReady) return fail(EPI_ENOTREADY, "scan not finished");
+    if (q != hipSuccess) return fail(EPI_EDEVICE, "scan failed: %s", hipGetErrorString(q));
+    const unsigned long long *w =
+        (const unsigned long long *)((const char *)p->h_out + std::max<long long>(p->out_bytes, 256)) + 2 * idx;
+    *n_scored = w[0];
+    *digest = w[1];
+    return EPI_OK;
+}
+
 int epi_scan_batch(epi_ctx *ctx, const epi_scan_desc *descs, int32_t n, void *stream, int32_t *scan_ids) {
     clear_error();
     CTX_OR_FAIL(ctx);
@@ -1601,7 +1651,9 @@ int epi_set_prefix_block(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_
     const bool ok3 = order == 3 && (block == 1 || block == 2 || block == 4 || block == 8 || block == kNpMfma ||
                                     block == kNpMfmaI8);
     const bool any = order >= EPI_MIN_ORDER && order <= EPI_MAX_ORDER && (block == 0 || block == EPI_BLOCK_SEGMENTED);
-    if (!ok2 && !ok3 && !any) return fail(EPI_EINVAL, "prefix block %d is not a kernel of order %d", block, order);
+    const bool all4 = order >= 4 && order <= EPI_MAX_ORDER && block == EPI_BLOCK_ALL_CELLS;
+    if (!ok2 && !ok3 && !any && !all4)
+        return fail(EPI_EINVAL, "prefix block %d is not a kernel of order %d", block, order);
     if (block == kNpMfma && !d->qa)
         return fail(EPI_EUNSUPPORTED, "dataset %d has no matrix-core operands (2^22 individuals or more)", dataset_id);
     if (block == kNpMfmaI8) {

@@ -93,6 +93,7 @@ struct LaunchGroup {
 struct Plan {
     int id = 0;
     bool persistent = false, use_graph = false, transient = false, ran = false, timed = false;
+    bool check = false;  // checking launch: the main passes also count and digest every combination
     int live_scans = 0;
     std::vector<PlanScan> scans;
     std::vector<LaunchGroup> groups;
@@ -109,6 +110,7 @@ struct Plan {
     void *h_stage = nullptr;              // pinned copies of the layout and task arrays, uploaded by every run
     size_t h_stage_cap = 0, stage_layout_bytes = 0, stage_tasks_bytes = 0;
     unsigned long long *d_queues = nullptr, *d_thr = nullptr;
+    unsigned long long *d_digest = nullptr;  // check: 2 words per scan, zeroed with the queues
     unsigned *d_cand_count = nullptr;
     unsigned *d_hist = nullptr;  // kHistWords per scan
     long long out_bytes = 0;
@@ -165,7 +167,7 @@ struct Ctx {
 // kernel launchers (kernels.hip)
 hipError_t launch_scan(int np2, int np3, int gk, int grid, hipStream_t st, const Task *tasks, int n_tasks,
                        unsigned long long total_items, unsigned long long *queue, const unsigned long long *binom,
-                       int bstride, int tab_cap, int kmax, int stage_cap);
+                       int bstride, int tab_cap, int kmax, int stage_cap, bool check = false);
 size_t scan_lds_bytes(int tab_cap, int kmax, int stage_cap);
 hipError_t scan_attributes(int np2, int np3, int gk, int *vgprs, int *lds_bytes);
 hipError_t launch_merge(int n_tasks, hipStream_t st, const Task *tasks, Cand *parts, Cand *results);
@@ -204,7 +206,9 @@ int group_tab_cap(int np2, int np3, int gk, int cap_both, int cap_first, int kma
 Ctx *as_ctx(epi_ctx *c);
 int key_bits_for(int order);
 void load_tune_cache(Ctx *c);
-int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool graph, Plan **out, int force_np);
+int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool graph, Plan **out, int force_np,
+               bool check = false);
+bool use_r4(Ctx *c, const Dataset *d);
 int plan_run(Ctx *c, Plan *p, hipStream_t st, unsigned long long item_cap);
 int plan_wait(Plan *p);
 int plan_results(Plan *p, int index, int capacity, int32_t *combos, float *scores, uint32_t *tables,

@@ -129,7 +129,7 @@ static int admit(Server *S, Request *r) {
         r->variant = kF3;
         r->np = default_np3(c, r->ds);
     } else {
-        r->variant = o == 4 && r4_fits(r->ds) ? kR4 : kGeneric;
+        r->variant = o == 4 && use_r4(c, r->ds) ? kR4 : kGeneric;
         r->np = kGenRanksHost;
         r->n_items = (r->n_combos + 64ull * kGenRanksHost - 1) / (64ull * kGenRanksHost);
     }

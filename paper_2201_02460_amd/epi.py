@@ -30,6 +30,7 @@ EPI_SERVE_MAX_ORDER = 5
 EPI_BLOCK_MFMA_FP4 = 16
 EPI_BLOCK_MFMA_I8 = 32
 EPI_BLOCK_SEGMENTED = 64
+EPI_BLOCK_ALL_CELLS = 81
 EPI_MAX_TOP_K = 256
 
 # Every function the header declares, with (restype, argtypes).
@@ -66,6 +67,8 @@ SIGNATURES = {
     "epi_scan_timing": (_c.c_int, [_vp, _i32, _P(_c.c_float)]),
     "epi_scan_info": (_c.c_int, [_vp, _i32, _P(_u64), _P(_i32), _P(_i32)]),
     "epi_release": (_c.c_int, [_vp, _i32]),
+    "epi_scan_check": (_c.c_int, [_vp, _i32, _i32, _i32, _vp, _P(_i32)]),
+    "epi_scan_digest": (_c.c_int, [_vp, _i32, _P(_u64), _P(_u64)]),
     "epi_batch_create": (_c.c_int, [_vp, _P(ScanDesc), _i32, _i32, _i32, _P(_i32)]),
     "epi_batch_run": (_c.c_int, [_vp, _i32, _vp]),
     "epi_batch_wait": (_c.c_int, [_vp, _i32]),
@@ -306,6 +309,19 @@ def epi_scan_info(ctx, scan_id):
 
 def epi_release(ctx, scan_id):
     _check(lib().epi_release(ctx, scan_id))
+
+
+def epi_scan_check(ctx, dataset_id, order, top_k, stream=None):
+    out = _i32()
+    _check(lib().epi_scan_check(ctx, dataset_id, order, top_k, _stream(stream), ctypes.byref(out)))
+    return out.value
+
+
+def epi_scan_digest(ctx, scan_id):
+    """(combinations scored, digest) of a finished scan from epi_scan_check."""
+    n, d = _u64(), _u64()
+    _check(lib().epi_scan_digest(ctx, scan_id, ctypes.byref(n), ctypes.byref(d)))
+    return n.value, d.value
 
 
 def epi_batch_create(ctx, descs, persistent=True, use_graph=True):

@@ -13,4 +13,5 @@ from .genotypes import (  # noqa: F401
     planted_penetrance,
     random_genotypes,
     served_pool_specs,
+    served_requests,
 )

@@ -37,6 +37,7 @@ __all__ = [
     "make_workload",
     "batched_specs",
     "served_pool_specs",
+    "served_requests",
 ]
 
 
@@ -205,3 +206,17 @@ def served_pool_specs(n=32, seed_base=2000, m_range=(50, 1500), n_range=(500, 16
         planted = tuple(int(v) for v in sorted(rng.choice(M, 3, replace=False)))
         out.append(dict(M=M, N=N, n_cases=n_cases, planted=planted, seed=seed + 10**6, orders=orders))
     return out
+
+
+def served_requests(pool, n, seed=7, rate=20.0):
+    """Request stream of the serving workload: each request picks a dataset of
+    the pool uniformly and one of the orders that dataset accepts; arrival
+    gaps are exponential with mean 1 / rate (Poisson arrivals).  Returns
+    ([(dataset index, order)] * n, gaps in seconds)."""
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for _ in range(n):
+        d = int(rng.integers(len(pool)))
+        reqs.append((d, int(rng.choice(pool[d]["orders"]))))
+    gaps = rng.exponential(1.0 / rate, n)
+    return reqs, gaps

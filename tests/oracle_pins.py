@@ -301,6 +301,56 @@ def pin_score_list(o, seed=21):
         assert np.array_equal(tables[2], tables[-1]) and scores[2] == scores[-1]
 
 
+_MASK64 = (1 << 64) - 1
+
+
+def _splitmix_out(z):
+    """SplitMix64's output function (Steele, Lea and Flood, 2014), in Python
+    integers reduced modulo 2^64."""
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+    return z ^ (z >> 31)
+
+
+def brute_digest(G, y, k):
+    """(count, digest) of all k-combinations, written out from the definition:
+    h folds the indices, s weighs the table's counts (numpy bincount), the
+    contribution is mix(h ^ s), summed modulo 2^64."""
+    count, total = 0, 0
+    for combo in itertools.combinations(range(G.shape[0]), k):
+        h = 0
+        for c in combo:
+            h = _splitmix_out((h + c + 1) & _MASK64)
+        tab = bincount_table(G, y, combo)
+        s = 0
+        for cls in (0, 1):
+            for x in range(3**k):
+                s = (s + int(tab[cls, x]) * _splitmix_out(2 * x + cls + 1)) & _MASK64
+        total = (total + _splitmix_out(h ^ s)) & _MASK64
+        count += 1
+    return count, total
+
+
+def pin_digest(o, seed=22):
+    """The completeness digest against its definition written out in Python
+    (count = C(M,k)), over rank splits that must add up, for every order."""
+    for M, N, k, frac in ((9, 50, 2, 0.5), (8, 67, 3, 0.3), (7, 40, 4, 0.6), (7, 33, 5, 0.45), (9, 20, 8, 0.5)):
+        G, y = random_genotypes(M, N, seed=seed + M + k, case_fraction=frac)
+        want = brute_digest(G, y, k)
+        assert want[0] == math.comb(M, k)
+        assert o.digest(G, y, k, nthreads=3) == want, (M, N, k)
+        n = math.comb(M, k)
+        parts = [o.digest(G, y, k, b, e, nthreads=2) for b, e in ((0, n // 3), (n // 3, n - 1), (n - 1, n))]
+        assert sum(p[0] for p in parts) == want[0]
+        assert sum(p[1] for p in parts) & _MASK64 == want[1]
+    # one count moved between the classes changes the digest
+    G, y = random_genotypes(6, 30, seed=seed, case_fraction=0.5)
+    y2 = y.copy()
+    y2[np.nonzero(y)[0][0]] = 0
+    y2[np.nonzero(y == 0)[0][0]] = 1
+    assert o.digest(G, y, 3) != o.digest(G, y2, 3)
+
+
 def _row_bits(word_list, n):
     """First n bits of a row (bit b of word w = individual 32 w + b) as a 0/1 string."""
     return "".join(str((int(word_list[b // 32]) >> (b % 32)) & 1) for b in range(n))
@@ -369,6 +419,7 @@ ALL_PINS = [
     pin_planted_recovery,
     pin_rank_ranges,
     pin_score_list,
+    pin_digest,
 ]
 
 

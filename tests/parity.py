@@ -5,10 +5,13 @@ The bar (per returned combination and per result set):
 * every returned float32 score is within 1e-5 relative of the oracle's
   float64 MI of that combination (an absolute 1e-9 only where the oracle's
   MI is zero up to its own float64 rounding, |MI| <= 1e-12);
-* the returned float32 scores never increase, and where two of them are
-  equal the lexicographically smaller combination comes first, unless the
-  oracle ranks the earlier one strictly higher (two different MI values that
-  round to the same float32);
+* the returned float32 scores never increase; where two of them are equal
+  and the later combination is lexicographically smaller, the two tables
+  must not hold the same multiset of cells (then their exact fixed-point
+  scores are equal and the tie goes to the smaller combination), and the
+  oracle must not rank the later one higher by more than 1e-9 relative (two
+  different MI values that round to the same float32, or equal MI values
+  whose fixed-point sums differ in the last units);
 * the returned set equals the oracle's best-K set, except that a member may
   be swapped with a non-member whose oracle score is within 1e-5 relative of
   the oracle's K-th score (a tie inside the tolerance).
@@ -41,16 +44,29 @@ def check_scores_tables(orc, G, y, combos, scores, tables):
     return o_scores
 
 
-def check_order(combos, scores, o_scores):
-    """Best first: float32 scores never increase; equal float32 scores list
-    the lexicographically smaller combination first, unless the oracle ranks
-    the earlier one strictly higher."""
+def cell_terms(table):
+    """The multiset of a table's mixed cells (both classes present) as
+    unordered (n_case, n_control) pairs.  The score is a sum of one term per
+    cell, symmetric in the two counts and exactly zero for a cell with an
+    empty class, so tables with the same multiset have the same score in any
+    arithmetic."""
+    t = np.asarray(table, np.int64).reshape(2, -1)
+    lo, hi = np.minimum(t[0], t[1]), np.maximum(t[0], t[1])
+    keep = lo > 0
+    return sorted(zip(lo[keep].tolist(), hi[keep].tolist()))
+
+
+def check_order(combos, scores, o_scores, tables):
+    """Best first (see the module docstring)."""
     got = [tuple(int(v) for v in c) for c in combos]
     s = np.asarray(scores, np.float32)
     for r in range(1, len(got)):
         assert s[r] <= s[r - 1], f"rank {r}: score {s[r]} above the previous {s[r - 1]}"
         if s[r] == s[r - 1] and got[r] < got[r - 1]:
-            assert o_scores[r - 1] > o_scores[r], f"rank {r}: equal scores not in lexicographic order"
+            assert cell_terms(tables[r]) != cell_terms(tables[r - 1]), \
+                f"rank {r}: exact tie {got[r - 1]}, {got[r]} not in lexicographic order"
+            assert o_scores[r] - o_scores[r - 1] <= 1e-9 * abs(o_scores[r]), \
+                f"rank {r}: equal scores, the later combination is better by the oracle"
 
 
 def check_topk(orc, G, y, order, top_k, combos, scores, tables, ref=None):
@@ -69,7 +85,7 @@ def check_topk(orc, G, y, order, top_k, combos, scores, tables, ref=None):
         assert all(c[t] < c[t + 1] for t in range(order - 1)), f"indices not ascending: {c}"
     got = [tuple(int(v) for v in c) for c in combos]
     assert len(set(got)) == len(got), "duplicate combinations returned"
-    check_order(combos, scores, o_scores)
+    check_order(combos, scores, o_scores, tables)
     kth = ref_scores[-1]
     tol = REL_TOL * max(abs(kth), 1e-30) + 1e-12
     for c in set(got) ^ set(ref_combos):

@@ -44,6 +44,13 @@ MUTANTS = {
     "score_list_combo_offset": ("combos + (int64_t)i * k, k, t)", "combos + (int64_t)i, k, t)"),
     # score list: every score written to the first slot
     "score_list_score_index": ("out_scores[i] = oracle_mi(t, k);", "out_scores[0] = oracle_mi(t, k);"),
+    # digest: indices folded without their offset
+    "digest_index_fold": ("h = splitmix_out(h + (uint64_t)c[t] + 1);", "h = splitmix_out(h + (uint64_t)c[t]);"),
+    # digest: cell weights indexed by the cell alone (classes share weights)
+    "digest_cell_weight": ("splitmix_out(2 * (uint64_t)x + (uint64_t)cls + 1)", "splitmix_out((uint64_t)x + 1)"),
+    # digest: the last combination of every thread's range left out
+    "digest_drop_last": ("j->sum += digest_term(c, j->k, j->table);",
+                         "if (r + 1 < j->end) j->sum += digest_term(c, j->k, j->table);"),
 }
 
 CHILD = r"""
