@@ -227,6 +227,38 @@ int epi_scan_check(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t top_
  * (a scan not started by epi_scan_check, null output). */
 int epi_scan_digest(epi_ctx *ctx, int32_t scan_id, uint64_t *n_scored, uint64_t *digest);
 
+/* ---- allocation-free scan ------------------------------------------------ */
+
+/* Bytes of the scratch array that every device holds for epi_scan_noalloc,
+ * from the library's load until the process ends (128 MiB). */
+#define EPI_NOALLOC_SCRATCH_BYTES 134217728
+
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  The same
+ * scan as epi_scan (same combinations, scores and tables), enqueued on
+ * `stream` (NULL: the context's) without allocating anything: no hipMalloc,
+ * hipFree, pinned host memory or events.  Every intermediate buffer (work
+ * queues, candidate lists, pair and triplet sub-tables, descriptor tables the
+ * context has not cached yet, the result block) is carved from the device's
+ * scratch array of EPI_NOALLOC_SCRATCH_BYTES.  Outputs are caller-owned
+ * device buffers, written when the stream reaches the scan's end:
+ *   d_combos: top_k * order int32, d_scores: top_k float,
+ *   d_tables: nullable, top_k * 2 * 3^order uint32 (layout of epi_results),
+ *   d_n: one int32, the number of results (min(top_k, C(M, order))), or -1
+ *        when the dataset's last packing had invalid input.
+ * The call returns once the work is enqueued; synchronise the stream before
+ * reading the outputs.  Every call on a device shares that device's array and
+ * it keeps the last call's contents (each call clears what must start at
+ * zero), so calls that overlap on one device race: serialise them (one
+ * stream, or a wait between them).  Served-style kernel choice: the fused
+ * kernels (segmented pins are ignored), and order 4 by reduced cells only
+ * when its sub-tables fit in half the array (else all cells; same results).
+ * Errors: as epi_scan, and EUNSUPPORTED when the scan's buffers exceed the
+ * array (the pair sub-table alone takes 32 C(M, 2) bytes at orders 3-4; order
+ * 3 at M = 1000 takes about 25 MB in all). */
+int epi_scan_noalloc(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t top_k, void *stream,
+                     int32_t *d_combos, float *d_scores, uint32_t *d_tables, int32_t *d_n);
+
 /* ---- re-runnable batches ------------------------------------------------- */
 
 /* Build a batch of n scans once: work queue, per-scan buffers and (if

@@ -120,6 +120,75 @@ struct Task {
                                       //   (null: no check)
 };
 
+// Work-item descriptor tables, one item per entry, in groups of consecutive
+// items (the layouts the kernels decode, see Task::items):
+//   kItemsF2   order 2, prefix block np: group ib (block of np first SNPs),
+//              items ib << 20 | mb for the ceil(max(0, M - 1 - ib np) / 64)
+//              blocks mb of 64 last SNPs;
+//   kItemsF3   order 3 by popcount, prefix block np: group j = 1 .. M - 2,
+//              items j << 40 | ib << 20 | mb for ib < ceil(j / np) (outer)
+//              and mb < ceil((M - 1 - j) / 64) (inner);
+//   kItemsF3M  order 3 by matrix cores: group (block ib of 16 first SNPs,
+//              block mb of 32 last SNPs), items j << 40 | ib << 20 | mb for
+//              every j with some i < j < m in the blocks, j fastest.  The
+//              groups go in tiles of 4 x 4 blocks (tile rows of mb outer,
+//              then tiles of ib; mb outer, ib inner within a tile), so the
+//              items in flight across the device share a few operand blocks.
+// The host counts a table's items with these functions and the device
+// writes them (items_kernel), group after group.
+enum ItemKind : int32_t { kItemsF2 = 0, kItemsF3 = 1, kItemsF3M = 2 };
+constexpr int kItemTile = 4;
+constexpr int kStoreChunkBytes = 1024;  // bytes per store_kernel launch
+
+struct ItemGroup {
+    unsigned long long base;  // descriptor of the group's first item
+    unsigned long long step;  // added per item (kItemsF3: per item of the inner run)
+    unsigned long long count; // items in the group
+    unsigned long long inner; // kItemsF3: items per ib (0: one run)
+};
+
+__host__ __device__ inline long long item_groups(int kind, int M, int np) {
+    if (kind == kItemsF2) return M >= 2 ? (M - 1 + np - 1) / np : 0;
+    if (kind == kItemsF3) return M >= 3 ? M - 2 : 0;
+    return (long long)((M + 31) / 32) * ((M + 15) / 16);
+}
+
+__host__ __device__ inline ItemGroup item_group(int kind, int M, int np, long long g) {
+    ItemGroup r{0, 1, 0, 0};
+    if (kind == kItemsF2) {
+        const long long ib = g, nm = M - 1 - ib * np;
+        r.base = (unsigned long long)ib << 20;
+        r.count = nm > 0 ? (unsigned long long)((nm + 63) / 64) : 0;
+        return r;
+    }
+    if (kind == kItemsF3) {
+        const long long j = g + 1, ni = (j + np - 1) / np, nm = (M - 1 - j + 63) / 64;
+        r.base = (unsigned long long)j << 40;
+        r.inner = (unsigned long long)nm;
+        r.count = (unsigned long long)(ni * nm);
+        return r;
+    }
+    const long long nmb = (M + 31) / 32, nib = (M + 15) / 16, T = kItemTile;
+    const long long mt = g / (T * nib), rr = g - mt * T * nib;
+    const long long mbs = nmb - mt * T < T ? nmb - mt * T : T;
+    const long long it = rr / (mbs * T), q = rr - it * mbs * T;
+    const long long ibs = nib - it * T < T ? nib - it * T : T;
+    const long long mb = mt * T + q / ibs, ib = it * T + q % ibs;
+    long long j0 = ib * 16 + 1, j1 = (mb * 32 + 31 < M - 1 ? mb * 32 + 31 : M - 1) - 1;
+    j0 = j0 > 1 ? j0 : 1;
+    j1 = j1 < M - 2 ? j1 : M - 2;
+    r.base = ((unsigned long long)j0 << 40) | ((unsigned long long)ib << 20) | (unsigned long long)mb;
+    r.step = 1ull << 40;
+    r.count = j1 >= j0 ? (unsigned long long)(j1 - j0 + 1) : 0;
+    return r;
+}
+
+// Descriptor of item t of a group.
+__host__ __device__ inline unsigned long long item_at(const ItemGroup &gr, unsigned long long t) {
+    if (gr.inner) return gr.base + ((t / gr.inner) << 20) + t % gr.inner;
+    return gr.base + t * gr.step;
+}
+
 // Completeness check of a scan (every combination exactly once, each with
 // its table).  mix64 is the output function of SplitMix64 (Steele, Lea and
 // Flood, "Fast splittable pseudorandom number generators", 2014).  A

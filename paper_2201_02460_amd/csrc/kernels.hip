@@ -34,6 +34,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cstring>
 #include <type_traits>
 
 #include "epi_internal.hpp"
@@ -2494,6 +2495,68 @@ __global__ void reseed_kernel(const Task *__restrict__ tasks, const Cand *__rest
     if (threadIdx.x == 0) *t.cand_count = (unsigned)n;
 }
 
+// Work-item descriptor table of one shape (kinds and layouts in
+// epi_internal.hpp), written by one workgroup: the groups go 1024 at a time,
+// a scan of their sizes gives each its offset, and each thread writes the
+// items of its group.  out holds exactly the sum of the group sizes, which
+// the host counts with the same functions.
+__global__ void __launch_bounds__(1024) items_kernel(int kind, int M, int np, unsigned long long *__restrict__ out) {
+    __shared__ unsigned long long s_scan[1024];
+    __shared__ unsigned long long s_base;
+    const long long G = item_groups(kind, M, np);
+    if (threadIdx.x == 0) s_base = 0;
+    __syncthreads();
+    for (long long g0 = 0; g0 < G; g0 += 1024) {
+        const long long g = g0 + threadIdx.x;
+        ItemGroup gr{0, 1, 0, 0};
+        if (g < G) gr = item_group(kind, M, np, g);
+        s_scan[threadIdx.x] = gr.count;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const unsigned long long v = (int)threadIdx.x >= off ? s_scan[threadIdx.x - off] : 0ull;
+            __syncthreads();
+            s_scan[threadIdx.x] += v;
+            __syncthreads();
+        }
+        const unsigned long long start = s_base + s_scan[threadIdx.x] - gr.count;
+        for (unsigned long long t = 0; t < gr.count; ++t) out[start + t] = item_at(gr, t);
+        __syncthreads();
+        if (threadIdx.x == 1023) s_base += s_scan[1023];
+        __syncthreads();
+    }
+}
+
+// Bytes carried to device memory in a kernel's arguments (the task array of
+// a launch sequence that may not copy from host memory).
+struct StoreChunk {
+    unsigned char b[kStoreChunkBytes];
+};
+
+__global__ void store_kernel(StoreChunk payload, int n, unsigned char *__restrict__ dst) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = payload.b[i];
+}
+
+// A result block (layout in epi_internal.hpp) copied to separate buffers of
+// the caller: combinations, scores and (tables non-null) tables of the
+// n_valid results; *n receives n_valid, or -1 when the dataset's last packing
+// had invalid input.
+__global__ void scatter_kernel(const char *__restrict__ block, int top_k, int order, int32_t *__restrict__ combos,
+                               float *__restrict__ scores, uint32_t *__restrict__ tables, int32_t *__restrict__ n) {
+    const int32_t *hdr = (const int32_t *)block;
+    const long long nv = hdr[0];
+    const long long nc = nv * order, ns = nv, nt = tables ? nv * 2 * pow3c(order) : 0;
+    const int32_t *src_c = (const int32_t *)(block + 16);
+    const float *src_s = (const float *)(block + 16 + (long long)top_k * order * 4);
+    const uint32_t *src_t = (const uint32_t *)(block + 16 + (long long)top_k * order * 4 + (long long)top_k * 4);
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nc + ns + nt;
+         i += (long long)gridDim.x * blockDim.x) {
+        if (i < nc) combos[i] = src_c[i];
+        else if (i < nc + ns) scores[i - nc] = src_s[i - nc];
+        else tables[i - nc - ns] = src_t[i - nc - ns];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *n = hdr[1] ? -1 : (int32_t)nv;
+}
+
 // Counters of a launch sequence: queues, candidate counts, thresholds.
 __global__ void init_counters_kernel(unsigned long long *queues, int nq, unsigned *cand_counts,
                                      unsigned long long *thrs, int n_tasks, unsigned *hist) {
@@ -2568,6 +2631,31 @@ hipError_t launch_init_counters(hipStream_t st, unsigned long long *queues, int 
     if (hist && (long long)n_tasks * kHistWords > n) n = (long long)n_tasks * kHistWords;
     hipLaunchKernelGGL(init_counters_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, queues, nq,
                        cand_counts, thrs, n_tasks, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_items(hipStream_t st, int kind, int M, int np, unsigned long long *out) {
+    hipLaunchKernelGGL(items_kernel, dim3(1), dim3(1024), 0, st, kind, M, np, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_store(hipStream_t st, const void *src, size_t bytes, void *dst) {
+    for (size_t off = 0; off < bytes; off += kStoreChunkBytes) {
+        StoreChunk c;
+        const size_t n = bytes - off < (size_t)kStoreChunkBytes ? bytes - off : (size_t)kStoreChunkBytes;
+        memcpy(c.b, (const char *)src + off, n);
+        hipLaunchKernelGGL(store_kernel, dim3(1), dim3(256), 0, st, c, (int)n, (unsigned char *)dst + off);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_scatter(hipStream_t st, const char *block, int top_k, int order, int32_t *combos, float *scores,
+                          uint32_t *tables, int32_t *n) {
+    const long long items = (long long)top_k * (order + 1 + (tables ? 2 * pow3i(order) : 0));
+    const int grid = (int)((items + 255) / 256 + 1 < 1024 ? (items + 255) / 256 + 1 : 1024);
+    hipLaunchKernelGGL(scatter_kernel, dim3(grid), dim3(256), 0, st, block, top_k, order, combos, scores, tables, n);
     return hipGetLastError();
 }
 

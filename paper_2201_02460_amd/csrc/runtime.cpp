@@ -139,6 +139,35 @@ uint64_t binom_u64(int64_t n, int64_t k) {
 int key_bits_for(int order) { return 64 / order; }
 
 // ---------------------------------------------------------------------------
+// Scratch of the allocation-free scan (epi_scan_noalloc): a fixed array in
+// every device's memory, held from the library's load until the process
+// ends.  In host code `scratch` names a host-side stand-in, not the device
+// array: its device address is taken once per device, at the first context
+// created on that device, and only that address is used.  Every
+// allocation-free scan on a device uses the whole array, so such calls must
+// not overlap on one device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::map<int, char *> g_scratch_ptr;  // device -> address of its scratch array
+
+// The device's scratch address (the device must be current).
+static int scratch_of(int device, char **out) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it == g_scratch_ptr.end()) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(EPI_EDEVICE, "scratch array of device %d: %s", device, hipGetErrorString(e));
+        it = g_scratch_ptr.emplace(device, (char *)ptr).first;
+    }
+    *out = it->second;
+    return EPI_OK;
+}
+
+// ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
 Ctx *as_ctx(epi_ctx *c) { return reinterpret_cast<Ctx *>(c); }
@@ -158,6 +187,7 @@ int ctx_init(Ctx *c, int device, uint64_t budget) {
     HIPCHK(hipMemGetInfo(&fr, &tot));
     c->alloc.budget = budget ? budget : (uint64_t)(0.9 * (double)fr);
     HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    if (int rc = scratch_of(device, &c->scratch)) return rc;
     // binomial table for colex unranking: rows t = 0..kMaxBinomOrder, n = 0..kBinomN-1
     c->bstride = kBinomN;
     std::vector<unsigned long long> h((size_t)(kMaxBinomOrder + 1) * kBinomN);
@@ -395,48 +425,19 @@ static int tuned_np(Ctx *c, int order, const Dataset *d) {
     return order == 2 ? 4 : kGenRanksHost;
 }
 
-// Work items of the order-2 kernels: (i-block ib of np SNPs, block mb of 64
-// SNPs m > i0), descriptor ib << 20 | mb.
-static void build_f2_items(int M, int np, std::vector<unsigned long long> &out) {
-    out.clear();
-    const int nib = std::max(0, (M - 1 + np - 1) / np);
-    for (int ib = 0; ib < nib; ++ib) {
-        const int nm = std::max(0, M - 1 - ib * np);
-        for (int mb = 0; mb < (nm + 63) / 64; ++mb) out.push_back(((unsigned long long)ib << 20) | (unsigned)mb);
-    }
+// Work items of the order-2 and order-3 kernels: kinds, groups and item
+// layouts in epi_internal.hpp (item_group); the device writes the tables
+// (items_kernel) and the host only counts their items.
+static int item_kind(int variant, int np) {
+    if (variant != kF3) return kItemsF2;
+    return np == kNpMfma || np == kNpMfmaI8 ? kItemsF3M : kItemsF3;
 }
 
-// Work items of the order-3 kernel: (j, block ib of np SNPs i < j, block mb
-// of 64 SNPs m > j), descriptor j << 40 | ib << 20 | mb.
-//
-// Matrix-core blocks (np = kNpMfma, kNpMfmaI8): (16-SNP block ib of i, 32-SNP
-// block mb of m, j) for every j with some i < j < m in the blocks.  j runs
-// fastest, so neighbouring items read the same i and m operand blocks, and
-// the (ib, mb) blocks go in tiles of 4 x 4, so the items in flight across the
-// device share a few operand blocks in L2.
-static void build_f3_items(int M, int np, std::vector<unsigned long long> &out) {
-    out.clear();
-    if (np == kNpMfma || np == kNpMfmaI8) {
-        const int T = 4;
-        for (int mt = 0; mt * 32 * T < M; ++mt)
-            for (int it = 0; it * 16 * T < M; ++it)
-                for (int mb = mt * T; mb < mt * T + T && mb * 32 < M; ++mb)
-                    for (int ib = it * T; ib < it * T + T && ib * 16 < M; ++ib) {
-                        const int j0 = std::max(1, ib * 16 + 1);
-                        const int j1 = std::min(std::min(mb * 32 + 31, M - 1) - 1, M - 2);
-                        for (int j = j0; j <= j1; ++j)
-                            out.push_back(((unsigned long long)j << 40) | ((unsigned long long)ib << 20) |
-                                          (unsigned)mb);
-                    }
-        return;
-    }
-    for (int j = 1; j <= M - 2; ++j) {
-        const int ni = (j + np - 1) / np;
-        const int nm = (M - 1 - j + 63) / 64;
-        for (int ib = 0; ib < ni; ++ib)
-            for (int mb = 0; mb < nm; ++mb)
-                out.push_back(((unsigned long long)j << 40) | ((unsigned long long)ib << 20) | (unsigned)mb);
-    }
+static unsigned long long item_count(int kind, int M, int np) {
+    unsigned long long n = 0;
+    const long long G = item_groups(kind, M, np);
+    for (long long g = 0; g < G; ++g) n += item_group(kind, M, np, g).count;
+    return n;
 }
 
 // Descriptor table of a shape, built once per context and cached.
@@ -445,18 +446,60 @@ int get_items(Ctx *c, int variant, int M, int np, const void **d, unsigned long 
     const auto key = std::make_tuple(variant, M, np);
     auto it = c->item_tables.find(key);
     if (it == c->item_tables.end()) {
-        std::vector<unsigned long long> h;
-        if (variant == kF3) build_f3_items(M, np, h);
-        else build_f2_items(M, np, h);
+        const int kind = item_kind(variant, np);
         ItemTable t;
-        t.n = h.size();
-        int rc = c->alloc.alloc(std::max<size_t>(h.size(), 1) * 8, &t.d);
+        t.n = item_count(kind, M, np);
+        int rc = c->alloc.alloc(std::max<unsigned long long>(t.n, 1) * 8, &t.d);
         if (rc) return rc;
-        if (!h.empty()) HIPCHK(hipMemcpy(t.d, h.data(), h.size() * 8, hipMemcpyHostToDevice));
+        if (t.n) {
+            hipError_t e = launch_items(c->stream, kind, M, np, (unsigned long long *)t.d);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) {
+                c->alloc.release(t.d);
+                return fail(EPI_EDEVICE, "descriptor table: %s", hipGetErrorString(e));
+            }
+        }
         it = c->item_tables.emplace(key, t).first;
     }
     *d = it->second.d;
     *n = it->second.n;
+    return EPI_OK;
+}
+
+// Device buffer of a plan: from the context's allocator, or (allocation-free
+// plans) the next 256-byte-aligned piece of the scratch array.
+static int plan_alloc(Ctx *c, Plan *p, size_t bytes, void **out) {
+    if (!p->arena) return c->alloc.alloc(bytes, out);
+    const size_t at = (p->arena_used + 255) & ~(size_t)255;
+    if (at + bytes > p->arena_cap)
+        return fail(EPI_EUNSUPPORTED, "the allocation-free scan needs more than its %zu-byte scratch array",
+                    p->arena_cap);
+    *out = p->arena + at;
+    p->arena_used = at + bytes;
+    return EPI_OK;
+}
+
+// Descriptor table of a shape for a plan: the context's cached table, else
+// (allocation-free plans) one built into the plan's scratch and uploaded by
+// its run, else a new cached table.
+static int plan_items(Ctx *c, Plan *p, int variant, int M, int np, const void **d, unsigned long long *n) {
+    if (p->arena) {
+        std::lock_guard<std::mutex> g(c->items_mu);
+        auto it = c->item_tables.find(std::make_tuple(variant, M, np));
+        if (it != c->item_tables.end()) {
+            *d = it->second.d;
+            *n = it->second.n;
+            return EPI_OK;
+        }
+    }
+    if (!p->arena) return get_items(c, variant, M, np, d, n);
+    const int kind = item_kind(variant, np);
+    const unsigned long long cnt = item_count(kind, M, np);
+    void *dev = nullptr;
+    if (int rc = plan_alloc(c, p, std::max<unsigned long long>(cnt, 1) * 8, &dev)) return rc;
+    if (cnt) p->item_gens.push_back(Plan::ItemGen{kind, M, np, dev});
+    *d = dev;
+    *n = cnt;
     return EPI_OK;
 }
 
@@ -541,7 +584,7 @@ void plan_free(Ctx *c, Plan *p) {
     c->alloc.release(p->d_layout);
     c->alloc.release(p->d_out);
     host_buf_put(c, p->h_out, p->h_out_cap);
-    host_buf_put(c, p->h_stage, p->h_stage_cap);
+    if (!p->arena) host_buf_put(c, p->h_stage, p->h_stage_cap);
     p->h_out = p->h_stage = nullptr;
     for (auto &e : p->ev) event_put(c, e);
     for (auto &e : p->ev) e = nullptr;
@@ -701,7 +744,7 @@ static bool needs_pairs(const PlanScan &s) {
 }
 
 int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool graph, Plan **out,
-               int force_np, bool check) {
+               int force_np, bool check, const PlanArena *arena) {
     if (n < 1) return fail(EPI_EINVAL, "empty scan list");
     std::vector<Dataset *> dss(n);
     for (int i = 0; i < n; ++i) {
@@ -712,6 +755,10 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
     p->persistent = persistent;
     p->use_graph = graph;
     p->check = check;
+    if (arena) {
+        p->arena = arena->base;
+        p->arena_cap = arena->cap;
+    }
     p->scans.resize(n);
     int rc = EPI_OK;
     auto cleanup = [&](int code) {
@@ -725,7 +772,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         s.ds = dss[i];
         s.n_combos = binom_u64(s.ds->M, s.desc.order);
         const int o = s.desc.order;
-        if (force_np <= 0 && seg_pinned(c, o, s.ds)) {
+        if (force_np <= 0 && !arena && seg_pinned(c, o, s.ds)) {
             s.variant = kSeg;
             s.np = kGenRanksHost;
             s.n_items = (s.n_combos + 64ull * kGenRanksHost - 1) / (64ull * kGenRanksHost);
@@ -736,7 +783,10 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
             s.variant = kF3;
             s.np = force_np > 0 ? force_np : tuned_np(c, 3, s.ds);
         } else {
-            s.variant = o == 4 && use_r4(c, s.ds) ? kR4 : kGeneric;
+            // an allocation-free plan takes the reduced-cell order-4 kernel
+            // only when its two sub-tables fit in half the scratch array
+            const bool r4_room = !arena || binom_u64(s.ds->M, 3) * 64 + binom_u64(s.ds->M, 2) * 32 <= arena->cap / 2;
+            s.variant = o == 4 && use_r4(c, s.ds) && r4_room ? kR4 : kGeneric;
             s.np = kGenRanksHost;
             s.n_items = (s.n_combos + 64ull * kGenRanksHost - 1) / (64ull * kGenRanksHost);
         }
@@ -807,18 +857,19 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
     // work-item descriptor tables and order-3 sub-table buffers
     for (auto &s : p->scans) {
         if (s.variant == kF2 || s.variant == kF3) {
-            if ((rc = get_items(c, s.variant, s.ds->M, s.np, &s.items, &s.n_items))) return cleanup(rc);
+            if ((rc = plan_items(c, p.get(), s.variant, s.ds->M, s.np, &s.items, &s.n_items))) return cleanup(rc);
         }
         if (needs_pairs(s)) {
             s.emit_np = 4;
-            if ((rc = get_items(c, kF2, s.ds->M, s.emit_np, &s.emit_items_d, &s.emit_items))) return cleanup(rc);
+            if ((rc = plan_items(c, p.get(), kF2, s.ds->M, s.emit_np, &s.emit_items_d, &s.emit_items)))
+                return cleanup(rc);
             const size_t pb = (size_t)binom_u64(s.ds->M, 2) * 32;
-            if ((rc = c->alloc.alloc(std::max<size_t>(pb, 32), &s.pairs))) return cleanup(rc);
+            if ((rc = plan_alloc(c, p.get(), std::max<size_t>(pb, 32), &s.pairs))) return cleanup(rc);
         }
         if (s.variant == kR4) {
-            if ((rc = get_items(c, kF3, s.ds->M, kNpMfma, &s.t3_items_d, &s.t3_items))) return cleanup(rc);
+            if ((rc = plan_items(c, p.get(), kF3, s.ds->M, kNpMfma, &s.t3_items_d, &s.t3_items))) return cleanup(rc);
             const size_t tb = (size_t)binom_u64(s.ds->M, 3) * 64;
-            if ((rc = c->alloc.alloc(std::max<size_t>(tb, 64), &s.triples))) return cleanup(rc);
+            if ((rc = plan_alloc(c, p.get(), std::max<size_t>(tb, 64), &s.triples))) return cleanup(rc);
         }
     }
     // tasks: [main tasks in scan order][pair passes][triplet passes]
@@ -864,11 +915,11 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         // each wave of the launch flushes at most top_k entries per task
         s.cand_cap = (unsigned)std::min<unsigned long long>((unsigned long long)grid * 4 * s.desc.top_k + 64,
                                                             0xffffffffull);
-        if ((rc = c->alloc.alloc((size_t)s.cand_cap * sizeof(Cand), &s.cand))) return cleanup(rc);
+        if ((rc = plan_alloc(c, p.get(), (size_t)s.cand_cap * sizeof(Cand), &s.cand))) return cleanup(rc);
         if (s.variant == kSeg) {
             // one block of 64 tables (2 x 3^k counts each) per wave slot of the launch
             const size_t sb = (size_t)grid * 4 * 64 * 2 * (size_t)pow3i(s.desc.order) * 4;
-            if ((rc = c->alloc.alloc(sb, &s.seg))) return cleanup(rc);
+            if ((rc = plan_alloc(c, p.get(), sb, &s.seg))) return cleanup(rc);
         }
         s.lay.offset = out_bytes;
         s.lay.top_k = s.desc.top_k;
@@ -883,19 +934,21 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
     p->n_queues = nq + ndig;
     const size_t cnt_bytes =
         (size_t)(nq + ndig) * 8 + (size_t)nt * 8 + (size_t)nt * 4 + (size_t)nt * kHistWords * 4;
-    if ((rc = c->alloc.alloc(cnt_bytes, &p->d_counters))) return cleanup(rc);
+    if ((rc = plan_alloc(c, p.get(), cnt_bytes, &p->d_counters))) return cleanup(rc);
     p->d_queues = (unsigned long long *)p->d_counters;
     p->d_digest = check ? p->d_queues + nq : nullptr;
     p->d_thr = p->d_queues + nq + ndig;
     p->d_cand_count = (unsigned *)(p->d_thr + nt);
     p->d_hist = p->d_cand_count + nt;
-    if ((rc = c->alloc.alloc((size_t)nt * kMaxTopK * sizeof(Cand), &p->d_results))) return cleanup(rc);
-    if ((rc = c->alloc.alloc((size_t)nt * kMergeParts * kMaxTopK * sizeof(Cand), &p->d_parts))) return cleanup(rc);
-    if ((rc = c->alloc.alloc((size_t)nt * sizeof(ResultLayout), &p->d_layout))) return cleanup(rc);
-    if ((rc = c->alloc.alloc((size_t)std::max<long long>(out_bytes, 256), &p->d_out))) return cleanup(rc);
-    // pinned results, then (checking plans) the digest words of every scan
-    if ((rc = host_buf_get(c, (size_t)std::max<long long>(out_bytes, 256) + (size_t)ndig * 8, &p->h_out,
-                           &p->h_out_cap)))
+    if ((rc = plan_alloc(c, p.get(), (size_t)nt * kMaxTopK * sizeof(Cand), &p->d_results))) return cleanup(rc);
+    if ((rc = plan_alloc(c, p.get(), (size_t)nt * kMergeParts * kMaxTopK * sizeof(Cand), &p->d_parts)))
+        return cleanup(rc);
+    if ((rc = plan_alloc(c, p.get(), (size_t)nt * sizeof(ResultLayout), &p->d_layout))) return cleanup(rc);
+    if ((rc = plan_alloc(c, p.get(), (size_t)std::max<long long>(out_bytes, 256), &p->d_out))) return cleanup(rc);
+    // pinned results, then (checking plans) the digest words of every scan;
+    // allocation-free plans scatter their results on the device instead
+    if (!arena && (rc = host_buf_get(c, (size_t)std::max<long long>(out_bytes, 256) + (size_t)ndig * 8, &p->h_out,
+                                     &p->h_out_cap)))
         return cleanup(rc);
     std::vector<ResultLayout> lay(nt);
     for (int i = 0; i < nt; ++i) lay[i] = p->scans[i].lay;
@@ -995,18 +1048,24 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
             tasks.push_back(t);
         }
     }
-    if ((rc = c->alloc.alloc(tasks.size() * sizeof(Task), &p->d_tasks))) return cleanup(rc);
+    if ((rc = plan_alloc(c, p.get(), tasks.size() * sizeof(Task), &p->d_tasks))) return cleanup(rc);
     // layout and task arrays staged in pinned memory; every run uploads them
     // on its own stream ahead of its kernels (no synchronous copy here)
     p->stage_layout_bytes = ((size_t)nt * sizeof(ResultLayout) + 255) & ~(size_t)255;
     p->stage_tasks_bytes = tasks.size() * sizeof(Task);
-    if ((rc = host_buf_get(c, p->stage_layout_bytes + p->stage_tasks_bytes, &p->h_stage, &p->h_stage_cap)))
+    if (arena) {
+        p->h_stage_mem.resize(p->stage_layout_bytes + p->stage_tasks_bytes);
+        p->h_stage = p->h_stage_mem.data();
+        p->h_stage_cap = 0;  // not from the pinned pool
+    } else if ((rc = host_buf_get(c, p->stage_layout_bytes + p->stage_tasks_bytes, &p->h_stage, &p->h_stage_cap))) {
         return cleanup(rc);
+    }
     memcpy(p->h_stage, lay.data(), (size_t)nt * sizeof(ResultLayout));
     memcpy((char *)p->h_stage + p->stage_layout_bytes, tasks.data(), p->stage_tasks_bytes);
     p->emit_total = emit_total;
-    for (auto &ev : p->ev)
-        if ((rc = event_get(c, &ev))) return cleanup(rc);
+    if (!arena)
+        for (auto &ev : p->ev)
+            if ((rc = event_get(c, &ev))) return cleanup(rc);
     *out = p.release();
     return EPI_OK;
 }
@@ -1017,9 +1076,16 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
 static int plan_enqueue(Ctx *c, Plan *p, hipStream_t st, bool timing, unsigned long long item_cap) {
     const Task *tasks = (const Task *)p->d_tasks;
     const int nt = (int)p->scans.size();
-    HIPCHK(hipMemcpyAsync(p->d_layout, p->h_stage, (size_t)nt * sizeof(ResultLayout), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(p->d_tasks, (const char *)p->h_stage + p->stage_layout_bytes, p->stage_tasks_bytes,
-                          hipMemcpyHostToDevice, st));
+    for (auto &g : p->item_gens) HIPCHK(launch_items(st, g.kind, g.M, g.np, (unsigned long long *)g.dst));
+    if (p->arena) {
+        // no copy from host memory: the arrays travel in kernel arguments
+        HIPCHK(launch_store(st, p->h_stage, (size_t)nt * sizeof(ResultLayout), p->d_layout));
+        HIPCHK(launch_store(st, (const char *)p->h_stage + p->stage_layout_bytes, p->stage_tasks_bytes, p->d_tasks));
+    } else {
+        HIPCHK(hipMemcpyAsync(p->d_layout, p->h_stage, (size_t)nt * sizeof(ResultLayout), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(p->d_tasks, (const char *)p->h_stage + p->stage_layout_bytes, p->stage_tasks_bytes,
+                              hipMemcpyHostToDevice, st));
+    }
     HIPCHK(launch_init_counters(st, p->d_queues, p->n_queues, p->d_cand_count, p->d_thr, nt, p->d_hist));
     int q = 0;
     const bool single = nt == 1 && !p->persistent;
@@ -1077,6 +1143,13 @@ static int plan_enqueue(Ctx *c, Plan *p, hipStream_t st, bool timing, unsigned l
             HIPCHK(launch_finalize(1, s.desc.top_k, st, tasks + i, (const Cand *)p->d_results + (size_t)i * kMaxTopK,
                                    (const ResultLayout *)p->d_layout + i, (char *)p->d_out));
         }
+    }
+    if (p->arena) {
+        // allocation-free plan (one scan): its result block to the caller's buffers
+        const PlanScan &s = p->scans[0];
+        HIPCHK(launch_scatter(st, (const char *)p->d_out + s.lay.offset, s.desc.top_k, s.desc.order, p->u_combos,
+                              p->u_scores, p->u_tables, p->u_n));
+        return EPI_OK;
     }
     HIPCHK(hipMemcpyAsync(p->h_out, p->d_out, (size_t)std::max<long long>(p->out_bytes, 256), hipMemcpyDeviceToHost, st));
     if (p->check)
@@ -1445,6 +1518,26 @@ int epi_scan_digest(epi_ctx *ctx, int32_t scan_id, uint64_t *n_scored, uint64_t 
     *n_scored = w[0];
     *digest = w[1];
     return EPI_OK;
+}
+
+int epi_scan_noalloc(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t top_k, void *stream,
+                     int32_t *d_combos, float *d_scores, uint32_t *d_tables, int32_t *d_n) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    if (!d_combos || !d_scores || !d_n) return fail(EPI_EINVAL, "null output buffer");
+    epi_scan_desc d{dataset_id, order, top_k, 0};
+    const PlanArena arena{C->scratch, kScratchBytes};
+    Plan *p = nullptr;
+    int rc = plan_build(C, &d, 1, false, false, &p, 0, false, &arena);
+    if (rc) return rc;
+    std::unique_ptr<Plan> hold(p);
+    p->u_combos = d_combos;
+    p->u_scores = d_scores;
+    p->u_tables = d_tables;
+    p->u_n = d_n;
+    rc = plan_enqueue(C, p, stream ? (hipStream_t)stream : C->stream, false, ~0ull);
+    plan_free(C, p);  // host state only: none of its device buffers came from an allocator
+    return rc;
 }
 
 int epi_scan_batch(epi_ctx *ctx, const epi_scan_desc *descs, int32_t n, void *stream, int32_t *scan_ids) {

@@ -21,6 +21,7 @@ namespace epi {
 
 constexpr int kBinomN = 65537;     // binomial table columns (n = 0 .. 65536)
 constexpr int kGenRanksHost = 4;   // ranks per lane of the per-combination kernel
+constexpr size_t kScratchBytes = EPI_NOALLOC_SCRATCH_BYTES;  // scratch array of allocation-free scans
 
 int fail(int code, const char *fmt, ...);
 void clear_error();
@@ -118,6 +119,23 @@ struct Plan {
     hipGraphExec_t exec = nullptr;
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     hipStream_t stream = nullptr;
+    // Allocation-free plans (epi_scan_noalloc): every device buffer is carved
+    // from the device's scratch array, the task and layout arrays reach the
+    // device in kernel arguments (no copy from host memory), descriptor
+    // tables the context has not cached yet are written into the scratch by
+    // the run, and there are no events.  The results go to the caller's
+    // device buffers.
+    char *arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
+    struct ItemGen {
+        int kind, M, np;
+        void *dst;
+    };
+    std::vector<ItemGen> item_gens;  // descriptor tables the run writes first
+    std::vector<char> h_stage_mem;   // host copy of the layout and task arrays
+    int32_t *u_combos = nullptr, *u_n = nullptr;
+    float *u_scores = nullptr;
+    uint32_t *u_tables = nullptr;
 };
 
 struct ScanRef {
@@ -162,6 +180,7 @@ struct Ctx {
     std::multimap<size_t, void *> host_pool;
     size_t host_pool_bytes = 0;
     std::vector<hipEvent_t> event_pool;
+    char *scratch = nullptr;  // this device's scratch array (allocation-free scans)
 };
 
 // kernel launchers (kernels.hip)
@@ -180,6 +199,10 @@ hipError_t launch_function(int fn, int order, hipStream_t st, const DsView &d, c
                            const uint32_t *tables, unsigned long long n, void *out, int *err, int grid,
                            long long score_const);
 hipError_t launch_reseed(int n_tasks, hipStream_t st, const Task *tasks, const Cand *results);
+hipError_t launch_items(hipStream_t st, int kind, int M, int np, unsigned long long *out);
+hipError_t launch_store(hipStream_t st, const void *src, size_t bytes, void *dst);
+hipError_t launch_scatter(hipStream_t st, const char *block, int top_k, int order, int32_t *combos, float *scores,
+                          uint32_t *tables, int32_t *n);
 hipError_t launch_pack(hipStream_t st, const uint8_t *geno, long long ld, const int32_t *idx, const DsView &d,
                        v4u *masks, int *err);
 hipError_t launch_classidx(hipStream_t st, const uint8_t *pheno, int N, int n_case, int32_t *idx, int *err);
@@ -206,8 +229,13 @@ int group_tab_cap(int np2, int np3, int gk, int cap_both, int cap_first, int kma
 Ctx *as_ctx(epi_ctx *c);
 int key_bits_for(int order);
 void load_tune_cache(Ctx *c);
+// Device memory an allocation-free plan is carved from.
+struct PlanArena {
+    char *base;
+    size_t cap;
+};
 int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool graph, Plan **out, int force_np,
-               bool check = false);
+               bool check = false, const PlanArena *arena = nullptr);
 bool use_r4(Ctx *c, const Dataset *d);
 int plan_run(Ctx *c, Plan *p, hipStream_t st, unsigned long long item_cap);
 int plan_wait(Plan *p);

@@ -31,6 +31,7 @@ EPI_BLOCK_MFMA_FP4 = 16
 EPI_BLOCK_MFMA_I8 = 32
 EPI_BLOCK_SEGMENTED = 64
 EPI_BLOCK_ALL_CELLS = 81
+EPI_NOALLOC_SCRATCH_BYTES = 134217728
 EPI_MAX_TOP_K = 256
 
 # Every function the header declares, with (restype, argtypes).
@@ -69,6 +70,7 @@ SIGNATURES = {
     "epi_release": (_c.c_int, [_vp, _i32]),
     "epi_scan_check": (_c.c_int, [_vp, _i32, _i32, _i32, _vp, _P(_i32)]),
     "epi_scan_digest": (_c.c_int, [_vp, _i32, _P(_u64), _P(_u64)]),
+    "epi_scan_noalloc": (_c.c_int, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "epi_batch_create": (_c.c_int, [_vp, _P(ScanDesc), _i32, _i32, _i32, _P(_i32)]),
     "epi_batch_run": (_c.c_int, [_vp, _i32, _vp]),
     "epi_batch_wait": (_c.c_int, [_vp, _i32]),
@@ -315,6 +317,19 @@ def epi_scan_check(ctx, dataset_id, order, top_k, stream=None):
     out = _i32()
     _check(lib().epi_scan_check(ctx, dataset_id, order, top_k, _stream(stream), ctypes.byref(out)))
     return out.value
+
+
+def epi_scan_noalloc(ctx, dataset_id, order, top_k, d_combos, d_scores, d_tables, d_n, stream=None):
+    """Enqueue an allocation-free scan writing into caller device tensors
+    (int32 [top_k, order], float32 [top_k], uint32-sized [top_k, 2, 3^order]
+    or None, int32 [1]); synchronise the stream before reading them."""
+    _device_buffer(d_combos, 4, top_k * order, "combinations")
+    _device_buffer(d_scores, 4, top_k, "scores")
+    if d_tables is not None:
+        _device_buffer(d_tables, 4, top_k * 2 * 3**order, "tables")
+    _device_buffer(d_n, 4, 1, "count")
+    _check(lib().epi_scan_noalloc(ctx, dataset_id, order, top_k, _stream(stream), _ptr(d_combos), _ptr(d_scores),
+                                  _ptr(d_tables) if d_tables is not None else None, _ptr(d_n)))
 
 
 def epi_scan_digest(ctx, scan_id):
