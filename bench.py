@@ -13,9 +13,11 @@ the plain single-scan path on the named workload; ``roofline`` reports the
 main counting kernel against the integer-VALU peak (HIP events on the scan's
 stream); ``cpu_baseline`` is the CPU oracle timed on a bounded slice of the
 same workload; ``batched`` compares one persistent, graph-captured launch of
-64 uneven scans with 64 back-to-back plain launches; ``served`` runs the
-continuous-batching server on Poisson arrivals and, for capacity, on the same
-requests submitted at once against back-to-back plain scans;
+64 uneven scans (kernels picked by the autotuner per order and size bucket)
+with 64 back-to-back plain launches, all K results of every scan compared;
+``served`` runs the continuous-batching server on a burst of requests at once
+against back-to-back plain scans (capacity, all K results compared), then on
+Poisson arrivals at the stated rate and near the measured capacity;
 ``pcie_inclusive_value`` is the same step with the genotypes handed over from
 host memory; ``orders`` times the other named workloads (orders 2, 4, 5).
 """
@@ -145,14 +147,22 @@ def plain_bench(epi, torch, spec, G, y, steps, warmup, block=None, extra=None):
     return dt, mains, alls, res, info, tuned
 
 
+def host_cores():
+    """Host cores for the CPU baseline: every core this process may run on,
+    within the per-GPU CPU share the host states in OMP_NUM_THREADS (a
+    one-GPU share of a larger machine)."""
+    affinity = len(os.sched_getaffinity(0))
+    share = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    return (min(affinity, share) if share > 0 else affinity), affinity, share or None
+
+
 def cpu_baseline(spec, G, y, seconds):
     """The oracle as it stands, on a bounded rank range of the workload."""
     import oracle
 
     o = oracle.default()
     order, N = spec["order"], spec["N"]
-    # the host share of one GPU is 16 cores, whatever the machine reports
-    threads = min(16, len(os.sched_getaffinity(0)))
+    threads, affinity, share = host_cores()
     total = o.binomial(spec["M"], order)
     # a probe of about half a second sizes the sample; a sample that still
     # ran short of half the requested time is sized again from its own rate
@@ -169,6 +179,9 @@ def cpu_baseline(spec, G, y, seconds):
         "value": n * N / dt / 1e12,
         "unit": UNIT,
         "cores": r["threads"],
+        "nproc": os.cpu_count(),
+        "affinity_cores": affinity,
+        "host_share_cores": share,
         "kind": "oracle",
         "sample": f"first {n} of {o.binomial(spec['M'], order)} combinations (lexicographic) of the same "
                   f"workload, all {N} individuals, {dt:.1f} s",
@@ -387,6 +400,8 @@ def functions_bench(epi, torch, reps=3, out_cap=1 << 30, table_cap=8 << 30):
 
 def batched_bench(epi, torch, n_scans, reps):
     """One persistent graph-captured launch of n uneven scans vs n back-to-back plain launches."""
+    import numpy as np
+
     from synth import batched_specs, make_case_control
 
     specs = batched_specs(n_scans)
@@ -400,6 +415,22 @@ def batched_bench(epi, torch, n_scans, reps):
     log(f"batched: {n_scans} datasets generated and loaded in {time.perf_counter() - t0:.1f}s, "
         f"{work:.3e} combos x individuals")
     descs = [(dss[i], specs[i]["order"], specs[i]["top_k"]) for i in range(n_scans)]
+    # the tuner picks the counting kernel of every (order, size bucket) of
+    # the mix, on one dataset of that bucket; the batch then uses the picks
+    tuned, seen = [], set()
+    for i, s in enumerate(specs):
+        n_case = s["n_cases"]
+        words = 4 * ((n_case + 127) // 128) + 4 * ((s["N"] - n_case + 127) // 128)
+        key = (s["order"], max(0, (words - 1).bit_length()))
+        if key in seen:
+            continue
+        seen.add(key)
+        choice = epi.epi_autotune(ctx, dss[i], s["order"])
+        rep = epi.epi_autotune_report(ctx, dss[i], s["order"])
+        tuned.append({"order": s["order"], "words_bucket": key[1], "tuned_on": {"M": s["M"], "N": s["N"]},
+                      "choice": choice, "ns_per_combination": {str(b): round(t, 6) for b, t in rep}})
+        log(f"batched tune order {s['order']} bucket {key[1]} (M={s['M']}, N={s['N']}): pick {choice}, "
+            + ", ".join(f"{b}: {t:.5f} ns" for b, t in rep))
     out = {}
     for name, persistent, graph in (("batched", True, True), ("back_to_back", False, False)):
         bid = epi.epi_batch_create(ctx, descs, persistent=persistent, use_graph=graph)
@@ -412,13 +443,14 @@ def batched_bench(epi, torch, n_scans, reps):
             epi.epi_batch_run(ctx, bid)
             epi.epi_batch_wait(ctx, bid)
             times.append(time.perf_counter() - t0)
-        first = [epi.epi_batch_results(ctx, bid, i, 1, specs[i]["order"], tables=False) for i in range(n_scans)]
-        out[name] = {"seconds": min(times), "value": work / min(times) / 1e12,
-                     "top1": [(tuple(int(v) for v in c[0]), float(s[0])) for c, s, _ in first]}
+        res = [epi.epi_batch_results(ctx, bid, i, specs[i]["top_k"], specs[i]["order"]) for i in range(n_scans)]
+        out[name] = {"seconds": min(times), "value": work / min(times) / 1e12, "results": res,
+                     "top1": [tuple(int(v) for v in c[0]) for c, _, _ in res]}
         epi.epi_batch_destroy(ctx, bid)
         log(f"{name}: {min(times) * 1e3:.1f} ms -> {out[name]['value']:.2f} T")
-    same = out["batched"]["top1"] == out["back_to_back"]["top1"]
-    planted_hits = sum(1 for s, (c, _) in zip(specs, out["batched"]["top1"]) if tuple(s["planted"]) == c)
+    same = all(np.array_equal(u, v) for a, b in zip(out["batched"]["results"], out["back_to_back"]["results"])
+               for u, v in zip(a, b))
+    planted_hits = sum(1 for s, c in zip(specs, out["batched"]["top1"]) if tuple(s["planted"]) == c)
     for d in dss:
         epi.epi_unload(ctx, d)
     epi.epi_destroy(ctx)
@@ -430,8 +462,9 @@ def batched_bench(epi, torch, n_scans, reps):
         "speedup": out["batched"]["value"] / out["back_to_back"]["value"],
         "seconds": out["batched"]["seconds"],
         "back_to_back_seconds": out["back_to_back"]["seconds"],
-        "identical_top1": same,
+        "identical_results": bool(same),
         "planted_top1": planted_hits,
+        "autotuned": tuned,
     }
 
 
@@ -449,72 +482,50 @@ def served_pool(epi, ctx):
     return pool, dss
 
 
-def served_requests(pool, n, seed=7):
-    """Request stream: (dataset, order) uniform over the pool and its orders."""
-    import numpy as np
-
-    rng = np.random.default_rng(seed)
-    reqs = []
-    for _ in range(n):
-        d = int(rng.integers(len(pool)))
-        reqs.append((d, int(rng.choice(pool[d]["orders"]))))
-    return reqs, rng
-
-
 def served_capacity(epi, ctx, pool, dss, cap, K=100):
     """The same requests submitted at once to a fresh server, against the same
-    requests as back-to-back plain scans (scan, wait, results)."""
+    requests as back-to-back plain scans (scan, wait, results): aggregate
+    rates, and whether every request's K results (combinations, scores,
+    tables) are the plain scan's."""
+    import numpy as np
+
     work = sum(math.comb(pool[d]["M"], o) * pool[d]["N"] for d, o in cap)
     sid = epi.epi_server_start(ctx, max_active=64)
     t0 = time.perf_counter()
     ids = [(epi.epi_server_submit(ctx, sid, dss[d], o, K), o) for d, o in cap]
-    served_top = []
+    served = []
     for rid, o in ids:
         while epi.epi_server_poll(ctx, sid, rid) != 2:
             time.sleep(0.0005)
-        c, s_, _, _ = epi.epi_server_results(ctx, sid, rid, K, o, tables=False)
-        served_top.append((tuple(c[0]), float(s_[0])))
+        served.append(epi.epi_server_results(ctx, sid, rid, K, o)[:3])
     burst_s = time.perf_counter() - t0
     stats = epi.epi_server_stats(ctx, sid)
     epi.epi_server_stop(ctx, sid)
     t0 = time.perf_counter()
-    plain_top = []
+    plain = []
     for d, o in cap:
         q = epi.epi_scan(ctx, dss[d], o, K)
         epi.epi_wait(ctx, q)
-        c, s_, _ = epi.epi_results(ctx, q, K, o, tables=False)
+        plain.append(epi.epi_results(ctx, q, K, o))
         epi.epi_release(ctx, q)
-        plain_top.append((tuple(c[0]), float(s_[0])))
     b2b_s = time.perf_counter() - t0
+    same = all(np.array_equal(u, v) for a, b in zip(served, plain) for u, v in zip(a, b))
     log(f"served capacity: {len(cap)} requests at once {burst_s:.3f}s ({stats['rounds']} rounds) "
-        f"vs back-to-back plain {b2b_s:.3f}s")
+        f"vs back-to-back plain {b2b_s:.3f}s, identical results {same}")
     return {"requests": len(cap), "combos_x_samples": int(work), "value": work / burst_s / 1e12,
             "back_to_back_value": work / b2b_s / 1e12, "speedup": b2b_s / burst_s, "rounds": stats["rounds"],
-            "identical_top1": served_top == plain_top}
+            "peak_active": stats["peak_active"], "identical_results": bool(same)}
 
 
-def served_bench(epi, torch, n_requests, rate, burst, seed=7):
-    """Poisson arrivals of scans on a resident dataset pool, served by the
-    continuous-batching server; latency from submission to results ready."""
+def served_leg(epi, ctx, pool, dss, reqs, gaps, K):
+    """Submit the requests at their Poisson arrival times to a fresh server
+    and collect each one's latency (submission to results ready)."""
     import threading
 
     import numpy as np
 
-    ctx = epi.epi_create(0)
-    pool, dss = served_pool(epi, ctx)
-    reqs, rng = served_requests(pool, max(n_requests, burst), seed)
-    cap = reqs[:burst]
-    reqs = reqs[:n_requests]
-    gaps = rng.exponential(1.0 / rate, n_requests)
     work = [math.comb(pool[d]["M"], o) * pool[d]["N"] for d, o in reqs]
-    K = 100
     sid = epi.epi_server_start(ctx, max_active=64)
-    # warm-up: one request of each order, not counted
-    for o in (2, 3, 4):
-        w = epi.epi_server_submit(ctx, sid, dss[0], o, K)
-        while epi.epi_server_poll(ctx, sid, w) != 2:
-            time.sleep(0.001)
-        epi.epi_server_results(ctx, sid, w, K, o)
     pending, lat, done_at = {}, [], []
     lock = threading.Lock()
     start = time.perf_counter()
@@ -532,8 +543,8 @@ def served_bench(epi, torch, n_requests, rate, burst, seed=7):
 
     th = threading.Thread(target=submit)
     th.start()
-    finished = 0
-    while finished < n_requests:
+    finished, last_log = 0, start
+    while finished < len(reqs):
         with lock:
             items = list(pending.items())
         for rid, o in items:
@@ -544,28 +555,70 @@ def served_bench(epi, torch, n_requests, rate, burst, seed=7):
                 with lock:
                     del pending[rid]
                 finished += 1
+        now = time.perf_counter()
+        if now - last_log > 20:
+            log(f"  served: {finished} of {len(reqs)} requests done after {now - start:.0f}s")
+            last_log = now
         time.sleep(0.0005)
     th.join()
     wall = max(done_at) - start
     stats = epi.epi_server_stats(ctx, sid)
     epi.epi_server_stop(ctx, sid)
-    capacity = served_capacity(epi, ctx, pool, dss, cap, K)
-    for d in dss:
-        epi.epi_unload(ctx, d)
-    epi.epi_destroy(ctx)
     lat = np.sort(np.asarray(lat))
     arrivals = float(np.sum(gaps))
     return {
-        "config": {"workload": f"{n_requests} requests, Poisson {rate}/s, orders 2-4 (order 4 on M<=200), "
-                               f"M in [50,1500], N in [500,16000], pool of {len(pool)} resident datasets, top-100",
-                   "combos_x_samples": int(sum(work))},
+        "requests": len(reqs),
+        "rate_per_s": len(reqs) / arrivals,
         "value": sum(work) / wall / 1e12,
+        "offered_T": sum(work) / arrivals / 1e12,
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
-        "offered_T": sum(work) / arrivals / 1e12,
+        "mean_ms": float(lat.mean()),
         "wall_s": wall,
         "rounds": stats["rounds"],
         "peak_active": stats["peak_active"],
+    }
+
+
+def served_bench(epi, torch, n_requests, rate, burst, load_frac=0.8, seed=7):
+    """The continuous-batching server on a resident dataset pool: capacity
+    (a burst of requests at once, results compared with plain scans), then
+    Poisson arrivals at the stated rate and at load_frac of the measured
+    capacity, p50/p99 latency from submission to results ready after a
+    warm-up."""
+    from synth import served_requests
+
+    ctx = epi.epi_create(0)
+    pool, dss = served_pool(epi, ctx)
+    K = 100
+    # warm-up: a short burst of every order, not counted
+    warm, _ = served_requests(pool, 24, seed=seed + 100)
+    served_capacity(epi, ctx, pool, dss, warm, K)
+    cap_reqs, _ = served_requests(pool, burst, seed=seed + 1)
+    capacity = served_capacity(epi, ctx, pool, dss, cap_reqs, K)
+    reqs, gaps = served_requests(pool, n_requests, seed=seed, rate=rate)
+    mean_work = sum(math.comb(pool[d]["M"], o) * pool[d]["N"] for d, o in reqs) / len(reqs)
+    log(f"served: {n_requests} requests at {rate}/s")
+    stated = served_leg(epi, ctx, pool, dss, reqs, gaps, K)
+    near_rate = load_frac * capacity["value"] * 1e12 / mean_work
+    reqs2, gaps2 = served_requests(pool, n_requests, seed=seed + 2, rate=near_rate)
+    log(f"served: {n_requests} requests at {near_rate:.1f}/s ({load_frac:.0%} of the burst capacity)")
+    near = served_leg(epi, ctx, pool, dss, reqs2, gaps2, K)
+    for d in dss:
+        epi.epi_unload(ctx, d)
+    epi.epi_destroy(ctx)
+    return {
+        "config": {"workload": f"{n_requests} Poisson requests per leg after a warm-up, orders 2-4 (order 4 on "
+                               f"M<=200), M in [50,1500], N in [500,16000], pool of {len(pool)} resident datasets, "
+                               "top-100",
+                   "mean_combos_x_samples_per_request": mean_work},
+        "value": stated["value"],
+        "p50_ms": stated["p50_ms"],
+        "p99_ms": stated["p99_ms"],
+        "offered_T": stated["offered_T"],
+        "peak_active": stated["peak_active"],
+        "stated_rate": stated,
+        "near_capacity": near,
         "capacity": capacity,
     }
 
@@ -581,7 +634,7 @@ def main():
     ap.add_argument("--batched-scans", type=int, default=64)
     ap.add_argument("--batched-reps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--served-requests", type=int, default=200)
+    ap.add_argument("--served-requests", type=int, default=2000, help="requests per Poisson leg")
     ap.add_argument("--served-rate", type=float, default=20.0)
     ap.add_argument("--served-burst", type=int, default=100,
                     help="requests of the served capacity comparison (all submitted at once)")

@@ -309,14 +309,29 @@ int epi_batch_destroy(epi_ctx *ctx, int32_t batch_id);
  * triplet sub-table fits, and this block pins the all-cell kernel instead. */
 #define EPI_BLOCK_ALL_CELLS 81
 
-/* Time the counting kernels above for `order` on a bounded slice of the
- * dataset's combination space and remember the fastest for datasets of the
- * same words-per-individual bucket.  The choice is also written to the cache
- * file named by EPI_TUNE_CACHE (if set).  Scans use tuned choices
- * automatically; untuned shapes use built-in defaults (order 3: the
- * matrix-core kernel where available).  *choice receives the chosen prefix
- * block. */
+/* Time every counting kernel of `order` on the dataset's own scan and
+ * remember the fastest for datasets of the same words-per-individual bucket.
+ * The candidates are the blocks listed above: order 2 prefix blocks 2, 4, 8;
+ * order 3 blocks 1, 2, 4, 8 and EPI_BLOCK_MFMA_FP4; order 4 the reduced-cell
+ * kernel (reported as 0), EPI_BLOCK_ALL_CELLS and EPI_BLOCK_SEGMENTED;
+ * orders 5-8 EPI_BLOCK_ALL_CELLS and EPI_BLOCK_SEGMENTED.  Each is timed on
+ * eight slices of work items spread evenly over the whole scan (about 32
+ * items per wave slot of the launch in all) and its time divided by the
+ * combinations those items score (counted on the host), so kernels whose
+ * items hold different numbers of combinations compare fairly.  The choice
+ * is also written to the cache file named by EPI_TUNE_CACHE (if set).  Scans
+ * (plain, batched and served) use tuned choices automatically; untuned
+ * shapes use built-in defaults (order 3: the matrix-core kernel where
+ * available).  *choice receives the chosen block. */
 int epi_autotune(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t *choice);
+
+/* The candidates of the last epi_autotune of `order` for the dataset's size
+ * bucket and their measured cost in nanoseconds per scored combination, in
+ * the order they were timed: blocks[i], ns_per_combination[i] for i <
+ * min(capacity, *n_candidates).  Errors: ENOTFOUND (no such autotune),
+ * EINVAL. */
+int epi_autotune_report(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t capacity, int32_t *blocks,
+                        double *ns_per_combination, int32_t *n_candidates);
 
 /* Pin the counting kernel for `order` on datasets of the same bucket as
  * `dataset_id`, as if the autotuner had chosen `block` (one of the blocks

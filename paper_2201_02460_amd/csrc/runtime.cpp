@@ -402,18 +402,14 @@ static int load_common(Ctx *c, const uint8_t *d_geno, int64_t ld, const uint8_t 
 // plans
 // ---------------------------------------------------------------------------
 int tuned_np_lookup(Ctx *c, int order, const Dataset *d) {
-    const int words = (d->w4[0] + d->w4[1]) * 4;
-    int bucket = 0;
-    while ((1 << bucket) < words) ++bucket;
+    const int bucket = size_bucket(d);
     std::lock_guard<std::mutex> g(c->tune_mu);
     auto it = c->tuned.find(TuneKey{order, bucket});
     return it != c->tuned.end() ? it->second : 0;
 }
 
 bool seg_pinned(Ctx *c, int order, const Dataset *d) {
-    const int words = (d->w4[0] + d->w4[1]) * 4;
-    int bucket = 0;
-    while ((1 << bucket) < words) ++bucket;
+    const int bucket = size_bucket(d);
     std::lock_guard<std::mutex> g(c->tune_mu);
     return c->seg_pins.count(TuneKey{order, bucket}) != 0;
 }
@@ -610,7 +606,7 @@ int check_desc(Ctx *c, const epi_scan_desc &d, Dataset **out) {
 }
 
 // Kernel instantiation for a group of tasks in one persistent launch.
-void pick_group_kernel(const std::vector<int> &orders, int np3_hint, int *np2, int *np3, int *gk) {
+void pick_group_kernel(const std::vector<int> &orders, int np_hint, int *np2, int *np3, int *gk) {
     bool has2 = false, has3 = false;
     int gen = 0;
     for (int o : orders) {
@@ -625,13 +621,18 @@ void pick_group_kernel(const std::vector<int> &orders, int np3_hint, int *np2, i
         *gk = gen;
         return;
     }
-    const int h = np3_hint <= 2 ? 2 : (np3_hint <= 4 ? 4 : 8);
-    if (has2) *np2 = 4;
-    if (has3) *np3 = has2 ? h : np3_hint;
+    const int h = np_hint <= 2 ? 2 : (np_hint <= 4 ? 4 : 8);
+    if (has2) *np2 = h;
+    if (has3) *np3 = has2 ? h : np_hint;
 }
 
-// Launch-group key of an order (order 3 is further split by prefix block).
-int group_of_order(int order) { return order; }
+// Launch-group key of a scan: one group per kernel instantiation (orders 2
+// and 3 are split by prefix block).
+int group_of_order(int order, int np) {
+    if (order == 2) return 20 + np;
+    if (order == 3) return 30 + np;
+    return order;
+}
 
 // Prefix block of an order-3 scan: the autotuned value for the dataset's
 // size bucket if there is one, else the matrix-core kernel when the dataset
@@ -772,13 +773,13 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         s.ds = dss[i];
         s.n_combos = binom_u64(s.ds->M, s.desc.order);
         const int o = s.desc.order;
-        if (force_np <= 0 && !arena && seg_pinned(c, o, s.ds)) {
+        if (force_np == EPI_BLOCK_SEGMENTED || (force_np <= 0 && !arena && seg_pinned(c, o, s.ds))) {
             s.variant = kSeg;
             s.np = kGenRanksHost;
             s.n_items = (s.n_combos + 64ull * kGenRanksHost - 1) / (64ull * kGenRanksHost);
         } else if (o == 2) {
             s.variant = kF2;
-            s.np = persistent ? 4 : (force_np > 0 ? force_np : tuned_np(c, 2, s.ds));
+            s.np = force_np > 0 ? force_np : tuned_np(c, 2, s.ds);
         } else if (o == 3) {
             s.variant = kF3;
             s.np = force_np > 0 ? force_np : tuned_np(c, 3, s.ds);
@@ -786,7 +787,10 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
             // an allocation-free plan takes the reduced-cell order-4 kernel
             // only when its two sub-tables fit in half the scratch array
             const bool r4_room = !arena || binom_u64(s.ds->M, 3) * 64 + binom_u64(s.ds->M, 2) * 32 <= arena->cap / 2;
-            s.variant = o == 4 && use_r4(c, s.ds) && r4_room ? kR4 : kGeneric;
+            bool r4 = o == 4 && r4_fits(s.ds) && r4_room;
+            if (force_np == EPI_BLOCK_ALL_CELLS) r4 = false;
+            else if (force_np != kForceReducedCells) r4 = r4 && use_r4(c, s.ds);
+            s.variant = r4 ? kR4 : kGeneric;
             s.np = kGenRanksHost;
             s.n_items = (s.n_combos + 64ull * kGenRanksHost - 1) / (64ull * kGenRanksHost);
         }
@@ -817,8 +821,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
             const PlanScan &s = p->scans[i];
             if (s.variant == kF2Fold) continue;  // runs in the pair pass
             const bool seg = s.variant == kSeg;
-            const int key = seg ? 200 + s.desc.order
-                                : (s.desc.order == 3 ? 30 + s.np : group_of_order(s.desc.order));
+            const int key = seg ? 200 + s.desc.order : group_of_order(s.desc.order, s.np);
             LaunchGroup &g = by_key[key];
             g.scans.push_back(i);
             std::vector<int> orders{s.desc.order};
@@ -1240,17 +1243,92 @@ void load_tune_cache(Ctx *c) {
     std::ifstream f(c->tune_path);
     std::string arch;
     int order, bucket, np;
-    while (f >> arch >> order >> bucket >> np)
-        if (arch == c->arch) c->tuned[TuneKey{order, bucket}] = np;
+    while (f >> arch >> order >> bucket >> np) {
+        if (arch != c->arch) continue;
+        if (np == EPI_BLOCK_SEGMENTED) c->seg_pins[TuneKey{order, bucket}] = 1;
+        else c->tuned[TuneKey{order, bucket}] = np;
+    }
 }
 
 static void save_tune_cache(Ctx *c) {
     if (c->tune_path.empty()) return;
     std::ofstream f(c->tune_path, std::ios::trunc);
     for (auto &kv : c->tuned) f << c->arch << " " << kv.first.order << " " << kv.first.bucket << " " << kv.second << "\n";
+    for (auto &kv : c->seg_pins)
+        f << c->arch << " " << kv.first.order << " " << kv.first.bucket << " " << EPI_BLOCK_SEGMENTED << "\n";
 }
 
+int size_bucket(const Dataset *d) {
+    const int words = (d->w4[0] + d->w4[1]) * 4;
+    int bucket = 0;
+    while ((1 << bucket) < words) ++bucket;
+    return bucket;
+}
+
+// Combinations a kernel scores in items [a, b) of a scan: the valid triplets
+// or pairs of each item's blocks (i < j < m, all below M), or the ranks of a
+// per-combination item that are below C(M, k).
+static unsigned long long valid_in_items(const PlanScan &s, unsigned long long a, unsigned long long b) {
+    const long long M = s.ds->M;
+    if (s.variant != kF2 && s.variant != kF3) {
+        const unsigned long long per = 64ull * kGenRanksHost;
+        const unsigned long long lo = std::min(a * per, s.n_combos), hi = std::min(b * per, s.n_combos);
+        return hi - lo;
+    }
+    const int kind = item_kind(s.variant, s.np);
+    const int np = s.np;
+    auto clip = [](long long lo, long long hi) { return hi > lo ? hi - lo : 0LL; };  // size of [lo, hi)
+    unsigned long long n = 0, at = 0;
+    const long long G = item_groups(kind, (int)M, np);
+    for (long long g = 0; g < G && at < b; ++g) {
+        const ItemGroup gr = item_group(kind, (int)M, np, g);
+        if (at + gr.count <= a) {
+            at += gr.count;
+            continue;
+        }
+        for (unsigned long long t = 0; t < gr.count && at < b; ++t, ++at) {
+            if (at < a) continue;
+            const unsigned long long dsc = item_at(gr, t);
+            const long long j = (long long)(dsc >> 40), ib = (long long)((dsc >> 20) & 0xfffff),
+                            mb = (long long)(dsc & 0xfffff);
+            if (kind == kItemsF2) {
+                const long long i0 = ib * np, m0 = i0 + 1 + mb * 64;
+                for (long long i = i0; i < i0 + np && i <= M - 2; ++i) n += clip(std::max(m0, i + 1), std::min(m0 + 64, M));
+            } else if (kind == kItemsF3) {
+                const long long m0 = j + 1 + mb * 64;
+                n += clip(ib * np, std::min(ib * np + np, j)) * clip(m0, std::min(m0 + 64, M));
+            } else {
+                n += clip(ib * 16, std::min(ib * 16 + 16, j)) * clip(std::max(mb * 32, j + 1), std::min(mb * 32 + 32, M));
+            }
+        }
+    }
+    return n;
+}
+
+// Candidate kernels of an order, by the block that pins them (order 4:
+// kForceReducedCells for the reduced-cell kernel, which epi_set_prefix_block
+// calls 0).
+static std::vector<int> tune_candidates(const Dataset *ds, int order) {
+    if (order == 2) return {2, 4, 8};
+    if (order == 3) {
+        std::vector<int> v{1, 2, 4, 8};
+        if (ds->qa) v.push_back(kNpMfma);
+        return v;
+    }
+    std::vector<int> v;
+    if (order == 4 && r4_fits(ds)) v.push_back(kForceReducedCells);
+    v.push_back(EPI_BLOCK_ALL_CELLS);
+    v.push_back(EPI_BLOCK_SEGMENTED);
+    return v;
+}
+
+// Time each candidate kernel on slices spread over the whole work-item space
+// of the dataset's own scan (kSlices contiguous runs at evenly spaced
+// starts, about 32 items per wave slot in all), normalised by the
+// combinations those items score (counted on the host from the items), and
+// keep the fastest per (order, size bucket).
 int autotune(Ctx *c, int ds_id, int order, int *choice) {
+    constexpr int kSlices = 8;
     Dataset *ds;
     epi_scan_desc d{ds_id, order, 16, 0};
     {
@@ -1258,53 +1336,56 @@ int autotune(Ctx *c, int ds_id, int order, int *choice) {
         int rc = check_desc(c, d, &ds);
         if (rc) return rc;
     }
-    std::vector<int> cands;
-    if (order == 2) cands = {2, 4, 8};
-    else if (order == 3) {
-        cands = {1, 2, 4, 8};
-        if (ds->qa) cands.push_back(kNpMfma);
-    }
-    else {
-        *choice = kGenRanksHost;
-        return EPI_OK;
-    }
+    const std::vector<int> cands = tune_candidates(ds, order);
+    std::vector<std::pair<int, double>> report;
     double best_t = 1e30;
     int best = cands[0];
-    for (int np : cands) {
+    for (int blk : cands) {
         Plan *p = nullptr;
-        int rc = plan_build(c, &d, 1, false, false, &p, np);
+        int rc = plan_build(c, &d, 1, false, false, &p, blk);
         if (rc) return rc;
-        // a bounded slice: about 32 items per wave slot
-        const unsigned long long cap = std::min<unsigned long long>(p->scans[0].n_items, (unsigned long long)p->groups[0].grid * 32);
-        double t = 1e30;
-        for (int rep = 0; rep < 4 && !rc; ++rep) {
-            rc = plan_run(c, p, c->stream, cap);
-            if (!rc) rc = plan_wait(p);
-            float ms = 0;
-            if (!rc && rep > 0 && hipEventElapsedTime(&ms, p->ev[2], p->ev[3]) == hipSuccess) {
-                // per combination: items cover np*64 combinations each (order 3) or 64*np (order 2)
-                const double per = ms / (double)cap / (double)np;
-                t = std::min(t, per);
+        const PlanScan &s = p->scans[0];
+        const unsigned long long total = s.n_items;
+        const unsigned long long len =
+            std::max<unsigned long long>(1, std::min<unsigned long long>(total, (unsigned long long)p->groups[0].grid * 32) / kSlices);
+        Task *staged = (Task *)((char *)p->h_stage + p->stage_layout_bytes);
+        double best_rep = 1e30;
+        for (int rep = 0; rep < 3 && !rc; ++rep) {
+            double ms_sum = 0;
+            unsigned long long valid = 0;
+            for (int k = 0; k < kSlices && !rc; ++k) {
+                const unsigned long long first = total > len ? (total - len) * (unsigned long long)k / (kSlices - 1) : 0;
+                const unsigned long long n = std::min(len, total - first);
+                staged[0].first_item = first;
+                rc = plan_run(c, p, c->stream, n);
+                if (!rc) rc = plan_wait(p);
+                float ms = 0;
+                if (!rc && hipEventElapsedTime(&ms, p->ev[2], p->ev[3]) == hipSuccess) ms_sum += ms;
+                valid += valid_in_items(s, first, first + n);
+                if (total <= len) break;
             }
+            if (!rc && rep > 0 && valid) best_rep = std::min(best_rep, ms_sum * 1e6 / (double)valid);
         }
         plan_free(c, p);
         delete p;
         if (rc) return rc;
-        if (t < best_t) {
-            best_t = t;
-            best = np;
+        report.emplace_back(blk == kForceReducedCells ? 0 : blk, best_rep);
+        if (best_rep < best_t) {
+            best_t = best_rep;
+            best = blk;
         }
     }
-    const int words = (ds->w4[0] + ds->w4[1]) * 4;
-    int bucket = 0;
-    while ((1 << bucket) < words) ++bucket;
+    const TuneKey key{order, size_bucket(ds)};
     {
         std::lock_guard<std::mutex> g(c->tune_mu);
-        c->tuned[TuneKey{order, bucket}] = best;
-        c->seg_pins.erase(TuneKey{order, bucket});
+        c->seg_pins.erase(key);
+        c->tuned.erase(key);
+        if (best == EPI_BLOCK_SEGMENTED) c->seg_pins[key] = 1;
+        else if (order <= 3 || (order == 4 && best == EPI_BLOCK_ALL_CELLS && r4_fits(ds))) c->tuned[key] = best;
+        c->tune_report[key] = report;
         save_tune_cache(c);
     }
-    *choice = best;
+    *choice = best == kForceReducedCells ? 0 : best;
     return EPI_OK;
 }
 
@@ -1755,12 +1836,9 @@ int epi_set_prefix_block(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_
         int rc = ds_ensure_i8(C, d);
         if (rc) return rc;
     }
-    const int words = (d->w4[0] + d->w4[1]) * 4;
-    int bucket = 0;
-    while ((1 << bucket) < words) ++bucket;
     {
         std::lock_guard<std::mutex> g(C->tune_mu);
-        const TuneKey key{order, bucket};
+        const TuneKey key{order, size_bucket(d)};
         if (block == EPI_BLOCK_SEGMENTED) {
             C->seg_pins[key] = 1;
         } else if (block == 0) {
@@ -1842,6 +1920,31 @@ int epi_contingency_tables(epi_ctx *ctx, int32_t dataset_id, int32_t order, cons
 int epi_mutual_information(epi_ctx *ctx, int32_t dataset_id, int32_t order, const uint32_t *d_tables, uint64_t n,
                            double *d_mi, float *kernel_ms) {
     return run_function(ctx, 2, dataset_id, order, nullptr, d_tables, n, d_mi, kernel_ms);
+}
+
+int epi_autotune_report(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t capacity, int32_t *blocks,
+                        double *ns_per_combination, int32_t *n_candidates) {
+    clear_error();
+    CTX_OR_FAIL(ctx);
+    if (!n_candidates || capacity < 0 || (capacity > 0 && (!blocks || !ns_per_combination)))
+        return fail(EPI_EINVAL, "bad report buffers");
+    Dataset *d;
+    {
+        std::lock_guard<std::mutex> g(C->mu);
+        auto it = C->datasets.find(dataset_id);
+        if (it == C->datasets.end()) return fail(EPI_ENOTFOUND, "unknown dataset %d", dataset_id);
+        d = it->second.get();
+    }
+    std::lock_guard<std::mutex> g(C->tune_mu);
+    auto it = C->tune_report.find(TuneKey{order, size_bucket(d)});
+    if (it == C->tune_report.end()) return fail(EPI_ENOTFOUND, "no autotune of order %d for this size bucket", order);
+    const int n = (int)it->second.size();
+    for (int i = 0; i < std::min(n, capacity); ++i) {
+        blocks[i] = it->second[i].first;
+        ns_per_combination[i] = it->second[i].second;
+    }
+    *n_candidates = n;
+    return EPI_OK;
 }
 
 int epi_autotune(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t *choice) {

@@ -22,6 +22,9 @@ namespace epi {
 constexpr int kBinomN = 65537;     // binomial table columns (n = 0 .. 65536)
 constexpr int kGenRanksHost = 4;   // ranks per lane of the per-combination kernel
 constexpr size_t kScratchBytes = EPI_NOALLOC_SCRATCH_BYTES;  // scratch array of allocation-free scans
+// plan_build's forced kernel for order 4: the reduced-cell kernel (the
+// blocks of the C ABI select the others)
+constexpr int kForceReducedCells = 1;
 
 int fail(int code, const char *fmt, ...);
 void clear_error();
@@ -169,6 +172,8 @@ struct Ctx {
     std::mutex tune_mu;
     std::map<TuneKey, int> tuned;
     std::map<TuneKey, int> seg_pins;  // (order, bucket) pinned to the segmented variant
+    // the last autotune of each (order, bucket): candidate block, ns per valid combination
+    std::map<TuneKey, std::vector<std::pair<int, double>>> tune_report;
     std::string tune_path;
     std::map<int, std::shared_ptr<Server>> servers;
     std::mutex items_mu;
@@ -214,8 +219,9 @@ hipError_t launch_qpack8(hipStream_t st, const DsView &d, v4u *qa8, v4u *qb8);
 uint64_t binom_u64(int64_t n, int64_t k);
 int get_items(Ctx *c, int variant, int M, int np, const void **d, unsigned long long *n);
 int check_desc(Ctx *c, const epi_scan_desc &d, Dataset **out);
-void pick_group_kernel(const std::vector<int> &orders, int np3_hint, int *np2, int *np3, int *gk);
-int group_of_order(int order);
+void pick_group_kernel(const std::vector<int> &orders, int np_hint, int *np2, int *np3, int *gk);
+int group_of_order(int order, int np);
+int size_bucket(const Dataset *d);
 bool r4_fits(const Dataset *d);
 int tuned_np_lookup(Ctx *c, int order, const Dataset *d);
 bool seg_pinned(Ctx *c, int order, const Dataset *d);

@@ -91,12 +91,9 @@ static const double kRoundWork = 4e11;
 static const int kQueues = 16;
 
 // Launch group of a request within a round, one per kernel instantiation:
-// order 2, order 3 per prefix block (its work items are built for that
-// block), and each generic order.
-static int round_group(const Request *r) {
-    if (r->desc.order == 3) return 30 + r->np;
-    return r->desc.order;
-}
+// orders 2 and 3 per prefix block (their work items are built for that
+// block), and each higher order.
+static int round_group(const Request *r) { return group_of_order(r->desc.order, r->np); }
 
 static void free_request_buffers(Server *S, Request *r) {
     S->ctx->alloc.release(r->pairs);
@@ -124,7 +121,8 @@ static int admit(Server *S, Request *r) {
     r->n_combos = binom_u64(r->ds->M, o);
     if (o == 2) {
         r->variant = kF2;
-        r->np = 4;
+        const int t = tuned_np_lookup(c, 2, r->ds);
+        r->np = t > 0 ? t : 4;
     } else if (o == 3) {
         r->variant = kF3;
         r->np = default_np3(c, r->ds);
@@ -260,7 +258,7 @@ static int run_round(Server *S) {
         unsigned long long total;
     };
     std::vector<G> groups;
-    for (int key : {30 + kNpMfma, 30 + kNpMfmaI8, 38, 34, 32, 31, 2, 4, 5}) {
+    for (int key : {30 + kNpMfma, 30 + kNpMfmaI8, 38, 34, 32, 31, 22, 24, 28, 4, 5}) {
         std::vector<int> orders;
         G g{0, 0, 0, ti, 0, 0, 1, 0, 0};
         for (int i = 0; i < nt; ++i) {
@@ -269,7 +267,7 @@ static int run_round(Server *S) {
             orders.push_back(r->desc.order);
         }
         if (orders.empty()) continue;
-        pick_group_kernel(orders, key > 30 ? key - 30 : 4, &g.np2, &g.np3, &g.gk);
+        pick_group_kernel(orders, key > 30 ? key - 30 : (key > 20 ? key - 20 : 4), &g.np2, &g.np3, &g.gk);
         g.stage = stage_cap_for(g.np2, g.np3, 0);
         int cap_both = 0, cap_first = 0;
         for (int i = 0; i < nt; ++i) {
@@ -477,7 +475,7 @@ int epi_server_start(epi_ctx *ctx, const epi_server_config *cfg, int32_t *server
     S->cfg = *cfg;
     S->budget = cfg->request_budget ? cfg->request_budget : C->alloc.budget;
     // the largest persistent grid any round may launch (in 4-wave workgroups)
-    static const int kRoundKernels[][3] = {{4, 0, 0}, {0, 1, 0}, {0, 2, 0}, {0, 4, 0},
+    static const int kRoundKernels[][3] = {{2, 0, 0}, {4, 0, 0}, {8, 0, 0}, {0, 1, 0}, {0, 2, 0}, {0, 4, 0},
                                            {0, 8, 0}, {0, kNpMfma, 0}, {0, kNpMfmaI8, 0}, {0, 0, 4}, {0, 0, 5}};
     S->grid_max = 1;
     for (const auto &k : kRoundKernels)

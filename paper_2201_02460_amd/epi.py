@@ -78,6 +78,7 @@ SIGNATURES = {
     "epi_batch_timing": (_c.c_int, [_vp, _i32, _P(_c.c_float)]),
     "epi_batch_destroy": (_c.c_int, [_vp, _i32]),
     "epi_autotune": (_c.c_int, [_vp, _i32, _i32, _P(_i32)]),
+    "epi_autotune_report": (_c.c_int, [_vp, _i32, _i32, _i32, _vp, _vp, _P(_i32)]),
     "epi_set_prefix_block": (_c.c_int, [_vp, _i32, _i32, _i32]),
     "epi_genotype_tables": (_c.c_int, [_vp, _i32, _i32, _vp, _u64, _vp, _P(_c.c_float)]),
     "epi_contingency_tables": (_c.c_int, [_vp, _i32, _i32, _vp, _u64, _vp, _P(_c.c_float)]),
@@ -377,6 +378,17 @@ def epi_autotune(ctx, dataset_id, order):
     out = _i32()
     _check(lib().epi_autotune(ctx, dataset_id, order, ctypes.byref(out)))
     return out.value
+
+
+def epi_autotune_report(ctx, dataset_id, order):
+    """[(block, ns per scored combination)] of the last autotune of the order
+    for the dataset's size bucket."""
+    blocks = np.zeros(16, np.int32)
+    ns = np.zeros(16, np.float64)
+    n = _i32()
+    _check(lib().epi_autotune_report(ctx, dataset_id, order, 16, _ptr(blocks), _ptr(ns), ctypes.byref(n)))
+    k = min(n.value, 16)
+    return [(int(b), float(t)) for b, t in zip(blocks[:k], ns[:k])]
 
 
 def epi_set_prefix_block(ctx, dataset_id, order, block):

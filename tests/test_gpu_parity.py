@@ -405,6 +405,42 @@ def test_autotune_keeps_results(cx, orc):
     epi.epi_unload(cx.ctx, ds)
 
 
+def test_autotune_every_order(cx, orc):
+    """The tuner times every counting kernel of orders 2-5 on slices spread
+    over the scan, reports ns per scored combination for each, and its
+    choice (which persistent batches use too, order 2 included) keeps the
+    results."""
+    from paper_2201_02460_amd import epi
+
+    G, y = random_genotypes(60, 900, seed=23, case_fraction=0.4)
+    ds = cx.load(G, y)
+    try:
+        K = 15
+        plain = {o: cx.scan(ds, o, K) for o in (2, 3, 4, 5)}
+        want = {2: [2, 4, 8], 3: [1, 2, 4, 8, 16], 4: [0, epi.EPI_BLOCK_ALL_CELLS, epi.EPI_BLOCK_SEGMENTED],
+                5: [epi.EPI_BLOCK_ALL_CELLS, epi.EPI_BLOCK_SEGMENTED]}
+        for o in (2, 3, 4, 5):
+            choice = epi.epi_autotune(cx.ctx, ds, o)
+            rep = epi.epi_autotune_report(cx.ctx, ds, o)
+            say("order", o, "choice", choice, "report", rep)
+            assert [b for b, _ in rep] == want[o]
+            assert all(t > 0 for _, t in rep)
+            assert choice == min(rep, key=lambda r: r[1])[0]
+            res = cx.scan(ds, o, K)
+            assert np.array_equal(res["combos"], plain[o]["combos"]) and np.array_equal(res["scores"], plain[o]["scores"])
+        ids = epi.epi_scan_batch(cx.ctx, [(ds, 2, K), (ds, 3, K)])
+        for o, sid in zip((2, 3), ids):
+            epi.epi_wait(cx.ctx, sid)
+            c, sc, t = epi.epi_results(cx.ctx, sid, K, o)
+            assert np.array_equal(c, plain[o]["combos"]) and np.array_equal(t, plain[o]["tables"])
+            epi.epi_release(cx.ctx, sid)
+        check_topk(orc, G, y, 4, K, plain[4]["combos"], plain[4]["scores"], plain[4]["tables"])
+    finally:
+        for o in (2, 3, 4, 5):
+            epi.epi_set_prefix_block(cx.ctx, ds, o, 0)
+        epi.epi_unload(cx.ctx, ds)
+
+
 @pytest.mark.parametrize("N", [9000, 17000])
 def test_large_n_screening_paths(cx, orc, N):
     """Orders 2-4 where the screening table's two halves do not fit in LDS
