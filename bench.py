@@ -421,15 +421,16 @@ def batched_bench(epi, torch, n_scans, reps):
     for i, s in enumerate(specs):
         n_case = s["n_cases"]
         words = 4 * ((n_case + 127) // 128) + 4 * ((s["N"] - n_case + 127) // 128)
-        key = (s["order"], max(0, (words - 1).bit_length()))
+        key = (s["order"], max(0, (words - 1).bit_length()), max(0, (s["M"] - 1).bit_length()))
         if key in seen:
             continue
         seen.add(key)
         choice = epi.epi_autotune(ctx, dss[i], s["order"])
         rep = epi.epi_autotune_report(ctx, dss[i], s["order"])
-        tuned.append({"order": s["order"], "words_bucket": key[1], "tuned_on": {"M": s["M"], "N": s["N"]},
+        tuned.append({"order": s["order"], "words_bucket": key[1], "snp_bucket": key[2],
+                      "tuned_on": {"M": s["M"], "N": s["N"]},
                       "choice": choice, "ns_per_combination": {str(b): round(t, 6) for b, t in rep}})
-        log(f"batched tune order {s['order']} bucket {key[1]} (M={s['M']}, N={s['N']}): pick {choice}, "
+        log(f"batched tune order {s['order']} buckets {key[1]}/{key[2]} (M={s['M']}, N={s['N']}): pick {choice}, "
             + ", ".join(f"{b}: {t:.5f} ns" for b, t in rep))
     out = {}
     for name, persistent, graph in (("batched", True, True), ("back_to_back", False, False)):
@@ -629,6 +630,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="order3_M1000_N4000")
+    ap.add_argument("--block", type=int, default=None,
+                    help="pin the counting kernel of the main workload (a block of epi_set_prefix_block) "
+                         "instead of running the autotuner")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--batched-scans", type=int, default=64)
@@ -674,7 +678,8 @@ def main():
         del b
 
     extra = {}
-    dt, mains, alls, res, sinfo, tuned = plain_bench(epi, torch, spec, G, y, args.steps, args.warmup, extra=extra)
+    dt, mains, alls, res, sinfo, tuned = plain_bench(epi, torch, spec, G, y, args.steps, args.warmup, block=args.block,
+                                                     extra=extra)
     combos, scores, tables = res
     value = n_combos * N * args.steps / dt / 1e12
     ms_main = sum(mains) / len(mains)

@@ -289,10 +289,15 @@ int epi_batch_destroy(epi_ctx *ctx, int32_t batch_id);
  *            32 (EPI_BLOCK_MFMA_I8) -- the same products with 8-bit integer
  *            operands and int32 sums (never chosen by the autotuner: it
  *            moves twice the operand bytes of the 4-bit form for the same
- *            products).
+ *            products);
+ *            48 (EPI_BLOCK_MFMA_FP4_2J) -- the 4-bit products with two
+ *            consecutive middle SNPs per work item, so each operand load
+ *            feeds twice the products (one wave per SIMD, its accumulators
+ *            in the accumulation registers).
  * Every kernel produces the same integers and therefore the same results. */
 #define EPI_BLOCK_MFMA_FP4 16
 #define EPI_BLOCK_MFMA_I8 32
+#define EPI_BLOCK_MFMA_FP4_2J 48
 /* Any order: the segmented exploration of Section 3.4 (Algorithm 2).  Each
  * wave counts the full 2 x 3^k tables of a block of 64 combinations into a
  * device buffer, then scores the block (the fused kernels score each table as
@@ -310,13 +315,17 @@ int epi_batch_destroy(epi_ctx *ctx, int32_t batch_id);
 #define EPI_BLOCK_ALL_CELLS 81
 
 /* Time every counting kernel of `order` on the dataset's own scan and
- * remember the fastest for datasets of the same words-per-individual bucket.
+ * remember the fastest for datasets of the same size bucket (the same
+ * power-of-two buckets of 32-bit words per SNP row and of the number of
+ * SNPs).
  * The candidates are the blocks listed above: order 2 prefix blocks 2, 4, 8;
- * order 3 blocks 1, 2, 4, 8 and EPI_BLOCK_MFMA_FP4; order 4 the reduced-cell
+ * order 3 blocks 1, 2, 4, 8, EPI_BLOCK_MFMA_FP4 and EPI_BLOCK_MFMA_FP4_2J;
+ * order 4 the reduced-cell
  * kernel (reported as 0), EPI_BLOCK_ALL_CELLS and EPI_BLOCK_SEGMENTED;
  * orders 5-8 EPI_BLOCK_ALL_CELLS and EPI_BLOCK_SEGMENTED.  Each is timed on
- * eight slices of work items spread evenly over the whole scan (about 32
- * items per wave slot of the launch in all) and its time divided by the
+ * eight slices of work items spread evenly over the whole scan (each about
+ * 8 items per wave of the launch, or an eighth of the scan if that is less)
+ * and its time divided by the
  * combinations those items score (counted on the host), so kernels whose
  * items hold different numbers of combinations compare fairly.  The choice
  * is also written to the cache file named by EPI_TUNE_CACHE (if set).  Scans

@@ -48,6 +48,11 @@ constexpr int kMergeParts = 32;        // first-stage merge workgroups per task
 constexpr int kMaxBinomOrder = 8;
 constexpr int kNpMfma = 16;            // order-3 block counted by matrix cores, 4-bit float operands
 constexpr int kNpMfmaI8 = 32;          // the same with 8-bit integer operands
+constexpr int kNpMfma2 = 48;           // 4-bit float operands, two middle SNPs per work item
+
+// Prefix blocks of the matrix-core order-3 kernels (their work items and
+// signed cell form differ from the popcount kernels').
+__host__ __device__ constexpr bool is_mfma_np(int np) { return np == kNpMfma || np == kNpMfmaI8 || np == kNpMfma2; }
 constexpr int kQStepMultiple = 4;      // qa / qb: steps per class padded to a multiple of this
 constexpr int kQStageSteps = 64;       // matrix-core kernels: steps of j-mask rows staged in LDS
 
@@ -93,7 +98,7 @@ struct Cand {
 
 struct Task {
     DsView ds;
-    uint32_t *pairs;                  // lex-ordered pair sub-table, 8 u32 per pair
+    uint32_t *pairs;                  // pair sub-table, 8 u32 per pair (lexicographic, or colex: pair_colex)
     uint32_t *triples;                // colex-ordered triplet sub-table, 16 u32 per triplet (kR4, kF3Emit)
     uint32_t *seg;                    // kSeg: per wave slot of the launch (4 per workgroup), 2 x 3^k x 64 u32
                                       //   counts, cell-major ([class][cell][lane])
@@ -116,6 +121,8 @@ struct Task {
     int32_t cell_shift;               // kF2Emit: pair cells are written as (count << cell_shift)
     uint32_t cell_bias;               //   + cell_bias, or with cell_neg as cell_bias - (count << cell_shift)
     int32_t cell_neg;
+    int32_t pair_colex;               // kF2Emit: pair rows at colex ranks C(m,2) + i (the reduced order-4
+                                      //   kernel's lanes vary the lowest index), else lexicographic
     unsigned long long *digest;       // checking launches: [0] combinations scored, [1] their digest sum
                                       //   (null: no check)
 };
@@ -133,10 +140,13 @@ struct Task {
 //              every j with some i < j < m in the blocks, j fastest.  The
 //              groups go in tiles of 4 x 4 blocks (tile rows of mb outer,
 //              then tiles of ib; mb outer, ib inner within a tile), so the
-//              items in flight across the device share a few operand blocks.
+//              items in flight across the device share a few operand blocks;
+//   kItemsF3M2 the same groups, one item per two consecutive middle SNPs j,
+//              j + 1 (descriptor of the first; the last item of an odd run
+//              has one).
 // The host counts a table's items with these functions and the device
 // writes them (items_kernel), group after group.
-enum ItemKind : int32_t { kItemsF2 = 0, kItemsF3 = 1, kItemsF3M = 2 };
+enum ItemKind : int32_t { kItemsF2 = 0, kItemsF3 = 1, kItemsF3M = 2, kItemsF3M2 = 3 };
 constexpr int kItemTile = 4;
 constexpr int kStoreChunkBytes = 1024;  // bytes per store_kernel launch
 
@@ -178,8 +188,9 @@ __host__ __device__ inline ItemGroup item_group(int kind, int M, int np, long lo
     j0 = j0 > 1 ? j0 : 1;
     j1 = j1 < M - 2 ? j1 : M - 2;
     r.base = ((unsigned long long)j0 << 40) | ((unsigned long long)ib << 20) | (unsigned long long)mb;
-    r.step = 1ull << 40;
-    r.count = j1 >= j0 ? (unsigned long long)(j1 - j0 + 1) : 0;
+    const unsigned long long run = j1 >= j0 ? (unsigned long long)(j1 - j0 + 1) : 0;
+    r.step = (kind == kItemsF3M2 ? 2ull : 1ull) << 40;
+    r.count = kind == kItemsF3M2 ? (run + 1) / 2 : run;
     return r;
 }
 

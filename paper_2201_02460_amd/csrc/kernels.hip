@@ -241,6 +241,12 @@ EPI_DEV void mobius4_signed(unsigned (&R)[81]) {
 // Sub-table passes keep no best-K list.
 EPI_DEV bool is_emit(int variant) { return variant == kF2Emit || variant == kF3Emit; }
 
+// Colex rank of x < y: C(y,2) + x.
+EPI_DEV unsigned long long colex2(int x, int y) {
+    const unsigned long long Y = (unsigned long long)y;
+    return Y * (Y - 1) / 2 + (unsigned long long)x;
+}
+
 // Colex rank of x < y < z: C(z,3) + C(y,2) + x (z < 2^21).
 EPI_DEV unsigned long long colex3(int x, int y, int z) {
     const unsigned long long Z = (unsigned long long)z, Y = (unsigned long long)y;
@@ -604,7 +610,7 @@ EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *li
         if constexpr (EMIT) {
             if (valid) {
                 v4u *pv = (v4u *)t.pairs;
-                const unsigned long long r = lexpair(i, m, d.M);
+                const unsigned long long r = t.pair_colex ? colex2(i, m) : lexpair(i, m, d.M);
                 const int sh = t.cell_shift;
                 v4u c0 = v4u{acc[p][0][0] << sh, acc[p][0][1] << sh, acc[p][0][2] << sh, acc[p][0][3] << sh};
                 v4u c1 = v4u{acc[p][1][0] << sh, acc[p][1][1] << sh, acc[p][1][2] << sh, acc[p][1][3] << sh};
@@ -873,8 +879,9 @@ struct QFmt<true> {
     }
 };
 
-template <bool LDS, bool REV, bool I8, bool EMIT = false, bool CHECK = false>
+template <bool LDS, bool REV, bool I8, bool EMIT = false, bool CHECK = false, int NJ = 1>
 EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr, v4u *stage) {
+    static_assert(NJ == 1 || (NJ == 2 && !EMIT && !I8), "two middle SNPs per item: 4-bit scoring kernel only");
     typedef QFmt<I8> Q;
     const DsView d = t.ds;
     const unsigned long long dsc = t.items[local];
@@ -883,8 +890,19 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
     const int mb = uni((int)(dsc & 0xfffffu));
     const int lane = lane_id(), h = lane >> 5;
     const int m = mb * 32 + (lane & 31);
-    const bool mv = m > j && m < d.M;
-    const int m_ld = mv ? m : j + 1;
+    // The item's middle SNPs jv[0] = j and (NJ = 2) jv[1] = j + 1, which
+    // share the i and m blocks and so every operand load of the counting
+    // loop.  jc is a middle SNP below M - 1 for the sub-table reads of lanes
+    // that have no valid triplet (jv[1] may be M - 1).
+    int jv[NJ], jc[NJ], m_ld[NJ];
+    bool mv[NJ];
+    #pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+        jv[jj] = j + jj;
+        jc[jj] = min(jv[jj], d.M - 2);
+        mv[jj] = m > jv[jj] && m < d.M;
+        m_ld[jj] = mv[jj] ? m : jc[jj] + 1;
+    }
 
     // sub-table rows the epilogue needs, issued before the counting loop; all
     // counts below are 4 n, in the signed form of the epilogue (the pair
@@ -893,12 +911,17 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
     gv4u *single4 = (gv4u *)d.single;
     gv4u *pair4 = (gv4u *)t.pairs;
     const unsigned B = q3_bias(d.N), B4 = 4u * B;
-    const v4u sm = (single4[m_ld] << kQScaleShift) - B4;
-    const v4u sj = (((cv4u *)d.single)[j] << kQScaleShift) - B4;  // uniform: a scalar load
+    const v4u sm = (single4[m_ld[0]] << kQScaleShift) - B4;
     const unsigned nall[2] = {13u * B - ((unsigned)d.ncls[0] << kQScaleShift),
                               13u * B - ((unsigned)d.ncls[1] << kQScaleShift)};
-    const unsigned long long rjm = pair_row(j, d.M) + (unsigned)(m_ld - j - 1);
-    const v4u pjm0 = pair4[2 * rjm], pjm1 = pair4[2 * rjm + 1];
+    v4u sj[NJ], pjm0[NJ], pjm1[NJ];
+    #pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+        sj[jj] = (((cv4u *)d.single)[jv[jj]] << kQScaleShift) - B4;  // uniform: a scalar load
+        const unsigned long long rjm = pair_row(jc[jj], d.M) + (unsigned)(m_ld[jj] - jc[jj] - 1);
+        pjm0[jj] = pair4[2 * rjm];
+        pjm1[jj] = pair4[2 * rjm + 1];
+    }
 
     // operands through buffer descriptors (scalar registers): a lane adds
     // its own constant byte offset and a step adds a scalar one, so a step
@@ -908,20 +931,25 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
     const v4u *qa = Q::qa(d), *qb = Q::qb(d);
     const __amdgpu_buffer_rsrc_t rA =
         __builtin_amdgcn_make_buffer_rsrc((void *)(qa + (long long)ib * KS * 64), 0, blk, kBufWord3);
-    const __amdgpu_buffer_rsrc_t rJ =
-        __builtin_amdgcn_make_buffer_rsrc((void *)(qa + (long long)(j >> 4) * KS * 64), 0, blk, kBufWord3);
+    __amdgpu_buffer_rsrc_t rJ[NJ];
+    #pragma unroll
+    for (int jj = 0; jj < NJ; ++jj)
+        rJ[jj] = __builtin_amdgcn_make_buffer_rsrc((void *)(qa + (long long)(jv[jj] >> 4) * KS * 64), 0, blk,
+                                                   kBufWord3);
     const __amdgpu_buffer_rsrc_t rB0 =
         __builtin_amdgcn_make_buffer_rsrc((void *)(qb + (long long)(2 * mb) * KS * 64), 0, blk, kBufWord3);
     const __amdgpu_buffer_rsrc_t rB1 =
         __builtin_amdgcn_make_buffer_rsrc((void *)(qb + (long long)(2 * mb + 1) * KS * 64), 0, blk, kBufWord3);
     const int vo = lane * 16;
-    typename Q::acc_t acc[2][2][2];
+    typename Q::acc_t acc[NJ][2][2][2];
     #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int jj = 0; jj < NJ; ++jj)
         #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int c = 0; c < 2; ++c)
             #pragma unroll
-            for (int e = 0; e < 2; ++e) acc[c][b][e] = (typename Q::acc_t){};
+            for (int b = 0; b < 2; ++b)
+                #pragma unroll
+                for (int e = 0; e < 2; ++e) acc[jj][c][b][e] = (typename Q::acc_t){};
     // Software pipeline: the operands of kQDepth steps are in flight while a
     // step is multiplied (a step's products take far less time than a load
     // from L2).  The steps of both classes form one stream, class 0's first
@@ -931,9 +959,10 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
     // the loads in step order, each step's refills right after its products:
     // left alone, the scheduler sinks all refills to the end of the unrolled
     // block, and the loop then waits for every load in flight at its top.
-    // The two mask rows of j are the same for every lane of a half wave: they
-    // are staged once per segment of kQSeg steps in the wave's LDS slot
-    // (entry 4 step + 2 h + b) and read back with broadcast loads.
+    // The two mask rows of a middle SNP are the same for every lane of a half
+    // wave: they are staged once per segment of kQSeg steps in the wave's LDS
+    // slot (entry jj 4 kQSeg + 4 step + 2 h + b) and read back with broadcast
+    // loads.
     lv4u *slot = (lv4u *)stage;
     const int ks0 = Q::ks(d, 0);
     v4u bA[kQDepth], bB0[kQDepth], bB1[kQDepth];
@@ -952,11 +981,13 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
         // all loads issued at once, no branch between them (entries past the
         // segment repeat its last step's; the slot has room for them)
         #pragma unroll
-        for (int e0 = 0; e0 < 4 * kQSeg; e0 += kWave) {
-            const int e = min(e0 + lane, 4 * n - 1);
-            const int vje = (((e >> 2) * 64) + 32 * ((e >> 1) & 1) + 2 * (j & 15) + (e & 1)) * 16;
-            slot[e0 + lane] = qload(rJ, vje, base * 1024);
-        }
+        for (int jj = 0; jj < NJ; ++jj)
+            #pragma unroll
+            for (int e0 = 0; e0 < 4 * kQSeg; e0 += kWave) {
+                const int e = min(e0 + lane, 4 * n - 1);
+                const int vje = (((e >> 2) * 64) + 32 * ((e >> 1) & 1) + 2 * (jv[jj] & 15) + (e & 1)) * 16;
+                slot[jj * 4 * kQSeg + e0 + lane] = qload(rJ[jj], vje, base * 1024);
+            }
         wave_sync();
     };
     int seg = 0;
@@ -974,13 +1005,16 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
             }
             #pragma unroll
             for (int u = 0; u < kQDepth; ++u) {
-                const int js = 4 * (g - seg + u) + 2 * h;
-                const v4u J0 = slot[js], J1 = slot[js + 1];
-                const v4u A0 = bA[u] & J0, A1 = bA[u] & J1;
-                acc[c][0][0] = Q::mma(A0, bB0[u], acc[c][0][0]);
-                acc[c][0][1] = Q::mma(A0, bB1[u], acc[c][0][1]);
-                acc[c][1][0] = Q::mma(A1, bB0[u], acc[c][1][0]);
-                acc[c][1][1] = Q::mma(A1, bB1[u], acc[c][1][1]);
+                #pragma unroll
+                for (int jj = 0; jj < NJ; ++jj) {
+                    const int js = jj * 4 * kQSeg + 4 * (g - seg + u) + 2 * h;
+                    const v4u J0 = slot[js], J1 = slot[js + 1];
+                    const v4u A0 = bA[u] & J0, A1 = bA[u] & J1;
+                    acc[jj][c][0][0] = Q::mma(A0, bB0[u], acc[jj][c][0][0]);
+                    acc[jj][c][0][1] = Q::mma(A0, bB1[u], acc[jj][c][0][1]);
+                    acc[jj][c][1][0] = Q::mma(A1, bB0[u], acc[jj][c][1][0]);
+                    acc[jj][c][1][1] = Q::mma(A1, bB1[u], acc[jj][c][1][1]);
+                }
                 // refill with the step kQDepth ahead in the stream (the last
                 // steps re-read the stream's last step)
                 const int so = min(g + u + kQDepth, KS - 1) * 1024;
@@ -1003,16 +1037,16 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
         for (int u = 0; u < 8; ++u) {
             const int i = ib * 16 + 2 * h + 4 * (u >> 1) + (u & 1);
             const int r0 = 4 * (u >> 1) + 2 * (u & 1);
-            if (mv && i < j) {
+            if (mv[0] && i < j) {
                 v4u *dst = (v4u *)(tv + 4 * colex3(i, j, m));
                 #pragma unroll
                 for (int c = 0; c < 2; ++c)
                     #pragma unroll
                     for (int a = 0; a < 2; ++a)
-                        dst[2 * c + a] = v4u{Bt - (unsigned)(int)acc[c][0][0][r0 + a],
-                                             Bt - (unsigned)(int)acc[c][0][1][r0 + a],
-                                             Bt - (unsigned)(int)acc[c][1][0][r0 + a],
-                                             Bt - (unsigned)(int)acc[c][1][1][r0 + a]};
+                        dst[2 * c + a] = v4u{Bt - (unsigned)(int)acc[0][c][0][0][r0 + a],
+                                             Bt - (unsigned)(int)acc[0][c][0][1][r0 + a],
+                                             Bt - (unsigned)(int)acc[0][c][1][0][r0 + a],
+                                             Bt - (unsigned)(int)acc[0][c][1][1][r0 + a]};
             }
         }
         return;
@@ -1029,88 +1063,93 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
     // The lane's eight SNPs i: i_local = 4 (u / 2) + 2 h + u % 2, genotype a
     // in register 4 (u / 2) + 2 (u % 2) + a.
     const int i_base = ib * 16 + 2 * h;
-    int i_n = min(i_base, j - 1);
-    unsigned long long row_n = pair_row(i_n, d.M);
-    unsigned long long rim = row_n + (unsigned)(m_ld - i_n - 1);
-    v4u pim_n0 = pair4[2 * rim], pim_n1 = pair4[2 * rim + 1];
     int sb = 0;
     if constexpr (LDS) sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.tq, 81);
     #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int i = i_base + 4 * (u >> 1) + (u & 1);
-        const int i_ld = i_n;
-        const unsigned long long row_i = row_n;
-        const bool valid = mv && i < j;
-        const v4u pim0 = pim_n0, pim1 = pim_n1;
-        if (u + 1 < 8) {
-            // next SNP's pair row, in flight while this one is scored
-            i_n = min(i_base + 4 * ((u + 1) >> 1) + ((u + 1) & 1), j - 1);
-            row_n = pair_row(i_n, d.M);
-            rim = row_n + (unsigned)(m_ld - i_n - 1);
-            pim_n0 = pair4[2 * rim];
-            pim_n1 = pair4[2 * rim + 1];
-        }
-        const v4u si = (single4[i_ld] << kQScaleShift) - B4;
-        const unsigned long long rij = row_i + (unsigned)(j - i_ld - 1);
-        const int r0 = 4 * (u >> 1) + 2 * (u & 1);
-        unsigned F[2][27];
+    for (int jj = 0; jj < NJ; ++jj) {
+        const int jm = jv[jj];
+        int i_n = min(i_base, jc[jj] - 1);  // i below the middle SNP for the sub-table reads
+        unsigned long long row_n = pair_row(i_n, d.M);
+        unsigned long long rim = row_n + (unsigned)(m_ld[jj] - i_n - 1);
+        v4u pim_n0 = pair4[2 * rim], pim_n1 = pair4[2 * rim + 1];
         #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const v4u pij = pair4[2 * rij + c];
-            const v4u pim = c == 0 ? pim0 : pim1;
-            const v4u pjm = c == 0 ? pjm0 : pjm1;
+        for (int u = 0; u < 8; ++u) {
+            const int i = i_base + 4 * (u >> 1) + (u & 1);
+            const int i_ld = i_n;
+            const unsigned long long row_i = row_n;
+            const bool valid = mv[jj] && i < jm;
+            const v4u pim0 = pim_n0, pim1 = pim_n1;
+            if (u + 1 < 8) {
+                // next SNP's pair row, in flight while this one is scored
+                i_n = min(i_base + 4 * ((u + 1) >> 1) + ((u + 1) & 1), jc[jj] - 1);
+                row_n = pair_row(i_n, d.M);
+                rim = row_n + (unsigned)(m_ld[jj] - i_n - 1);
+                pim_n0 = pair4[2 * rim];
+                pim_n1 = pair4[2 * rim + 1];
+            }
+            const v4u si = (single4[i_ld] << kQScaleShift) - B4;
+            const unsigned long long rij = row_i + (unsigned)(jc[jj] - i_ld - 1);
+            const int r0 = 4 * (u >> 1) + 2 * (u & 1);
+            unsigned F[2][27];
             #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int c = 0; c < 2; ++c) {
+                const v4u pij = pair4[2 * rij + c];
+                const v4u pim = c == 0 ? pim0 : pim1;
+                const v4u pjm = c == 0 ? pjm0[jj] : pjm1[jj];
+                #pragma unroll
+                for (int a = 0; a < 2; ++a)
+                    #pragma unroll
+                    for (int b = 0; b < 2; ++b)
+                        #pragma unroll
+                        for (int e = 0; e < 2; ++e)
+                            F[c][9 * a + 3 * b + e] = (unsigned)(int)acc[jj][c][b][e][r0 + a];
+                #pragma unroll
+                for (int a = 0; a < 2; ++a)
+                    #pragma unroll
+                    for (int b = 0; b < 2; ++b) F[c][9 * a + 3 * b + 2] = pij[2 * a + b];
+                #pragma unroll
+                for (int a = 0; a < 2; ++a)
+                    #pragma unroll
+                    for (int e = 0; e < 2; ++e) F[c][9 * a + 6 + e] = pim[2 * a + e];
                 #pragma unroll
                 for (int b = 0; b < 2; ++b)
                     #pragma unroll
-                    for (int e = 0; e < 2; ++e) F[c][9 * a + 3 * b + e] = (unsigned)(int)acc[c][b][e][r0 + a];
-            #pragma unroll
-            for (int a = 0; a < 2; ++a)
-                #pragma unroll
-                for (int b = 0; b < 2; ++b) F[c][9 * a + 3 * b + 2] = pij[2 * a + b];
-            #pragma unroll
-            for (int a = 0; a < 2; ++a)
-                #pragma unroll
-                for (int e = 0; e < 2; ++e) F[c][9 * a + 6 + e] = pim[2 * a + e];
-            #pragma unroll
-            for (int b = 0; b < 2; ++b)
-                #pragma unroll
-                for (int e = 0; e < 2; ++e) F[c][18 + 3 * b + e] = pjm[2 * b + e];
-            F[c][9 * 0 + 8] = si[2 * c + 0];
-            F[c][9 * 1 + 8] = si[2 * c + 1];
-            F[c][18 + 2] = sj[2 * c + 0];
-            F[c][18 + 5] = sj[2 * c + 1];
-            F[c][24] = sm[2 * c + 0];
-            F[c][25] = sm[2 * c + 1];
-            F[c][26] = nall[c];
-            mobius3_signed(F[c]);
-        }
-        if constexpr (CHECK) {
-            unsigned long long sum = 0;
-            #pragma unroll
-            for (int x = 0; x < 27; ++x) {
-                const unsigned n0 = (odd_twos(x) ? B - F[0][x] : F[0][x]) >> kQScaleShift;
-                const unsigned n1 = (odd_twos(x) ? B - F[1][x] : F[1][x]) >> kQScaleShift;
-                sum += (unsigned long long)n0 * cell_weight(0, x) + (unsigned long long)n1 * cell_weight(1, x);
+                    for (int e = 0; e < 2; ++e) F[c][18 + 3 * b + e] = pjm[2 * b + e];
+                F[c][9 * 0 + 8] = si[2 * c + 0];
+                F[c][9 * 1 + 8] = si[2 * c + 1];
+                F[c][18 + 2] = sj[jj][2 * c + 0];
+                F[c][18 + 5] = sj[jj][2 * c + 1];
+                F[c][24] = sm[2 * c + 0];
+                F[c][25] = sm[2 * c + 1];
+                F[c][26] = nall[c];
+                mobius3_signed(F[c]);
             }
-            const int cc[3] = {i, j, m};
-            digest_add(tk, valid, combo_hash<3>(cc), sum);
-        }
-        bool pass = valid;
-        if constexpr (LDS) pass = pass && screen_sum_signed<27, REV>(F[0], F[1], B) >= sb;
-        if (__ballot(pass)) {
-            long long num = t.score_const;
-            #pragma unroll
-            for (int x = 0; x < 27; ++x) {
-                const unsigned n0 = (odd_twos(x) ? B - F[0][x] : F[0][x]) >> kQScaleShift;
-                const unsigned n1 = (odd_twos(x) ? B - F[1][x] : F[1][x]) >> kQScaleShift;
-                num += cell_term(d.tlog, (int)n0, (int)n1, (unsigned)d.N);
+            if constexpr (CHECK) {
+                unsigned long long sum = 0;
+                #pragma unroll
+                for (int x = 0; x < 27; ++x) {
+                    const unsigned n0 = (odd_twos(x) ? B - F[0][x] : F[0][x]) >> kQScaleShift;
+                    const unsigned n1 = (odd_twos(x) ? B - F[1][x] : F[1][x]) >> kQScaleShift;
+                    sum += (unsigned long long)n0 * cell_weight(0, x) + (unsigned long long)n1 * cell_weight(1, x);
+                }
+                const int cc[3] = {i, jm, m};
+                digest_add(tk, valid, combo_hash<3>(cc), sum);
             }
-            const unsigned long long key =
-                ((unsigned long long)i << 42) | ((unsigned long long)j << 21) | (unsigned long long)m;
-            tk_offer(tk, list, pass, num, key, gthr);
-            if constexpr (LDS) sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.tq, 81);
+            bool pass = valid;
+            if constexpr (LDS) pass = pass && screen_sum_signed<27, REV>(F[0], F[1], B) >= sb;
+            if (__ballot(pass)) {
+                long long num = t.score_const;
+                #pragma unroll
+                for (int x = 0; x < 27; ++x) {
+                    const unsigned n0 = (odd_twos(x) ? B - F[0][x] : F[0][x]) >> kQScaleShift;
+                    const unsigned n1 = (odd_twos(x) ? B - F[1][x] : F[1][x]) >> kQScaleShift;
+                    num += cell_term(d.tlog, (int)n0, (int)n1, (unsigned)d.N);
+                }
+                const unsigned long long key =
+                    ((unsigned long long)i << 42) | ((unsigned long long)jm << 21) | (unsigned long long)m;
+                tk_offer(tk, list, pass, num, key, gthr);
+                if constexpr (LDS) sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.tq, 81);
+            }
         }
     }
 }
@@ -1139,6 +1178,76 @@ EPI_DEV void colex_unrank(unsigned long long rank, int M, const unsigned long lo
         rank -= row[lo];
     }
 }
+
+// The combinations of a wave's 64 consecutive colex ranks first .. first +
+// 63: c enters as the combination of rank first (the same in every lane) and
+// leaves as that of rank first + lane, by steps through the colex order,
+// where the lowest index rises until it meets the next one, and the next
+// combination then raises the lowest index that can grow and resets those
+// below it to 0, 1, ...  A lane passes the loop once per run of its lowest
+// index that it crosses, a few times at most.  Lanes past the last
+// combination (valid false) get the first one, 0, 1, ..., K - 1.
+template <int K>
+EPI_DEV void colex_advance(int (&c)[K], int steps, bool valid) {
+    if (!valid) {
+        #pragma unroll
+        for (int t = 0; t < K; ++t) c[t] = t;
+        return;
+    }
+    #pragma unroll 1
+    while (steps > 0) {
+        const int room = c[1] - 1 - c[0];
+        if (steps <= room) {
+            c[0] += steps;
+            break;
+        }
+        steps -= room + 1;
+        int t = 1;
+        #pragma unroll 1
+        while (t < K - 1 && c[t] + 1 >= c[t + 1]) ++t;
+        #pragma unroll
+        for (int u = 0; u < K; ++u) {
+            if (u == t) c[u] += 1;
+            else if (u < t) c[u] = u;
+        }
+    }
+}
+
+// The combination after c in the colex order (wave-uniform values).
+template <int K>
+EPI_DEV void colex_next(int (&c)[K]) {
+    int t = 0;
+    #pragma unroll 1
+    while (t < K - 1 && c[t] + 1 >= c[t + 1]) ++t;
+    #pragma unroll
+    for (int u = 0; u < K; ++u) {
+        if (u == t) c[u] += 1;
+        else if (u < t) c[u] = u;
+    }
+}
+
+// Lane combinations of a per-combination work item, one block of 64 colex
+// ranks after another: the item's first rank is unranked once, each block
+// starts at the successor of the previous block's last combination, and the
+// lanes step from there.
+template <int K>
+struct ColexWalk {
+    int first[K];
+    EPI_DEV void start(unsigned long long rank, int M, const unsigned long long *binom, int bstride) {
+        colex_unrank<K>(rank, M, binom, bstride, first);
+        #pragma unroll
+        for (int t = 0; t < K; ++t) first[t] = uni(first[t]);
+    }
+    // this lane's combination of the block (c), then the next block's first
+    EPI_DEV void lane(int (&c)[K], bool valid) {
+        #pragma unroll
+        for (int t = 0; t < K; ++t) c[t] = first[t];
+        colex_advance<K>(c, lane_id(), valid);
+        #pragma unroll
+        for (int t = 0; t < K; ++t) first[t] = __builtin_amdgcn_readlane(c[t], kWave - 1);
+        colex_next<K>(first);
+    }
+};
 
 // Grouped counting for K >= 5: the three 27-cell chunks that differ only in
 // the genotype of the last prefix SNP c[K-4] are counted in one pass over the
@@ -1342,12 +1451,13 @@ EPI_DEV void item_generic(const Task &t, unsigned long long local, TopK &tk, Can
                           const unsigned long long *binom, int bstride) {
     const DsView d = t.ds;
     const int bits = t.key_bits;
+    ColexWalk<K> walk;
+    walk.start(local * kGenRanks * kWave, d.M, binom, bstride);
     for (int rr = 0; rr < kGenRanks; ++rr) {
-        unsigned long long rank = (local * kGenRanks + rr) * kWave + lane_id();
+        const unsigned long long rank = (local * kGenRanks + rr) * kWave + lane_id();
         const bool valid = rank < t.n_combos;
-        rank = valid ? rank : 0ull;
         int c[K];
-        colex_unrank<K>(rank, d.M, binom, bstride, c);
+        walk.lane(c, valid);
         unsigned long long sum = 0;
         const long long num = generic_num<K, false, LDT, CHECK>(d, c, t.score_const, nullptr, kWave, &sum);
         if constexpr (CHECK) digest_add(tk, valid, combo_hash<K>(c), sum);
@@ -1375,13 +1485,14 @@ EPI_DEV void item_seg(const Task &t, unsigned long long local, TopK &tk, Cand *l
     const int bits = t.key_bits;
     const int lane = lane_id();
     uint32_t *mine = slot + lane;
+    ColexWalk<K> walk;
+    walk.start(local * kGenRanks * kWave, d.M, binom, bstride);
     #pragma unroll 1
     for (int rr = 0; rr < kGenRanks; ++rr) {
-        unsigned long long rank = (local * kGenRanks + rr) * kWave + lane;
+        const unsigned long long rank = (local * kGenRanks + rr) * kWave + lane;
         const bool valid = rank < t.n_combos;
-        rank = valid ? rank : 0ull;
         int c[K];
-        colex_unrank<K>(rank, d.M, binom, bstride, c);
+        walk.lane(c, valid);
         // phase 1: the block's tables
         (void)generic_num<K, true>(d, c, 0, mine);
         // phase 2: their scores
@@ -1424,13 +1535,14 @@ EPI_DEV void item_r4(const Task &t, unsigned long long local, TopK &tk, Cand *li
     gv4u *pair4 = (gv4u *)t.pairs;
     gv4u *trip4 = (gv4u *)t.triples;
     const long long Mp = d.Mp;
+    ColexWalk<4> walk;
+    walk.start(local * kGenRanks * kWave, d.M, binom, bstride);
     #pragma unroll 1
     for (int rr = 0; rr < kGenRanks; ++rr) {
-        unsigned long long rank = (local * kGenRanks + rr) * kWave + lane_id();
+        const unsigned long long rank = (local * kGenRanks + rr) * kWave + lane_id();
         const bool valid = rank < t.n_combos;
-        rank = valid ? rank : 0ull;
         int c[4];
-        colex_unrank<4>(rank, d.M, binom, bstride, c);
+        walk.lane(c, valid);
         unsigned acc[2][16];
         // consecutive colex ranks share their two last SNPs almost always:
         // then their rows are wave-uniform scalar loads and their four
@@ -1539,7 +1651,7 @@ EPI_DEV void item_r4(const Task &t, unsigned long long local, TopK &tk, Cand *li
         for (int u0 = 0; u0 < 4; ++u0)
             #pragma unroll
             for (int u1 = u0 + 1; u1 < 4; ++u1) {
-                const unsigned long long pr = lexpair(c[u0], c[u1], d.M);
+                const unsigned long long pr = colex2(c[u0], c[u1]);  // the pair sub-table in colex order
                 #pragma unroll
                 for (int cl = 0; cl < 2; ++cl) {
                     const v4u pv = pair4[2 * pr + cl];
@@ -1607,10 +1719,12 @@ EPI_DEV void item_r4(const Task &t, unsigned long long local, TopK &tk, Cand *li
 // ---------------------------------------------------------------------------
 // Register budget per instantiation: enough waves per SIMD to hide load
 // latency; the accumulators (16 per prefix for order 3, 8 for order 2, 128
-// for the matrix-core order-3 kernel) set the floor.
+// for the matrix-core order-3 kernel, 256 for its two-middle-SNP form, which
+// takes a whole SIMD's registers) set the floor.
 template <int NP2, int NP3, int GK>
 constexpr int scan_waves_per_eu() {
-    return GK >= 4 ? 2 : (GK == 3 ? 3 : (NP3 >= 8 ? 2 : (NP3 >= 4 ? 3 : (NP3 >= 2 ? 4 : (NP2 >= 8 ? 3 : 4)))));
+    return NP3 == kNpMfma2 ? 1
+                           : (GK >= 4 ? 2 : (GK == 3 ? 3 : (NP3 >= 8 ? 2 : (NP3 >= 4 ? 3 : (NP3 >= 2 ? 4 : (NP2 >= 8 ? 3 : 4))))));
 }
 
 // CHECK: the checking instantiation, which also adds every scored
@@ -1682,7 +1796,7 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
             const bool want = (T0.variant == kF2 || T0.variant == kF2Fold || T0.variant == kF3 || T0.variant == kR4) &&
                               ent_fwd <= tab_cap &&
                               (unsigned)(uintptr_t)(lu32 *)s_tab == 0u;
-            const bool sgn = (T0.variant == kF3 && (T0.np == kNpMfma || T0.np == kNpMfmaI8)) || T0.variant == kR4;
+            const bool sgn = (T0.variant == kF3 && is_mfma_np(T0.np)) || T0.variant == kR4;
             const bool rev = want && sgn && ent_rev <= tab_cap;  // read only in the signed cell form
             if (want && (loaded != T0.ds.itab || (rev && !loaded_rev))) {
                 const int ent = rev ? ent_rev : ent_fwd;
@@ -1768,11 +1882,13 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
                 }
                 break;
             case kF3:
-                if constexpr (NP3 == kNpMfma || NP3 == kNpMfmaI8) {
+                if constexpr (is_mfma_np(NP3)) {
                     constexpr bool i8 = NP3 == kNpMfmaI8;
-                    if (lds && loaded_rev) item_f3m<true, true, i8, false, CHECK>(T, local, tk, s_list, gthr, s_stage);
-                    else if (lds) item_f3m<true, false, i8, false, CHECK>(T, local, tk, s_list, gthr, s_stage);
-                    else item_f3m<false, false, i8, false, CHECK>(T, local, tk, s_list, gthr, s_stage);
+                    constexpr int nj = NP3 == kNpMfma2 ? 2 : 1;
+                    if (lds && loaded_rev)
+                        item_f3m<true, true, i8, false, CHECK, nj>(T, local, tk, s_list, gthr, s_stage);
+                    else if (lds) item_f3m<true, false, i8, false, CHECK, nj>(T, local, tk, s_list, gthr, s_stage);
+                    else item_f3m<false, false, i8, false, CHECK, nj>(T, local, tk, s_list, gthr, s_stage);
                 } else if constexpr (NP3 > 0) {
                     if (lds) item_f3<NP3, true, CHECK>(T, local, tk, s_list, gthr, s_stage, stage_cap);
                     else item_f3<NP3, false, CHECK>(T, local, tk, s_list, gthr, s_stage, stage_cap);
@@ -1845,7 +1961,8 @@ struct ScanKernelEntry {
         {0, 0, kSegGk + 7, scan_persistent<0, 0, kSegGk + 7, CK>},                                                 \
         {0, 0, kSegGk + 8, scan_persistent<0, 0, kSegGk + 8, CK>},                                                 \
         {0, kNpMfma, 0, scan_persistent<0, kNpMfma, 0, CK>}, /* order 3, matrix cores */                         \
-        {0, kNpMfmaI8, 0, scan_persistent<0, kNpMfmaI8, 0, CK>},
+        {0, kNpMfmaI8, 0, scan_persistent<0, kNpMfmaI8, 0, CK>},                                                  \
+        {0, kNpMfma2, 0, scan_persistent<0, kNpMfma2, 0, CK>},
 
 #ifdef EPI_SCAN_CHECK
 static const ScanKernelEntry kScanKernelsCheck[] = {EPI_SCAN_KERNELS(true)};

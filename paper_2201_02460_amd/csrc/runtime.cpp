@@ -426,7 +426,8 @@ static int tuned_np(Ctx *c, int order, const Dataset *d) {
 // (items_kernel) and the host only counts their items.
 static int item_kind(int variant, int np) {
     if (variant != kF3) return kItemsF2;
-    return np == kNpMfma || np == kNpMfmaI8 ? kItemsF3M : kItemsF3;
+    if (np == kNpMfma2) return kItemsF3M2;
+    return is_mfma_np(np) ? kItemsF3M : kItemsF3;
 }
 
 static unsigned long long item_count(int kind, int M, int np) {
@@ -639,7 +640,7 @@ int group_of_order(int order, int np) {
 // has its operand copies, else 4.
 int default_np3(Ctx *c, const Dataset *d) {
     const int t = tuned_np_lookup(c, 3, d);
-    if (t > 0 && (t != kNpMfma || d->qa) && (t != kNpMfmaI8 || d->qa8)) return t;
+    if (t > 0 && ((t != kNpMfma && t != kNpMfma2) || d->qa) && (t != kNpMfmaI8 || d->qa8)) return t;
     return d->qa ? kNpMfma : 4;
 }
 
@@ -656,7 +657,8 @@ static int wgs_per_cu(int np2, int np3, int gk, int tab_cap, int kmax, int stage
         lds_static = 0;
     }
     const int alloc = std::max(8, (vgprs + 7) / 8 * 8);
-    int waves = std::min(8, 512 / alloc);
+    // the two-middle-SNP matrix-core kernel also fills the accumulation registers
+    int waves = np3 == kNpMfma2 ? 1 : std::min(8, 512 / alloc);
     if (const char *e = getenv("EPI_WAVES_PER_SIMD")) waves = std::max(1, std::min(16, atoi(e)));
     const size_t lds = scan_lds_bytes(tab_cap, kmax, stage_cap) + (size_t)lds_static;
     const int by_lds = (int)std::max<size_t>(1, (160 * 1024) / std::max<size_t>(lds, 1));
@@ -675,8 +677,8 @@ int grid_for(Ctx *c, int np2, int np3, int gk, unsigned long long items, int tab
 // (at most 16 groups of 4 words, 2048 individuals of a class, which keeps
 // three 4-wave workgroups per CU next to an 8001-entry screening table).
 int stage_cap_for(int np2, int np3, int w4_max) {
-    const bool mfma = np3 == kNpMfma || np3 == kNpMfmaI8;
-    if (mfma) return 4 * kQStageSteps;  // j-mask rows: 4 entries per step
+    if (np3 == kNpMfma2) return 8 * kQStageSteps;  // two middle SNPs' mask rows: 4 entries per step each
+    if (is_mfma_np(np3)) return 4 * kQStageSteps;  // j-mask rows: 4 entries per step
     const int rows = std::max(np2 > 0 ? 2 * np2 : 0, np3 > 0 ? 2 * (np3 + 1) : 0);
     if (rows == 0) return 0;
     return rows * std::max(1, std::min(w4_max, 16));
@@ -685,11 +687,12 @@ int stage_cap_for(int np2, int np3, int w4_max) {
 // Cell form of the pair sub-table a scan's pair pass writes (the consumers'
 // signed cell form, layout in epi_internal.hpp).
 void set_pair_form(Task &t, const Dataset *d, int order, int variant, int np) {
-    const bool q3 = order == 3 && (np == kNpMfma || np == kNpMfmaI8);
+    const bool q3 = order == 3 && is_mfma_np(np);
     const bool r4 = variant == kR4;
     t.cell_shift = q3 || r4 ? kQScaleShift : 0;
     t.cell_bias = q3 ? q3_bias(d->N) : (r4 ? 0u - 4u * q3_bias(d->N) : 0u);
     t.cell_neg = q3 ? 1 : 0;
+    t.pair_colex = r4 ? 1 : 0;
 }
 
 // Screening-table entries a scan takes in LDS: the first half (N + 1) when
@@ -701,7 +704,7 @@ int tab_entries_for(const Dataset *d, int variant, int np, bool both) {
     if (variant == kGeneric || variant == kSeg)  // exact int64 table, n = 0 .. N
         return 2 * (d->N + 1) <= Plan::kTabMax ? 2 * (d->N + 1) : 0;
     if (variant != kF2 && variant != kF3 && variant != kR4) return 0;
-    const bool sgn = (variant == kF3 && (np == kNpMfma || np == kNpMfmaI8)) || variant == kR4;
+    const bool sgn = (variant == kF3 && is_mfma_np(np)) || variant == kR4;
     if (both && sgn && 2 * d->N + 2 <= Plan::kTabMax) return 2 * d->N + 2;
     return d->N + 1 <= Plan::kTabMax ? d->N + 1 : 0;
 }
@@ -1258,11 +1261,15 @@ static void save_tune_cache(Ctx *c) {
         f << c->arch << " " << kv.first.order << " " << kv.first.bucket << " " << EPI_BLOCK_SEGMENTED << "\n";
 }
 
+// Size bucket of a dataset for tuned choices: the power-of-two buckets of
+// its 32-bit words per SNP row (both classes) and of its number of SNPs, as
+// 64 x words bucket + SNP bucket.
 int size_bucket(const Dataset *d) {
     const int words = (d->w4[0] + d->w4[1]) * 4;
-    int bucket = 0;
-    while ((1 << bucket) < words) ++bucket;
-    return bucket;
+    int wb = 0, mb = 0;
+    while ((1 << wb) < words) ++wb;
+    while ((1 << mb) < d->M) ++mb;
+    return wb * 64 + mb;
 }
 
 // Combinations a kernel scores in items [a, b) of a scan: the valid triplets
@@ -1312,7 +1319,10 @@ static std::vector<int> tune_candidates(const Dataset *ds, int order) {
     if (order == 2) return {2, 4, 8};
     if (order == 3) {
         std::vector<int> v{1, 2, 4, 8};
-        if (ds->qa) v.push_back(kNpMfma);
+        if (ds->qa) {
+            v.push_back(kNpMfma);
+            v.push_back(kNpMfma2);
+        }
         return v;
     }
     std::vector<int> v;
@@ -1324,9 +1334,10 @@ static std::vector<int> tune_candidates(const Dataset *ds, int order) {
 
 // Time each candidate kernel on slices spread over the whole work-item space
 // of the dataset's own scan (kSlices contiguous runs at evenly spaced
-// starts, about 32 items per wave slot in all), normalised by the
-// combinations those items score (counted on the host from the items), and
-// keep the fastest per (order, size bucket).
+// starts, each about 8 items per wave of its launch, so the launch's start
+// and drain do not decide), normalised by the combinations those items score
+// (counted on the host from the items), and keep the fastest per (order,
+// size bucket).
 int autotune(Ctx *c, int ds_id, int order, int *choice) {
     constexpr int kSlices = 8;
     Dataset *ds;
@@ -1346,8 +1357,8 @@ int autotune(Ctx *c, int ds_id, int order, int *choice) {
         if (rc) return rc;
         const PlanScan &s = p->scans[0];
         const unsigned long long total = s.n_items;
-        const unsigned long long len =
-            std::max<unsigned long long>(1, std::min<unsigned long long>(total, (unsigned long long)p->groups[0].grid * 32) / kSlices);
+        const unsigned long long len = std::max<unsigned long long>(
+            1, std::min<unsigned long long>(total / kSlices, (unsigned long long)p->groups[0].grid * 4 * 8));
         Task *staged = (Task *)((char *)p->h_stage + p->stage_layout_bytes);
         double best_rep = 1e30;
         for (int rep = 0; rep < 3 && !rc; ++rep) {
@@ -1369,7 +1380,7 @@ int autotune(Ctx *c, int ds_id, int order, int *choice) {
         plan_free(c, p);
         delete p;
         if (rc) return rc;
-        report.emplace_back(blk == kForceReducedCells ? 0 : blk, best_rep);
+        report.emplace_back(order >= 4 && blk == kForceReducedCells ? 0 : blk, best_rep);
         if (best_rep < best_t) {
             best_t = best_rep;
             best = blk;
@@ -1385,7 +1396,7 @@ int autotune(Ctx *c, int ds_id, int order, int *choice) {
         c->tune_report[key] = report;
         save_tune_cache(c);
     }
-    *choice = best == kForceReducedCells ? 0 : best;
+    *choice = order >= 4 && best == kForceReducedCells ? 0 : best;
     return EPI_OK;
 }
 
@@ -1822,13 +1833,12 @@ int epi_set_prefix_block(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_
         d = it->second.get();
     }
     const bool ok2 = order == 2 && (block == 2 || block == 4 || block == 8);
-    const bool ok3 = order == 3 && (block == 1 || block == 2 || block == 4 || block == 8 || block == kNpMfma ||
-                                    block == kNpMfmaI8);
+    const bool ok3 = order == 3 && (block == 1 || block == 2 || block == 4 || block == 8 || is_mfma_np(block));
     const bool any = order >= EPI_MIN_ORDER && order <= EPI_MAX_ORDER && (block == 0 || block == EPI_BLOCK_SEGMENTED);
     const bool all4 = order >= 4 && order <= EPI_MAX_ORDER && block == EPI_BLOCK_ALL_CELLS;
     if (!ok2 && !ok3 && !any && !all4)
         return fail(EPI_EINVAL, "prefix block %d is not a kernel of order %d", block, order);
-    if (block == kNpMfma && !d->qa)
+    if ((block == kNpMfma || block == kNpMfma2) && !d->qa)
         return fail(EPI_EUNSUPPORTED, "dataset %d has no matrix-core operands (2^22 individuals or more)", dataset_id);
     if (block == kNpMfmaI8) {
         if (d->N >= (1 << 22))

@@ -258,7 +258,7 @@ static int run_round(Server *S) {
         unsigned long long total;
     };
     std::vector<G> groups;
-    for (int key : {30 + kNpMfma, 30 + kNpMfmaI8, 38, 34, 32, 31, 22, 24, 28, 4, 5}) {
+    for (int key : {30 + kNpMfma, 30 + kNpMfma2, 30 + kNpMfmaI8, 38, 34, 32, 31, 22, 24, 28, 4, 5}) {
         std::vector<int> orders;
         G g{0, 0, 0, ti, 0, 0, 1, 0, 0};
         for (int i = 0; i < nt; ++i) {
@@ -476,7 +476,8 @@ int epi_server_start(epi_ctx *ctx, const epi_server_config *cfg, int32_t *server
     S->budget = cfg->request_budget ? cfg->request_budget : C->alloc.budget;
     // the largest persistent grid any round may launch (in 4-wave workgroups)
     static const int kRoundKernels[][3] = {{2, 0, 0}, {4, 0, 0}, {8, 0, 0}, {0, 1, 0}, {0, 2, 0}, {0, 4, 0},
-                                           {0, 8, 0}, {0, kNpMfma, 0}, {0, kNpMfmaI8, 0}, {0, 0, 4}, {0, 0, 5}};
+                                           {0, 8, 0}, {0, kNpMfma, 0}, {0, kNpMfma2, 0}, {0, kNpMfmaI8, 0},
+                                           {0, 0, 4}, {0, 0, 5}};
     S->grid_max = 1;
     for (const auto &k : kRoundKernels)
         S->grid_max = std::max(S->grid_max,

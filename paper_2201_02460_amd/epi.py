@@ -29,6 +29,7 @@ EPI_MAX_ORDER = 8
 EPI_SERVE_MAX_ORDER = 5
 EPI_BLOCK_MFMA_FP4 = 16
 EPI_BLOCK_MFMA_I8 = 32
+EPI_BLOCK_MFMA_FP4_2J = 48
 EPI_BLOCK_SEGMENTED = 64
 EPI_BLOCK_ALL_CELLS = 81
 EPI_NOALLOC_SCRATCH_BYTES = 134217728

@@ -42,7 +42,8 @@ def kernels_of(order):
     if order == 2:
         return [2, 4, 8, epi.EPI_BLOCK_SEGMENTED]
     if order == 3:
-        return [1, 2, 4, 8, epi.EPI_BLOCK_MFMA_FP4, epi.EPI_BLOCK_MFMA_I8, epi.EPI_BLOCK_SEGMENTED]
+        return [1, 2, 4, 8, epi.EPI_BLOCK_MFMA_FP4, epi.EPI_BLOCK_MFMA_FP4_2J, epi.EPI_BLOCK_MFMA_I8,
+                epi.EPI_BLOCK_SEGMENTED]
     if order == 4:
         return [0, epi.EPI_BLOCK_ALL_CELLS, epi.EPI_BLOCK_SEGMENTED]  # 0: reduced cells
     return [0, epi.EPI_BLOCK_SEGMENTED]  # 0: all cells

@@ -398,7 +398,7 @@ def test_autotune_keeps_results(cx, orc):
     ds = cx.load(G, y)
     before = cx.scan(ds, 3, 20)
     choice = epi.epi_autotune(cx.ctx, ds, 3)
-    assert choice in (1, 2, 4, 8, 16)  # 16: the matrix-core kernel
+    assert choice in (1, 2, 4, 8, 16, 48)  # 16, 48: the matrix-core kernels
     after = cx.scan(ds, 3, 20)
     assert np.array_equal(before["combos"], after["combos"]) and np.array_equal(before["scores"], after["scores"])
     check_topk(orc, G, y, 3, 20, after["combos"], after["scores"], after["tables"])
@@ -417,7 +417,7 @@ def test_autotune_every_order(cx, orc):
     try:
         K = 15
         plain = {o: cx.scan(ds, o, K) for o in (2, 3, 4, 5)}
-        want = {2: [2, 4, 8], 3: [1, 2, 4, 8, 16], 4: [0, epi.EPI_BLOCK_ALL_CELLS, epi.EPI_BLOCK_SEGMENTED],
+        want = {2: [2, 4, 8], 3: [1, 2, 4, 8, 16, 48], 4: [0, epi.EPI_BLOCK_ALL_CELLS, epi.EPI_BLOCK_SEGMENTED],
                 5: [epi.EPI_BLOCK_ALL_CELLS, epi.EPI_BLOCK_SEGMENTED]}
         for o in (2, 3, 4, 5):
             choice = epi.epi_autotune(cx.ctx, ds, o)
@@ -493,7 +493,7 @@ def test_counting_kernels_agree(cx, orc):
     G, y = random_genotypes(150, 1100, seed=31, case_fraction=0.35)
     ds = cx.load(G, y)
     ref = None
-    for block in (1, 2, 4, 8, epi.EPI_BLOCK_MFMA_FP4, epi.EPI_BLOCK_MFMA_I8):
+    for block in (1, 2, 4, 8, epi.EPI_BLOCK_MFMA_FP4, epi.EPI_BLOCK_MFMA_FP4_2J, epi.EPI_BLOCK_MFMA_I8):
         say("prefix block", block)
         epi.epi_set_prefix_block(cx.ctx, ds, 3, block)
         res = cx.scan(ds, 3, 30)
