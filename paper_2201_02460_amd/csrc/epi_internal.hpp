@@ -99,7 +99,7 @@ struct Cand {
 struct Task {
     DsView ds;
     uint32_t *pairs;                  // pair sub-table, 8 u32 per pair (lexicographic, or colex: pair_colex)
-    uint32_t *triples;                // colex-ordered triplet sub-table, 16 u32 per triplet (kR4, kF3Emit)
+    uint32_t *triples;                // colex-ordered triplet sub-table, 8 u32 per triplet (kR4, kF3Emit)
     uint32_t *seg;                    // kSeg: per wave slot of the launch (4 per workgroup), 2 x 3^k x 64 u32
                                       //   counts, cell-major ([class][cell][lane])
     const unsigned long long *items;  // per-item descriptors: kF3 j<<40 | ib<<20 | mb, kF2 ib<<20 | mb
@@ -121,8 +121,9 @@ struct Task {
     int32_t cell_shift;               // kF2Emit: pair cells are written as (count << cell_shift)
     uint32_t cell_bias;               //   + cell_bias, or with cell_neg as cell_bias - (count << cell_shift)
     int32_t cell_neg;
-    int32_t pair_colex;               // kF2Emit: pair rows at colex ranks C(m,2) + i (the reduced order-4
-                                      //   kernel's lanes vary the lowest index), else lexicographic
+    int32_t pair_colex;               // kF2Emit: pair rows at colex ranks C(m,2) + i, one word per cell
+                                      //   with both classes (the reduced order-4 kernel's lanes vary the
+                                      //   lowest index), else lexicographic
     unsigned long long *digest;       // checking launches: [0] combinations scored, [1] their digest sum
                                       //   (null: no check)
 };
@@ -229,14 +230,15 @@ constexpr int kHistWords = 64 * kHistFine;
 
 // Matrix-core order-3 kernels count 4 x n (their B operand holds 4 for a set
 // bit), so a count is also the byte offset of its screening-table entry.
-// Their epilogue, and that of order 4 by reduced cells, hold a cell with an
-// odd number of marginal SNPs as q3_bias(N) - 4n and the others as 4n, and
-// take their marginal inputs with offsets that keep that form through the
-// inclusion-exclusion (a multiple o_t of q3_bias(N) for t marginal SNPs:
-// 1, -4, 13, -40 for t = 1 .. 4, sign (-1)^t on the 4n).  So the pair
-// sub-table is written with cell_shift = kQScaleShift and (order 3)
-// cell_bias = q3_bias(N), cell_neg = 1, or (order 4) cell_bias =
-// -4 q3_bias(N), cell_neg = 0; the triplet sub-table as q3_bias(N) - 4n.
+// Their epilogue holds a cell with an odd number of marginal SNPs as
+// q3_bias(N) - 4n and the others as 4n, and takes its marginal inputs with
+// offsets that keep that form through the inclusion-exclusion (a multiple
+// o_t of q3_bias(N) for t marginal SNPs: 1, -4, 13 for t = 1 .. 3, sign
+// (-1)^t on the 4n).  So their pair sub-table is written with cell_shift =
+// kQScaleShift, cell_bias = q3_bias(N), cell_neg = 1.  Order 4 by reduced
+// cells holds both classes of a cell in one word instead, 4 n(cases) |
+// 4 n(controls) << 16 (pair_colex pair sub-table, 16 B per pair; triplet
+// sub-table 32 B per triplet).
 constexpr int kQScaleShift = 2;
 
 // Byte offset just past the screening table's two halves (2N + 2 entries):

@@ -202,7 +202,8 @@ EPI_DEV void mobius3(int (&R)[27]) {
     for (int ab = 0; ab < 9; ++ab) R[3 * ab + 2] -= R[3 * ab] + R[3 * ab + 1];
 }
 
-EPI_DEV void mobius4(int (&R)[81]) {
+template <class T>
+EPI_DEV void mobius4(T (&R)[81]) {
     #pragma unroll
     for (int st = 27; st >= 1; st /= 3)
         #pragma unroll
@@ -229,14 +230,6 @@ EPI_DEV void mobius3_signed(unsigned (&R)[27]) {
     for (int ab = 0; ab < 9; ++ab) R[3 * ab + 2] += R[3 * ab] + R[3 * ab + 1];
 }
 
-// mobius4 on the signed cell form.
-EPI_DEV void mobius4_signed(unsigned (&R)[81]) {
-    #pragma unroll
-    for (int st = 27; st >= 1; st /= 3)
-        #pragma unroll
-        for (int x = 0; x < 81; ++x)
-            if ((x / st) % 3 == 2) R[x] += R[x - 2 * st] + R[x - st];
-}
 
 // Sub-table passes keep no best-K list.
 EPI_DEV bool is_emit(int variant) { return variant == kF2Emit || variant == kF3Emit; }
@@ -519,6 +512,23 @@ EPI_DEV int screen_sum_signed(const unsigned (&F0)[CELLS], const unsigned (&F1)[
     return (int)(p - q - qh);
 }
 
+// Same for the packed cell form of order 4 by reduced cells (both classes of
+// a cell in one register, 4 n(cases) | 4 n(controls) << 16: each half is its
+// entry's byte address).
+template <int CELLS>
+EPI_DEV int screen_sum_packed(const unsigned (&F)[CELLS]) {
+    unsigned p = 0, q = 0, qh = 0;
+    #pragma unroll
+    for (int x = 0; x < CELLS; ++x) {
+        const unsigned a0 = F[x] & 0xffffu, a1 = F[x] >> 16;
+        p = add3(p, ltab(a0), ltab(a1));
+        // the subtracted terms in pairs
+        if (x & 1) q = add3(q, qh, ltab(a0 + a1));
+        else qh = ltab(a0 + a1);
+    }
+    return (int)(p - q - ((CELLS & 1) ? qh : 0u));
+}
+
 // Smallest screening sum of a combination whose num can reach te, for sums
 // of `reads` table values.  Each table value and each exact term is within
 // 1/2 of its scaled n ln n, so a sum and the num it screens for differ by at
@@ -611,6 +621,12 @@ EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *li
             if (valid) {
                 v4u *pv = (v4u *)t.pairs;
                 const unsigned long long r = t.pair_colex ? colex2(i, m) : lexpair(i, m, d.M);
+                if (t.pair_colex) {
+                    // order 4 by reduced cells: one word per cell, both classes
+                    // (4 n(cases) | 4 n(controls) << 16)
+                    pv[r] = v4u{(acc[p][0][0] << 2) | (acc[p][1][0] << 18), (acc[p][0][1] << 2) | (acc[p][1][1] << 18),
+                                (acc[p][0][2] << 2) | (acc[p][1][2] << 18), (acc[p][0][3] << 2) | (acc[p][1][3] << 18)};
+                } else {
                 const int sh = t.cell_shift;
                 v4u c0 = v4u{acc[p][0][0] << sh, acc[p][0][1] << sh, acc[p][0][2] << sh, acc[p][0][3] << sh};
                 v4u c1 = v4u{acc[p][1][0] << sh, acc[p][1][1] << sh, acc[p][1][2] << sh, acc[p][1][3] << sh};
@@ -623,6 +639,7 @@ EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *li
                 }
                 pv[2 * r + 0] = c0;
                 pv[2 * r + 1] = c1;
+                }
             }
         }
         if constexpr (SCORE) {
@@ -1028,25 +1045,24 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
     wave_sync();  // the slot's rows have been read
 
     if constexpr (EMIT) {
-        // triplet sub-table: the cells of the lane's eight triplets at their
-        // colex ranks, class 0 cells 4a + 2b + d first, as q3_bias(N) - 4n
-        // (the sums are 4n; the signed form of order 4 by reduced cells)
+        // triplet sub-table: the 8 cells 4a + 2b + d of the lane's eight
+        // triplets at their colex ranks, both classes of a cell in one word
+        // (the sums are 4n: 4 n(cases) | 4 n(controls) << 16, the packed form
+        // of order 4 by reduced cells)
         gv4u *tv = (gv4u *)t.triples;
-        const unsigned Bt = q3_bias(d.N);
         #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int i = ib * 16 + 2 * h + 4 * (u >> 1) + (u & 1);
             const int r0 = 4 * (u >> 1) + 2 * (u & 1);
             if (mv[0] && i < j) {
-                v4u *dst = (v4u *)(tv + 4 * colex3(i, j, m));
+                v4u *dst = (v4u *)(tv + 2 * colex3(i, j, m));
                 #pragma unroll
-                for (int c = 0; c < 2; ++c)
-                    #pragma unroll
-                    for (int a = 0; a < 2; ++a)
-                        dst[2 * c + a] = v4u{Bt - (unsigned)(int)acc[0][c][0][0][r0 + a],
-                                             Bt - (unsigned)(int)acc[0][c][0][1][r0 + a],
-                                             Bt - (unsigned)(int)acc[0][c][1][0][r0 + a],
-                                             Bt - (unsigned)(int)acc[0][c][1][1][r0 + a]};
+                for (int a = 0; a < 2; ++a) {
+                    auto pk = [&](int b, int e) {
+                        return (unsigned)(int)acc[0][0][b][e][r0 + a] | ((unsigned)(int)acc[0][1][b][e][r0 + a] << 16);
+                    };
+                    dst[a] = v4u{pk(0, 0), pk(0, 1), pk(1, 0), pk(1, 1)};
+                }
             }
         }
         return;
@@ -1520,13 +1536,14 @@ EPI_DEV void item_seg(const Task &t, unsigned long long local, TopK &tk, Cand *l
 // individuals: 4 pair ANDs, then one three-input AND and one popcount per
 // cell); every other cell follows by inclusion-exclusion from the triplet
 // sub-table (written by the matrix-core kernel), the pair sub-table and the
-// single-SNP counts, as for order 3.
+// single-SNP counts, as for order 3; the sub-tables hold both classes of a
+// cell in one register (4 n(cases) | 4 n(controls) << 16), and so do the
+// lane's 81 cells.
 // ---------------------------------------------------------------------------
-template <bool LDS, bool REV, bool CHECK = false>
+template <bool LDS, bool CHECK = false>
 EPI_DEV void item_r4(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr,
                      const unsigned long long *binom, int bstride) {
     const DsView d = t.ds;
-    const unsigned B = q3_bias(d.N), B13 = 13u * B, B40 = 40u * B;
     int sb = 0;
     if constexpr (LDS) sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.tq, 243);
     const int bits = t.key_bits;
@@ -1612,18 +1629,20 @@ EPI_DEV void item_r4(const Task &t, unsigned long long local, TopK &tk, Cand *li
             for (int x = 0; x < 16; ++x) asm volatile("" : "+v"(acc[cl][x]));
         }
         // F[27 a + 9 b + 3 g + e]; digit 2 = marginal over that SNP, genotype
-        // 2 once the inclusion-exclusion has run.  Signed cell form (as in
-        // item_f3m): cells with an odd number of digits 2 held as B - 4n, the
-        // others as 4n; the marginal inputs carry the offsets o_t B for t
-        // digits 2 (1, -4, 13, -40) with sign (-1)^t on the 4n, which the
-        // sub-table passes write in and the singles and class sizes get here.
-        unsigned F[2][81];
+        // 2 once the inclusion-exclusion has run.  Packed cell form: a
+        // register holds 4 n(cases) in its low half and 4 n(controls) in its
+        // high half (classes of at most 16383 individuals), so one
+        // subtraction steps both classes (no half ever goes below zero: a
+        // marginal is at least the sum of its cells), and each half is the
+        // byte address of its count's screening-table entry.  The
+        // sub-table passes write their cells in this form.
+        unsigned F[81];
         #pragma unroll
         for (int x = 0; x < 81; ++x) {
             const int a = x / 27, b = (x / 9) % 3, g = (x / 3) % 3, e = x % 3;
             if (a < 2 && b < 2 && g < 2 && e < 2) {
-                F[0][x] = acc[0][8 * a + 4 * b + 2 * g + e] << kQScaleShift;
-                F[1][x] = acc[1][8 * a + 4 * b + 2 * g + e] << kQScaleShift;
+                const int i = 8 * a + 4 * b + 2 * g + e;
+                F[x] = (acc[0][i] << kQScaleShift) | (acc[1][i] << (16 + kQScaleShift));
             }
         }
         // triplets: drop one SNP (its digit 2), cells 4a' + 2b' + d' of the rest
@@ -1634,16 +1653,13 @@ EPI_DEV void item_r4(const Task &t, unsigned long long local, TopK &tk, Cand *li
             for (int u = 0; u < 4; ++u)
                 if (u != drop) s3[k++] = c[u];
             const unsigned long long tr = colex3(s3[0], s3[1], s3[2]);
+            const v4u lo = trip4[2 * tr], hi = trip4[2 * tr + 1];
             #pragma unroll
-            for (int cl = 0; cl < 2; ++cl) {
-                const v4u lo = trip4[4 * tr + 2 * cl], hi = trip4[4 * tr + 2 * cl + 1];
+            for (int y = 0; y < 8; ++y) {
+                int dig[4], k2 = 0;
                 #pragma unroll
-                for (int y = 0; y < 8; ++y) {
-                    int dig[4], k2 = 0;
-                    #pragma unroll
-                    for (int u = 0; u < 4; ++u) dig[u] = u == drop ? 2 : (y >> (2 - k2++)) & 1;
-                    F[cl][27 * dig[0] + 9 * dig[1] + 3 * dig[2] + dig[3]] = y < 4 ? lo[y] : hi[y - 4];
-                }
+                for (int u = 0; u < 4; ++u) dig[u] = u == drop ? 2 : (y >> (2 - k2++)) & 1;
+                F[27 * dig[0] + 9 * dig[1] + 3 * dig[2] + dig[3]] = y < 4 ? lo[y] : hi[y - 4];
             }
         }
         // pairs: keep two SNPs
@@ -1651,57 +1667,45 @@ EPI_DEV void item_r4(const Task &t, unsigned long long local, TopK &tk, Cand *li
         for (int u0 = 0; u0 < 4; ++u0)
             #pragma unroll
             for (int u1 = u0 + 1; u1 < 4; ++u1) {
-                const unsigned long long pr = colex2(c[u0], c[u1]);  // the pair sub-table in colex order
+                const v4u pv = pair4[colex2(c[u0], c[u1])];  // the pair sub-table in colex order
                 #pragma unroll
-                for (int cl = 0; cl < 2; ++cl) {
-                    const v4u pv = pair4[2 * pr + cl];
+                for (int y = 0; y < 4; ++y) {
+                    int dig[4];
                     #pragma unroll
-                    for (int y = 0; y < 4; ++y) {
-                        int dig[4];
-                        #pragma unroll
-                        for (int u = 0; u < 4; ++u) dig[u] = u == u0 ? (y >> 1) : (u == u1 ? (y & 1) : 2);
-                        F[cl][27 * dig[0] + 9 * dig[1] + 3 * dig[2] + dig[3]] = pv[y];
-                    }
+                    for (int u = 0; u < 4; ++u) dig[u] = u == u0 ? (y >> 1) : (u == u1 ? (y & 1) : 2);
+                    F[27 * dig[0] + 9 * dig[1] + 3 * dig[2] + dig[3]] = pv[y];
                 }
             }
-        // singles (13B - 4n) and the class sizes (4n - 40B)
+        // singles and the class sizes
         #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const v4u sv = single4[c[u]];
             #pragma unroll
-            for (int cl = 0; cl < 2; ++cl)
+            for (int g = 0; g < 2; ++g) {
+                int dig[4];
                 #pragma unroll
-                for (int g = 0; g < 2; ++g) {
-                    int dig[4];
-                    #pragma unroll
-                    for (int v = 0; v < 4; ++v) dig[v] = v == u ? g : 2;
-                    F[cl][27 * dig[0] + 9 * dig[1] + 3 * dig[2] + dig[3]] = B13 - (sv[2 * cl + g] << kQScaleShift);
-                }
+                for (int v = 0; v < 4; ++v) dig[v] = v == u ? g : 2;
+                F[27 * dig[0] + 9 * dig[1] + 3 * dig[2] + dig[3]] =
+                    (sv[g] << kQScaleShift) | (sv[2 + g] << (16 + kQScaleShift));
+            }
         }
-        F[0][80] = ((unsigned)d.ncls[0] << kQScaleShift) - B40;
-        F[1][80] = ((unsigned)d.ncls[1] << kQScaleShift) - B40;
-        mobius4_signed(F[0]);
-        mobius4_signed(F[1]);
+        F[80] = ((unsigned)d.ncls[0] << kQScaleShift) | ((unsigned)d.ncls[1] << (16 + kQScaleShift));
+        mobius4(F);
         if constexpr (CHECK) {
             unsigned long long sum = 0;
             #pragma unroll
-            for (int x = 0; x < 81; ++x) {
-                const unsigned n0 = (odd_twos(x) ? B - F[0][x] : F[0][x]) >> kQScaleShift;
-                const unsigned n1 = (odd_twos(x) ? B - F[1][x] : F[1][x]) >> kQScaleShift;
-                sum += (unsigned long long)n0 * cell_weight(0, x) + (unsigned long long)n1 * cell_weight(1, x);
-            }
+            for (int x = 0; x < 81; ++x)
+                sum += (unsigned long long)((F[x] & 0xffffu) >> kQScaleShift) * cell_weight(0, x) +
+                       (unsigned long long)(F[x] >> (16 + kQScaleShift)) * cell_weight(1, x);
             digest_add(tk, valid, combo_hash<4>(c), sum);
         }
         bool pass = valid;
-        if constexpr (LDS) pass = pass && screen_sum_signed<81, REV>(F[0], F[1], B) >= sb;
+        if constexpr (LDS) pass = pass && screen_sum_packed<81>(F) >= sb;
         if (__ballot(pass)) {
             long long num = t.score_const;
             #pragma unroll
-            for (int x = 0; x < 81; ++x) {
-                const unsigned n0 = (odd_twos(x) ? B - F[0][x] : F[0][x]) >> kQScaleShift;
-                const unsigned n1 = (odd_twos(x) ? B - F[1][x] : F[1][x]) >> kQScaleShift;
-                num += cell_term(d.tlog, (int)n0, (int)n1, (unsigned)d.N);
-            }
+            for (int x = 0; x < 81; ++x)
+                num += cell_term_counted(d.tlog, (F[x] & 0xffffu) >> kQScaleShift, F[x] >> (16 + kQScaleShift));
             unsigned long long key = 0;
             #pragma unroll
             for (int u = 0; u < 4; ++u) key = (key << bits) | (unsigned long long)c[u];
@@ -1796,7 +1800,7 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
             const bool want = (T0.variant == kF2 || T0.variant == kF2Fold || T0.variant == kF3 || T0.variant == kR4) &&
                               ent_fwd <= tab_cap &&
                               (unsigned)(uintptr_t)(lu32 *)s_tab == 0u;
-            const bool sgn = (T0.variant == kF3 && is_mfma_np(T0.np)) || T0.variant == kR4;
+            const bool sgn = T0.variant == kF3 && is_mfma_np(T0.np);
             const bool rev = want && sgn && ent_rev <= tab_cap;  // read only in the signed cell form
             if (want && (loaded != T0.ds.itab || (rev && !loaded_rev))) {
                 const int ent = rev ? ent_rev : ent_fwd;
@@ -1876,9 +1880,8 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
                 break;
             case kR4:
                 if constexpr (GK == 4) {
-                    if (lds && loaded_rev) item_r4<true, true, CHECK>(T, local, tk, s_list, gthr, binom, bstride);
-                    else if (lds) item_r4<true, false, CHECK>(T, local, tk, s_list, gthr, binom, bstride);
-                    else item_r4<false, false, CHECK>(T, local, tk, s_list, gthr, binom, bstride);
+                    if (lds) item_r4<true, CHECK>(T, local, tk, s_list, gthr, binom, bstride);
+                    else item_r4<false, CHECK>(T, local, tk, s_list, gthr, binom, bstride);
                 }
                 break;
             case kF3:

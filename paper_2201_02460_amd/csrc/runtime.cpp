@@ -689,11 +689,17 @@ int stage_cap_for(int np2, int np3, int w4_max) {
 void set_pair_form(Task &t, const Dataset *d, int order, int variant, int np) {
     const bool q3 = order == 3 && is_mfma_np(np);
     const bool r4 = variant == kR4;
-    t.cell_shift = q3 || r4 ? kQScaleShift : 0;
-    t.cell_bias = q3 ? q3_bias(d->N) : (r4 ? 0u - 4u * q3_bias(d->N) : 0u);
+    t.cell_shift = q3 ? kQScaleShift : 0;
+    t.cell_bias = q3 ? q3_bias(d->N) : 0u;
     t.cell_neg = q3 ? 1 : 0;
-    t.pair_colex = r4 ? 1 : 0;
+    t.pair_colex = r4 ? 1 : 0;  // colex order, both classes of a cell in one word
 }
+
+// Bytes of a scan's pair sub-table (order 4 by reduced cells: 16 per pair,
+// both classes of a cell in one word; else 32) and triplet sub-table (32 per
+// triplet, both classes in one word).
+uint64_t pair_table_bytes(int variant, int M) { return binom_u64(M, 2) * (variant == kR4 ? 16 : 32); }
+uint64_t triple_table_bytes(int M) { return binom_u64(M, 3) * 32; }
 
 // Screening-table entries a scan takes in LDS: the first half (N + 1) when
 // it fits in kTabMax entries, else none (the exact score path for every
@@ -704,7 +710,7 @@ int tab_entries_for(const Dataset *d, int variant, int np, bool both) {
     if (variant == kGeneric || variant == kSeg)  // exact int64 table, n = 0 .. N
         return 2 * (d->N + 1) <= Plan::kTabMax ? 2 * (d->N + 1) : 0;
     if (variant != kF2 && variant != kF3 && variant != kR4) return 0;
-    const bool sgn = (variant == kF3 && is_mfma_np(np)) || variant == kR4;
+    const bool sgn = variant == kF3 && is_mfma_np(np);
     if (both && sgn && 2 * d->N + 2 <= Plan::kTabMax) return 2 * d->N + 2;
     return d->N + 1 <= Plan::kTabMax ? d->N + 1 : 0;
 }
@@ -739,7 +745,10 @@ static void pick_tab_cap(const Plan *p, LaunchGroup &g) {
 // triplet sub-table pass) and a triplet sub-table of C(M,3) x 64 bytes; larger
 // ones take the per-combination kernel.
 static constexpr unsigned long long kMaxTripleBytes = 8ull << 30;
-bool r4_fits(const Dataset *d) { return d->qa && binom_u64(d->M, 3) <= kMaxTripleBytes / 64; }
+// (its cells hold 4 n of each class in 16 bits: classes of at most 16383)
+bool r4_fits(const Dataset *d) {
+    return d->qa && triple_table_bytes(d->M) <= kMaxTripleBytes && d->n_case <= 16383 && d->n_ctrl <= 16383;
+}
 // Order 4 runs by reduced cells when they fit, unless the all-cell kernel is
 // pinned for the dataset's size bucket.
 bool use_r4(Ctx *c, const Dataset *d) { return r4_fits(d) && tuned_np_lookup(c, 4, d) != EPI_BLOCK_ALL_CELLS; }
@@ -789,7 +798,8 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         } else {
             // an allocation-free plan takes the reduced-cell order-4 kernel
             // only when its two sub-tables fit in half the scratch array
-            const bool r4_room = !arena || binom_u64(s.ds->M, 3) * 64 + binom_u64(s.ds->M, 2) * 32 <= arena->cap / 2;
+            const bool r4_room =
+                !arena || triple_table_bytes(s.ds->M) + pair_table_bytes(kR4, s.ds->M) <= arena->cap / 2;
             bool r4 = o == 4 && r4_fits(s.ds) && r4_room;
             if (force_np == EPI_BLOCK_ALL_CELLS) r4 = false;
             else if (force_np != kForceReducedCells) r4 = r4 && use_r4(c, s.ds);
@@ -869,12 +879,12 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
             s.emit_np = 4;
             if ((rc = plan_items(c, p.get(), kF2, s.ds->M, s.emit_np, &s.emit_items_d, &s.emit_items)))
                 return cleanup(rc);
-            const size_t pb = (size_t)binom_u64(s.ds->M, 2) * 32;
+            const size_t pb = (size_t)pair_table_bytes(s.variant, s.ds->M);
             if ((rc = plan_alloc(c, p.get(), std::max<size_t>(pb, 32), &s.pairs))) return cleanup(rc);
         }
         if (s.variant == kR4) {
             if ((rc = plan_items(c, p.get(), kF3, s.ds->M, kNpMfma, &s.t3_items_d, &s.t3_items))) return cleanup(rc);
-            const size_t tb = (size_t)binom_u64(s.ds->M, 3) * 64;
+            const size_t tb = (size_t)triple_table_bytes(s.ds->M);
             if ((rc = plan_alloc(c, p.get(), std::max<size_t>(tb, 64), &s.triples))) return cleanup(rc);
         }
     }

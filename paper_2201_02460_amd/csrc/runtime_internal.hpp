@@ -243,6 +243,8 @@ struct PlanArena {
 int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool graph, Plan **out, int force_np,
                bool check = false, const PlanArena *arena = nullptr);
 bool use_r4(Ctx *c, const Dataset *d);
+uint64_t pair_table_bytes(int variant, int M);
+uint64_t triple_table_bytes(int M);
 int plan_run(Ctx *c, Plan *p, hipStream_t st, unsigned long long item_cap);
 int plan_wait(Plan *p);
 int plan_results(Plan *p, int index, int capacity, int32_t *combos, float *scores, uint32_t *tables,

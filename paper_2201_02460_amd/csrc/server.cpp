@@ -138,8 +138,8 @@ static int admit(Server *S, Request *r) {
     if (sub && (rc = get_items(c, kF2, r->ds->M, 4, &r->emit_items, &r->emit_n))) return rc;
     if (r->variant == kR4 && (rc = get_items(c, kF3, r->ds->M, kNpMfma, &r->t3_items, &r->t3_n))) return rc;
     r->cand_cap = (unsigned)((unsigned long long)S->grid_max * 4 * r->desc.top_k + r->desc.top_k + 64);
-    const uint64_t pair_bytes = sub ? binom_u64(r->ds->M, 2) * 32 : 0;
-    const uint64_t trip_bytes = r->variant == kR4 ? binom_u64(r->ds->M, 3) * 64 : 0;
+    const uint64_t pair_bytes = sub ? pair_table_bytes(r->variant, r->ds->M) : 0;
+    const uint64_t trip_bytes = r->variant == kR4 ? triple_table_bytes(r->ds->M) : 0;
     r->footprint = pair_bytes + trip_bytes + (uint64_t)r->cand_cap * sizeof(Cand);
     if (S->used + r->footprint > S->budget) return EPI_ENOMEM;
     auto undo = [&](int code) {
