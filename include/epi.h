@@ -292,9 +292,20 @@ int epi_batch_destroy(epi_ctx *ctx, int32_t batch_id);
  *            products);
  *            48 (EPI_BLOCK_MFMA_FP4_2J) -- the 4-bit products with two
  *            consecutive middle SNPs per work item, so each operand load
- *            feeds twice the products (one wave per SIMD, its accumulators
- *            in the accumulation registers).
- * Every kernel produces the same integers and therefore the same results. */
+ *            feeds twice the products; the control steps' products are
+ *            scaled by 2^(T-2) (the matrix instruction's exponent scale), so
+ *            one float accumulator holds 4 n(cases) + 2^T n(controls), T = 2
+ *            + the bit width of the case count: only for datasets where
+ *            4 n_cases + 2^T n_controls < 2^24 (e.g. up to 2047 individuals
+ *            per class).
+ * Every kernel produces the same integers and therefore the same results.
+ * Plain scans on the matrix-core blocks with at least 64 work items per wave
+ * first run a pilot pass: one work item per wave, from the middle of the
+ * scan, whose best screening sums, lowered by the screen's error bound, go
+ * into the scan's score histogram; the K-th best of those is a lower bound
+ * of the final K-th best score, which every wave of the scan then starts
+ * from (same results, fewer combinations scored exactly while the bound
+ * rises). */
 #define EPI_BLOCK_MFMA_FP4 16
 #define EPI_BLOCK_MFMA_I8 32
 #define EPI_BLOCK_MFMA_FP4_2J 48
@@ -349,7 +360,8 @@ int epi_autotune_report(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t
  * operand copies on the context stream and waits for them (no other work on
  * the dataset may be in flight).  EPI_EINVAL for a block not listed for the
  * order, EPI_EUNSUPPORTED for a matrix-core block on a dataset with 2^22
- * individuals or more, EPI_ENOMEM if the copies do not fit. */
+ * individuals or more and for EPI_BLOCK_MFMA_FP4_2J on one whose class sizes
+ * do not fit its accumulator, EPI_ENOMEM if the copies do not fit. */
 int epi_set_prefix_block(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_t block);
 
 /* ---- the steps of the method as separate passes ------------------------- */

@@ -48,12 +48,27 @@ constexpr int kMergeParts = 32;        // first-stage merge workgroups per task
 constexpr int kMaxBinomOrder = 8;
 constexpr int kNpMfma = 16;            // order-3 block counted by matrix cores, 4-bit float operands
 constexpr int kNpMfmaI8 = 32;          // the same with 8-bit integer operands
-constexpr int kNpMfma2 = 48;           // 4-bit float operands, two middle SNPs per work item
+constexpr int kNpMfma2 = 48;           // 4-bit float operands, two middle SNPs per work item, both
+                                       // classes in one accumulator
 
 // Prefix blocks of the matrix-core order-3 kernels (their work items and
 // signed cell form differ from the popcount kernels').
 __host__ __device__ constexpr bool is_mfma_np(int np) { return np == kNpMfma || np == kNpMfmaI8 || np == kNpMfma2; }
 constexpr int kQStepMultiple = 4;      // qa / qb: steps per class padded to a multiple of this
+
+// The two-middle-SNP matrix-core kernel scales the control steps' products by
+// 2^(T - 2) (the MFMA's per-block exponent scale), so one float accumulator
+// holds 4 n(cases) + 2^T n(controls) with T = 2 + bit width of the case
+// count: the cases' field is below 2^T and the sum stays an exact float
+// integer while it is below 2^24.
+__host__ __device__ inline int q3_pack_shift(int n_cases) {
+    return n_cases <= 0 ? 2 : 34 - __builtin_clz((unsigned)n_cases);
+}
+__host__ __device__ inline bool q3_pack_fits(int n_cases, int n_controls) {
+    const int T = q3_pack_shift(n_cases);
+    return n_cases >= 0 && n_controls >= 0 && T <= 24 &&
+           4ull * (unsigned long long)n_cases + ((unsigned long long)n_controls << T) < (1ull << 24);
+}
 constexpr int kQStageSteps = 64;       // matrix-core kernels: steps of j-mask rows staged in LDS
 
 enum Variant : int32_t {
@@ -126,6 +141,8 @@ struct Task {
                                       //   lowest index), else lexicographic
     unsigned long long *digest;       // checking launches: [0] combinations scored, [1] their digest sum
                                       //   (null: no check)
+    unsigned long long pilot_first;   // matrix-core order 3: items pilot_first .. + pilot_n - 1 were
+    int32_t pilot_n;                  //   counted into the histogram by the pilot pass (0: none)
 };
 
 // Work-item descriptor tables, one item per entry, in groups of consecutive

@@ -258,6 +258,7 @@ struct TopK {
     int top;         // highest histogram bin this wave has counted (-1: none)
     unsigned long long dsum;  // checking launches: this lane's digest sum and count since the last flush
     unsigned dn;
+    int nohist;      // the item's combinations are already in the histogram (a pilot item)
 };
 
 // ---------------------------------------------------------------------------
@@ -359,7 +360,8 @@ EPI_DEV void tk_offer(TopK &t, Cand *list, bool valid, long long num, unsigned l
     unsigned long long mask = __ballot(want);
     // counted once the list is full or a bound exists: the unbounded filling
     // of the lists at the start would only add contention
-    if (mask && t.hist && (t.n == t.K || gthr != (long long)0x8000000000000000ull)) hist_add(t, want, num);
+    if (mask && t.hist && !t.nohist && (t.n == t.K || gthr != (long long)0x8000000000000000ull))
+        hist_add(t, want, num);
     while (mask) {
         const int src = __builtin_ctzll(mask);
         const long long cn = (long long)readlane64((unsigned long long)num, src);
@@ -876,11 +878,12 @@ struct QFmt<false> {
     static EPI_DEV const v4u *qa(const DsView &d) { return d.qa; }
     static EPI_DEV const v4u *qb(const DsView &d) { return d.qb; }
     static EPI_DEV int ks(const DsView &d, int c) { return d.ks[c]; }
-    static EPI_DEV acc_t mma(v4u a, v4u b, acc_t c) {
+    // sb: exponent scale of the B operand (E8M0, 127 = 2^0)
+    static EPI_DEV acc_t mma(v4u a, v4u b, acc_t c, int sb = 127) {
         const v8i a8 = {(int)a[0], (int)a[1], (int)a[2], (int)a[3], 0, 0, 0, 0};
         const v8i b8 = {(int)b[0], (int)b[1], (int)b[2], (int)b[3], 0, 0, 0, 0};
-        // formats 4 / 4: e2m1 for both operands; scales 127 = 2^0
-        return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, c, 4, 4, 0, 127, 0, 127);
+        // formats 4 / 4: e2m1 for both operands; A scale 127 = 2^0
+        return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, c, 4, 4, 0, 127, 0, sb);
     }
 };
 
@@ -890,16 +893,25 @@ struct QFmt<true> {
     static EPI_DEV const v4u *qa(const DsView &d) { return d.qa8; }
     static EPI_DEV const v4u *qb(const DsView &d) { return d.qb8; }
     static EPI_DEV int ks(const DsView &d, int c) { return d.ks8[c]; }
-    static EPI_DEV acc_t mma(v4u a, v4u b, acc_t c) {
+    static EPI_DEV acc_t mma(v4u a, v4u b, acc_t c, int = 127) {
         return __builtin_amdgcn_mfma_i32_32x32x32_i8(__builtin_bit_cast(v4i, a), __builtin_bit_cast(v4i, b), c, 0, 0,
                                                      0);
     }
 };
 
-template <bool LDS, bool REV, bool I8, bool EMIT = false, bool CHECK = false, int NJ = 1>
+// PILOT: the histogram-only pass over an item (needs the screening table in
+// LDS): lower bounds of the scores are counted, nothing is offered.
+template <bool LDS, bool REV, bool I8, bool EMIT = false, bool CHECK = false, int NJ = 1, bool PILOT = false>
 EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr, v4u *stage) {
     static_assert(NJ == 1 || (NJ == 2 && !EMIT && !I8), "two middle SNPs per item: 4-bit scoring kernel only");
     typedef QFmt<I8> Q;
+    // PK (two middle SNPs): one accumulator per tile for both classes, the
+    // control steps' products scaled by 2^(T - 2), so the tile holds
+    // 4 n(cases) + 2^T n(controls) (q3_pack_shift; the host takes this kernel
+    // only where q3_pack_fits)
+    constexpr bool PK = NJ == 2;
+    constexpr int NC = PK ? 1 : 2;
+    const int T = PK ? q3_pack_shift(t.ds.ncls[0]) : 0;
     const DsView d = t.ds;
     const unsigned long long dsc = t.items[local];
     const int j = uni((int)((dsc >> 40) & 0xfffffu));
@@ -958,11 +970,11 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
     const __amdgpu_buffer_rsrc_t rB1 =
         __builtin_amdgcn_make_buffer_rsrc((void *)(qb + (long long)(2 * mb + 1) * KS * 64), 0, blk, kBufWord3);
     const int vo = lane * 16;
-    typename Q::acc_t acc[NJ][2][2][2];
+    typename Q::acc_t acc[NJ][NC][2][2];
     #pragma unroll
     for (int jj = 0; jj < NJ; ++jj)
         #pragma unroll
-        for (int c = 0; c < 2; ++c)
+        for (int c = 0; c < NC; ++c)
             #pragma unroll
             for (int b = 0; b < 2; ++b)
                 #pragma unroll
@@ -1013,6 +1025,8 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
     for (int c = 0; c < 2; ++c) {
         const int c0 = c == 0 ? 0 : ks0;
         const int cn = Q::ks(d, c);
+        const int cc = PK ? 0 : c;                      // accumulator set of the class
+        const int bsc = PK && c == 1 ? 125 + T : 127;   // B scale: 2^(T - 2) for PK's controls
         #pragma unroll 1
         for (int k = 0; k < cn; k += kQDepth) {
             const int g = c0 + k;  // the group's first step in the stream
@@ -1027,10 +1041,10 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
                     const int js = jj * 4 * kQSeg + 4 * (g - seg + u) + 2 * h;
                     const v4u J0 = slot[js], J1 = slot[js + 1];
                     const v4u A0 = bA[u] & J0, A1 = bA[u] & J1;
-                    acc[jj][c][0][0] = Q::mma(A0, bB0[u], acc[jj][c][0][0]);
-                    acc[jj][c][0][1] = Q::mma(A0, bB1[u], acc[jj][c][0][1]);
-                    acc[jj][c][1][0] = Q::mma(A1, bB0[u], acc[jj][c][1][0]);
-                    acc[jj][c][1][1] = Q::mma(A1, bB1[u], acc[jj][c][1][1]);
+                    acc[jj][cc][0][0] = Q::mma(A0, bB0[u], acc[jj][cc][0][0], bsc);
+                    acc[jj][cc][0][1] = Q::mma(A0, bB1[u], acc[jj][cc][0][1], bsc);
+                    acc[jj][cc][1][0] = Q::mma(A1, bB0[u], acc[jj][cc][1][0], bsc);
+                    acc[jj][cc][1][1] = Q::mma(A1, bB1[u], acc[jj][cc][1][1], bsc);
                 }
                 // refill with the step kQDepth ahead in the stream (the last
                 // steps re-read the stream's last step)
@@ -1059,7 +1073,7 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
                 #pragma unroll
                 for (int a = 0; a < 2; ++a) {
                     auto pk = [&](int b, int e) {
-                        return (unsigned)(int)acc[0][0][b][e][r0 + a] | ((unsigned)(int)acc[0][1][b][e][r0 + a] << 16);
+                        return (unsigned)(int)acc[0][0][b][e][r0 + a] | ((unsigned)(int)acc[0][NC - 1][b][e][r0 + a] << 16);
                     };
                     dst[a] = v4u{pk(0, 0), pk(0, 1), pk(1, 0), pk(1, 1)};
                 }
@@ -1079,6 +1093,7 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
     // The lane's eight SNPs i: i_local = 4 (u / 2) + 2 h + u % 2, genotype a
     // in register 4 (u / 2) + 2 (u % 2) + a.
     const int i_base = ib * 16 + 2 * h;
+    int pilot_best = (int)0x80000000u;  // PILOT: the lane's best screening sum
     int sb = 0;
     if constexpr (LDS) sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.tq, 81);
     #pragma unroll
@@ -1117,8 +1132,16 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
                     #pragma unroll
                     for (int b = 0; b < 2; ++b)
                         #pragma unroll
-                        for (int e = 0; e < 2; ++e)
-                            F[c][9 * a + 3 * b + e] = (unsigned)(int)acc[jj][c][b][e][r0 + a];
+                        for (int e = 0; e < 2; ++e) {
+                            if constexpr (PK) {
+                                // 4 n(cases) + 2^T n(controls): the cases are the low
+                                // T bits, the controls' 4n is the rest shifted down
+                                const unsigned v = (unsigned)acc[jj][0][b][e][r0 + a];
+                                F[c][9 * a + 3 * b + e] = c == 0 ? v & ((1u << T) - 1u) : (v >> (T - 2)) & ~3u;
+                            } else {
+                                F[c][9 * a + 3 * b + e] = (unsigned)(int)acc[jj][c][b][e][r0 + a];
+                            }
+                        }
                 #pragma unroll
                 for (int a = 0; a < 2; ++a)
                     #pragma unroll
@@ -1139,6 +1162,14 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
                 F[c][25] = sm[2 * c + 1];
                 F[c][26] = nall[c];
                 mobius3_signed(F[c]);
+            }
+            if constexpr (PILOT) {
+                static_assert(LDS && !CHECK && !EMIT, "the pilot pass reads the screening table from LDS");
+                if (valid) {
+                    const int S = screen_sum_signed<27, REV>(F[0], F[1], B);
+                    pilot_best = S > pilot_best ? S : pilot_best;
+                }
+                continue;
             }
             if constexpr (CHECK) {
                 unsigned long long sum = 0;
@@ -1167,6 +1198,20 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
                 if constexpr (LDS) sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.tq, 81);
             }
         }
+    }
+    if constexpr (PILOT) {
+        // one count per item, the best of its combinations (one atomic per
+        // wave; the K-th best of such maxima is close to that of all): the
+        // screening sum S is within 81 units (2^-tq) of (num - score_const)
+        // 2^(tq - shift), so score_const + (S - 82) 2^(shift - tq) is below
+        // that combination's num
+        #pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const int o = __shfl_xor(pilot_best, off);
+            pilot_best = o > pilot_best ? o : pilot_best;
+        }
+        hist_add(tk, lane_id() == 0 && pilot_best != (int)0x80000000u,
+                 t.score_const + (long long)(pilot_best - 82) * (1ll << (d.shift - d.tq)));
     }
 }
 
@@ -1723,12 +1768,17 @@ EPI_DEV void item_r4(const Task &t, unsigned long long local, TopK &tk, Cand *li
 // ---------------------------------------------------------------------------
 // Register budget per instantiation: enough waves per SIMD to hide load
 // latency; the accumulators (16 per prefix for order 3, 8 for order 2, 128
-// for the matrix-core order-3 kernel, 256 for its two-middle-SNP form, which
-// takes a whole SIMD's registers) set the floor.
+// for the matrix-core order-3 kernels: two classes of one middle SNP, or one
+// accumulator for both classes of each of two) set the floor.
 template <int NP2, int NP3, int GK>
 constexpr int scan_waves_per_eu() {
-    return NP3 == kNpMfma2 ? 1
+    return NP3 == kNpMfma2 ? 2
                            : (GK >= 4 ? 2 : (GK == 3 ? 3 : (NP3 >= 8 ? 2 : (NP3 >= 4 ? 3 : (NP3 >= 2 ? 4 : (NP2 >= 8 ? 3 : 4))))));
+}
+
+// Items of a task's pilot pass: pilot_n consecutive ones from pilot_first.
+EPI_DEV bool is_pilot_item(const Task &t, unsigned long long local) {
+    return local >= t.pilot_first && local - t.pilot_first < (unsigned long long)t.pilot_n;
 }
 
 // CHECK: the checking instantiation, which also adds every scored
@@ -1761,6 +1811,7 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
     tk.top = -1;
     tk.dsum = 0;
     tk.dn = 0;
+    tk.nohist = 0;
     int cur = -1;
     long long gthr = (long long)0x8000000000000000ull;
     const uint32_t *loaded = nullptr;  // dataset whose screening table is in s_tab
@@ -1858,6 +1909,8 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
             const unsigned long long local = item - T.item_base + T.first_item;
             const bool lds = loaded != nullptr && T.ds.itab == loaded;
             const bool ldt = loaded != nullptr && (const uint32_t *)T.ds.tlog == loaded;
+            // the pilot pass has counted the combinations of its items
+            tk.nohist = is_pilot_item(T, local);
             switch (T.variant) {
             case kF2:
                 if constexpr (NP2 > 0) {
@@ -1976,6 +2029,75 @@ ScanKernelFn find_scan_kernel_check(int np2, int np3, int gk) {
     return nullptr;
 }
 #else
+// ---------------------------------------------------------------------------
+// Pilot pass of a matrix-core order-3 scan, launched before its main launch:
+// the waves pass over the task's pilot items (consecutive, so that they share
+// operand blocks in L2 as the main launch's do), count the best lower bound
+// of each step into the task's histogram, then publish the
+// bound the histogram gives (the K-th best of lower bounds of distinct
+// combinations is at most the task's final K-th best).  Every wave of the
+// main launch starts from that bound, and it does not count the pilot items
+// again.  Same launch shape and LDS layout as the scan kernel.
+// ---------------------------------------------------------------------------
+template <int NP3>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<0, NP3, 0>())))
+scan_pilot(const Task *__restrict__ tasks, int tab_cap, int kmax, int stage_cap, unsigned *__restrict__ done) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
+    unsigned *s_tab = (unsigned *)s_dyn;
+    const Task &T = tasks[0];
+    const int wave = uni((int)(threadIdx.x >> 6));
+    const long long lists_off = ((long long)tab_cap * 4 + 15) & ~15LL;
+    const long long stage_off = lists_off + (long long)4 * kmax * sizeof(Cand);
+    Cand *s_list = (Cand *)(s_dyn + lists_off) + wave * kmax;
+    v4u *s_stage = (v4u *)(s_dyn + stage_off) + wave * stage_cap;
+    // the screening table at LDS address 0, with its mirrored half when it fits
+    const int ent_fwd = T.ds.N + 1, ent_rev = 2 * T.ds.N + 2;
+    if (ent_fwd > tab_cap || (unsigned)(uintptr_t)(lu32 *)s_tab != 0u) return;  // every wave alike: no bound
+    const bool rev = ent_rev <= tab_cap;
+    const int ent = rev ? ent_rev : ent_fwd;
+    #pragma unroll 1
+    for (int x = threadIdx.x; x < ent; x += blockDim.x) s_tab[x] = T.ds.itab[x];
+    __syncthreads();
+    TopK tk;
+    tk.n = 0;
+    tk.K = T.top_k;
+    tk.wi = 0;
+    tk.wn = 0;
+    tk.wk = 0;
+    tk.hist = T.hist;
+    tk.added = 0;
+    tk.top = -1;
+    tk.dsum = 0;
+    tk.dn = 0;
+    tk.nohist = 0;
+    constexpr bool i8 = NP3 == kNpMfmaI8;
+    constexpr int nj = NP3 == kNpMfma2 ? 2 : 1;
+    const long long none = (long long)0x8000000000000000ull;
+    // wave w takes pilot items w, w + (waves of the grid), ...
+    const unsigned long long n_waves = (unsigned long long)gridDim.x * 4;
+    #pragma unroll 1
+    for (unsigned long long w = (unsigned long long)blockIdx.x * 4 + (unsigned long long)wave;
+         w < (unsigned long long)T.pilot_n && T.pilot_first + w < T.n_items; w += n_waves) {
+        if (rev) item_f3m<true, true, i8, false, false, nj, true>(T, T.pilot_first + w, tk, s_list, none, s_stage);
+        else item_f3m<true, false, i8, false, false, nj, true>(T, T.pilot_first + w, tk, s_list, none, s_stage);
+    }
+    // the last wave to finish reads the bound off the histogram (from one
+    // octave above its own best count down) and publishes it, then clears
+    // the counter for the next pilot pass
+    __threadfence();
+    unsigned prev = 0;
+    if (lane_id() == 0) prev = atomicAdd(done, 1u);
+    prev = (unsigned)__builtin_amdgcn_readfirstlane((int)prev);
+    if (prev + 1 == gridDim.x * 4) {
+        __threadfence();
+        if (tk.top >= 0) {
+            const long long hb = hist_bound(tk.hist, tk.K, tk.top);
+            if (hb != none && lane_id() == 0) atomicMax(T.thr, bias(hb));
+        }
+        if (lane_id() == 0) atomicExch(done, 0u);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Best-K selection over a task's candidate buffer: one 1024-thread workgroup
 // per task; candidates below the task's final threshold are dropped, the rest
@@ -2716,6 +2838,18 @@ hipError_t launch_scan(int np2, int np3, int gk, int grid, hipStream_t st, const
     const size_t lds = scan_lds_bytes(tab_cap, kmax, stage_cap);
     hipLaunchKernelGGL(fn, dim3(grid), dim3(4 * kWave), lds, st, tasks, n_tasks, total_items, queue, binom, bstride,
                        tab_cap, kmax, stage_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_pilot(int np3, int grid, hipStream_t st, const Task *tasks, int tab_cap, int kmax, int stage_cap,
+                        unsigned *done) {
+    void (*fn)(const Task *, int, int, int, unsigned *) = np3 == kNpMfma     ? scan_pilot<kNpMfma>
+                                              : np3 == kNpMfmaI8 ? scan_pilot<kNpMfmaI8>
+                                              : np3 == kNpMfma2  ? scan_pilot<kNpMfma2>
+                                                                 : nullptr;
+    if (!fn) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(4 * kWave), scan_lds_bytes(tab_cap, kmax, stage_cap), st, tasks, tab_cap,
+                       kmax, stage_cap, done);
     return hipGetLastError();
 }
 

@@ -640,8 +640,18 @@ int group_of_order(int order, int np) {
 // has its operand copies, else 4.
 int default_np3(Ctx *c, const Dataset *d) {
     const int t = tuned_np_lookup(c, 3, d);
-    if (t > 0 && ((t != kNpMfma && t != kNpMfma2) || d->qa) && (t != kNpMfmaI8 || d->qa8)) return t;
+    if (t > 0 && np3_usable(d, t)) return t;
     return d->qa ? kNpMfma : 4;
+}
+
+// Whether the dataset can run order-3 block np: the matrix-core blocks need
+// their operand copies, and the two-middle-SNP one its class sizes to fit
+// one float accumulator (q3_pack_fits).
+bool np3_usable(const Dataset *d, int np) {
+    if (np == kNpMfma) return d->qa != nullptr;
+    if (np == kNpMfma2) return d->qa != nullptr && q3_pack_fits(d->n_case, d->n_ctrl);
+    if (np == kNpMfmaI8) return d->qa8 != nullptr;
+    return np == 1 || np == 2 || np == 4 || np == 8;
 }
 
 // Persistent grid, in 4-wave workgroups (one wave per SIMD each): as many as
@@ -657,8 +667,7 @@ static int wgs_per_cu(int np2, int np3, int gk, int tab_cap, int kmax, int stage
         lds_static = 0;
     }
     const int alloc = std::max(8, (vgprs + 7) / 8 * 8);
-    // the two-middle-SNP matrix-core kernel also fills the accumulation registers
-    int waves = np3 == kNpMfma2 ? 1 : std::min(8, 512 / alloc);
+    int waves = std::min(8, 512 / alloc);
     if (const char *e = getenv("EPI_WAVES_PER_SIMD")) waves = std::max(1, std::min(16, atoi(e)));
     const size_t lds = scan_lds_bytes(tab_cap, kmax, stage_cap) + (size_t)lds_static;
     const int by_lds = (int)std::max<size_t>(1, (160 * 1024) / std::max<size_t>(lds, 1));
@@ -996,6 +1005,22 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         t.n_blocks = 0;
         t.key_bits = key_bits_for(s.desc.order);
         t.digest = check ? p->d_digest + 2 * i : nullptr;
+        // pilot pass (back-to-back launches of the matrix-core order-3
+        // kernels, screening table in LDS, at least 64 items per wave of the
+        // main launch): one item per wave of the main launch, consecutive
+        // items from the middle of the task
+        s.pilot_n = 0;
+        s.pilot_first = 0;
+        if (!persistent && s.variant == kF3 && is_mfma_np(s.np)) {
+            const LaunchGroup &g = p->groups[i];
+            const unsigned long long waves = (unsigned long long)g.grid * 4;
+            if (g.tab_cap >= s.ds->N + 1 && s.n_items >= 64 * waves) {
+                s.pilot_n = (int)waves;
+                s.pilot_first = s.n_items / 2 - waves / 2;
+            }
+        }
+        t.pilot_first = s.pilot_first;
+        t.pilot_n = s.pilot_n;
     }
     {
         int e = nt;
@@ -1008,6 +1033,8 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
             t = tasks[i];
             t.variant = kF2Emit;
             t.digest = nullptr;
+            t.pilot_first = 0;
+            t.pilot_n = 0;
             t.items = (const unsigned long long *)s.emit_items_d;
             t.n_items = s.emit_items;
             t.item_base = persistent ? base : 0;
@@ -1041,6 +1068,8 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
             t = tasks[i];
             t.variant = kF3Emit;
             t.digest = nullptr;
+            t.pilot_first = 0;
+            t.pilot_n = 0;
             t.items = (const unsigned long long *)s.t3_items_d;
             t.n_items = s.t3_items;
             t.item_base = persistent ? base : 0;
@@ -1150,6 +1179,11 @@ static int plan_enqueue(Ctx *c, Plan *p, hipStream_t st, bool timing, unsigned l
                 HIPCHK(launch_init_counters(st, p->d_queues, 1, nullptr, nullptr, 0, nullptr));
             }
             if (timing && single) HIPCHK(hipEventRecord(p->ev[2], st));
+            if (s.pilot_n > 0)
+                // its wave counter: the pair pass's queue word, cleared
+                // after that pass and by the pilot's last wave
+                HIPCHK(launch_pilot(g.np3, std::min(g.grid, (s.pilot_n + 3) / 4), st, tasks + i, g.tab_cap, g.kmax,
+                                    g.stage_cap, (unsigned *)(p->d_queues + 0)));
             HIPCHK(launch_scan(g.np2, g.np3, g.gk, g.grid, st, tasks + i, 1, std::min(s.n_items, item_cap),
                                p->d_queues + 1, c->d_binom, c->bstride, g.tab_cap, g.kmax, g.stage_cap, p->check));
             HIPCHK(launch_init_counters(st, p->d_queues + 1, 1, nullptr, nullptr, 0, nullptr));
@@ -1331,7 +1365,7 @@ static std::vector<int> tune_candidates(const Dataset *ds, int order) {
         std::vector<int> v{1, 2, 4, 8};
         if (ds->qa) {
             v.push_back(kNpMfma);
-            v.push_back(kNpMfma2);
+            if (np3_usable(ds, kNpMfma2)) v.push_back(kNpMfma2);
         }
         return v;
     }
@@ -1370,6 +1404,10 @@ int autotune(Ctx *c, int ds_id, int order, int *choice) {
         const unsigned long long len = std::max<unsigned long long>(
             1, std::min<unsigned long long>(total / kSlices, (unsigned long long)p->groups[0].grid * 4 * 8));
         Task *staged = (Task *)((char *)p->h_stage + p->stage_layout_bytes);
+        // slices are timed without the pilot pass (its items span the task)
+        p->scans[0].pilot_n = 0;
+        staged[0].pilot_n = 0;
+        staged[0].pilot_first = 0;
         double best_rep = 1e30;
         for (int rep = 0; rep < 3 && !rc; ++rep) {
             double ms_sum = 0;
@@ -1850,6 +1888,10 @@ int epi_set_prefix_block(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_
         return fail(EPI_EINVAL, "prefix block %d is not a kernel of order %d", block, order);
     if ((block == kNpMfma || block == kNpMfma2) && !d->qa)
         return fail(EPI_EUNSUPPORTED, "dataset %d has no matrix-core operands (2^22 individuals or more)", dataset_id);
+    if (block == kNpMfma2 && !np3_usable(d, block))
+        return fail(EPI_EUNSUPPORTED,
+                    "dataset %d: %d cases and %d controls do not fit one accumulator (4 cases + controls 2^T < 2^24)",
+                    dataset_id, d->n_case, d->n_ctrl);
     if (block == kNpMfmaI8) {
         if (d->N >= (1 << 22))
             return fail(EPI_EUNSUPPORTED, "dataset %d: 2^22 individuals or more for the integer kernel", dataset_id);

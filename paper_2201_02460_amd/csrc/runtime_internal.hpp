@@ -83,6 +83,10 @@ struct PlanScan {
     unsigned cand_cap = 0;
     ResultLayout lay{};
     int scan_id = -1;
+    // matrix-core order 3, plans of back-to-back launches: pilot pass over
+    // items pilot_first .. pilot_first + pilot_n - 1 (pilot_n 0: none)
+    int pilot_n = 0;
+    unsigned long long pilot_first = 0;
 };
 
 struct LaunchGroup {
@@ -189,6 +193,8 @@ struct Ctx {
 };
 
 // kernel launchers (kernels.hip)
+hipError_t launch_pilot(int np3, int grid, hipStream_t st, const Task *tasks, int tab_cap, int kmax, int stage_cap,
+                        unsigned *done);
 hipError_t launch_scan(int np2, int np3, int gk, int grid, hipStream_t st, const Task *tasks, int n_tasks,
                        unsigned long long total_items, unsigned long long *queue, const unsigned long long *binom,
                        int bstride, int tab_cap, int kmax, int stage_cap, bool check = false);
@@ -226,6 +232,7 @@ bool r4_fits(const Dataset *d);
 int tuned_np_lookup(Ctx *c, int order, const Dataset *d);
 bool seg_pinned(Ctx *c, int order, const Dataset *d);
 int default_np3(Ctx *c, const Dataset *d);
+bool np3_usable(const Dataset *d, int np);
 int grid_for(Ctx *c, int np2, int np3, int gk, unsigned long long items, int tab_cap, int kmax, int stage_cap);
 int stage_cap_for(int np2, int np3, int w4_max);
 int tab_entries_for(const Dataset *d, int variant, int np, bool both);

@@ -516,3 +516,76 @@ def test_counting_kernels_agree(cx, orc):
     epi.epi_set_prefix_block(cx.ctx, ds, 3, 0)
     assert cx.scan(ds, 3, 30)["prefix_block"] == epi.EPI_BLOCK_MFMA_FP4
     epi.epi_unload(cx.ctx, ds)
+
+
+def test_two_middle_kernel_class_size_limit(cx, orc):
+    """The two-middle-SNP 4-bit kernel holds both classes of a cell in one
+    float accumulator, 4 n(cases) + 2^T n(controls) with T = 2 + the bit width
+    of the case count: at 2047 cases and 2047 controls a cell that holds every
+    individual reaches 2^24 - 4, the largest such sum; one control more does
+    not fit and the block is refused for that dataset."""
+    from paper_2201_02460_amd import epi
+
+    G, y = random_genotypes(37, 4094, seed=47, case_fraction=0.5)
+    y = np.zeros(4094, np.uint8)
+    y[:2047] = 1
+    G[[0, 5, 17, 36]] = 0  # monomorphic SNPs: cells that hold every individual
+    G[9, ::3] = 2
+    ds = cx.load(G, y)
+    try:
+        epi.epi_set_prefix_block(cx.ctx, ds, 3, epi.EPI_BLOCK_MFMA_FP4_2J)
+        res = cx.scan(ds, 3, 40)
+        assert res["prefix_block"] == epi.EPI_BLOCK_MFMA_FP4_2J
+        check_topk(orc, G, y, 3, 40, res["combos"], res["scores"], res["tables"])
+        epi.epi_set_prefix_block(cx.ctx, ds, 3, epi.EPI_BLOCK_MFMA_FP4)
+        ref = cx.scan(ds, 3, 40)
+        for k in ("combos", "scores", "tables"):
+            assert np.array_equal(res[k], ref[k])
+    finally:
+        epi.epi_set_prefix_block(cx.ctx, ds, 3, 0)
+        epi.epi_unload(cx.ctx, ds)
+    G2 = np.concatenate([G, G[:, :1]], axis=1)
+    y2 = np.concatenate([y, np.zeros(1, np.uint8)])
+    ds = cx.load(G2, y2)
+    try:
+        with pytest.raises(epi.EpiError) as e:
+            epi.epi_set_prefix_block(cx.ctx, ds, 3, epi.EPI_BLOCK_MFMA_FP4_2J)
+        assert e.value.code == epi.EPI_EUNSUPPORTED
+    finally:
+        epi.epi_unload(cx.ctx, ds)
+
+
+def test_full_size_order3_every_matrix_core_block(cx, orc):
+    """The order-3 workload (M = 1000, N = 4000) on each matrix-core kernel:
+    these launches run the pilot pass first (one item per wave counted into
+    the histogram for a first bound), so a bound above the K-th best would
+    drop results; every block must give the stored oracle top K exactly."""
+    from paper_2201_02460_amd import epi
+
+    name = "order3_M1000_N4000"
+    with open(os.path.join(GOLDEN, name + ".json")) as f:
+        gold = json.load(f)
+    G, y, spec, _ = make_workload(name)
+    K = spec["top_k"]
+    ref = {"combos": np.asarray(gold["combos"], np.int32), "scores": np.asarray(gold["scores"])}
+    gold_tab = {tuple(c): np.asarray(t, np.int64) for c, t in zip(gold["combos"], gold["tables"])}
+    ds = cx.load(G, y)
+    first = None
+    try:
+        for block in (epi.EPI_BLOCK_MFMA_FP4, epi.EPI_BLOCK_MFMA_I8, epi.EPI_BLOCK_MFMA_FP4_2J):
+            say("prefix block", block)
+            epi.epi_set_prefix_block(cx.ctx, ds, 3, block)
+            res = cx.scan(ds, 3, K)
+            assert res["prefix_block"] == block
+            if first is None:
+                check_topk(orc, G, y, 3, K, res["combos"], res["scores"], res["tables"], ref=ref)
+                for c, t in zip(res["combos"], res["tables"]):
+                    if tuple(c) in gold_tab:
+                        assert np.array_equal(t.astype(np.int64), gold_tab[tuple(c)])
+                first = res
+            else:
+                for k in ("combos", "scores", "tables"):
+                    assert np.array_equal(res[k], first[k])
+    finally:
+        epi.epi_set_prefix_block(cx.ctx, ds, 3, 0)
+        epi.epi_unload(cx.ctx, ds)
