@@ -899,6 +899,23 @@ struct QFmt<true> {
     }
 };
 
+// Pilot pass over an item: the wave's best screening sum S (best over its
+// lanes' combinations; INT_MIN: none) becomes one histogram count.  S is
+// within `reads` units (2^-tq) of (num - score_const) 2^(tq - shift) (each
+// table value within one unit of its n ln n, as in screen_bound), so
+// score_const + (S - reads - 1) 2^(shift - tq) is below that combination's
+// num; one atomic per wave, and the K-th best of such maxima is close to the
+// K-th best of all the item's combinations.
+EPI_DEV void pilot_count(TopK &tk, const Task &t, int best, int reads) {
+    #pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const int o = __shfl_xor(best, off);
+        best = o > best ? o : best;
+    }
+    hist_add(tk, lane_id() == 0 && best != (int)0x80000000u,
+             t.score_const + (long long)(best - reads - 1) * (1ll << (t.ds.shift - t.ds.tq)));
+}
+
 // PILOT: the histogram-only pass over an item (needs the screening table in
 // LDS): lower bounds of the scores are counted, nothing is offered.
 template <bool LDS, bool REV, bool I8, bool EMIT = false, bool CHECK = false, int NJ = 1, bool PILOT = false>
@@ -1199,20 +1216,7 @@ EPI_DEV void item_f3m(const Task &t, unsigned long long local, TopK &tk, Cand *l
             }
         }
     }
-    if constexpr (PILOT) {
-        // one count per item, the best of its combinations (one atomic per
-        // wave; the K-th best of such maxima is close to that of all): the
-        // screening sum S is within 81 units (2^-tq) of (num - score_const)
-        // 2^(tq - shift), so score_const + (S - 82) 2^(shift - tq) is below
-        // that combination's num
-        #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const int o = __shfl_xor(pilot_best, off);
-            pilot_best = o > pilot_best ? o : pilot_best;
-        }
-        hist_add(tk, lane_id() == 0 && pilot_best != (int)0x80000000u,
-                 t.score_const + (long long)(pilot_best - 82) * (1ll << (d.shift - d.tq)));
-    }
+    if constexpr (PILOT) pilot_count(tk, t, pilot_best, 81);
 }
 
 // ---------------------------------------------------------------------------
@@ -1585,10 +1589,12 @@ EPI_DEV void item_seg(const Task &t, unsigned long long local, TopK &tk, Cand *l
 // cell in one register (4 n(cases) | 4 n(controls) << 16), and so do the
 // lane's 81 cells.
 // ---------------------------------------------------------------------------
-template <bool LDS, bool CHECK = false>
+// PILOT: the histogram-only pass (as for order 3).
+template <bool LDS, bool CHECK = false, bool PILOT = false>
 EPI_DEV void item_r4(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr,
                      const unsigned long long *binom, int bstride) {
     const DsView d = t.ds;
+    int pilot_best = (int)0x80000000u;  // PILOT: the lane's best screening sum
     int sb = 0;
     if constexpr (LDS) sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.tq, 243);
     const int bits = t.key_bits;
@@ -1736,6 +1742,14 @@ EPI_DEV void item_r4(const Task &t, unsigned long long local, TopK &tk, Cand *li
         }
         F[80] = ((unsigned)d.ncls[0] << kQScaleShift) | ((unsigned)d.ncls[1] << (16 + kQScaleShift));
         mobius4(F);
+        if constexpr (PILOT) {
+            static_assert(LDS && !CHECK, "the pilot pass reads the screening table from LDS");
+            if (valid) {
+                const int S = screen_sum_packed<81>(F);
+                pilot_best = S > pilot_best ? S : pilot_best;
+            }
+            continue;
+        }
         if constexpr (CHECK) {
             unsigned long long sum = 0;
             #pragma unroll
@@ -1758,6 +1772,7 @@ EPI_DEV void item_r4(const Task &t, unsigned long long local, TopK &tk, Cand *li
             if constexpr (LDS) sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.tq, 243);
         }
     }
+    if constexpr (PILOT) pilot_count(tk, t, pilot_best, 243);
 }
 
 // ---------------------------------------------------------------------------
@@ -2030,7 +2045,8 @@ ScanKernelFn find_scan_kernel_check(int np2, int np3, int gk) {
 }
 #else
 // ---------------------------------------------------------------------------
-// Pilot pass of a matrix-core order-3 scan, launched before its main launch:
+// Pilot pass of a matrix-core order-3 or reduced-cell order-4 scan, launched
+// before its main launch:
 // the waves pass over the task's pilot items (consecutive, so that they share
 // operand blocks in L2 as the main launch's do), count the best lower bound
 // of each step into the task's histogram, then publish the
@@ -2039,9 +2055,10 @@ ScanKernelFn find_scan_kernel_check(int np2, int np3, int gk) {
 // main launch starts from that bound, and it does not count the pilot items
 // again.  Same launch shape and LDS layout as the scan kernel.
 // ---------------------------------------------------------------------------
-template <int NP3>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<0, NP3, 0>())))
-scan_pilot(const Task *__restrict__ tasks, int tab_cap, int kmax, int stage_cap, unsigned *__restrict__ done) {
+template <int NP3, int GK>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<0, NP3, GK>())))
+scan_pilot(const Task *__restrict__ tasks, const unsigned long long *__restrict__ binom, int bstride, int tab_cap,
+           int kmax, int stage_cap, unsigned *__restrict__ done) {
     extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
     unsigned *s_tab = (unsigned *)s_dyn;
     const Task &T = tasks[0];
@@ -2053,7 +2070,7 @@ scan_pilot(const Task *__restrict__ tasks, int tab_cap, int kmax, int stage_cap,
     // the screening table at LDS address 0, with its mirrored half when it fits
     const int ent_fwd = T.ds.N + 1, ent_rev = 2 * T.ds.N + 2;
     if (ent_fwd > tab_cap || (unsigned)(uintptr_t)(lu32 *)s_tab != 0u) return;  // every wave alike: no bound
-    const bool rev = ent_rev <= tab_cap;
+    const bool rev = NP3 != 0 && ent_rev <= tab_cap;  // mirrored half: the signed cell form of order 3
     const int ent = rev ? ent_rev : ent_fwd;
     #pragma unroll 1
     for (int x = threadIdx.x; x < ent; x += blockDim.x) s_tab[x] = T.ds.itab[x];
@@ -2078,8 +2095,13 @@ scan_pilot(const Task *__restrict__ tasks, int tab_cap, int kmax, int stage_cap,
     #pragma unroll 1
     for (unsigned long long w = (unsigned long long)blockIdx.x * 4 + (unsigned long long)wave;
          w < (unsigned long long)T.pilot_n && T.pilot_first + w < T.n_items; w += n_waves) {
-        if (rev) item_f3m<true, true, i8, false, false, nj, true>(T, T.pilot_first + w, tk, s_list, none, s_stage);
-        else item_f3m<true, false, i8, false, false, nj, true>(T, T.pilot_first + w, tk, s_list, none, s_stage);
+        const unsigned long long local = T.pilot_first + w;
+        if constexpr (GK == 4) {
+            item_r4<true, false, true>(T, local, tk, s_list, none, binom, bstride);
+        } else {
+            if (rev) item_f3m<true, true, i8, false, false, nj, true>(T, local, tk, s_list, none, s_stage);
+            else item_f3m<true, false, i8, false, false, nj, true>(T, local, tk, s_list, none, s_stage);
+        }
     }
     // the last wave to finish reads the bound off the histogram (from one
     // octave above its own best count down) and publishes it, then clears
@@ -2841,15 +2863,18 @@ hipError_t launch_scan(int np2, int np3, int gk, int grid, hipStream_t st, const
     return hipGetLastError();
 }
 
-hipError_t launch_pilot(int np3, int grid, hipStream_t st, const Task *tasks, int tab_cap, int kmax, int stage_cap,
+hipError_t launch_pilot(int np3, int gk, int grid, hipStream_t st, const Task *tasks,
+                        const unsigned long long *binom, int bstride, int tab_cap, int kmax, int stage_cap,
                         unsigned *done) {
-    void (*fn)(const Task *, int, int, int, unsigned *) = np3 == kNpMfma     ? scan_pilot<kNpMfma>
-                                              : np3 == kNpMfmaI8 ? scan_pilot<kNpMfmaI8>
-                                              : np3 == kNpMfma2  ? scan_pilot<kNpMfma2>
-                                                                 : nullptr;
+    void (*fn)(const Task *, const unsigned long long *, int, int, int, int, unsigned *) =
+        gk == 4               ? scan_pilot<0, 4>
+        : np3 == kNpMfma      ? scan_pilot<kNpMfma, 0>
+        : np3 == kNpMfmaI8    ? scan_pilot<kNpMfmaI8, 0>
+        : np3 == kNpMfma2     ? scan_pilot<kNpMfma2, 0>
+                              : nullptr;
     if (!fn) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(4 * kWave), scan_lds_bytes(tab_cap, kmax, stage_cap), st, tasks, tab_cap,
-                       kmax, stage_cap, done);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(4 * kWave), scan_lds_bytes(tab_cap, kmax, stage_cap), st, tasks, binom,
+                       bstride, tab_cap, kmax, stage_cap, done);
     return hipGetLastError();
 }
 

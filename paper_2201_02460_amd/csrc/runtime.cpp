@@ -1006,12 +1006,12 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         t.key_bits = key_bits_for(s.desc.order);
         t.digest = check ? p->d_digest + 2 * i : nullptr;
         // pilot pass (back-to-back launches of the matrix-core order-3
-        // kernels, screening table in LDS, at least 64 items per wave of the
-        // main launch): one item per wave of the main launch, consecutive
-        // items from the middle of the task
+        // kernels and of order 4 by reduced cells, screening table in LDS,
+        // at least 64 items per wave of the main launch): one item per wave
+        // of the main launch, consecutive items from the middle of the task
         s.pilot_n = 0;
         s.pilot_first = 0;
-        if (!persistent && s.variant == kF3 && is_mfma_np(s.np)) {
+        if (!persistent && ((s.variant == kF3 && is_mfma_np(s.np)) || s.variant == kR4)) {
             const LaunchGroup &g = p->groups[i];
             const unsigned long long waves = (unsigned long long)g.grid * 4;
             if (g.tab_cap >= s.ds->N + 1 && s.n_items >= 64 * waves) {
@@ -1182,8 +1182,8 @@ static int plan_enqueue(Ctx *c, Plan *p, hipStream_t st, bool timing, unsigned l
             if (s.pilot_n > 0)
                 // its wave counter: the pair pass's queue word, cleared
                 // after that pass and by the pilot's last wave
-                HIPCHK(launch_pilot(g.np3, std::min(g.grid, (s.pilot_n + 3) / 4), st, tasks + i, g.tab_cap, g.kmax,
-                                    g.stage_cap, (unsigned *)(p->d_queues + 0)));
+                HIPCHK(launch_pilot(g.np3, g.gk, std::min(g.grid, (s.pilot_n + 3) / 4), st, tasks + i, c->d_binom,
+                                    c->bstride, g.tab_cap, g.kmax, g.stage_cap, (unsigned *)(p->d_queues + 0)));
             HIPCHK(launch_scan(g.np2, g.np3, g.gk, g.grid, st, tasks + i, 1, std::min(s.n_items, item_cap),
                                p->d_queues + 1, c->d_binom, c->bstride, g.tab_cap, g.kmax, g.stage_cap, p->check));
             HIPCHK(launch_init_counters(st, p->d_queues + 1, 1, nullptr, nullptr, 0, nullptr));

@@ -83,8 +83,9 @@ struct PlanScan {
     unsigned cand_cap = 0;
     ResultLayout lay{};
     int scan_id = -1;
-    // matrix-core order 3, plans of back-to-back launches: pilot pass over
-    // items pilot_first .. pilot_first + pilot_n - 1 (pilot_n 0: none)
+    // matrix-core order 3 and reduced-cell order 4, plans of back-to-back
+    // launches: pilot pass over items pilot_first .. pilot_first + pilot_n - 1
+    // (pilot_n 0: none)
     int pilot_n = 0;
     unsigned long long pilot_first = 0;
 };
@@ -193,7 +194,8 @@ struct Ctx {
 };
 
 // kernel launchers (kernels.hip)
-hipError_t launch_pilot(int np3, int grid, hipStream_t st, const Task *tasks, int tab_cap, int kmax, int stage_cap,
+hipError_t launch_pilot(int np3, int gk, int grid, hipStream_t st, const Task *tasks,
+                        const unsigned long long *binom, int bstride, int tab_cap, int kmax, int stage_cap,
                         unsigned *done);
 hipError_t launch_scan(int np2, int np3, int gk, int grid, hipStream_t st, const Task *tasks, int n_tasks,
                        unsigned long long total_items, unsigned long long *queue, const unsigned long long *binom,
