@@ -141,8 +141,10 @@ struct Task {
                                       //   lowest index), else lexicographic
     unsigned long long *digest;       // checking launches: [0] combinations scored, [1] their digest sum
                                       //   (null: no check)
-    unsigned long long pilot_first;   // matrix-core order 3: items pilot_first .. + pilot_n - 1 were
-    int32_t pilot_n;                  //   counted into the histogram by the pilot pass (0: none)
+    unsigned long long pilot_first;   // matrix-core order 3, order 4 by reduced cells: items
+    int32_t pilot_n;                  //   pilot_first .. + pilot_n - 1 were counted into the histogram by
+                                      //   the pilot pass (0: none; a multiple of 4)
+    unsigned long long pilot_base;    // the task's first item in its pilot launch (a multiple of 4)
 };
 
 // Work-item descriptor tables, one item per entry, in groups of consecutive
@@ -238,12 +240,17 @@ __host__ __device__ constexpr unsigned long long cell_weight(int cls, int x) {
 }
 
 // Score histogram of a task: how many distinct combinations entered some
-// wave's best-K list, by the position of the leading bit of their num and the
-// next kHistFineBits bits (64 x 2^kHistFineBits counters).  It turns the
-// lists of all waves into one lower bound of the task's K-th best.
+// wave's best-K list (or, pilot items, lower bounds of their best scores), by
+// the position of the leading bit of their num and the next kHistFineBits
+// bits (64 x 2^kHistFineBits counters).  It turns the lists of all waves
+// into one lower bound of the task's K-th best.  A positive num has its
+// leading bit at position 62 at most, so the bins of position 63 are never
+// counted; the last word is the task's pilot counter instead.
 constexpr int kHistFineBits = 5;
 constexpr int kHistFine = 1 << kHistFineBits;
 constexpr int kHistWords = 64 * kHistFine;
+constexpr int kHistTop = 63 * kHistFine - 1;  // highest bin a positive num reaches
+constexpr int kPilotWord = kHistWords - 1;    // pilot items of the task done so far
 
 // Matrix-core order-3 kernels count 4 x n (their B operand holds 4 for a set
 // bit), so a count is also the byte offset of its screening-table entry.

@@ -144,7 +144,7 @@ EPI_DEV unsigned wave_scan_incl(unsigned v) {
 EPI_DEV long long hist_bound(const unsigned *h, int K, int top) {
     const int lane = lane_id();
     int start = top + kHistFine;
-    start = start < kHistWords - 1 ? start : kHistWords - 1;
+    start = start < kHistTop ? start : kHistTop;
     unsigned carry = 0;
     #pragma unroll 1
     for (int w = 0; w < 2; ++w, start -= kWave) {
@@ -2045,43 +2045,39 @@ ScanKernelFn find_scan_kernel_check(int np2, int np3, int gk) {
 }
 #else
 // ---------------------------------------------------------------------------
-// Pilot pass of a matrix-core order-3 or reduced-cell order-4 scan, launched
-// before its main launch:
-// the waves pass over the task's pilot items (consecutive, so that they share
-// operand blocks in L2 as the main launch's do), count the best lower bound
-// of each step into the task's histogram, then publish the
-// bound the histogram gives (the K-th best of lower bounds of distinct
-// combinations is at most the task's final K-th best).  Every wave of the
-// main launch starts from that bound, and it does not count the pilot items
-// again.  Same launch shape and LDS layout as the scan kernel.
+// Pilot pass of the matrix-core order-3 and reduced-cell order-4 scans of a
+// launch group, launched before its main launch.  Each task with pilot_n > 0
+// has pilot_n consecutive pilot items (from the middle of its scan, sharing
+// operand blocks in L2 as the main launch's items do), numbered from
+// pilot_base in the pilot launch; a workgroup takes 4 of them (one per wave,
+// never two tasks).  A wave passes over its item counting the best lower
+// bound of its scores into the task's histogram (one count); the last wave of
+// a task reads the bound the histogram gives (the K-th best of lower bounds
+// of distinct combinations is at most the task's final K-th best) and
+// publishes it.  Every wave of the main launch starts from that bound, and
+// the main launch does not count the pilot items again.  Same launch shape
+// and LDS layout as the scan kernel.
 // ---------------------------------------------------------------------------
 template <int NP3, int GK>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<0, NP3, GK>())))
-scan_pilot(const Task *__restrict__ tasks, const unsigned long long *__restrict__ binom, int bstride, int tab_cap,
-           int kmax, int stage_cap, unsigned *__restrict__ done) {
+scan_pilot(const Task *__restrict__ tasks, int n_tasks, unsigned long long total, const unsigned long long *binom,
+           int bstride, int tab_cap, int kmax, int stage_cap) {
     extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
     unsigned *s_tab = (unsigned *)s_dyn;
-    const Task &T = tasks[0];
+    // the screening reads address the table from LDS address 0
+    if ((unsigned)(uintptr_t)(lu32 *)s_tab != 0u) return;
     const int wave = uni((int)(threadIdx.x >> 6));
     const long long lists_off = ((long long)tab_cap * 4 + 15) & ~15LL;
     const long long stage_off = lists_off + (long long)4 * kmax * sizeof(Cand);
     Cand *s_list = (Cand *)(s_dyn + lists_off) + wave * kmax;
     v4u *s_stage = (v4u *)(s_dyn + stage_off) + wave * stage_cap;
-    // the screening table at LDS address 0, with its mirrored half when it fits
-    const int ent_fwd = T.ds.N + 1, ent_rev = 2 * T.ds.N + 2;
-    if (ent_fwd > tab_cap || (unsigned)(uintptr_t)(lu32 *)s_tab != 0u) return;  // every wave alike: no bound
-    const bool rev = NP3 != 0 && ent_rev <= tab_cap;  // mirrored half: the signed cell form of order 3
-    const int ent = rev ? ent_rev : ent_fwd;
-    #pragma unroll 1
-    for (int x = threadIdx.x; x < ent; x += blockDim.x) s_tab[x] = T.ds.itab[x];
-    __syncthreads();
     TopK tk;
     tk.n = 0;
-    tk.K = T.top_k;
+    tk.K = 1;
     tk.wi = 0;
     tk.wn = 0;
     tk.wk = 0;
-    tk.hist = T.hist;
+    tk.hist = nullptr;
     tk.added = 0;
     tk.top = -1;
     tk.dsum = 0;
@@ -2090,33 +2086,53 @@ scan_pilot(const Task *__restrict__ tasks, const unsigned long long *__restrict_
     constexpr bool i8 = NP3 == kNpMfmaI8;
     constexpr int nj = NP3 == kNpMfma2 ? 2 : 1;
     const long long none = (long long)0x8000000000000000ull;
-    // wave w takes pilot items w, w + (waves of the grid), ...
-    const unsigned long long n_waves = (unsigned long long)gridDim.x * 4;
+    const uint32_t *loaded = nullptr;
+    bool loaded_rev = false;
     #pragma unroll 1
-    for (unsigned long long w = (unsigned long long)blockIdx.x * 4 + (unsigned long long)wave;
-         w < (unsigned long long)T.pilot_n && T.pilot_first + w < T.n_items; w += n_waves) {
-        const unsigned long long local = T.pilot_first + w;
-        if constexpr (GK == 4) {
-            item_r4<true, false, true>(T, local, tk, s_list, none, binom, bstride);
-        } else {
-            if (rev) item_f3m<true, true, i8, false, false, nj, true>(T, local, tk, s_list, none, s_stage);
-            else item_f3m<true, false, i8, false, false, nj, true>(T, local, tk, s_list, none, s_stage);
+    for (unsigned long long g = (unsigned long long)blockIdx.x * 4; g < total; g += (unsigned long long)gridDim.x * 4) {
+        int lo = 0, hi = n_tasks - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tasks[mid].pilot_base <= g) lo = mid; else hi = mid - 1;
         }
-    }
-    // the last wave to finish reads the bound off the histogram (from one
-    // octave above its own best count down) and publishes it, then clears
-    // the counter for the next pilot pass
-    __threadfence();
-    unsigned prev = 0;
-    if (lane_id() == 0) prev = atomicAdd(done, 1u);
-    prev = (unsigned)__builtin_amdgcn_readfirstlane((int)prev);
-    if (prev + 1 == gridDim.x * 4) {
+        const Task &T = tasks[lo];
+        // the task's screening table (the host takes only tasks whose table
+        // fits), with its mirrored half for the signed cell form of order 3
+        const int ent_fwd = T.ds.N + 1, ent_rev = 2 * T.ds.N + 2;
+        const bool rev = NP3 != 0 && ent_rev <= tab_cap;
+        if (ent_fwd <= tab_cap && (loaded != T.ds.itab || (rev && !loaded_rev))) {
+            __syncthreads();  // every wave is done with the previous table
+            const int ent = rev ? ent_rev : ent_fwd;
+            #pragma unroll 1
+            for (int x = threadIdx.x; x < ent; x += blockDim.x) s_tab[x] = T.ds.itab[x];
+            __syncthreads();
+            loaded = T.ds.itab;
+            loaded_rev = rev;
+        }
+        const unsigned long long local = T.pilot_first + (g - T.pilot_base) + (unsigned long long)wave;
+        tk.hist = T.hist;
+        tk.K = T.top_k;
+        tk.top = -1;
+        tk.added = 0;
+        if (ent_fwd <= tab_cap && local < T.n_items) {
+            if constexpr (GK == 4) {
+                item_r4<true, false, true>(T, local, tk, s_list, none, binom, bstride);
+            } else {
+                if (rev) item_f3m<true, true, i8, false, false, nj, true>(T, local, tk, s_list, none, s_stage);
+                else item_f3m<true, false, i8, false, false, nj, true>(T, local, tk, s_list, none, s_stage);
+            }
+        }
+        // the task's last pilot wave takes the bound (from one octave above
+        // its own count down)
         __threadfence();
-        if (tk.top >= 0) {
-            const long long hb = hist_bound(tk.hist, tk.K, tk.top);
+        unsigned prev = 0;
+        if (lane_id() == 0) prev = atomicAdd(T.hist + kPilotWord, 1u);
+        prev = (unsigned)__builtin_amdgcn_readfirstlane((int)prev);
+        if (prev + 1 == (unsigned)T.pilot_n && tk.top >= 0) {
+            __threadfence();
+            const long long hb = hist_bound(T.hist, T.top_k, tk.top);
             if (hb != none && lane_id() == 0) atomicMax(T.thr, bias(hb));
         }
-        if (lane_id() == 0) atomicExch(done, 0u);
     }
 }
 
@@ -2863,18 +2879,18 @@ hipError_t launch_scan(int np2, int np3, int gk, int grid, hipStream_t st, const
     return hipGetLastError();
 }
 
-hipError_t launch_pilot(int np3, int gk, int grid, hipStream_t st, const Task *tasks,
-                        const unsigned long long *binom, int bstride, int tab_cap, int kmax, int stage_cap,
-                        unsigned *done) {
-    void (*fn)(const Task *, const unsigned long long *, int, int, int, int, unsigned *) =
+hipError_t launch_pilot(int np3, int gk, int grid, hipStream_t st, const Task *tasks, int n_tasks,
+                        unsigned long long total, const unsigned long long *binom, int bstride, int tab_cap, int kmax,
+                        int stage_cap) {
+    void (*fn)(const Task *, int, unsigned long long, const unsigned long long *, int, int, int, int) =
         gk == 4               ? scan_pilot<0, 4>
         : np3 == kNpMfma      ? scan_pilot<kNpMfma, 0>
         : np3 == kNpMfmaI8    ? scan_pilot<kNpMfmaI8, 0>
         : np3 == kNpMfma2     ? scan_pilot<kNpMfma2, 0>
                               : nullptr;
     if (!fn) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(4 * kWave), scan_lds_bytes(tab_cap, kmax, stage_cap), st, tasks, binom,
-                       bstride, tab_cap, kmax, stage_cap, done);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(4 * kWave), scan_lds_bytes(tab_cap, kmax, stage_cap), st, tasks, n_tasks,
+                       total, binom, bstride, tab_cap, kmax, stage_cap);
     return hipGetLastError();
 }
 

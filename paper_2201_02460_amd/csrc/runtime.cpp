@@ -644,6 +644,12 @@ int default_np3(Ctx *c, const Dataset *d) {
     return d->qa ? kNpMfma : 4;
 }
 
+int pilot_items_for(int variant, int np, unsigned long long n_items, int top_k, int N, int tab_cap, int waves) {
+    if (!((variant == kF3 && is_mfma_np(np)) || variant == kR4) || tab_cap < N + 1) return 0;
+    const unsigned long long n = std::min<unsigned long long>((unsigned long long)waves, n_items / 32) & ~3ull;
+    return n >= 2ull * (unsigned long long)std::max(top_k, 1) ? (int)n : 0;
+}
+
 // Whether the dataset can run order-3 block np: the matrix-core blocks need
 // their operand copies, and the two-middle-SNP one its class sizes to fit
 // one float accumulator (q3_pack_fits).
@@ -1005,22 +1011,16 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         t.n_blocks = 0;
         t.key_bits = key_bits_for(s.desc.order);
         t.digest = check ? p->d_digest + 2 * i : nullptr;
-        // pilot pass (back-to-back launches of the matrix-core order-3
-        // kernels and of order 4 by reduced cells, screening table in LDS,
-        // at least 64 items per wave of the main launch): one item per wave
-        // of the main launch, consecutive items from the middle of the task
+        // pilot pass: consecutive items from the middle of the task
         s.pilot_n = 0;
         s.pilot_first = 0;
-        if (!persistent && ((s.variant == kF3 && is_mfma_np(s.np)) || s.variant == kR4)) {
-            const LaunchGroup &g = p->groups[i];
-            const unsigned long long waves = (unsigned long long)g.grid * 4;
-            if (g.tab_cap >= s.ds->N + 1 && s.n_items >= 64 * waves) {
-                s.pilot_n = (int)waves;
-                s.pilot_first = s.n_items / 2 - waves / 2;
-            }
-        }
+        for (const LaunchGroup &g : p->groups)
+            if (std::find(g.scans.begin(), g.scans.end(), i) != g.scans.end())
+                s.pilot_n = pilot_items_for(s.variant, s.np, s.n_items, s.desc.top_k, s.ds->N, g.tab_cap, g.grid * 4);
+        s.pilot_first = (s.n_items - (unsigned long long)s.pilot_n) / 2;
         t.pilot_first = s.pilot_first;
         t.pilot_n = s.pilot_n;
+        t.pilot_base = 0;
     }
     {
         int e = nt;
@@ -1035,6 +1035,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
             t.digest = nullptr;
             t.pilot_first = 0;
             t.pilot_n = 0;
+            t.pilot_base = 0;
             t.items = (const unsigned long long *)s.emit_items_d;
             t.n_items = s.emit_items;
             t.item_base = persistent ? base : 0;
@@ -1070,6 +1071,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
             t.digest = nullptr;
             t.pilot_first = 0;
             t.pilot_n = 0;
+            t.pilot_base = 0;
             t.items = (const unsigned long long *)s.t3_items_d;
             t.n_items = s.t3_items;
             t.item_base = persistent ? base : 0;
@@ -1082,16 +1084,20 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         LaunchGroup &g = p->groups[gi];
         if (!persistent) {
             g.task_off = g.scans.front();
+            g.pilot_total = (unsigned long long)tasks[g.task_off].pilot_n;
             continue;
         }
         g.task_off = (int)tasks.size();
-        unsigned long long base = 0;
+        unsigned long long base = 0, pbase = 0;
         for (int i : g.scans) {
             Task t = tasks[i];
             t.item_base = base;
             base += t.n_items;
+            t.pilot_base = pbase;
+            pbase += (unsigned long long)t.pilot_n;
             tasks.push_back(t);
         }
+        g.pilot_total = pbase;
     }
     if ((rc = plan_alloc(c, p.get(), tasks.size() * sizeof(Task), &p->d_tasks))) return cleanup(rc);
     // layout and task arrays staged in pinned memory; every run uploads them
@@ -1148,6 +1154,10 @@ static int plan_enqueue(Ctx *c, Plan *p, hipStream_t st, bool timing, unsigned l
         ++q;
         if (timing && single) HIPCHK(hipEventRecord(p->ev[2], st));
         for (auto &g : p->groups) {
+            if (g.pilot_total > 0 && item_cap == ~0ull)
+                HIPCHK(launch_pilot(g.np3, g.gk, (int)std::min<unsigned long long>(g.grid, g.pilot_total / 4), st,
+                                    tasks + g.task_off, (int)g.scans.size(), g.pilot_total, c->d_binom, c->bstride,
+                                    g.tab_cap, g.kmax, g.stage_cap));
             HIPCHK(launch_scan(g.np2, g.np3, g.gk, g.grid, st, tasks + g.task_off, (int)g.scans.size(),
                                std::min(g.total_items, item_cap), p->d_queues + q, c->d_binom, c->bstride,
                                g.tab_cap, g.kmax, g.stage_cap, p->check));
@@ -1179,11 +1189,10 @@ static int plan_enqueue(Ctx *c, Plan *p, hipStream_t st, bool timing, unsigned l
                 HIPCHK(launch_init_counters(st, p->d_queues, 1, nullptr, nullptr, 0, nullptr));
             }
             if (timing && single) HIPCHK(hipEventRecord(p->ev[2], st));
-            if (s.pilot_n > 0)
-                // its wave counter: the pair pass's queue word, cleared
-                // after that pass and by the pilot's last wave
-                HIPCHK(launch_pilot(g.np3, g.gk, std::min(g.grid, (s.pilot_n + 3) / 4), st, tasks + i, c->d_binom,
-                                    c->bstride, g.tab_cap, g.kmax, g.stage_cap, (unsigned *)(p->d_queues + 0)));
+            if (s.pilot_n > 0 && item_cap == ~0ull)
+                HIPCHK(launch_pilot(g.np3, g.gk, std::min(g.grid, s.pilot_n / 4), st, tasks + i, 1,
+                                    (unsigned long long)s.pilot_n, c->d_binom, c->bstride, g.tab_cap, g.kmax,
+                                    g.stage_cap));
             HIPCHK(launch_scan(g.np2, g.np3, g.gk, g.grid, st, tasks + i, 1, std::min(s.n_items, item_cap),
                                p->d_queues + 1, c->d_binom, c->bstride, g.tab_cap, g.kmax, g.stage_cap, p->check));
             HIPCHK(launch_init_counters(st, p->d_queues + 1, 1, nullptr, nullptr, 0, nullptr));

@@ -83,9 +83,8 @@ struct PlanScan {
     unsigned cand_cap = 0;
     ResultLayout lay{};
     int scan_id = -1;
-    // matrix-core order 3 and reduced-cell order 4, plans of back-to-back
-    // launches: pilot pass over items pilot_first .. pilot_first + pilot_n - 1
-    // (pilot_n 0: none)
+    // matrix-core order 3 and reduced-cell order 4: pilot pass over items
+    // pilot_first .. pilot_first + pilot_n - 1 (pilot_n 0: none)
     int pilot_n = 0;
     unsigned long long pilot_first = 0;
 };
@@ -97,6 +96,7 @@ struct LaunchGroup {
     int task_off = 0;  // first task of the group in the plan's task array
     std::vector<int> scans;
     unsigned long long total_items = 0;
+    unsigned long long pilot_total = 0;  // pilot items of the group's tasks (0: no pilot launch)
 };
 
 struct Plan {
@@ -194,9 +194,14 @@ struct Ctx {
 };
 
 // kernel launchers (kernels.hip)
-hipError_t launch_pilot(int np3, int gk, int grid, hipStream_t st, const Task *tasks,
-                        const unsigned long long *binom, int bstride, int tab_cap, int kmax, int stage_cap,
-                        unsigned *done);
+hipError_t launch_pilot(int np3, int gk, int grid, hipStream_t st, const Task *tasks, int n_tasks,
+                        unsigned long long total, const unsigned long long *binom, int bstride, int tab_cap, int kmax,
+                        int stage_cap);
+// Pilot items of a task (a multiple of 4; 0: none): up to one per wave of its
+// launch, when the task has at least 32 items per pilot item and the pilot
+// counts can reach a bound (twice top_k of them), and its screening table
+// fits the launch's LDS table (tab_cap entries).
+int pilot_items_for(int variant, int np, unsigned long long n_items, int top_k, int N, int tab_cap, int waves);
 hipError_t launch_scan(int np2, int np3, int gk, int grid, hipStream_t st, const Task *tasks, int n_tasks,
                        unsigned long long total_items, unsigned long long *queue, const unsigned long long *binom,
                        int bstride, int tab_cap, int kmax, int stage_cap, bool check = false);

@@ -39,6 +39,10 @@ struct Request {
     const void *items = nullptr, *emit_items = nullptr, *t3_items = nullptr;
     unsigned long long n_items = 0, cursor = 0, emit_n = 0, t3_n = 0, n_combos = 0;
     bool emit_done = false;
+    // pilot pass in the request's first round (matrix-core order 3, order 4
+    // by reduced cells): items pilot_first .. + pilot_n - 1
+    int pilot_n = 0;
+    unsigned long long pilot_first = 0;
     void *pairs = nullptr, *triples = nullptr, *cand = nullptr;
     unsigned cand_cap = 0;
     uint64_t footprint = 0;
@@ -138,6 +142,9 @@ static int admit(Server *S, Request *r) {
     if (sub && (rc = get_items(c, kF2, r->ds->M, 4, &r->emit_items, &r->emit_n))) return rc;
     if (r->variant == kR4 && (rc = get_items(c, kF3, r->ds->M, kNpMfma, &r->t3_items, &r->t3_n))) return rc;
     r->cand_cap = (unsigned)((unsigned long long)S->grid_max * 4 * r->desc.top_k + r->desc.top_k + 64);
+    r->pilot_n = pilot_items_for(r->variant, r->np, r->n_items, r->desc.top_k, r->ds->N, Plan::kTabMax,
+                                 S->grid_max * 4);
+    r->pilot_first = (r->n_items - (unsigned long long)r->pilot_n) / 2;
     const uint64_t pair_bytes = sub ? pair_table_bytes(r->variant, r->ds->M) : 0;
     const uint64_t trip_bytes = r->variant == kR4 ? triple_table_bytes(r->ds->M) : 0;
     r->footprint = pair_bytes + trip_bytes + (uint64_t)r->cand_cap * sizeof(Cand);
@@ -179,6 +186,8 @@ static Task make_task(Server *S, Request *r) {
     t.top_k = r->desc.top_k;
     t.np = r->np;
     t.key_bits = key_bits_for(r->desc.order);
+    t.pilot_first = r->pilot_first;
+    t.pilot_n = r->pilot_n;
     return t;
 }
 
@@ -256,11 +265,13 @@ static int run_round(Server *S) {
     struct G {
         int np2, np3, gk, off, n, tab_cap, kmax, stage;
         unsigned long long total;
+        int pilot_off, pilot_tasks;  // the pilot launch's task copies (requests in their first round)
+        unsigned long long pilot_total;
     };
     std::vector<G> groups;
     for (int key : {30 + kNpMfma, 30 + kNpMfma2, 30 + kNpMfmaI8, 38, 34, 32, 31, 22, 24, 28, 4, 5}) {
         std::vector<int> orders;
-        G g{0, 0, 0, ti, 0, 0, 1, 0, 0};
+        G g{0, 0, 0, ti, 0, 0, 1, 0, 0, 0, 0, 0};
         for (int i = 0; i < nt; ++i) {
             Request *r = order[i].first;
             if (round_group(r) != key) continue;
@@ -270,9 +281,11 @@ static int run_round(Server *S) {
         pick_group_kernel(orders, key > 30 ? key - 30 : (key > 20 ? key - 20 : 4), &g.np2, &g.np3, &g.gk);
         g.stage = stage_cap_for(g.np2, g.np3, 0);
         int cap_both = 0, cap_first = 0;
+        std::vector<Request *> members;  // the group's requests, in copy order
         for (int i = 0; i < nt; ++i) {
             Request *r = order[i].first;
             if (round_group(r) != key) continue;
+            members.push_back(r);
             Task t = ht[i];
             t.item_base = g.total;
             t.first_item = r->cursor;
@@ -285,6 +298,19 @@ static int run_round(Server *S) {
             cap_first = std::max(cap_first, tab_entries_for(r->ds, r->variant, r->np, false));
         }
         g.tab_cap = group_tab_cap(g.np2, g.np3, g.gk, cap_both, cap_first, g.kmax, g.stage);
+        // requests in their first round with a pilot pass: copies numbered
+        // in the pilot launch
+        g.pilot_off = ti;
+        for (int k = 0; k < g.n; ++k) {
+            Request *r = members[k];
+            if (r->cursor != 0 || r->pilot_n == 0) continue;
+            if (ti >= S->max_round_tasks) return fail(EPI_EDEVICE, "server round task array overflow");
+            Task t = ht[g.off + k];
+            t.pilot_base = g.pilot_total;
+            g.pilot_total += (unsigned long long)r->pilot_n;
+            ht[ti++] = t;
+            g.pilot_tasks++;
+        }
         groups.push_back(g);
     }
     if (ti > S->max_round_tasks) return fail(EPI_EDEVICE, "server round task array overflow");
@@ -308,6 +334,11 @@ static int run_round(Server *S) {
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         const G &g = groups[gi];
         const int grid = grid_for(c, g.np2, g.np3, g.gk, g.total, g.tab_cap, g.kmax, g.stage);
+        if (g.pilot_total > 0)
+            SRV_HIPCHK(launch_pilot(g.np3, g.gk,
+                                    (int)std::min<unsigned long long>(std::min(grid, S->grid_max), g.pilot_total / 4),
+                                    st, dt + g.pilot_off, g.pilot_tasks, g.pilot_total, c->d_binom, c->bstride,
+                                    g.tab_cap, g.kmax, g.stage));
         SRV_HIPCHK(launch_scan(g.np2, g.np3, g.gk, std::min(grid, S->grid_max), st, dt + g.off, g.n, g.total,
                                S->d_queues + 2 + gi, c->d_binom, c->bstride, g.tab_cap, g.kmax, g.stage));
     }
@@ -483,7 +514,7 @@ int epi_server_start(epi_ctx *ctx, const epi_server_config *cfg, int32_t *server
         S->grid_max = std::max(S->grid_max,
                                grid_for(C, k[0], k[1], k[2], ~0ull >> 8, 0, 1, stage_cap_for(k[0], k[1], 1)));
     const int A = cfg->max_active;
-    S->max_round_tasks = 4 * A + 4;  // main, pair passes, triplet passes, group copies
+    S->max_round_tasks = 5 * A + 4;  // main, pair passes, triplet passes, group copies, pilot copies
     S->out_block = result_block_bytes(EPI_MAX_TOP_K, EPI_SERVE_MAX_ORDER);
     int rc;
     auto cleanup = [&](int code) {
