@@ -665,7 +665,7 @@ bool np3_usable(const Dataset *d, int np) {
 // at most 8 waves per SIMD) and LDS use (160 KiB per CU).
 // EPI_WAVES_PER_SIMD overrides the register-based count.  Extra workgroups
 // only queue: the work queue drains either way.
-static int wgs_per_cu(int np2, int np3, int gk, int tab_cap, int kmax, int stage_cap) {
+int wgs_per_cu(int np2, int np3, int gk, int tab_cap, int kmax, int stage_cap) {
     int vgprs = 128, lds_static = 0;
     if (scan_attributes(np2, np3, gk, &vgprs, &lds_static) != hipSuccess) {
         (void)hipGetLastError();
@@ -843,13 +843,24 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
     // launch groups
     if (persistent) {
         // one launch group per kernel instantiation: order 2, order 3 per
-        // prefix block, each generic order
+        // prefix block, each generic order; apart from those, the scans
+        // whose screening table would cost their kernel workgroups per CU
+        // (a group's LDS table takes its largest dataset)
         std::map<int, LaunchGroup> by_key;
         for (int i = 0; i < n; ++i) {
             const PlanScan &s = p->scans[i];
             if (s.variant == kF2Fold) continue;  // runs in the pair pass
             const bool seg = s.variant == kSeg;
-            const int key = seg ? 200 + s.desc.order : group_of_order(s.desc.order, s.np);
+            int key = seg ? 200 + s.desc.order : group_of_order(s.desc.order, s.np);
+            if (!seg) {
+                const int o = s.desc.order;
+                const int np2 = o == 2 ? s.np : 0, np3 = o == 3 ? s.np : 0, gk = o >= 4 ? o : 0;
+                const int stage = stage_cap_for(np2, np3, std::max(s.ds->w4[0], s.ds->w4[1]));
+                const int ent = tab_entries_for(s.ds, s.variant, s.np, false);
+                if (ent > 0 && wgs_per_cu(np2, np3, gk, ent, s.desc.top_k, stage) <
+                                   wgs_per_cu(np2, np3, gk, 0, s.desc.top_k, stage))
+                    key += 100;
+            }
             LaunchGroup &g = by_key[key];
             g.scans.push_back(i);
             std::vector<int> orders{s.desc.order};

@@ -202,6 +202,9 @@ hipError_t launch_pilot(int np3, int gk, int grid, hipStream_t st, const Task *t
 // counts can reach a bound (twice top_k of them), and its screening table
 // fits the launch's LDS table (tab_cap entries).
 int pilot_items_for(int variant, int np, unsigned long long n_items, int top_k, int N, int tab_cap, int waves);
+// 4-wave workgroups per CU of a scan kernel instantiation (VGPRs and LDS:
+// screening-table entries, best-K list entries per wave, staged rows).
+int wgs_per_cu(int np2, int np3, int gk, int tab_cap, int kmax, int stage_cap);
 hipError_t launch_scan(int np2, int np3, int gk, int grid, hipStream_t st, const Task *tasks, int n_tasks,
                        unsigned long long total_items, unsigned long long *queue, const unsigned long long *binom,
                        int bstride, int tab_cap, int kmax, int stage_cap, bool check = false);

@@ -43,6 +43,7 @@ struct Request {
     // by reduced cells): items pilot_first .. + pilot_n - 1
     int pilot_n = 0;
     unsigned long long pilot_first = 0;
+    bool big_tab = false;  // its screening table lowers the kernel's workgroups per CU
     void *pairs = nullptr, *triples = nullptr, *cand = nullptr;
     unsigned cand_cap = 0;
     uint64_t footprint = 0;
@@ -92,12 +93,15 @@ struct Server {
 // more requests in flight each still gets a useful slice per round, up to
 // eight times that.
 static const double kRoundWork = 4e11;
-static const int kQueues = 16;
+static const int kQueues = 32;
 
 // Launch group of a request within a round, one per kernel instantiation:
 // orders 2 and 3 per prefix block (their work items are built for that
 // block), and each higher order.
-static int round_group(const Request *r) { return group_of_order(r->desc.order, r->np); }
+// Launch group of a request in a round: its kernel instantiation, and apart
+// from the others of that kernel when its screening table would cost the
+// launch workgroups per CU (the group's LDS table takes its largest dataset).
+static int round_group(const Request *r) { return group_of_order(r->desc.order, r->np) + (r->big_tab ? 100 : 0); }
 
 static void free_request_buffers(Server *S, Request *r) {
     S->ctx->alloc.release(r->pairs);
@@ -144,6 +148,13 @@ static int admit(Server *S, Request *r) {
     r->cand_cap = (unsigned)((unsigned long long)S->grid_max * 4 * r->desc.top_k + r->desc.top_k + 64);
     r->pilot_n = pilot_items_for(r->variant, r->np, r->n_items, r->desc.top_k, r->ds->N, Plan::kTabMax,
                                  S->grid_max * 4);
+    {
+        const int np2 = o == 2 ? r->np : 0, np3 = o == 3 ? r->np : 0, gk = o >= 4 ? o : 0;
+        const int stage = stage_cap_for(np2, np3, std::max(r->ds->w4[0], r->ds->w4[1]));
+        const int ent = tab_entries_for(r->ds, r->variant, r->np, false);
+        r->big_tab = ent > 0 && wgs_per_cu(np2, np3, gk, ent, r->desc.top_k, stage) <
+                                    wgs_per_cu(np2, np3, gk, 0, r->desc.top_k, stage);
+    }
     r->pilot_first = (r->n_items - (unsigned long long)r->pilot_n) / 2;
     const uint64_t pair_bytes = sub ? pair_table_bytes(r->variant, r->ds->M) : 0;
     const uint64_t trip_bytes = r->variant == kR4 ? triple_table_bytes(r->ds->M) : 0;
@@ -269,7 +280,9 @@ static int run_round(Server *S) {
         unsigned long long pilot_total;
     };
     std::vector<G> groups;
-    for (int key : {30 + kNpMfma, 30 + kNpMfma2, 30 + kNpMfmaI8, 38, 34, 32, 31, 22, 24, 28, 4, 5}) {
+    for (int key : {30 + kNpMfma, 30 + kNpMfma2, 30 + kNpMfmaI8, 38, 34, 32, 31, 22, 24, 28, 4, 5,
+                    130 + kNpMfma, 130 + kNpMfma2, 130 + kNpMfmaI8, 138, 134, 132, 131, 122, 124, 128, 104, 105}) {
+        const int base = key % 100;
         std::vector<int> orders;
         G g{0, 0, 0, ti, 0, 0, 1, 0, 0, 0, 0, 0};
         for (int i = 0; i < nt; ++i) {
@@ -278,7 +291,7 @@ static int run_round(Server *S) {
             orders.push_back(r->desc.order);
         }
         if (orders.empty()) continue;
-        pick_group_kernel(orders, key > 30 ? key - 30 : (key > 20 ? key - 20 : 4), &g.np2, &g.np3, &g.gk);
+        pick_group_kernel(orders, base > 30 ? base - 30 : (base > 20 ? base - 20 : 4), &g.np2, &g.np3, &g.gk);
         g.stage = stage_cap_for(g.np2, g.np3, 0);
         int cap_both = 0, cap_first = 0;
         std::vector<Request *> members;  // the group's requests, in copy order
