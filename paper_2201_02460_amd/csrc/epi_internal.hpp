@@ -42,6 +42,14 @@ typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 namespace epi {
 
 constexpr int kMaxTopK = 256;
+// Entries of a wave's best-K list in LDS for a best-K of top_k: room for a
+// wave's worth of new candidates past K, a power of two (the list is sorted
+// in place when a batch of candidates overflows it).
+__host__ __device__ constexpr int list_cap(int top_k) {
+    int c = 64;
+    while (c < top_k + 64) c <<= 1;
+    return c;
+}
 constexpr int kWave = 64;
 constexpr int kMergeSlots = 4096;      // LDS entries of the top-K merge
 constexpr int kMergeParts = 32;        // first-stage merge workgroups per task

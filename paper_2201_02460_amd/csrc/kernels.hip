@@ -251,6 +251,7 @@ EPI_DEV unsigned long long colex3(int x, int y, int z) {
 // ---------------------------------------------------------------------------
 struct TopK {
     int n, K, wi;
+    int cap;         // entries of the list in LDS (list_cap of the launch's largest K)
     long long wn;
     unsigned long long wk;
     unsigned *hist;  // the task's score histogram (null: none)
@@ -355,6 +356,47 @@ EPI_DEV void tk_recompute(TopK &t, const Cand *list) {
     t.wi = __builtin_amdgcn_readfirstlane(bi);
 }
 
+// Power of two a list of n entries is sorted in (at least 64).
+EPI_DEV int tk_sort_size(int n) {
+    int P = 64;
+    while (P < n) P <<= 1;
+    return P;
+}
+
+// Sort the first n entries of a wave's list best first, in place (entries
+// n .. P - 1, P = tk_sort_size(n), hold the worst value meanwhile: the
+// caller makes sure the list has P entries).  Bitonic network, each lane a
+// pair per compare-exchange step.
+EPI_DEV void tk_sort(Cand *a, int n) {
+    const int P = tk_sort_size(n);
+    for (int i = n + lane_id(); i < P; i += kWave) a[i] = Cand{(long long)0x8000000000000000ull, ~0ull};
+    wave_sync();
+    #pragma unroll 1
+    for (int k = 2; k <= P; k <<= 1) {
+        #pragma unroll 1
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            #pragma unroll 1
+            for (int q = lane_id(); q < P / 2; q += kWave) {
+                const int i = ((q & ~(j - 1)) << 1) | (q & (j - 1));
+                const int l = i | j;
+                const Cand x = a[i], y = a[l];
+                // best first where bit k of i is clear, worst first elsewhere
+                const bool swap = (i & k) == 0 ? better(y.num, y.key, x.num, x.key) : better(x.num, x.key, y.num, y.key);
+                if (swap) {
+                    a[i] = y;
+                    a[l] = x;
+                }
+            }
+            wave_sync();
+        }
+    }
+}
+
+// Candidates wanted by a wave at once past which they go to the list as a
+// batch (appended, then the list sorted and cut back to K) instead of one
+// replacement and rescan each.
+constexpr int kBatchOffer = 8;
+
 EPI_DEV void tk_offer(TopK &t, Cand *list, bool valid, long long num, unsigned long long key, long long gthr) {
     bool want = valid && num >= gthr && (t.n < t.K || better(num, key, t.wn, t.wk));
     unsigned long long mask = __ballot(want);
@@ -362,6 +404,26 @@ EPI_DEV void tk_offer(TopK &t, Cand *list, bool valid, long long num, unsigned l
     // of the lists at the start would only add contention
     if (mask && t.hist && !t.nohist && (t.n == t.K || gthr != (long long)0x8000000000000000ull))
         hist_add(t, want, num);
+    const int cnt = __popcll(mask);
+    if (cnt >= kBatchOffer && tk_sort_size(t.n + cnt) <= t.cap) {
+        wave_sync();
+        if (want) list[t.n + (int)lane_prefix(mask)] = Cand{num, key};
+        const int n2 = t.n + cnt;
+        wave_sync();
+        if (n2 < t.K) {
+            t.n = n2;
+            return;
+        }
+        tk_sort(list, n2);
+        // the best K stay, the K-th best is the entry the next better
+        // candidate replaces
+        t.n = t.K;
+        const Cand w = list[t.K - 1];
+        t.wn = (long long)rfl64((unsigned long long)w.num);
+        t.wk = rfl64(w.key);
+        t.wi = t.K - 1;
+        return;
+    }
     while (mask) {
         const int src = __builtin_ctzll(mask);
         const long long cn = (long long)readlane64((unsigned long long)num, src);
@@ -1818,6 +1880,7 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
     TopK tk;
     tk.n = 0;
     tk.K = 1;
+    tk.cap = kmax;
     tk.wi = 0;
     tk.wn = 0;
     tk.wk = 0;
@@ -2074,6 +2137,7 @@ scan_pilot(const Task *__restrict__ tasks, int n_tasks, unsigned long long total
     TopK tk;
     tk.n = 0;
     tk.K = 1;
+    tk.cap = kmax;
     tk.wi = 0;
     tk.wn = 0;
     tk.wk = 0;

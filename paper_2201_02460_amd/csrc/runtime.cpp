@@ -650,6 +650,13 @@ int pilot_items_for(int variant, int np, unsigned long long n_items, int top_k, 
     return n >= 2ull * (unsigned long long)std::max(top_k, 1) ? (int)n : 0;
 }
 
+int group_list_cap(int np2, int np3, int gk, int tab_cap, int top_k, int stage_cap) {
+    const int big = list_cap(top_k);
+    return wgs_per_cu(np2, np3, gk, tab_cap, big, stage_cap) >= wgs_per_cu(np2, np3, gk, tab_cap, top_k, stage_cap)
+               ? big
+               : top_k;
+}
+
 // Whether the dataset can run order-3 block np: the matrix-core blocks need
 // their operand copies, and the two-middle-SNP one its class sizes to fit
 // one float accumulator (q3_pack_fits).
@@ -754,6 +761,7 @@ static void pick_tab_cap(const Plan *p, LaunchGroup &g) {
         cap_first = std::max(cap_first, tab_entries_for(s.ds, s.variant, s.np, false));
     }
     g.tab_cap = group_tab_cap(g.np2, g.np3, g.gk, cap_both, cap_first, g.kmax, g.stage_cap);
+    g.kmax = group_list_cap(g.np2, g.np3, g.gk, g.tab_cap, g.kmax, g.stage_cap);
 }
 
 // Order 4 by reduced cells needs the dataset's matrix-core operands (for the
@@ -857,8 +865,8 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
                 const int np2 = o == 2 ? s.np : 0, np3 = o == 3 ? s.np : 0, gk = o >= 4 ? o : 0;
                 const int stage = stage_cap_for(np2, np3, std::max(s.ds->w4[0], s.ds->w4[1]));
                 const int ent = tab_entries_for(s.ds, s.variant, s.np, false);
-                if (ent > 0 && wgs_per_cu(np2, np3, gk, ent, s.desc.top_k, stage) <
-                                   wgs_per_cu(np2, np3, gk, 0, s.desc.top_k, stage))
+                const int lc = list_cap(s.desc.top_k);
+                if (ent > 0 && wgs_per_cu(np2, np3, gk, ent, lc, stage) < wgs_per_cu(np2, np3, gk, 0, lc, stage))
                     key += 100;
             }
             LaunchGroup &g = by_key[key];
@@ -941,7 +949,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
         if (needs_pairs(s)) emit_w4 = std::max(emit_w4, std::max(s.ds->w4[0], s.ds->w4[1]));
     p->emit_stage = stage_cap_for(4, 0, emit_w4);
     for (int j = 0; j < n; ++j)
-        if (fold_of[j] >= 0) p->emit_kmax = std::max(p->emit_kmax, p->scans[fold_of[j]].desc.top_k);
+        if (fold_of[j] >= 0) p->emit_kmax = std::max(p->emit_kmax, list_cap(p->scans[fold_of[j]].desc.top_k));
     p->emit_grid = grid_for(c, 4, 0, 0, std::max<unsigned long long>(emit_total, 1), 0, p->emit_kmax, p->emit_stage);
     p->t3_total = t3_total;
     p->t3_stage = stage_cap_for(0, kNpMfma, 0);

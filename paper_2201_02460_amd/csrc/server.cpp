@@ -152,8 +152,8 @@ static int admit(Server *S, Request *r) {
         const int np2 = o == 2 ? r->np : 0, np3 = o == 3 ? r->np : 0, gk = o >= 4 ? o : 0;
         const int stage = stage_cap_for(np2, np3, std::max(r->ds->w4[0], r->ds->w4[1]));
         const int ent = tab_entries_for(r->ds, r->variant, r->np, false);
-        r->big_tab = ent > 0 && wgs_per_cu(np2, np3, gk, ent, r->desc.top_k, stage) <
-                                    wgs_per_cu(np2, np3, gk, 0, r->desc.top_k, stage);
+        const int lc = list_cap(r->desc.top_k);
+        r->big_tab = ent > 0 && wgs_per_cu(np2, np3, gk, ent, lc, stage) < wgs_per_cu(np2, np3, gk, 0, lc, stage);
     }
     r->pilot_first = (r->n_items - (unsigned long long)r->pilot_n) / 2;
     const uint64_t pair_bytes = sub ? pair_table_bytes(r->variant, r->ds->M) : 0;
@@ -311,6 +311,7 @@ static int run_round(Server *S) {
             cap_first = std::max(cap_first, tab_entries_for(r->ds, r->variant, r->np, false));
         }
         g.tab_cap = group_tab_cap(g.np2, g.np3, g.gk, cap_both, cap_first, g.kmax, g.stage);
+        g.kmax = group_list_cap(g.np2, g.np3, g.gk, g.tab_cap, g.kmax, g.stage);
         // requests in their first round with a pilot pass: copies numbered
         // in the pilot launch
         g.pilot_off = ti;
