@@ -241,13 +241,57 @@ def orders_bench(epi, torch, names, steps):
                 mains.append(ms[2])
         epi.epi_unload(ctx, ds)
         kms = sorted(mains)[len(mains) // 2]
-        # reduced-cell variants count 2^k cells, the generic one all 3^k
+        # reduced-cell variants count 2^k cells, the generic one all 3^k;
+        # order 2 may run on the matrix cores (2 x 2^2 flops per unit)
+        mfma2 = order == 2 and info["prefix_block"] == BLOCK_MFMA_FP4
         opu = ops_per_unit(order) if info["variant"] in (1, 2, 5) else ops_per_unit_3k(order)
         out[name] = {"value": work * len(walls) / sum(walls) / 1e12, "kernel_ms": kms,
                      "kernel_value": work / (kms * 1e-3) / 1e12, "variant": info["variant"],
-                     "ops_per_unit": opu, "frac": work * opu / (kms * 1e-3) / 1e12 / VALU_PEAK_TOPS,
+                     "prefix_block": info["prefix_block"],
+                     "ops_per_unit": mfma_flops_per_unit(2) if mfma2 else opu,
+                     "bound": "mfma" if mfma2 else "alu",
+                     "frac": (work * mfma_flops_per_unit(2) / (kms * 1e-3) / 1e12 / MFMA_FP4_PEAK_TFLOPS if mfma2
+                              else work * opu / (kms * 1e-3) / 1e12 / VALU_PEAK_TOPS),
                      "frac_3k_cells": work * ops_per_unit_3k(order) / (kms * 1e-3) / 1e12 / VALU_PEAK_TOPS}
         log(f"{name}: kernel {kms:.3f} ms, {out[name]['kernel_value']:.2f} T, frac {out[name]['frac']:.3f}")
+    epi.epi_destroy(ctx)
+    return out
+
+
+def pairs_bench(epi, steps, M=4000, N=4000, K=100):
+    """Order 2 at a size where the counting matters (M = 4000 SNPs, N = 4000
+    individuals, the workloads' generator with one planted pair): the
+    popcount prefix blocks against the pair counts as fp4 0/1 matrix
+    products, kernel time and identical results."""
+    import numpy as np
+    from synth import make_case_control
+
+    G, y, _ = make_case_control(M, N, N // 2, [17, 113], seed=5)
+    work = math.comb(M, 2) * N
+    ctx = epi.epi_create(0)
+    ds = epi.epi_load_genotypes(ctx, G, y)
+    out, ref = {"workload": f"order 2, M={M}, N={N}, top-{K}"}, None
+    for block in (2, 4, 8, BLOCK_MFMA_FP4):
+        epi.epi_set_prefix_block(ctx, ds, 2, block)
+        mains, res = [], None
+        for i in range(steps + 1):
+            sid = epi.epi_scan(ctx, ds, 2, K)
+            epi.epi_wait(ctx, sid)
+            res = epi.epi_results(ctx, sid, K, 2)
+            ms = epi.epi_scan_timing(ctx, sid)
+            epi.epi_release(ctx, sid)
+            if i:
+                mains.append(ms[2])
+        kms = sorted(mains)[len(mains) // 2]
+        ref = res if ref is None else ref
+        mf = block == BLOCK_MFMA_FP4
+        opu = mfma_flops_per_unit(2) if mf else ops_per_unit(2)
+        peak = MFMA_FP4_PEAK_TFLOPS if mf else VALU_PEAK_TOPS
+        out[f"block_{block}"] = {"kernel_ms": round(kms, 4), "kernel_value": round(work / (kms * 1e-3) / 1e12, 3),
+                                 "bound": "mfma" if mf else "alu", "frac": round(work * opu / (kms * 1e-3) / 1e12 / peak, 4),
+                                 "identical_results": bool(all(np.array_equal(u, v) for u, v in zip(res, ref)))}
+        log(f"pairs M={M}: block {block} kernel {kms:.3f} ms")
+    epi.epi_unload(ctx, ds)
     epi.epi_destroy(ctx)
     return out
 
@@ -649,6 +693,7 @@ def main():
     ap.add_argument("--served-burst", type=int, default=100,
                     help="requests of the served capacity comparison (all submitted at once)")
     ap.add_argument("--no-orders", action="store_true")
+    ap.add_argument("--no-pairs", action="store_true")
     ap.add_argument("--no-segmented", action="store_true", help="skip the segmented-vs-fused comparison")
     ap.add_argument("--no-functions", action="store_true", help="skip the per-step (GT, CT, MI) timings")
     ap.add_argument("--no-orders-pass", action="store_true", help="skip the all-orders-in-one-pass comparison")
@@ -770,6 +815,8 @@ def main():
         others = [n for n in ("order2_M200_N1000", "order4_M200_N2000", "order5_M60_N2000", "order8_M23_N2048")
                   if n != args.workload]
         out["orders"] = orders_bench(epi, torch, others, 5)
+    if not args.no_pairs:
+        out["pairs"] = pairs_bench(epi, 5)
     if not args.no_orders_pass:
         out["orders_one_pass"] = orders_pass_bench(
             epi, [args.workload, "order4_M200_N2000", "order5_M60_N2000"], 5)

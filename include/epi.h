@@ -281,7 +281,10 @@ int epi_batch_destroy(epi_ctx *ctx, int32_t batch_id);
 
 /* Counting kernels by prefix block (the number of first SNPs a work item
  * shares; Section 2.4 reuses such prefixes of the enumeration):
- *   order 2: 2, 4, 8 -- popcount kernels;
+ *   order 2: 2, 4, 8 -- popcount kernels; 16 (EPI_BLOCK_MFMA_FP4) -- the four
+ *            reduced pair cells as 0/1 matrix products on the matrix cores
+ *            (the order-3 products below without the middle SNP's mask;
+ *            datasets with fewer than 2^22 individuals);
  *   order 3: 1, 2, 4, 8 -- popcount kernels (Section 2.2: AND + popcount);
  *            16 (EPI_BLOCK_MFMA_FP4) -- the reduced cells as 0/1 matrix
  *            products on the matrix cores, 4-bit float operands (1.0 = 0x2),
@@ -329,7 +332,8 @@ int epi_batch_destroy(epi_ctx *ctx, int32_t batch_id);
  * remember the fastest for datasets of the same size bucket (the same
  * power-of-two buckets of 32-bit words per SNP row and of the number of
  * SNPs).
- * The candidates are the blocks listed above: order 2 prefix blocks 2, 4, 8;
+ * The candidates are the blocks listed above: order 2 prefix blocks 2, 4, 8
+ * and EPI_BLOCK_MFMA_FP4;
  * order 3 blocks 1, 2, 4, 8, EPI_BLOCK_MFMA_FP4 and EPI_BLOCK_MFMA_FP4_2J;
  * order 4 the reduced-cell
  * kernel (reported as 0), EPI_BLOCK_ALL_CELLS and EPI_BLOCK_SEGMENTED;

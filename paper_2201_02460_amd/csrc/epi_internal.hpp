@@ -171,10 +171,13 @@ struct Task {
 //              items in flight across the device share a few operand blocks;
 //   kItemsF3M2 the same groups, one item per two consecutive middle SNPs j,
 //              j + 1 (descriptor of the first; the last item of an odd run
-//              has one).
+//              has one);
+//   kItemsF2M  order 2 by matrix cores: group ib (block of 32 first SNPs
+//              i0 = 32 ib), items ib << 20 | mb for the blocks mb of 32 last
+//              SNPs (m = 32 mb ..) from the one holding i0 + 1 on.
 // The host counts a table's items with these functions and the device
 // writes them (items_kernel), group after group.
-enum ItemKind : int32_t { kItemsF2 = 0, kItemsF3 = 1, kItemsF3M = 2, kItemsF3M2 = 3 };
+enum ItemKind : int32_t { kItemsF2 = 0, kItemsF3 = 1, kItemsF3M = 2, kItemsF3M2 = 3, kItemsF2M = 4 };
 constexpr int kItemTile = 4;
 constexpr int kStoreChunkBytes = 1024;  // bytes per store_kernel launch
 
@@ -188,6 +191,7 @@ struct ItemGroup {
 __host__ __device__ inline long long item_groups(int kind, int M, int np) {
     if (kind == kItemsF2) return M >= 2 ? (M - 1 + np - 1) / np : 0;
     if (kind == kItemsF3) return M >= 3 ? M - 2 : 0;
+    if (kind == kItemsF2M) return M >= 2 ? (M + 31) / 32 : 0;
     return (long long)((M + 31) / 32) * ((M + 15) / 16);
 }
 
@@ -197,6 +201,12 @@ __host__ __device__ inline ItemGroup item_group(int kind, int M, int np, long lo
         const long long ib = g, nm = M - 1 - ib * np;
         r.base = (unsigned long long)ib << 20;
         r.count = nm > 0 ? (unsigned long long)((nm + 63) / 64) : 0;
+        return r;
+    }
+    if (kind == kItemsF2M) {
+        const long long i0 = g * 32, mb0 = (i0 + 1) / 32, nmb = (M + 31) / 32;
+        r.base = ((unsigned long long)g << 20) | (unsigned long long)mb0;
+        r.count = i0 + 1 < M ? (unsigned long long)(nmb - mb0) : 0;
         return r;
     }
     if (kind == kItemsF3) {

@@ -394,9 +394,12 @@ EPI_DEV void tk_sort(Cand *a, int n) {
 
 // Candidates wanted by a wave at once past which they go to the list as a
 // batch (appended, then the list sorted and cut back to K) instead of one
-// replacement and rescan each.
+// replacement and rescan each.  BATCH: the kernels whose waves see few
+// combinations each (order 2, no pilot pass on small scans); in the others
+// the extra code costs the scoring loops registers.
 constexpr int kBatchOffer = 8;
 
+template <bool BATCH = false>
 EPI_DEV void tk_offer(TopK &t, Cand *list, bool valid, long long num, unsigned long long key, long long gthr) {
     bool want = valid && num >= gthr && (t.n < t.K || better(num, key, t.wn, t.wk));
     unsigned long long mask = __ballot(want);
@@ -405,7 +408,7 @@ EPI_DEV void tk_offer(TopK &t, Cand *list, bool valid, long long num, unsigned l
     if (mask && t.hist && !t.nohist && (t.n == t.K || gthr != (long long)0x8000000000000000ull))
         hist_add(t, want, num);
     const int cnt = __popcll(mask);
-    if (cnt >= kBatchOffer && tk_sort_size(t.n + cnt) <= t.cap) {
+    if (BATCH && cnt >= kBatchOffer && tk_sort_size(t.n + cnt) <= t.cap) {
         wave_sync();
         if (want) list[t.n + (int)lane_prefix(mask)] = Cand{num, key};
         const int n2 = t.n + cnt;
@@ -608,6 +611,23 @@ EPI_DEV long long entry_bound(const TopK &tk, long long gthr) {
     return tk.n < tk.K ? gthr : (tk.wn > gthr ? tk.wn : gthr);
 }
 
+// Pilot pass over an item: the wave's best screening sum S (best over its
+// lanes' combinations; INT_MIN: none) becomes one histogram count.  S is
+// within `reads` units (2^-tq) of (num - score_const) 2^(tq - shift) (each
+// table value within one unit of its n ln n, as in screen_bound), so
+// score_const + (S - reads - 1) 2^(shift - tq) is below that combination's
+// num; one atomic per wave, and the K-th best of such maxima is close to the
+// K-th best of all the item's combinations.
+EPI_DEV void pilot_count(TopK &tk, const Task &t, int best, int reads) {
+    #pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const int o = __shfl_xor(best, off);
+        best = o > best ? o : best;
+    }
+    hist_add(tk, lane_id() == 0 && best != (int)0x80000000u,
+             t.score_const + (long long)(best - reads - 1) * (1ll << (t.ds.shift - t.ds.tq)));
+}
+
 // ---------------------------------------------------------------------------
 // kF2 / kF2Emit / kF2Fold: order 2.  A work item is (block of NP SNPs i,
 // block of 64 SNPs m > i); lane = m.  Reduced cells (a, d) in {0,1}^2 per
@@ -615,10 +635,12 @@ EPI_DEV long long entry_bound(const TopK &tk, long long gthr) {
 // (kF2Fold: a scan of all orders takes its order-2 results from the pair
 // sub-table pass of its higher orders instead of counting the pairs twice).
 // ---------------------------------------------------------------------------
-template <int NP, bool EMIT, bool LDS, bool SCORE = !EMIT, bool CHECK = false>
+template <int NP, bool EMIT, bool LDS, bool SCORE = !EMIT, bool CHECK = false, bool PILOT = false>
 EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr, v4u *stage,
                      int stage_cap) {
+    static_assert(!PILOT || (LDS && SCORE && !EMIT && !CHECK), "the pilot pass scores from the LDS table");
     const DsView d = t.ds;
+    int pilot_best = (int)0x80000000u;  // PILOT: the lane's best screening sum
     const unsigned long long dsc = t.items[local];
     const int ib = uni((int)((dsc >> 20) & 0xfffffu));
     const int mb = uni((int)(dsc & 0xfffffu));
@@ -722,6 +744,13 @@ EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *li
                 F[c][8] = d.ncls[c];
                 mobius2(F[c]);
             }
+            if constexpr (PILOT) {
+                if (valid) {
+                    const int S = screen_sum<9>(F[0], F[1]);
+                    pilot_best = S > pilot_best ? S : pilot_best;
+                }
+                continue;
+            }
             if constexpr (CHECK) {
                 const int cc[2] = {i, m};
                 digest_add(tk, valid, combo_hash<2>(cc), table_sum<9>(F[0], F[1]));
@@ -736,10 +765,11 @@ EPI_DEV void item_f2(const Task &t, unsigned long long local, TopK &tk, Cand *li
                 #pragma unroll
                 for (int x = 0; x < 9; ++x) num += cell_term(d.tlog, F[0][x], F[1][x], (unsigned)d.N);
                 const unsigned long long key = ((unsigned long long)i << 32) | (unsigned long long)m;
-                tk_offer(tk, list, pass, num, key, gthr);
+                tk_offer<true>(tk, list, pass, num, key, gthr);
             }
         }
     }
+    if constexpr (PILOT) pilot_count(tk, t, pilot_best, 27);
 }
 
 // ---------------------------------------------------------------------------
@@ -961,21 +991,143 @@ struct QFmt<true> {
     }
 };
 
-// Pilot pass over an item: the wave's best screening sum S (best over its
-// lanes' combinations; INT_MIN: none) becomes one histogram count.  S is
-// within `reads` units (2^-tq) of (num - score_const) 2^(tq - shift) (each
-// table value within one unit of its n ln n, as in screen_bound), so
-// score_const + (S - reads - 1) 2^(shift - tq) is below that combination's
-// num; one atomic per wave, and the K-th best of such maxima is close to the
-// K-th best of all the item's combinations.
-EPI_DEV void pilot_count(TopK &tk, const Task &t, int best, int reads) {
+// ---------------------------------------------------------------------------
+// kF2 with prefix block kNpMfma: order 2 on the matrix cores, the products of
+// the order-3 kernel below without the middle SNP's mask.  A work item is
+// (block ib of 32 SNPs i, block mb of 32 SNPs m); per step and class four
+// products, A0 and A1 (32 rows each: the genotype-0 and -1 rows of the
+// item's two 16-SNP blocks of i) times B0 and B1 (the 32 m's genotype-0 and
+// -1 rows), 4 n per cell: four operand loads feed four products (two A
+// blocks, so that the loads per product are those of the order-3 kernel).
+// Lane l holds column m = 32 mb + l % 32 and both genotypes a of eight SNPs
+// i of each A block (the layout of item_f3m); the epilogue is item_f2's.
+// ---------------------------------------------------------------------------
+template <bool LDS, bool CHECK = false, bool PILOT = false>
+EPI_DEV void item_f2m(const Task &t, unsigned long long local, TopK &tk, Cand *list, long long gthr) {
+    static_assert(!PILOT || (LDS && !CHECK), "the pilot pass scores from the LDS table");
+    typedef QFmt<false> Q;
+    int pilot_best = (int)0x80000000u;  // PILOT: the lane's best screening sum
+    const DsView d = t.ds;
+    const unsigned long long dsc = t.items[local];
+    const int ib = uni((int)((dsc >> 20) & 0xfffffu));
+    const int mb = uni((int)(dsc & 0xfffffu));
+    const int lane = lane_id(), h = lane >> 5;
+    const int m = mb * 32 + (lane & 31);
+    const bool mv = m < d.M;
+    const int m_ld = mv ? m : d.M - 1;
+    const int KS = Q::ks(d, 0) + Q::ks(d, 1);
+    const int blk = KS * 1024;  // bytes of one row block
+    const v4u *qa = Q::qa(d), *qb = Q::qb(d);
+    // the second 16-SNP block of i; past the operand copy's last block (its
+    // SNPs would be M or more) the first block again, its lanes invalid
+    const int nib = (d.M + 15) / 16;
+    const int ib1 = 2 * ib + 1 < nib ? 2 * ib + 1 : 2 * ib;
+    __amdgpu_buffer_rsrc_t rA[2];
+    rA[0] = __builtin_amdgcn_make_buffer_rsrc((void *)(qa + (long long)(2 * ib) * KS * 64), 0, blk, kBufWord3);
+    rA[1] = __builtin_amdgcn_make_buffer_rsrc((void *)(qa + (long long)ib1 * KS * 64), 0, blk, kBufWord3);
+    const __amdgpu_buffer_rsrc_t rB0 =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(qb + (long long)(2 * mb) * KS * 64), 0, blk, kBufWord3);
+    const __amdgpu_buffer_rsrc_t rB1 =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(qb + (long long)(2 * mb + 1) * KS * 64), 0, blk, kBufWord3);
+    const int vo = lane * 16;
+    typename Q::acc_t acc[2][2][2];  // [class][A block][genotype of m]
     #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const int o = __shfl_xor(best, off);
-        best = o > best ? o : best;
+    for (int c = 0; c < 2; ++c)
+        #pragma unroll
+        for (int a = 0; a < 2; ++a)
+            #pragma unroll
+            for (int e = 0; e < 2; ++e) acc[c][a][e] = (typename Q::acc_t){};
+    // the software pipeline of item_f3m: kQDepth steps in flight, both
+    // classes one stream
+    const int ks0 = Q::ks(d, 0);
+    v4u bA0[kQDepth], bA1[kQDepth], bB0[kQDepth], bB1[kQDepth];
+    #pragma unroll
+    for (int u = 0; u < kQDepth; ++u) {
+        const int so = min(u, KS - 1) * 1024;
+        bA0[u] = qload(rA[0], vo, so);
+        bA1[u] = qload(rA[1], vo, so);
+        bB0[u] = qload(rB0, vo, so);
+        bB1[u] = qload(rB1, vo, so);
+        __builtin_amdgcn_sched_barrier(0);
     }
-    hist_add(tk, lane_id() == 0 && best != (int)0x80000000u,
-             t.score_const + (long long)(best - reads - 1) * (1ll << (t.ds.shift - t.ds.tq)));
+    #pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int c0 = c == 0 ? 0 : ks0;
+        const int cn = Q::ks(d, c);
+        #pragma unroll 1
+        for (int k = 0; k < cn; k += kQDepth) {
+            const int g = c0 + k;
+            #pragma unroll
+            for (int u = 0; u < kQDepth; ++u) {
+                acc[c][0][0] = Q::mma(bA0[u], bB0[u], acc[c][0][0]);
+                acc[c][0][1] = Q::mma(bA0[u], bB1[u], acc[c][0][1]);
+                acc[c][1][0] = Q::mma(bA1[u], bB0[u], acc[c][1][0]);
+                acc[c][1][1] = Q::mma(bA1[u], bB1[u], acc[c][1][1]);
+                const int so = min(g + u + kQDepth, KS - 1) * 1024;
+                bA0[u] = qload(rA[0], vo, so);
+                bA1[u] = qload(rA[1], vo, so);
+                bB0[u] = qload(rB0, vo, so);
+                bB1[u] = qload(rB1, vo, so);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+    const v4u *single4 = (const v4u *)d.single;
+    const v4u sm = single4[m_ld];
+    // the eight pairs of a lane in each A block (a function per block, so
+    // that each loop over them unrolls and every accumulator index is a
+    // constant)
+    auto score_block = [&](const typename Q::acc_t (&c0)[2], const typename Q::acc_t (&c1)[2], int ab)
+                           __attribute__((always_inline)) {
+        const int i_base = ib * 32 + 16 * ab + 2 * h;
+        #pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i_base + 4 * (u >> 1) + (u & 1);
+            const int r0 = 4 * (u >> 1) + 2 * (u & 1);
+            const bool valid = mv && i < m;
+            const v4u si = single4[min(i, d.M - 1)];
+            int F[2][9];
+            #pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                #pragma unroll
+                for (int a = 0; a < 2; ++a)
+                    #pragma unroll
+                    for (int e = 0; e < 2; ++e) F[c][3 * a + e] = (int)(c == 0 ? c0 : c1)[e][r0 + a] >> kQScaleShift;
+                F[c][2] = si[2 * c + 0];
+                F[c][5] = si[2 * c + 1];
+                F[c][6] = sm[2 * c + 0];
+                F[c][7] = sm[2 * c + 1];
+                F[c][8] = d.ncls[c];
+                mobius2(F[c]);
+            }
+            if constexpr (PILOT) {
+                if (valid) {
+                    const int S = screen_sum<9>(F[0], F[1]);
+                    pilot_best = S > pilot_best ? S : pilot_best;
+                }
+                continue;
+            }
+            if constexpr (CHECK) {
+                const int cc[2] = {i, m};
+                digest_add(tk, valid, combo_hash<2>(cc), table_sum<9>(F[0], F[1]));
+            }
+            bool pass = valid;
+            if constexpr (LDS) {
+                const int sb = screen_bound(entry_bound(tk, gthr), t.score_const, d.shift, d.tq, 27);
+                pass = pass && screen_sum<9>(F[0], F[1]) >= sb;
+            }
+            if (__ballot(pass)) {
+                long long num = t.score_const;
+                #pragma unroll
+                for (int x = 0; x < 9; ++x) num += cell_term(d.tlog, F[0][x], F[1][x], (unsigned)d.N);
+                const unsigned long long key = ((unsigned long long)i << 32) | (unsigned long long)m;
+                tk_offer<true>(tk, list, pass, num, key, gthr);
+            }
+        }
+    };
+    score_block(acc[0][0], acc[1][0], 0);
+    score_block(acc[0][1], acc[1][1], 1);
+    if constexpr (PILOT) pilot_count(tk, t, pilot_best, 27);
 }
 
 // PILOT: the histogram-only pass over an item (needs the screening table in
@@ -1846,10 +1998,11 @@ EPI_DEV void item_r4(const Task &t, unsigned long long local, TopK &tk, Cand *li
 // Register budget per instantiation: enough waves per SIMD to hide load
 // latency; the accumulators (16 per prefix for order 3, 8 for order 2, 128
 // for the matrix-core order-3 kernels: two classes of one middle SNP, or one
-// accumulator for both classes of each of two) set the floor.
+// accumulator for both classes of each of two; 128 for order 2 on the
+// matrix cores too) set the floor.
 template <int NP2, int NP3, int GK>
 constexpr int scan_waves_per_eu() {
-    return NP3 == kNpMfma2 ? 2
+    return NP3 == kNpMfma2 || NP2 == kNpMfma ? 2
                            : (GK >= 4 ? 2 : (GK == 3 ? 3 : (NP3 >= 8 ? 2 : (NP3 >= 4 ? 3 : (NP3 >= 2 ? 4 : (NP2 >= 8 ? 3 : 4))))));
 }
 
@@ -1991,17 +2144,20 @@ scan_persistent(const Task *__restrict__ tasks, int n_tasks, unsigned long long 
             tk.nohist = is_pilot_item(T, local);
             switch (T.variant) {
             case kF2:
-                if constexpr (NP2 > 0) {
+                if constexpr (NP2 == kNpMfma) {
+                    if (lds) item_f2m<true, CHECK>(T, local, tk, s_list, gthr);
+                    else item_f2m<false, CHECK>(T, local, tk, s_list, gthr);
+                } else if constexpr (NP2 > 0) {
                     if (lds) item_f2<NP2, false, true, true, CHECK>(T, local, tk, s_list, gthr, s_stage, stage_cap);
                     else item_f2<NP2, false, false, true, CHECK>(T, local, tk, s_list, gthr, s_stage, stage_cap);
                 }
                 break;
             case kF2Emit:
-                if constexpr (NP2 > 0)
+                if constexpr (NP2 > 0 && NP2 != kNpMfma)
                     item_f2<NP2, true, false>(T, local, tk, s_list, gthr, s_stage, stage_cap);
                 break;
             case kF2Fold:
-                if constexpr (NP2 > 0) {
+                if constexpr (NP2 > 0 && NP2 != kNpMfma) {
                     if (lds) item_f2<NP2, true, true, true, CHECK>(T, local, tk, s_list, gthr, s_stage, stage_cap);
                     else item_f2<NP2, true, false, true, CHECK>(T, local, tk, s_list, gthr, s_stage, stage_cap);
                 }
@@ -2082,6 +2238,7 @@ struct ScanKernelEntry {
 #define EPI_SCAN_KERNELS(CK)                                                                                     \
     {2, 0, 0, scan_persistent<2, 0, 0, CK>}, {4, 0, 0, scan_persistent<4, 0, 0, CK>},                             \
         {8, 0, 0, scan_persistent<8, 0, 0, CK>}, /* order 2 / pair sub-table */                                  \
+        {kNpMfma, 0, 0, scan_persistent<kNpMfma, 0, 0, CK>}, /* order 2, matrix cores */                         \
         {0, 1, 0, scan_persistent<0, 1, 0, CK>}, {0, 2, 0, scan_persistent<0, 2, 0, CK>},                         \
         {0, 4, 0, scan_persistent<0, 4, 0, CK>}, {0, 8, 0, scan_persistent<0, 8, 0, CK>}, /* order 3 */          \
         {0, 0, 4, scan_persistent<0, 0, 4, CK>}, {0, 0, 5, scan_persistent<0, 0, 5, CK>}, /* per combination */ \
@@ -2121,8 +2278,8 @@ ScanKernelFn find_scan_kernel_check(int np2, int np3, int gk) {
 // the main launch does not count the pilot items again.  Same launch shape
 // and LDS layout as the scan kernel.
 // ---------------------------------------------------------------------------
-template <int NP3, int GK>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<0, NP3, GK>())))
+template <int NP2, int NP3, int GK>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<NP2, NP3, GK>())))
 scan_pilot(const Task *__restrict__ tasks, int n_tasks, unsigned long long total, const unsigned long long *binom,
            int bstride, int tab_cap, int kmax, int stage_cap) {
     extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
@@ -2181,6 +2338,10 @@ scan_pilot(const Task *__restrict__ tasks, int n_tasks, unsigned long long total
         if (ent_fwd <= tab_cap && local < T.n_items) {
             if constexpr (GK == 4) {
                 item_r4<true, false, true>(T, local, tk, s_list, none, binom, bstride);
+            } else if constexpr (NP2 == kNpMfma) {
+                item_f2m<true, false, true>(T, local, tk, s_list, none);
+            } else if constexpr (NP2 > 0) {
+                item_f2<NP2, false, true, true, false, true>(T, local, tk, s_list, none, s_stage, stage_cap);
             } else {
                 if (rev) item_f3m<true, true, i8, false, false, nj, true>(T, local, tk, s_list, none, s_stage);
                 else item_f3m<true, false, i8, false, false, nj, true>(T, local, tk, s_list, none, s_stage);
@@ -2943,14 +3104,18 @@ hipError_t launch_scan(int np2, int np3, int gk, int grid, hipStream_t st, const
     return hipGetLastError();
 }
 
-hipError_t launch_pilot(int np3, int gk, int grid, hipStream_t st, const Task *tasks, int n_tasks,
+hipError_t launch_pilot(int np2, int np3, int gk, int grid, hipStream_t st, const Task *tasks, int n_tasks,
                         unsigned long long total, const unsigned long long *binom, int bstride, int tab_cap, int kmax,
                         int stage_cap) {
     void (*fn)(const Task *, int, unsigned long long, const unsigned long long *, int, int, int, int) =
-        gk == 4               ? scan_pilot<0, 4>
-        : np3 == kNpMfma      ? scan_pilot<kNpMfma, 0>
-        : np3 == kNpMfmaI8    ? scan_pilot<kNpMfmaI8, 0>
-        : np3 == kNpMfma2     ? scan_pilot<kNpMfma2, 0>
+        gk == 4               ? scan_pilot<0, 0, 4>
+        : np3 == kNpMfma      ? scan_pilot<0, kNpMfma, 0>
+        : np3 == kNpMfmaI8    ? scan_pilot<0, kNpMfmaI8, 0>
+        : np3 == kNpMfma2     ? scan_pilot<0, kNpMfma2, 0>
+        : np2 == kNpMfma      ? scan_pilot<kNpMfma, 0, 0>
+        : np2 == 2            ? scan_pilot<2, 0, 0>
+        : np2 == 4            ? scan_pilot<4, 0, 0>
+        : np2 == 8            ? scan_pilot<8, 0, 0>
                               : nullptr;
     if (!fn) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fn, dim3(grid), dim3(4 * kWave), scan_lds_bytes(tab_cap, kmax, stage_cap), st, tasks, n_tasks,

@@ -417,7 +417,7 @@ bool seg_pinned(Ctx *c, int order, const Dataset *d) {
 static int tuned_np(Ctx *c, int order, const Dataset *d) {
     if (order == 3) return default_np3(c, d);
     const int t = tuned_np_lookup(c, order, d);
-    if (t > 0) return t;
+    if (t > 0 && (order != 2 || t != kNpMfma || d->qa)) return t;
     return order == 2 ? 4 : kGenRanksHost;
 }
 
@@ -425,7 +425,7 @@ static int tuned_np(Ctx *c, int order, const Dataset *d) {
 // layouts in epi_internal.hpp (item_group); the device writes the tables
 // (items_kernel) and the host only counts their items.
 static int item_kind(int variant, int np) {
-    if (variant != kF3) return kItemsF2;
+    if (variant != kF3) return np == kNpMfma ? kItemsF2M : kItemsF2;
     if (np == kNpMfma2) return kItemsF3M2;
     return is_mfma_np(np) ? kItemsF3M : kItemsF3;
 }
@@ -623,7 +623,7 @@ void pick_group_kernel(const std::vector<int> &orders, int np_hint, int *np2, in
         return;
     }
     const int h = np_hint <= 2 ? 2 : (np_hint <= 4 ? 4 : 8);
-    if (has2) *np2 = h;
+    if (has2) *np2 = np_hint == kNpMfma ? kNpMfma : h;  // order 2: a popcount block or the matrix cores
     if (has3) *np3 = has2 ? h : np_hint;
 }
 
@@ -645,7 +645,7 @@ int default_np3(Ctx *c, const Dataset *d) {
 }
 
 int pilot_items_for(int variant, int np, unsigned long long n_items, int top_k, int N, int tab_cap, int waves) {
-    if (!((variant == kF3 && is_mfma_np(np)) || variant == kR4) || tab_cap < N + 1) return 0;
+    if (!((variant == kF3 && is_mfma_np(np)) || variant == kR4 || variant == kF2) || tab_cap < N + 1) return 0;
     const unsigned long long n = std::min<unsigned long long>((unsigned long long)waves, n_items / 32) & ~3ull;
     return n >= 2ull * (unsigned long long)std::max(top_k, 1) ? (int)n : 0;
 }
@@ -699,6 +699,7 @@ int grid_for(Ctx *c, int np2, int np3, int gk, unsigned long long items, int tab
 // (at most 16 groups of 4 words, 2048 individuals of a class, which keeps
 // three 4-wave workgroups per CU next to an 8001-entry screening table).
 int stage_cap_for(int np2, int np3, int w4_max) {
+    if (np2 == kNpMfma) return 0;  // order 2 on the matrix cores stages nothing
     if (np3 == kNpMfma2) return 8 * kQStageSteps;  // two middle SNPs' mask rows: 4 entries per step each
     if (is_mfma_np(np3)) return 4 * kQStageSteps;  // j-mask rows: 4 entries per step
     const int rows = std::max(np2 > 0 ? 2 * np2 : 0, np3 > 0 ? 2 * (np3 + 1) : 0);
@@ -1174,7 +1175,7 @@ static int plan_enqueue(Ctx *c, Plan *p, hipStream_t st, bool timing, unsigned l
         if (timing && single) HIPCHK(hipEventRecord(p->ev[2], st));
         for (auto &g : p->groups) {
             if (g.pilot_total > 0 && item_cap == ~0ull)
-                HIPCHK(launch_pilot(g.np3, g.gk, (int)std::min<unsigned long long>(g.grid, g.pilot_total / 4), st,
+                HIPCHK(launch_pilot(g.np2, g.np3, g.gk, (int)std::min<unsigned long long>(g.grid, g.pilot_total / 4), st,
                                     tasks + g.task_off, (int)g.scans.size(), g.pilot_total, c->d_binom, c->bstride,
                                     g.tab_cap, g.kmax, g.stage_cap));
             HIPCHK(launch_scan(g.np2, g.np3, g.gk, g.grid, st, tasks + g.task_off, (int)g.scans.size(),
@@ -1209,7 +1210,7 @@ static int plan_enqueue(Ctx *c, Plan *p, hipStream_t st, bool timing, unsigned l
             }
             if (timing && single) HIPCHK(hipEventRecord(p->ev[2], st));
             if (s.pilot_n > 0 && item_cap == ~0ull)
-                HIPCHK(launch_pilot(g.np3, g.gk, std::min(g.grid, s.pilot_n / 4), st, tasks + i, 1,
+                HIPCHK(launch_pilot(g.np2, g.np3, g.gk, std::min(g.grid, s.pilot_n / 4), st, tasks + i, 1,
                                     (unsigned long long)s.pilot_n, c->d_binom, c->bstride, g.tab_cap, g.kmax,
                                     g.stage_cap));
             HIPCHK(launch_scan(g.np2, g.np3, g.gk, g.grid, st, tasks + i, 1, std::min(s.n_items, item_cap),
@@ -1373,6 +1374,9 @@ static unsigned long long valid_in_items(const PlanScan &s, unsigned long long a
             if (kind == kItemsF2) {
                 const long long i0 = ib * np, m0 = i0 + 1 + mb * 64;
                 for (long long i = i0; i < i0 + np && i <= M - 2; ++i) n += clip(std::max(m0, i + 1), std::min(m0 + 64, M));
+            } else if (kind == kItemsF2M) {
+                for (long long i = ib * 32; i < ib * 32 + 32 && i <= M - 2; ++i)
+                    n += clip(std::max(mb * 32, i + 1), std::min(mb * 32 + 32, M));
             } else if (kind == kItemsF3) {
                 const long long m0 = j + 1 + mb * 64;
                 n += clip(ib * np, std::min(ib * np + np, j)) * clip(m0, std::min(m0 + 64, M));
@@ -1388,7 +1392,11 @@ static unsigned long long valid_in_items(const PlanScan &s, unsigned long long a
 // kForceReducedCells for the reduced-cell kernel, which epi_set_prefix_block
 // calls 0).
 static std::vector<int> tune_candidates(const Dataset *ds, int order) {
-    if (order == 2) return {2, 4, 8};
+    if (order == 2) {
+        std::vector<int> v{2, 4, 8};
+        if (ds->qa) v.push_back(kNpMfma);
+        return v;
+    }
     if (order == 3) {
         std::vector<int> v{1, 2, 4, 8};
         if (ds->qa) {
@@ -1908,7 +1916,7 @@ int epi_set_prefix_block(epi_ctx *ctx, int32_t dataset_id, int32_t order, int32_
         if (it == C->datasets.end()) return fail(EPI_ENOTFOUND, "unknown dataset %d", dataset_id);
         d = it->second.get();
     }
-    const bool ok2 = order == 2 && (block == 2 || block == 4 || block == 8);
+    const bool ok2 = order == 2 && (block == 2 || block == 4 || block == 8 || block == kNpMfma);
     const bool ok3 = order == 3 && (block == 1 || block == 2 || block == 4 || block == 8 || is_mfma_np(block));
     const bool any = order >= EPI_MIN_ORDER && order <= EPI_MAX_ORDER && (block == 0 || block == EPI_BLOCK_SEGMENTED);
     const bool all4 = order >= 4 && order <= EPI_MAX_ORDER && block == EPI_BLOCK_ALL_CELLS;

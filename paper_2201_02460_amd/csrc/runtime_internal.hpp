@@ -194,7 +194,7 @@ struct Ctx {
 };
 
 // kernel launchers (kernels.hip)
-hipError_t launch_pilot(int np3, int gk, int grid, hipStream_t st, const Task *tasks, int n_tasks,
+hipError_t launch_pilot(int np2, int np3, int gk, int grid, hipStream_t st, const Task *tasks, int n_tasks,
                         unsigned long long total, const unsigned long long *binom, int bstride, int tab_cap, int kmax,
                         int stage_cap);
 // Pilot items of a task (a multiple of 4; 0: none): up to one per wave of its

@@ -130,7 +130,7 @@ static int admit(Server *S, Request *r) {
     if (o == 2) {
         r->variant = kF2;
         const int t = tuned_np_lookup(c, 2, r->ds);
-        r->np = t > 0 ? t : 4;
+        r->np = t > 0 && (t != kNpMfma || r->ds->qa) ? t : 4;
     } else if (o == 3) {
         r->variant = kF3;
         r->np = default_np3(c, r->ds);
@@ -280,18 +280,20 @@ static int run_round(Server *S) {
         unsigned long long pilot_total;
     };
     std::vector<G> groups;
-    for (int key : {30 + kNpMfma, 30 + kNpMfma2, 30 + kNpMfmaI8, 38, 34, 32, 31, 22, 24, 28, 4, 5,
-                    130 + kNpMfma, 130 + kNpMfma2, 130 + kNpMfmaI8, 138, 134, 132, 131, 122, 124, 128, 104, 105}) {
-        const int base = key % 100;
+    for (int key : {30 + kNpMfma, 30 + kNpMfma2, 30 + kNpMfmaI8, 38, 34, 32, 31, 20 + kNpMfma, 22, 24, 28, 4, 5,
+                    130 + kNpMfma, 130 + kNpMfma2, 130 + kNpMfmaI8, 138, 134, 132, 131, 120 + kNpMfma, 122, 124, 128,
+                    104, 105}) {
         std::vector<int> orders;
         G g{0, 0, 0, ti, 0, 0, 1, 0, 0, 0, 0, 0};
+        int np_hint = 4;  // the group's prefix block: every request of a key has the same
         for (int i = 0; i < nt; ++i) {
             Request *r = order[i].first;
             if (round_group(r) != key) continue;
             orders.push_back(r->desc.order);
+            np_hint = r->np;
         }
         if (orders.empty()) continue;
-        pick_group_kernel(orders, base > 30 ? base - 30 : (base > 20 ? base - 20 : 4), &g.np2, &g.np3, &g.gk);
+        pick_group_kernel(orders, np_hint, &g.np2, &g.np3, &g.gk);
         g.stage = stage_cap_for(g.np2, g.np3, 0);
         int cap_both = 0, cap_first = 0;
         std::vector<Request *> members;  // the group's requests, in copy order
@@ -349,7 +351,7 @@ static int run_round(Server *S) {
         const G &g = groups[gi];
         const int grid = grid_for(c, g.np2, g.np3, g.gk, g.total, g.tab_cap, g.kmax, g.stage);
         if (g.pilot_total > 0)
-            SRV_HIPCHK(launch_pilot(g.np3, g.gk,
+            SRV_HIPCHK(launch_pilot(g.np2, g.np3, g.gk,
                                     (int)std::min<unsigned long long>(std::min(grid, S->grid_max), g.pilot_total / 4),
                                     st, dt + g.pilot_off, g.pilot_tasks, g.pilot_total, c->d_binom, c->bstride,
                                     g.tab_cap, g.kmax, g.stage));
@@ -522,7 +524,7 @@ int epi_server_start(epi_ctx *ctx, const epi_server_config *cfg, int32_t *server
     // the largest persistent grid any round may launch (in 4-wave workgroups)
     static const int kRoundKernels[][3] = {{2, 0, 0}, {4, 0, 0}, {8, 0, 0}, {0, 1, 0}, {0, 2, 0}, {0, 4, 0},
                                            {0, 8, 0}, {0, kNpMfma, 0}, {0, kNpMfma2, 0}, {0, kNpMfmaI8, 0},
-                                           {0, 0, 4}, {0, 0, 5}};
+                                           {0, 0, 4}, {0, 0, 5}, {kNpMfma, 0, 0}};
     S->grid_max = 1;
     for (const auto &k : kRoundKernels)
         S->grid_max = std::max(S->grid_max,

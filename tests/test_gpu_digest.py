@@ -40,7 +40,7 @@ def kernels_of(order):
     from paper_2201_02460_amd import epi
 
     if order == 2:
-        return [2, 4, 8, epi.EPI_BLOCK_SEGMENTED]
+        return [2, 4, 8, epi.EPI_BLOCK_MFMA_FP4, epi.EPI_BLOCK_SEGMENTED]
     if order == 3:
         return [1, 2, 4, 8, epi.EPI_BLOCK_MFMA_FP4, epi.EPI_BLOCK_MFMA_FP4_2J, epi.EPI_BLOCK_MFMA_I8,
                 epi.EPI_BLOCK_SEGMENTED]

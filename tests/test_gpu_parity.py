@@ -5,6 +5,7 @@ import itertools
 import json
 import math
 import os
+import time
 
 import numpy as np
 import pytest
@@ -417,7 +418,7 @@ def test_autotune_every_order(cx, orc):
     try:
         K = 15
         plain = {o: cx.scan(ds, o, K) for o in (2, 3, 4, 5)}
-        want = {2: [2, 4, 8], 3: [1, 2, 4, 8, 16, 48], 4: [0, epi.EPI_BLOCK_ALL_CELLS, epi.EPI_BLOCK_SEGMENTED],
+        want = {2: [2, 4, 8, 16], 3: [1, 2, 4, 8, 16, 48], 4: [0, epi.EPI_BLOCK_ALL_CELLS, epi.EPI_BLOCK_SEGMENTED],
                 5: [epi.EPI_BLOCK_ALL_CELLS, epi.EPI_BLOCK_SEGMENTED]}
         for o in (2, 3, 4, 5):
             choice = epi.epi_autotune(cx.ctx, ds, o)
@@ -509,8 +510,9 @@ def test_counting_kernels_agree(cx, orc):
         with pytest.raises(epi.EpiError) as e:
             epi.epi_set_prefix_block(cx.ctx, ds, 3, bad)
         assert e.value.code == epi.EPI_EINVAL
-    with pytest.raises(epi.EpiError):
-        epi.epi_set_prefix_block(cx.ctx, ds, 2, epi.EPI_BLOCK_MFMA_FP4)
+    for bad2 in (epi.EPI_BLOCK_MFMA_FP4_2J, epi.EPI_BLOCK_MFMA_I8):  # order-3 only blocks
+        with pytest.raises(epi.EpiError):
+            epi.epi_set_prefix_block(cx.ctx, ds, 2, bad2)
     # the choice holds for every dataset of the same size bucket: block 0
     # restores the built-in default (the 4-bit matrix-core kernel here)
     epi.epi_set_prefix_block(cx.ctx, ds, 3, 0)
@@ -588,4 +590,97 @@ def test_full_size_order3_every_matrix_core_block(cx, orc):
                     assert np.array_equal(res[k], first[k])
     finally:
         epi.epi_set_prefix_block(cx.ctx, ds, 3, 0)
+        epi.epi_unload(cx.ctx, ds)
+
+
+@pytest.mark.parametrize("M,N,nc", [(2, 40, 17), (17, 300, 120), (33, 129, 64), (70, 1100, 700), (131, 385, 100)])
+def test_order2_matrix_core_kernel(cx, orc, M, N, nc):
+    """Order 2 on the matrix cores (prefix block EPI_BLOCK_MFMA_FP4 at order
+    2: the order-3 products without the middle SNP's mask) against the
+    oracle, on SNP counts that leave partial 16- and 32-SNP blocks and class
+    sizes that leave partial 64-individual steps, and equal to the popcount
+    kernel."""
+    from paper_2201_02460_amd import epi
+
+    G, y = random_genotypes(M, N, seed=M + N, case_fraction=nc / N)
+    ds = cx.load(G, y)
+    K = min(25, M * (M - 1) // 2)
+    try:
+        epi.epi_set_prefix_block(cx.ctx, ds, 2, epi.EPI_BLOCK_MFMA_FP4)
+        res = cx.scan(ds, 2, K)
+        assert res["prefix_block"] == epi.EPI_BLOCK_MFMA_FP4
+        check_topk(orc, G, y, 2, K, res["combos"], res["scores"], res["tables"])
+        epi.epi_set_prefix_block(cx.ctx, ds, 2, 4)
+        ref = cx.scan(ds, 2, K)
+        for k in ("combos", "scores", "tables"):
+            assert np.array_equal(res[k], ref[k])
+    finally:
+        epi.epi_set_prefix_block(cx.ctx, ds, 2, 0)
+        epi.epi_unload(cx.ctx, ds)
+
+
+def test_order2_pilot_pass_keeps_results(cx, orc):
+    """An order-2 scan large enough for the pilot pass (at least 32 items per
+    pilot item and 2K pilot items), on the popcount and the matrix-core
+    kernel: the bound the pilot publishes must not drop any of the oracle's
+    best K."""
+    from paper_2201_02460_amd import epi
+
+    G, y = random_genotypes(720, 600, seed=71, case_fraction=0.45)
+    ds = cx.load(G, y)
+    K = 10
+    try:
+        first = None
+        for block in (4, epi.EPI_BLOCK_MFMA_FP4):
+            epi.epi_set_prefix_block(cx.ctx, ds, 2, block)
+            res = cx.scan(ds, 2, K)
+            assert res["prefix_block"] == block
+            if first is None:
+                check_topk(orc, G, y, 2, K, res["combos"], res["scores"], res["tables"])
+                first = res
+            else:
+                for k in ("combos", "scores", "tables"):
+                    assert np.array_equal(res[k], first[k])
+    finally:
+        epi.epi_set_prefix_block(cx.ctx, ds, 2, 0)
+        epi.epi_unload(cx.ctx, ds)
+
+
+def test_pinned_blocks_in_batches_and_server(cx, orc):
+    """Every order-2 and order-3 block pinned for a dataset's size bucket is
+    the kernel its scans run in a persistent batch and in served requests
+    too (the launch group takes the scan's own block, the matrix-core order-2
+    block included): results equal the plain scan's, which the oracle
+    checks."""
+    from paper_2201_02460_amd import epi
+
+    G, y = random_genotypes(150, 700, seed=83, case_fraction=0.4)
+    ds = cx.load(G, y)
+    K = 12
+    try:
+        for order, blocks in ((2, (2, 4, 8, epi.EPI_BLOCK_MFMA_FP4)), (3, (1, 8, epi.EPI_BLOCK_MFMA_FP4))):
+            for block in blocks:
+                say("order", order, "block", block)
+                epi.epi_set_prefix_block(cx.ctx, ds, order, block)
+                plain = cx.scan(ds, order, K)
+                assert plain["prefix_block"] == block
+                check_topk(orc, G, y, order, K, plain["combos"], plain["scores"], plain["tables"])
+                bid = epi.epi_batch_create(cx.ctx, [(ds, order, K), (ds, order, K + 3)], persistent=True,
+                                           use_graph=False)
+                epi.epi_batch_run(cx.ctx, bid)
+                epi.epi_batch_wait(cx.ctx, bid)
+                c, s, t = epi.epi_batch_results(cx.ctx, bid, 0, K, order)
+                epi.epi_batch_destroy(cx.ctx, bid)
+                assert np.array_equal(c, plain["combos"]) and np.array_equal(s, plain["scores"])
+                assert np.array_equal(t, plain["tables"])
+                sid = epi.epi_server_start(cx.ctx, max_active=4)
+                rid = epi.epi_server_submit(cx.ctx, sid, ds, order, K)
+                while epi.epi_server_poll(cx.ctx, sid, rid) != 2:
+                    time.sleep(0.001)
+                c, s, t, _ = epi.epi_server_results(cx.ctx, sid, rid, K, order)
+                epi.epi_server_stop(cx.ctx, sid)
+                assert np.array_equal(c, plain["combos"]) and np.array_equal(s, plain["scores"])
+                assert np.array_equal(t, plain["tables"])
+            epi.epi_set_prefix_block(cx.ctx, ds, order, 0)
+    finally:
         epi.epi_unload(cx.ctx, ds)
