@@ -533,42 +533,47 @@ def served_pool(epi, ctx):
     return pool, dss
 
 
-def served_capacity(epi, ctx, pool, dss, cap, K=100):
+def served_capacity(epi, ctx, pool, dss, cap, K=100, depth=0, reps=3):
     """The same requests submitted at once to a fresh server, against the same
     requests as back-to-back plain scans (scan, wait, results): aggregate
-    rates, and whether every request's K results (combinations, scores,
-    tables) are the plain scan's."""
+    rates (median of ``reps`` interleaved repetitions of each), and whether
+    every request's K results (combinations, scores, tables) are the plain
+    scan's in every repetition."""
     import numpy as np
 
     work = sum(math.comb(pool[d]["M"], o) * pool[d]["N"] for d, o in cap)
-    sid = epi.epi_server_start(ctx, max_active=64)
-    t0 = time.perf_counter()
-    ids = [(epi.epi_server_submit(ctx, sid, dss[d], o, K), o) for d, o in cap]
-    served = []
-    for rid, o in ids:
-        while epi.epi_server_poll(ctx, sid, rid) != 2:
-            time.sleep(0.0005)
-        served.append(epi.epi_server_results(ctx, sid, rid, K, o)[:3])
-    burst_s = time.perf_counter() - t0
-    stats = epi.epi_server_stats(ctx, sid)
-    epi.epi_server_stop(ctx, sid)
-    t0 = time.perf_counter()
-    plain = []
-    for d, o in cap:
-        q = epi.epi_scan(ctx, dss[d], o, K)
-        epi.epi_wait(ctx, q)
-        plain.append(epi.epi_results(ctx, q, K, o))
-        epi.epi_release(ctx, q)
-    b2b_s = time.perf_counter() - t0
-    same = all(np.array_equal(u, v) for a, b in zip(served, plain) for u, v in zip(a, b))
-    log(f"served capacity: {len(cap)} requests at once {burst_s:.3f}s ({stats['rounds']} rounds) "
-        f"vs back-to-back plain {b2b_s:.3f}s, identical results {same}")
+    burst, b2b, same, rounds, peak = [], [], True, 0, 0
+    for _ in range(reps):
+        sid = epi.epi_server_start(ctx, max_active=64, rounds_in_flight=depth)
+        t0 = time.perf_counter()
+        ids = [(epi.epi_server_submit(ctx, sid, dss[d], o, K), o) for d, o in cap]
+        served = []
+        for rid, o in ids:
+            while epi.epi_server_poll(ctx, sid, rid) != 2:
+                time.sleep(0.0005)
+            served.append(epi.epi_server_results(ctx, sid, rid, K, o)[:3])
+        burst.append(time.perf_counter() - t0)
+        stats = epi.epi_server_stats(ctx, sid)
+        rounds, peak = stats["rounds"], stats["peak_active"]
+        epi.epi_server_stop(ctx, sid)
+        t0 = time.perf_counter()
+        plain = []
+        for d, o in cap:
+            q = epi.epi_scan(ctx, dss[d], o, K)
+            epi.epi_wait(ctx, q)
+            plain.append(epi.epi_results(ctx, q, K, o))
+            epi.epi_release(ctx, q)
+        b2b.append(time.perf_counter() - t0)
+        same = same and all(np.array_equal(u, v) for a, b in zip(served, plain) for u, v in zip(a, b))
+    burst_s, b2b_s = float(np.median(burst)), float(np.median(b2b))
+    log(f"served capacity: {len(cap)} requests at once {burst_s:.3f}s ({rounds} rounds) "
+        f"vs back-to-back plain {b2b_s:.3f}s (medians of {reps}), identical results {same}")
     return {"requests": len(cap), "combos_x_samples": int(work), "value": work / burst_s / 1e12,
-            "back_to_back_value": work / b2b_s / 1e12, "speedup": b2b_s / burst_s, "rounds": stats["rounds"],
-            "peak_active": stats["peak_active"], "identical_results": bool(same)}
+            "back_to_back_value": work / b2b_s / 1e12, "speedup": b2b_s / burst_s, "rounds": rounds,
+            "peak_active": peak, "repetitions": reps, "identical_results": bool(same)}
 
 
-def served_leg(epi, ctx, pool, dss, reqs, gaps, K):
+def served_leg(epi, ctx, pool, dss, reqs, gaps, K, depth=0):
     """Submit the requests at their Poisson arrival times to a fresh server
     and collect each one's latency (submission to results ready)."""
     import threading
@@ -576,7 +581,7 @@ def served_leg(epi, ctx, pool, dss, reqs, gaps, K):
     import numpy as np
 
     work = [math.comb(pool[d]["M"], o) * pool[d]["N"] for d, o in reqs]
-    sid = epi.epi_server_start(ctx, max_active=64)
+    sid = epi.epi_server_start(ctx, max_active=64, rounds_in_flight=depth)
     pending, lat, done_at = {}, [], []
     lock = threading.Lock()
     start = time.perf_counter()
@@ -634,9 +639,10 @@ def served_leg(epi, ctx, pool, dss, reqs, gaps, K):
 def served_bench(epi, torch, n_requests, rate, burst, load_frac=0.8, seed=7):
     """The continuous-batching server on a resident dataset pool: capacity
     (a burst of requests at once, results compared with plain scans), then
-    Poisson arrivals at the stated rate and at load_frac of the measured
-    capacity, p50/p99 latency from submission to results ready after a
-    warm-up."""
+    Poisson arrivals at the stated rate and at load_frac of the capacity
+    measured on the same request sequence submitted at once (the order-4
+    share of a sample sets its rate), p50/p99 latency from submission to
+    results ready after a warm-up."""
     from synth import served_requests
 
     ctx = epi.epi_create(0)
@@ -644,16 +650,21 @@ def served_bench(epi, torch, n_requests, rate, burst, load_frac=0.8, seed=7):
     K = 100
     # warm-up: a short burst of every order, not counted
     warm, _ = served_requests(pool, 24, seed=seed + 100)
-    served_capacity(epi, ctx, pool, dss, warm, K)
+    served_capacity(epi, ctx, pool, dss, warm, K, reps=1)
     cap_reqs, _ = served_requests(pool, burst, seed=seed + 1)
     capacity = served_capacity(epi, ctx, pool, dss, cap_reqs, K)
     reqs, gaps = served_requests(pool, n_requests, seed=seed, rate=rate)
     mean_work = sum(math.comb(pool[d]["M"], o) * pool[d]["N"] for d, o in reqs) / len(reqs)
     log(f"served: {n_requests} requests at {rate}/s")
     stated = served_leg(epi, ctx, pool, dss, reqs, gaps, K)
-    near_rate = load_frac * capacity["value"] * 1e12 / mean_work
+    # the request sequence does not depend on the rate (only the gaps do)
+    reqs2, _ = served_requests(pool, n_requests, seed=seed + 2)
+    log(f"served: the {n_requests} requests of the near-capacity leg at once")
+    mix_cap = served_capacity(epi, ctx, pool, dss, reqs2, K, reps=1)
+    mean_work2 = mix_cap["combos_x_samples"] / len(reqs2)
+    near_rate = load_frac * mix_cap["value"] * 1e12 / mean_work2
     reqs2, gaps2 = served_requests(pool, n_requests, seed=seed + 2, rate=near_rate)
-    log(f"served: {n_requests} requests at {near_rate:.1f}/s ({load_frac:.0%} of the burst capacity)")
+    log(f"served: {n_requests} requests at {near_rate:.1f}/s ({load_frac:.0%} of their capacity)")
     near = served_leg(epi, ctx, pool, dss, reqs2, gaps2, K)
     for d in dss:
         epi.epi_unload(ctx, d)
@@ -670,6 +681,7 @@ def served_bench(epi, torch, n_requests, rate, burst, load_frac=0.8, seed=7):
         "peak_active": stated["peak_active"],
         "stated_rate": stated,
         "near_capacity": near,
+        "near_capacity_mix_at_once": mix_cap,
         "capacity": capacity,
     }
 

@@ -410,7 +410,14 @@ int epi_mutual_information(epi_ctx *ctx, int32_t dataset_id, int32_t order, cons
 
 typedef struct {
     int32_t max_active;        /* requests resident on the device at once (>= 1) */
-    int32_t round_items;       /* work items per launch round (0 = auto) */
+    int32_t rounds_in_flight;  /* launch rounds on the device at once: 1 = the host
+                                * reads a round's results before it builds the next
+                                * (new requests join at the next round); 2 = it
+                                * builds and enqueues the next round while the
+                                * device runs the current one (no device idle
+                                * between rounds; a request that arrives meanwhile
+                                * waits one round more); 0 = 2 while the next round
+                                * is short, else 1.  EINVAL outside 0..2. */
     uint64_t request_budget;   /* device bytes for request buffers (0 = ctx budget) */
 } epi_server_config;
 

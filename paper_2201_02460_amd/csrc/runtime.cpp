@@ -743,6 +743,17 @@ int tab_entries_for(const Dataset *d, int variant, int np, bool both) {
 // keeps as many workgroups per CU.  A workgroup reloads the table when a
 // chunk of work starts another dataset, and takes the mirrored half for the
 // chunks that use it when it fits the capacity.
+// Whether a scan's screening table (its first half) costs its kernel
+// workgroups per CU even with the smallest best-K list a launch group may
+// give it (K entries): such scans go to launch groups of their own, so that
+// they do not lower the occupancy of the others.
+bool table_lowers_occupancy(const Dataset *d, int variant, int np, int order, int top_k) {
+    const int np2 = order == 2 ? np : 0, np3 = order == 3 ? np : 0, gk = order >= 4 ? order : 0;
+    const int stage = stage_cap_for(np2, np3, std::max(d->w4[0], d->w4[1]));
+    const int ent = tab_entries_for(d, variant, np, false);
+    return ent > 0 && wgs_per_cu(np2, np3, gk, ent, top_k, stage) < wgs_per_cu(np2, np3, gk, 0, top_k, stage);
+}
+
 int group_tab_cap(int np2, int np3, int gk, int cap_both, int cap_first, int kmax, int stage_cap) {
     if (cap_both <= cap_first) return cap_first;
     const int w_both = wgs_per_cu(np2, np3, gk, cap_both, kmax, stage_cap);
@@ -861,15 +872,7 @@ int plan_build(Ctx *c, const epi_scan_desc *descs, int n, bool persistent, bool 
             if (s.variant == kF2Fold) continue;  // runs in the pair pass
             const bool seg = s.variant == kSeg;
             int key = seg ? 200 + s.desc.order : group_of_order(s.desc.order, s.np);
-            if (!seg) {
-                const int o = s.desc.order;
-                const int np2 = o == 2 ? s.np : 0, np3 = o == 3 ? s.np : 0, gk = o >= 4 ? o : 0;
-                const int stage = stage_cap_for(np2, np3, std::max(s.ds->w4[0], s.ds->w4[1]));
-                const int ent = tab_entries_for(s.ds, s.variant, s.np, false);
-                const int lc = list_cap(s.desc.top_k);
-                if (ent > 0 && wgs_per_cu(np2, np3, gk, ent, lc, stage) < wgs_per_cu(np2, np3, gk, 0, lc, stage))
-                    key += 100;
-            }
+            if (!seg && table_lowers_occupancy(s.ds, s.variant, s.np, s.desc.order, s.desc.top_k)) key += 100;
             LaunchGroup &g = by_key[key];
             g.scans.push_back(i);
             std::vector<int> orders{s.desc.order};

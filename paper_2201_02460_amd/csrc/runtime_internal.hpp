@@ -207,6 +207,7 @@ int pilot_items_for(int variant, int np, unsigned long long n_items, int top_k, 
 int wgs_per_cu(int np2, int np3, int gk, int tab_cap, int kmax, int stage_cap);
 // Best-K list entries per wave of a launch group: room for batched insertion
 // (list_cap) unless that costs workgroups per CU, else top_k.
+bool table_lowers_occupancy(const Dataset *d, int variant, int np, int order, int top_k);
 int group_list_cap(int np2, int np3, int gk, int tab_cap, int top_k, int stage_cap);
 hipError_t launch_scan(int np2, int np3, int gk, int grid, hipStream_t st, const Task *tasks, int n_tasks,
                        unsigned long long total_items, unsigned long long *queue, const unsigned long long *binom,

@@ -39,6 +39,7 @@ struct Request {
     const void *items = nullptr, *emit_items = nullptr, *t3_items = nullptr;
     unsigned long long n_items = 0, cursor = 0, emit_n = 0, t3_n = 0, n_combos = 0;
     bool emit_done = false;
+    bool finishing = false;  // its last slice is in the round in flight (results not yet read)
     // pilot pass in the request's first round (matrix-core order 3, order 4
     // by reduced cells): items pilot_first .. + pilot_n - 1
     int pilot_n = 0;
@@ -62,7 +63,7 @@ struct Server {
     int id = 0;
     epi_server_config cfg{};
     hipStream_t stream = nullptr;
-    hipEvent_t ev = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};  // end of the two rounds that may be in flight
     std::thread thread;
     std::mutex mu;
     std::condition_variable cv;
@@ -77,7 +78,10 @@ struct Server {
     // device state: per-slot counters, per-round scratch
     void *d_counters = nullptr, *d_tasks = nullptr, *d_results = nullptr, *d_parts = nullptr, *d_layout = nullptr,
          *d_out = nullptr;
-    void *h_tasks = nullptr, *h_out = nullptr, *h_layout = nullptr;
+    // host staging of a round's task and layout arrays, one per round in
+    // flight (a round's copies read them when the stream reaches them)
+    void *h_tasks[2] = {nullptr, nullptr}, *h_out = nullptr, *h_layout[2] = {nullptr, nullptr};
+    int buf = 0;  // staging buffer and event of the next round
     unsigned long long *d_queues = nullptr, *d_thr = nullptr;
     unsigned *d_hist = nullptr;  // kHistWords per slot
     unsigned *d_cand_count = nullptr;
@@ -93,6 +97,11 @@ struct Server {
 // more requests in flight each still gets a useful slice per round, up to
 // eight times that.
 static const double kRoundWork = 4e11;
+// With rounds_in_flight = 0, a second round is enqueued behind the running one
+// only while the next round's work stays below this (about 5 ms of the order-3
+// kernel): the host's round gap then costs several per cent of the device
+// time, while a request that arrives meanwhile waits at most that long more.
+static const double kPipelineWork = 2 * kRoundWork;
 static const int kQueues = 32;
 
 // Launch group of a request within a round, one per kernel instantiation:
@@ -148,13 +157,7 @@ static int admit(Server *S, Request *r) {
     r->cand_cap = (unsigned)((unsigned long long)S->grid_max * 4 * r->desc.top_k + r->desc.top_k + 64);
     r->pilot_n = pilot_items_for(r->variant, r->np, r->n_items, r->desc.top_k, r->ds->N, Plan::kTabMax,
                                  S->grid_max * 4);
-    {
-        const int np2 = o == 2 ? r->np : 0, np3 = o == 3 ? r->np : 0, gk = o >= 4 ? o : 0;
-        const int stage = stage_cap_for(np2, np3, std::max(r->ds->w4[0], r->ds->w4[1]));
-        const int ent = tab_entries_for(r->ds, r->variant, r->np, false);
-        const int lc = list_cap(r->desc.top_k);
-        r->big_tab = ent > 0 && wgs_per_cu(np2, np3, gk, ent, lc, stage) < wgs_per_cu(np2, np3, gk, 0, lc, stage);
-    }
+    r->big_tab = table_lowers_occupancy(r->ds, r->variant, r->np, o, r->desc.top_k);
     r->pilot_first = (r->n_items - (unsigned long long)r->pilot_n) / 2;
     const uint64_t pair_bytes = sub ? pair_table_bytes(r->variant, r->ds->M) : 0;
     const uint64_t trip_bytes = r->variant == kR4 ? triple_table_bytes(r->ds->M) : 0;
@@ -208,32 +211,72 @@ static Task make_task(Server *S, Request *r) {
         if (e_ != hipSuccess) return fail(EPI_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
     } while (0)
 
-// One round: returns EPI_OK or a device error (which stops the server).
-static int run_round(Server *S) {
+// combos x individuals of one work item of a request
+static unsigned long long item_work(const Request *r) {
+    return (unsigned long long)(r->variant == kGeneric ? 64 * kGenRanksHost : 64 * r->np) * r->ds->N;
+}
+
+// Each request's share of the next round's work: a round is kRoundWork split
+// equally, growing up to 8x with more than four requests (so that one slice
+// per request stays useful).
+static double round_share(const Server *S) {
+    size_t live = 0;
+    for (auto &r : S->active) live += r->finishing ? 0 : 1;
+    const double na = (double)std::max<size_t>(1, live);
+    return kRoundWork * std::min(8.0, std::max(1.0, na / 4.0)) / na;
+}
+
+// Work items of a request's slice in the next round (its remaining items if
+// they fit its share).
+static unsigned long long slice_items(const Request *r, double share) {
+    const unsigned long long n =
+        (unsigned long long)std::max(1.0, share / (double)std::max<unsigned long long>(item_work(r), 1));
+    return std::min(n, r->n_items - r->cursor);
+}
+
+// combos x individuals the next round would cover; -1 if no request is left
+// to run (every active one is finishing in the round in flight).
+static double next_round_work(const Server *S) {
+    const double share = round_share(S);
+    double w = -1;
+    for (auto &r : S->active)
+        if (!r->finishing) w = std::max(w, 0.0) + (double)slice_items(r.get(), share) * (double)item_work(r.get());
+    return w;
+}
+
+// A round enqueued on the server stream: the requests it finishes and its
+// event.  Two rounds may be in flight: the host builds and enqueues the next
+// round while the device runs the current one, then reads the current one's
+// results.
+struct RoundDone {
+    std::vector<Request *> fin;
+    int ev = 0;
+};
+
+// Build and enqueue one round over the active requests that are not already
+// finishing; returns EPI_OK or a device error (which stops the server).
+static int run_round(Server *S, RoundDone *done) {
     Ctx *c = S->ctx;
     hipStream_t st = S->stream;
     // newly admitted requests: zero their counters
     for (auto &r : S->active)
-        if (!r->emit_done && r->cursor == 0) {
+        if (!r->finishing && !r->emit_done && r->cursor == 0) {
             SRV_HIPCHK(launch_init_counters(st, nullptr, 0, S->d_cand_count + r->slot, S->d_thr + r->slot, 1,
                                             S->d_hist + (size_t)r->slot * kHistWords));
         }
     // slices: finishing requests first (their merge results feed finalize)
-    const double na = (double)std::max<size_t>(1, S->active.size());
-    const double share = kRoundWork * std::min(8.0, std::max(1.0, na / 4.0)) / na;
+    const double share = round_share(S);
     std::vector<std::pair<Request *, unsigned long long>> fin, cont;
     for (auto &r : S->active) {
-        const unsigned long long per_item =
-            (unsigned long long)(r->variant == kGeneric ? 64 * kGenRanksHost : 64 * r->np) * r->ds->N;
-        unsigned long long n = (unsigned long long)std::max(1.0, share / (double)std::max<unsigned long long>(per_item, 1));
-        n = std::min(n, r->n_items - r->cursor);
+        if (r->finishing) continue;
+        const unsigned long long n = slice_items(r.get(), share);
         (r->cursor + n >= r->n_items ? fin : cont).push_back({r.get(), n});
     }
     std::vector<std::pair<Request *, unsigned long long>> order = fin;
     order.insert(order.end(), cont.begin(), cont.end());
     const int nt = (int)order.size();
     // task array: [main tasks][emit tasks][launch-group copies]
-    Task *ht = (Task *)S->h_tasks;
+    Task *ht = (Task *)S->h_tasks[S->buf];
     int ti = 0;
     for (auto &pr : order) ht[ti++] = make_task(S, pr.first);
     const int emit_off = ti;
@@ -362,7 +405,7 @@ static int run_round(Server *S) {
     SRV_HIPCHK(launch_merge(nt, st, dt, (Cand *)S->d_parts, (Cand *)S->d_results));
     SRV_HIPCHK(launch_reseed(nt, st, dt, (const Cand *)S->d_results));
     if (!fin.empty()) {
-        ResultLayout *hl = (ResultLayout *)S->h_layout;
+        ResultLayout *hl = (ResultLayout *)S->h_layout[S->buf];
         int maxk = 1;
         for (size_t i = 0; i < fin.size(); ++i) {
             Request *r = fin[i].first;
@@ -382,25 +425,47 @@ static int run_round(Server *S) {
                                       st));
         }
     }
-    SRV_HIPCHK(hipEventRecord(S->ev, st));
-    SRV_HIPCHK(hipEventSynchronize(S->ev));
-    // bookkeeping
+    SRV_HIPCHK(hipEventRecord(S->ev[S->buf], st));
+    done->ev = S->buf;
+    S->buf ^= 1;
+    // bookkeeping of what was enqueued: the next round takes the following
+    // items, and the finishing requests sit out until their results are read
     std::lock_guard<std::mutex> g(S->mu);
     S->rounds++;
     for (auto &pr : order) {
         Request *r = pr.first;
+        // combinations covered so far, estimated as items x the combinations
+        // of a full item up to the request's total, and the total once its
+        // last item is in
+        const unsigned long long per = item_work(r) / (unsigned long long)r->ds->N;
+        auto covered = [&] {
+            return r->cursor >= r->n_items ? r->n_combos : std::min<unsigned long long>(r->cursor * per, r->n_combos);
+        };
+        const unsigned long long before = covered();
         r->cursor += pr.second;
         r->emit_done = true;
-        const unsigned long long per = (unsigned long long)(r->variant == kGeneric ? 64 * kGenRanksHost : 64 * r->np);
-        S->work_done += std::min<unsigned long long>(pr.second * per, r->n_combos) * (unsigned long long)r->ds->N;
+        const unsigned long long after = covered();
+        S->work_done += (after - before) * (unsigned long long)r->ds->N;
     }
+    done->fin.clear();
     for (auto &pr : fin) {
-        Request *r = pr.first;
+        pr.first->finishing = true;
+        done->fin.push_back(pr.first);
+    }
+    return EPI_OK;
+}
+
+// Wait for an enqueued round and hand its finishing requests their results.
+static int complete_round(Server *S, const RoundDone &done) {
+    SRV_HIPCHK(hipEventSynchronize(S->ev[done.ev]));
+    std::lock_guard<std::mutex> g(S->mu);
+    for (Request *r : done.fin) {
         const long long off = (long long)r->slot * S->out_block;
         const long long bytes = result_block_bytes(r->desc.top_k, r->desc.order);
         r->out.assign((char *)S->h_out + off, (char *)S->h_out + off + bytes);
         r->state = 2;
         r->t_done = Clock::now();
+        r->finishing = false;
         free_request_buffers(S, r);
         drop_dataset(r);
         S->n_done++;
@@ -413,7 +478,10 @@ static int run_round(Server *S) {
 
 static void server_main(Server *S) {
     (void)hipSetDevice(S->ctx->device);
+    RoundDone pending;
+    bool have_pending = false;
     for (;;) {
+        double work = -1;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             S->cv.wait_for(lk, std::chrono::milliseconds(50),
@@ -439,9 +507,27 @@ static void server_main(Server *S) {
                 if (S->stopping && S->queue.empty()) return;
                 continue;
             }
+            work = next_round_work(S);
         }
-        const int rc = run_round(S);
+        const int depth = S->cfg.rounds_in_flight;
+        const bool overlap = work >= 0 && (depth == 2 || (depth == 0 && work <= kPipelineWork));
+        int rc = EPI_OK;
+        if (have_pending && !overlap) {
+            // read the round in flight first; requests that arrive meanwhile
+            // then join the next round
+            rc = complete_round(S, pending);
+            have_pending = false;
+            if (rc == EPI_OK) continue;
+        } else if (work >= 0) {
+            // enqueue the next round, then read the one before it
+            RoundDone next;
+            rc = run_round(S, &next);
+            if (rc == EPI_OK && have_pending) rc = complete_round(S, pending);
+            have_pending = rc == EPI_OK;
+            pending = next;
+        }
         if (rc != EPI_OK) {
+            (void)hipStreamSynchronize(S->stream);  // no round in flight past this point
             std::lock_guard<std::mutex> g(S->mu);
             S->fatal = rc;
             for (auto &r : S->active) fail_request(S, r.get(), rc, "device error in a serving round");
@@ -465,10 +551,12 @@ static void server_free(Server *S) {
     c->alloc.release(S->d_parts);
     c->alloc.release(S->d_layout);
     c->alloc.release(S->d_out);
-    if (S->h_tasks) (void)hipHostFree(S->h_tasks);
+    for (int b = 0; b < 2; ++b) {
+        if (S->h_tasks[b]) (void)hipHostFree(S->h_tasks[b]);
+        if (S->h_layout[b]) (void)hipHostFree(S->h_layout[b]);
+        if (S->ev[b]) (void)hipEventDestroy(S->ev[b]);
+    }
     if (S->h_out) (void)hipHostFree(S->h_out);
-    if (S->h_layout) (void)hipHostFree(S->h_layout);
-    if (S->ev) (void)hipEventDestroy(S->ev);
     if (S->stream) (void)hipStreamDestroy(S->stream);
 }
 
@@ -515,7 +603,8 @@ extern "C" {
 int epi_server_start(epi_ctx *ctx, const epi_server_config *cfg, int32_t *server_id) {
     clear_error();
     CTX_OR_FAIL(ctx);
-    if (!cfg || !server_id || cfg->max_active < 1 || cfg->max_active > 4096)
+    if (!cfg || !server_id || cfg->max_active < 1 || cfg->max_active > 4096 || cfg->rounds_in_flight < 0 ||
+        cfg->rounds_in_flight > 2)
         return fail(EPI_EINVAL, "bad server configuration");
     auto S = std::make_shared<Server>();
     S->ctx = C;
@@ -551,11 +640,13 @@ int epi_server_start(epi_ctx *ctx, const epi_server_config *cfg, int32_t *server
     if ((rc = C->alloc.alloc((size_t)A * kMergeParts * kMaxTopK * sizeof(Cand), &S->d_parts))) return cleanup(rc);
     if ((rc = C->alloc.alloc((size_t)A * sizeof(ResultLayout), &S->d_layout))) return cleanup(rc);
     if ((rc = C->alloc.alloc((size_t)A * S->out_block, &S->d_out))) return cleanup(rc);
-    HIPCHK(hipHostMalloc(&S->h_tasks, (size_t)S->max_round_tasks * sizeof(Task), hipHostMallocDefault));
+    for (int b = 0; b < 2; ++b) {
+        HIPCHK(hipHostMalloc(&S->h_tasks[b], (size_t)S->max_round_tasks * sizeof(Task), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc(&S->h_layout[b], (size_t)A * sizeof(ResultLayout), hipHostMallocDefault));
+        HIPCHK(hipEventCreateWithFlags(&S->ev[b], hipEventDisableTiming));
+    }
     HIPCHK(hipHostMalloc(&S->h_out, (size_t)A * S->out_block, hipHostMallocDefault));
-    HIPCHK(hipHostMalloc(&S->h_layout, (size_t)A * sizeof(ResultLayout), hipHostMallocDefault));
     HIPCHK(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&S->ev, hipEventDisableTiming));
     for (int i = A - 1; i >= 0; --i) S->free_slots.push_back(i);
     {
         std::lock_guard<std::mutex> g(C->mu);

@@ -46,7 +46,7 @@ class ScanDesc(_c.Structure):
 
 
 class ServerConfig(_c.Structure):
-    _fields_ = [("max_active", _i32), ("round_items", _i32), ("request_budget", _u64)]
+    _fields_ = [("max_active", _i32), ("rounds_in_flight", _i32), ("request_budget", _u64)]
 
 
 SIGNATURES = {
@@ -453,8 +453,8 @@ def epi_mutual_information(ctx, dataset_id, order, d_tables, d_mi):
     return ms.value
 
 
-def epi_server_start(ctx, max_active=64, round_items=0, request_budget=0):
-    cfg = ServerConfig(max_active, round_items, request_budget)
+def epi_server_start(ctx, max_active=64, rounds_in_flight=0, request_budget=0):
+    cfg = ServerConfig(max_active, rounds_in_flight, request_budget)
     out = _i32()
     _check(lib().epi_server_start(ctx, ctypes.byref(cfg), ctypes.byref(out)))
     return out.value

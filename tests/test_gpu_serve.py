@@ -6,6 +6,7 @@ shared its launch rounds; a sample is also checked against the oracle.
 """
 from __future__ import annotations
 
+import math
 import threading
 import time
 
@@ -46,9 +47,12 @@ def _wait(epi, cx, sid, rid, timeout=120.0):
         time.sleep(0.002)
 
 
-def test_served_equals_alone(cx, orc):
+@pytest.mark.parametrize("depth", [0, 1, 2])
+def test_served_equals_alone(cx, orc, depth):
+    """Same results with one round in flight, two, or the adaptive choice."""
     from paper_2201_02460_amd import epi
 
+    say("rounds in flight", depth)
     data = _datasets(cx)
     reqs = [(0, 3, 20), (1, 2, 15), (2, 3, 40), (3, 4, 12), (4, 2, 9), (0, 2, 30), (1, 4, 7), (2, 2, 50),
             (3, 3, 25), (4, 3, 11), (4, 5, 6), (3, 5, 8)]
@@ -56,7 +60,7 @@ def test_served_equals_alone(cx, orc):
     for di, order, K in reqs:
         ds = data[di][0]
         alone[(di, order, K)] = cx.scan(ds, order, K)
-    sid = epi.epi_server_start(cx.ctx, max_active=4)
+    sid = epi.epi_server_start(cx.ctx, max_active=4, rounds_in_flight=depth)
     ids = []
 
     def submitter():
@@ -77,11 +81,19 @@ def test_served_equals_alone(cx, orc):
     stats = epi.epi_server_stats(cx.ctx, sid)
     say("server stats", stats)
     assert stats["requests_done"] == len(reqs) and stats["peak_active"] <= 4
+    # every combination of every request counted once
+    want = sum(math.comb(data[di][1].shape[0], order) * data[di][1].shape[1] for di, order, _ in reqs)
+    assert stats["combo_samples"] == want
     # orders above the served maximum are refused at submission (plain scans take them)
     with pytest.raises(epi.EpiError) as e:
         epi.epi_server_submit(cx.ctx, sid, data[4][0], epi.EPI_SERVE_MAX_ORDER + 1, 5)
     assert e.value.code == epi.EPI_EUNSUPPORTED
     epi.epi_server_stop(cx.ctx, sid)
+    # a depth outside 0..2 is refused
+    for bad in (-1, 3):
+        with pytest.raises(epi.EpiError) as e:
+            epi.epi_server_start(cx.ctx, max_active=4, rounds_in_flight=bad)
+        assert e.value.code == epi.EPI_EINVAL
     # one served result against the oracle as well
     di, order, K = reqs[2]
     a = alone[reqs[2]]
