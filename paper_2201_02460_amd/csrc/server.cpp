@@ -82,6 +82,7 @@ struct Server {
     // flight (a round's copies read them when the stream reaches them)
     void *h_tasks[2] = {nullptr, nullptr}, *h_out = nullptr, *h_layout[2] = {nullptr, nullptr};
     int buf = 0;  // staging buffer and event of the next round
+    bool backlog = false;  // requests waiting for admission (server thread only)
     unsigned long long *d_queues = nullptr, *d_thr = nullptr;
     unsigned *d_hist = nullptr;  // kHistWords per slot
     unsigned *d_cand_count = nullptr;
@@ -218,12 +219,16 @@ static unsigned long long item_work(const Request *r) {
 
 // Each request's share of the next round's work: a round is kRoundWork split
 // equally, growing up to 8x with more than four requests (so that one slice
-// per request stays useful).
+// per request stays useful), and kBacklogRounds times that while requests
+// wait for admission: rounds of small slices cost the scan kernels several
+// per cent of their time, which only matters while the device is the
+// bottleneck; otherwise short rounds let new requests start sooner.
+static const double kBacklogRounds = 4;
 static double round_share(const Server *S) {
     size_t live = 0;
     for (auto &r : S->active) live += r->finishing ? 0 : 1;
     const double na = (double)std::max<size_t>(1, live);
-    return kRoundWork * std::min(8.0, std::max(1.0, na / 4.0)) / na;
+    return kRoundWork * std::min(8.0, std::max(1.0, na / 4.0)) * (S->backlog ? kBacklogRounds : 1.0) / na;
 }
 
 // Work items of a request's slice in the next round (its remaining items if
@@ -234,13 +239,20 @@ static unsigned long long slice_items(const Request *r, double share) {
     return std::min(n, r->n_items - r->cursor);
 }
 
+// Each running request's slice of the next round, in work items.
+static std::vector<std::pair<Request *, unsigned long long>> round_slices(const Server *S) {
+    const double share = round_share(S);
+    std::vector<std::pair<Request *, unsigned long long>> sl;
+    for (auto &r : S->active)
+        if (!r->finishing) sl.push_back({r.get(), slice_items(r.get(), share)});
+    return sl;
+}
+
 // combos x individuals the next round would cover; -1 if no request is left
 // to run (every active one is finishing in the round in flight).
 static double next_round_work(const Server *S) {
-    const double share = round_share(S);
     double w = -1;
-    for (auto &r : S->active)
-        if (!r->finishing) w = std::max(w, 0.0) + (double)slice_items(r.get(), share) * (double)item_work(r.get());
+    for (auto &p : round_slices(S)) w = std::max(w, 0.0) + (double)p.second * (double)item_work(p.first);
     return w;
 }
 
@@ -265,13 +277,8 @@ static int run_round(Server *S, RoundDone *done) {
                                             S->d_hist + (size_t)r->slot * kHistWords));
         }
     // slices: finishing requests first (their merge results feed finalize)
-    const double share = round_share(S);
     std::vector<std::pair<Request *, unsigned long long>> fin, cont;
-    for (auto &r : S->active) {
-        if (r->finishing) continue;
-        const unsigned long long n = slice_items(r.get(), share);
-        (r->cursor + n >= r->n_items ? fin : cont).push_back({r.get(), n});
-    }
+    for (auto &p : round_slices(S)) (p.first->cursor + p.second >= p.first->n_items ? fin : cont).push_back(p);
     std::vector<std::pair<Request *, unsigned long long>> order = fin;
     order.insert(order.end(), cont.begin(), cont.end());
     const int nt = (int)order.size();
@@ -503,6 +510,7 @@ static void server_main(Server *S) {
                 S->active.push_back(r);
             }
             S->peak_active = std::max<uint64_t>(S->peak_active, S->active.size());
+            S->backlog = !S->queue.empty();
             if (S->active.empty()) {
                 if (S->stopping && S->queue.empty()) return;
                 continue;
