@@ -84,12 +84,15 @@ def _draw_genotypes(rng, probs, n):
     return ((u >= c0).astype(np.uint8) + (u >= c1).astype(np.uint8)).astype(np.uint8)
 
 
-def make_case_control(M, N, n_cases, planted, seed, prevalence=0.1, h2=0.1):
+def make_case_control(M, N, n_cases, planted, seed, prevalence=0.1, h2=0.1, planted_maf=(0.3, 0.5)):
     """Genotypes ``G`` (uint8, M x N, SNP-major) and phenotype ``y`` (uint8, 1 = case).
 
     ``planted`` is a sequence of distinct SNP indices (may be empty for null
-    data).  Returns ``(G, y, info)`` with ``info`` holding the MAFs, the
-    planted set and the achieved heritability.
+    data).  The planted SNPs draw their MAF from ``planted_maf`` (the other
+    SNPs from U(0.05, 0.5)): a rare planted allele makes the penetrance
+    table's extreme cells cap the interaction's effect far below ``h2``.
+    Returns ``(G, y, info)`` with ``info`` holding the MAFs, the planted set
+    and the achieved heritability.
     """
     M, N, n_cases = int(M), int(N), int(n_cases)
     if not (0 < n_cases < N):
@@ -99,6 +102,8 @@ def make_case_control(M, N, n_cases, planted, seed, prevalence=0.1, h2=0.1):
         raise ValueError("planted SNPs must be distinct indices in [0, M)")
     rng = np.random.default_rng(seed)
     maf = rng.uniform(0.05, 0.5, M)
+    if planted:
+        maf[planted] = rng.uniform(planted_maf[0], planted_maf[1], len(planted))
     probs = hwe_probs(maf)
     n_ctrl = N - n_cases
     info = {"maf": maf, "planted": tuple(planted), "h2": 0.0, "seed": seed}

@@ -3,7 +3,8 @@ import itertools
 
 import numpy as np
 
-from synth import WORKLOADS, batched_specs, hwe_probs, make_case_control, planted_penetrance, served_pool_specs
+from synth import (WORKLOADS, batched_specs, hwe_probs, make_case_control, make_workload, planted_penetrance,
+                   served_pool_specs)
 
 
 def test_deterministic_and_sized():
@@ -34,6 +35,18 @@ def test_penetrance_has_no_marginal_effect():
                 marg = (joint * f).sum(axis=rest) / joint.sum(axis=rest)
                 assert np.allclose(marg, 0.1, atol=1e-12)
         assert 0 < h2 <= 0.1 + 1e-12 and (f >= 0).all() and (f <= 1).all()
+
+
+def test_planted_maf_and_strength():
+    # planted SNPs draw their MAF from [0.3, 0.5], which keeps the achieved
+    # heritability of every named workload well above the cap that rare
+    # planted alleles impose
+    for name in WORKLOADS:
+        G, y, spec, info = make_workload(name)
+        pm = info["maf"][list(spec["planted"])]
+        assert np.all((pm >= 0.3) & (pm <= 0.5)), name
+        assert info["h2"] >= 0.02, (name, info["h2"])
+        assert abs(info["h2"] - planted_penetrance(pm, 0.1, 0.1)[1]) < 1e-15
 
 
 def test_hwe_frequencies():
