@@ -64,6 +64,12 @@ struct Server {
     epi_server_config cfg{};
     hipStream_t stream = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};  // end of the two rounds that may be in flight
+    // side streams for a round's launch groups: each group's launch ends in a
+    // tail (the waves that finish first wait for the last items), which the
+    // next group, on another stream, fills
+    static constexpr int kSide = 2;
+    hipStream_t side[kSide] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[kSide] = {};
     std::thread thread;
     std::mutex mu;
     std::condition_variable cv;
@@ -397,16 +403,30 @@ static int run_round(Server *S, RoundDone *done) {
         SRV_HIPCHK(launch_scan(0, kNpMfma, 0, tg, st, dt + t3_off, n_t3, t3_total, S->d_queues + 1, c->d_binom,
                                c->bstride, 0, 1, ts));
     }
+    // launch groups round-robin over the server stream and the side streams
+    // (they touch disjoint requests and queue counters; the side streams
+    // start after the pair passes above and the merge below waits for them)
+    const int n_side = std::min<int>(Server::kSide, (int)groups.size() - 1);
+    if (n_side > 0) {
+        SRV_HIPCHK(hipEventRecord(S->ev_fork, st));
+        for (int k = 0; k < n_side; ++k) SRV_HIPCHK(hipStreamWaitEvent(S->side[k], S->ev_fork, 0));
+    }
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         const G &g = groups[gi];
+        const int lane_s = (int)(gi % (size_t)(Server::kSide + 1));
+        hipStream_t gs = lane_s == 0 ? st : S->side[lane_s - 1];
         const int grid = grid_for(c, g.np2, g.np3, g.gk, g.total, g.tab_cap, g.kmax, g.stage);
         if (g.pilot_total > 0)
             SRV_HIPCHK(launch_pilot(g.np2, g.np3, g.gk,
                                     (int)std::min<unsigned long long>(std::min(grid, S->grid_max), g.pilot_total / 4),
-                                    st, dt + g.pilot_off, g.pilot_tasks, g.pilot_total, c->d_binom, c->bstride,
+                                    gs, dt + g.pilot_off, g.pilot_tasks, g.pilot_total, c->d_binom, c->bstride,
                                     g.tab_cap, g.kmax, g.stage));
-        SRV_HIPCHK(launch_scan(g.np2, g.np3, g.gk, std::min(grid, S->grid_max), st, dt + g.off, g.n, g.total,
+        SRV_HIPCHK(launch_scan(g.np2, g.np3, g.gk, std::min(grid, S->grid_max), gs, dt + g.off, g.n, g.total,
                                S->d_queues + 2 + gi, c->d_binom, c->bstride, g.tab_cap, g.kmax, g.stage));
+    }
+    for (int k = 0; k < n_side; ++k) {
+        SRV_HIPCHK(hipEventRecord(S->ev_join[k], S->side[k]));
+        SRV_HIPCHK(hipStreamWaitEvent(st, S->ev_join[k], 0));
     }
     // compact every request's candidates to its best K; finish the done ones
     SRV_HIPCHK(launch_merge(nt, st, dt, (Cand *)S->d_parts, (Cand *)S->d_results));
@@ -535,7 +555,9 @@ static void server_main(Server *S) {
             pending = next;
         }
         if (rc != EPI_OK) {
-            (void)hipStreamSynchronize(S->stream);  // no round in flight past this point
+            // no round in flight past this point
+            (void)hipStreamSynchronize(S->stream);
+            for (int k = 0; k < Server::kSide; ++k) (void)hipStreamSynchronize(S->side[k]);
             std::lock_guard<std::mutex> g(S->mu);
             S->fatal = rc;
             for (auto &r : S->active) fail_request(S, r.get(), rc, "device error in a serving round");
@@ -565,6 +587,11 @@ static void server_free(Server *S) {
         if (S->ev[b]) (void)hipEventDestroy(S->ev[b]);
     }
     if (S->h_out) (void)hipHostFree(S->h_out);
+    for (int k = 0; k < Server::kSide; ++k) {
+        if (S->side[k]) (void)hipStreamDestroy(S->side[k]);
+        if (S->ev_join[k]) (void)hipEventDestroy(S->ev_join[k]);
+    }
+    if (S->ev_fork) (void)hipEventDestroy(S->ev_fork);
     if (S->stream) (void)hipStreamDestroy(S->stream);
 }
 
@@ -655,6 +682,11 @@ int epi_server_start(epi_ctx *ctx, const epi_server_config *cfg, int32_t *server
     }
     HIPCHK(hipHostMalloc(&S->h_out, (size_t)A * S->out_block, hipHostMallocDefault));
     HIPCHK(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
+    for (int k = 0; k < Server::kSide; ++k) {
+        HIPCHK(hipStreamCreateWithFlags(&S->side[k], hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&S->ev_join[k], hipEventDisableTiming));
+    }
+    HIPCHK(hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming));
     for (int i = A - 1; i >= 0; --i) S->free_slots.push_back(i);
     {
         std::lock_guard<std::mutex> g(C->mu);
